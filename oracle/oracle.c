@@ -1,0 +1,899 @@
+/*
+ * Plain FP64 CPU oracle of the nested continuation-value Monte Carlo
+ * (Doan et al., INRIA RR-6530, 2008).  TEST INFRASTRUCTURE ONLY: it checks the
+ * GPU library and is never part of the product path.
+ *
+ * Written for a reader holding the paper: every routine follows the method's
+ * steps in the paper's order, with no blocking, fusion or reordering.  Build
+ * with -ffp-contract=off so that every product and sum rounds as written.
+ *
+ * Paper map:
+ *   GBM market model, payoffs ............ Section 2.2 and Section 3.2
+ *   continuation ("small BA option") ...... Section 3.2, data-generation step
+ *   CMC stopping rule tau = min{F > 0} .... Section 3.2
+ *   CMC training points by Brownian bridge  Section 3.2 and Section 3.3
+ *   boosting classification [class] ....... Section 3.2, Algorithm 2
+ *   I&Z matched condition P_t(S*) = I(S*) . Section 2.1, eq. (1)
+ *   I&Z boundary-point iteration, eps ..... Section 2.4
+ *   lattice points [glp], regression [reg]  Section 2.3, Algorithm 1
+ *   final pricing [mc] and merge .......... Algorithms 1 and 2
+ * Readings where the paper is silent (random-number layout, features, the
+ * boosting base learner, lattice choice) are the written definitions the GPU
+ * library also follows; each is stated at the routine that implements it.
+ */
+#define _GNU_SOURCE
+#include "oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <sched.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The paper names no
+ * generator; a counter-based one lets every (date, point, path, step) draw be
+ * addressed directly.                                                        */
+
+void orc_philox(uint32_t k0, uint32_t k1, const uint32_t ctr[4], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in (0,1): u = (x + 1/2) / 2^32, exact in double. */
+static double word_to_uniform(uint32_t x)
+{
+    return ((double)x + 0.5) * 0x1p-32;
+}
+
+/* Box-Muller on word pairs (0,1) and (2,3):
+ *   z0 = sqrt(-2 ln u0) cos(2 pi u1),  z1 = sqrt(-2 ln u0) sin(2 pi u1),
+ *   z2, z3 likewise from (u2, u3). */
+void orc_normal_block(uint32_t k0, uint32_t k1, const uint32_t ctr[4], double z[4])
+{
+    uint32_t w[4];
+    orc_philox(k0, k1, ctr, w);
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    for (int h = 0; h < 2; ++h) {
+        double ua = word_to_uniform(w[2 * h]);
+        double ub = word_to_uniform(w[2 * h + 1]);
+        double radius = sqrt(-2.0 * log(ua));
+        z[2 * h] = radius * cos(two_pi * ub);
+        z[2 * h + 1] = radius * sin(two_pi * ub);
+    }
+}
+
+/* Key: (seed, stream << 16 | date).  The date field keeps the draws of
+ * different dates independent. */
+static uint32_t key_hi(int stream, int date)
+{
+    return ((uint32_t)stream << 16) | ((uint32_t)date & 0xFFFFu);
+}
+
+/* The d normals of one GBM step.  Step k (absolute date index 1..N_T) of path
+ * p from point j uses B = ceil(d/4) blocks with counters (k*B + b, p, j, 0);
+ * asset i takes normal i mod 4 of block i / 4. */
+static void step_normals(int d, uint32_t k0, uint32_t k1, int k, uint32_t p,
+                         uint32_t j, double *z)
+{
+    int nblk = (d + 3) / 4;
+    for (int b = 0; b < nblk; ++b) {
+        uint32_t ctr[4] = {(uint32_t)(k * nblk + b), p, j, 0u};
+        double blk[4];
+        orc_normal_block(k0, k1, ctr, blk);
+        for (int w = 0; w < 4 && 4 * b + w < d; ++w)
+            z[4 * b + w] = blk[w];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Correlation: lower Cholesky factor L with L L^T = rho.                     */
+
+int orc_cholesky(int d, const double *rho, double *L)
+{
+    for (int i = 0; i < d * d; ++i) L[i] = 0.0;
+    for (int i = 0; i < d; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double acc = rho[i * d + j];
+            for (int l = 0; l < j; ++l) acc -= L[i * d + l] * L[j * d + l];
+            if (i == j) {
+                if (!(acc > 0.0)) return ORC_ENOTSPD;
+                L[i * d + i] = sqrt(acc);
+            } else {
+                L[i * d + j] = acc / L[j * d + j];
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Spec helpers.                                                              */
+
+static double date_of(const orc_spec *s, int k)
+{
+    return k == 0 ? 0.0 : s->dates[k - 1];
+}
+
+static int check_spec(const orc_spec *s)
+{
+    if (!s || s->d < 1 || s->d > 64 || s->n_dates < 1 || s->n_dates > 65535) return ORC_EINVAL;
+    if (!(s->K > 0.0) || !(s->T > 0.0)) return ORC_EINVAL;
+    double prev = 0.0;
+    for (int k = 0; k < s->n_dates; ++k) {
+        if (!(s->dates[k] > prev)) return ORC_EINVAL;
+        prev = s->dates[k];
+    }
+    if (fabs(prev - s->T) > 1e-12 * s->T) return ORC_EINVAL;
+    for (int i = 0; i < s->d; ++i) {
+        if (!(s->sigma[i] >= 0.0) || !(s->S0[i] > 0.0)) return ORC_EINVAL;
+        if (fabs(s->rho[i * s->d + i] - 1.0) > 1e-12) return ORC_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (fabs(s->rho[i * s->d + j] - s->rho[j * s->d + i]) > 1e-12) return ORC_EINVAL;
+    }
+    if (s->payoff < ORC_PUT_BASKET || s->payoff > ORC_PUT_GEO) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+/* Payoffs of Sections 2.1-2.2 and 3.2, evaluated from S_i = exp(logS_i):
+ * arithmetic basket put (K - mean S)^+, max-call (max S - K)^+,
+ * geometric-average put (K - (prod S)^(1/d))^+. */
+double orc_payoff(const orc_spec *s, const double *logS)
+{
+    int d = s->d;
+    double v = 0.0;
+    if (s->payoff == ORC_PUT_BASKET) {
+        double mean = 0.0;
+        for (int i = 0; i < d; ++i) mean += exp(logS[i]);
+        mean /= d;
+        v = s->K - mean;
+    } else if (s->payoff == ORC_CALL_MAX) {
+        double mx = exp(logS[0]);
+        for (int i = 1; i < d; ++i) {
+            double Si = exp(logS[i]);
+            if (Si > mx) mx = Si;
+        }
+        v = mx - s->K;
+    } else {
+        double meanlog = 0.0;
+        for (int i = 0; i < d; ++i) meanlog += logS[i];
+        v = s->K - exp(meanlog / d);
+    }
+    return v > 0.0 ? v : 0.0;
+}
+
+int orc_rule_width(int method, int d)
+{
+    if (method == ORC_CMC) return 2 * d + 3;
+    int q = d - 1;
+    return 1 + q + q * (q + 1) / 2;
+}
+
+/* CMC features (reading of Section 3.2; the paper defers the classifier's
+ * inputs to the Picazo reference): with u_i = ln(S_i / K) and g = Phi(S)/K,
+ *   phi(S) = [1, u_1..u_d, u_1^2..u_d^2, g, g^2]. */
+static void cmc_features(const orc_spec *s, const double *logS, double payoff, double *phi)
+{
+    int d = s->d;
+    double lnK = log(s->K);
+    phi[0] = 1.0;
+    for (int i = 0; i < d; ++i) {
+        double u = logS[i] - lnK;
+        phi[1 + i] = u;
+        phi[1 + d + i] = u * u;
+    }
+    double g = payoff / s->K;
+    phi[1 + 2 * d] = g;
+    phi[2 + 2 * d] = g * g;
+}
+
+/* I&Z boundary features: full quadratic in v_i = ln(S_i/K) of assets 2..d,
+ * ordered [1, v_2..v_d, v_a v_b for a <= b]. */
+static void iz_features(const orc_spec *s, const double *logS, double *xi)
+{
+    int q = s->d - 1;
+    double lnK = log(s->K);
+    xi[0] = 1.0;
+    for (int a = 0; a < q; ++a) xi[1 + a] = logS[1 + a] - lnK;
+    int f = 1 + q;
+    for (int a = 0; a < q; ++a)
+        for (int b = a; b < q; ++b) xi[f++] = xi[1 + a] * xi[1 + b];
+}
+
+/* I&Z searches the first asset.  Puts exercise below the boundary; the
+ * one-asset call exercises above it. */
+static int iz_direction_is_call(const orc_spec *s)
+{
+    return s->payoff == ORC_CALL_MAX;
+}
+
+static const double IZ_NEVER = 1e300;
+
+/* Exercise test at an intermediate date (Section 3.2 stopping time for CMC;
+ * crossing of the regressed boundary for I&Z).  Ties continue. */
+static int exercise_now(const orc_spec *s, int method, const double *row,
+                        const double *logS, double payoff)
+{
+    if (!(payoff > 0.0)) return 0;
+    if (method == ORC_CMC) {
+        double phi[2 * 64 + 3];
+        cmc_features(s, logS, payoff, phi);
+        int p = orc_rule_width(ORC_CMC, s->d);
+        double F = 0.0;
+        for (int f = 0; f < p; ++f) F += row[f] * phi[f];
+        return F > 0.0;
+    }
+    double xi[1 + 63 + 63 * 64 / 2];
+    iz_features(s, logS, xi);
+    int p = orc_rule_width(ORC_IZ, s->d);
+    double bnd = 0.0;
+    for (int f = 0; f < p; ++f) bnd += row[f] * xi[f];
+    if (iz_direction_is_call(s)) return logS[0] > bnd;
+    return logS[0] < bnd;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Inner paths: the "small BA option" on [t_m, T] started at one point.       */
+
+typedef struct {
+    const orc_spec *s;
+    int method;
+    const double *rules;
+    int width;
+    int m;
+    const double *L;     /* d*d */
+    uint32_t k0, k1;
+} path_ctx;
+
+/* Runs paths p_lo..p_hi-1 of point j from log-point logx; accumulates the
+ * discounted payoffs (sum, sum of squares) and executed path-steps. */
+static void run_paths(const path_ctx *c, const double *logx, uint32_t j,
+                      int64_t p_lo, int64_t p_hi, double *sum, double *sumsq,
+                      int64_t *steps)
+{
+    const orc_spec *s = c->s;
+    int d = s->d, NT = s->n_dates, m = c->m;
+    double logS[64], z[64];
+    double tm = date_of(s, m);
+    for (int64_t p = p_lo; p < p_hi; ++p) {
+        for (int i = 0; i < d; ++i) logS[i] = logx[i];
+        for (int k = m + 1; k <= NT; ++k) {
+            double dt = date_of(s, k) - date_of(s, k - 1);
+            step_normals(d, c->k0, c->k1, k, (uint32_t)p, j, z);
+            for (int i = 0; i < d; ++i) {
+                double corr = 0.0;
+                for (int l = 0; l <= i; ++l) corr += c->L[i * d + l] * z[l];
+                double drift = s->r - s->delta[i] - 0.5 * s->sigma[i] * s->sigma[i];
+                logS[i] += drift * dt + s->sigma[i] * sqrt(dt) * corr;
+            }
+            double payoff = orc_payoff(s, logS);
+            int stop = (k == NT);
+            if (!stop) stop = exercise_now(s, c->method, c->rules + (size_t)k * c->width, logS, payoff);
+            if (stop) {
+                double pay = exp(-s->r * (date_of(s, k) - tm)) * payoff;
+                *sum += pay;
+                *sumsq += pay * pay;
+                *steps += k - m;
+                break;
+            }
+        }
+    }
+}
+
+static int resolve_threads(int nthreads)
+{
+    if (nthreads > 0) return nthreads;
+    cpu_set_t set;
+    if (sched_getaffinity(0, sizeof(set), &set) == 0) {
+        int c = CPU_COUNT(&set);
+        if (c > 0) return c;
+    }
+    return 1;
+}
+
+/* Work split: items are (point, chunk of CHUNK paths).  Partial sums of each
+ * chunk are merged in chunk order, so results do not depend on the thread
+ * count. */
+enum { CHUNK = 4096 };
+
+typedef struct {
+    const path_ctx *c;
+    const double *x;
+    int64_t N, n, nchunk;
+    double *psum, *psq;
+    int64_t *pst;
+    int64_t next_item;
+    pthread_mutex_t lock;
+} cont_job;
+
+static void *cont_worker(void *arg)
+{
+    cont_job *job = (cont_job *)arg;
+    int d = job->c->s->d;
+    double logx[64];
+    for (;;) {
+        pthread_mutex_lock(&job->lock);
+        int64_t item = job->next_item++;
+        pthread_mutex_unlock(&job->lock);
+        if (item >= job->N * job->nchunk) break;
+        int64_t j = item / job->nchunk, ch = item % job->nchunk;
+        for (int i = 0; i < d; ++i) logx[i] = log(job->x[(size_t)i * job->N + j]);
+        int64_t lo = ch * CHUNK, hi = lo + CHUNK < job->n ? lo + CHUNK : job->n;
+        double sum = 0.0, sq = 0.0;
+        int64_t st = 0;
+        run_paths(job->c, logx, (uint32_t)j, lo, hi, &sum, &sq, &st);
+        job->psum[item] = sum;
+        job->psq[item] = sq;
+        job->pst[item] = st;
+    }
+    return NULL;
+}
+
+int orc_continuation(const orc_spec *s, int method, const double *rules, int m,
+                     const double *x, int64_t N, int64_t n, uint32_t seed,
+                     int stream, int nthreads, double *cont, double *se,
+                     int64_t *steps, double *sum, double *sumsq)
+{
+    int rc = check_spec(s);
+    if (rc) return rc;
+    if (m < 0 || m >= s->n_dates || N < 1 || n < 2 || n > 0xFFFFFFFFll || N > 0xFFFFFFFFll)
+        return ORC_EINVAL;
+    int d = s->d;
+    double *L = malloc(sizeof(double) * d * d);
+    if (!L) return ORC_ENOMEM;
+    rc = orc_cholesky(d, s->rho, L);
+    if (rc) { free(L); return rc; }
+    path_ctx c = {s, method, rules, orc_rule_width(method, d), m, L, seed, key_hi(stream, m)};
+    cont_job job;
+    job.c = &c; job.x = x; job.N = N; job.n = n;
+    job.nchunk = (n + CHUNK - 1) / CHUNK;
+    job.psum = malloc(sizeof(double) * N * job.nchunk);
+    job.psq = malloc(sizeof(double) * N * job.nchunk);
+    job.pst = malloc(sizeof(int64_t) * N * job.nchunk);
+    job.next_item = 0;
+    pthread_mutex_init(&job.lock, NULL);
+    if (!job.psum || !job.psq || !job.pst) {
+        free(job.psum); free(job.psq); free(job.pst); free(L);
+        return ORC_ENOMEM;
+    }
+    int nt = resolve_threads(nthreads);
+    if (nt > N * job.nchunk) nt = (int)(N * job.nchunk);
+    pthread_t *th = malloc(sizeof(pthread_t) * nt);
+    for (int t = 0; t < nt; ++t) pthread_create(&th[t], NULL, cont_worker, &job);
+    for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+    free(th);
+    for (int64_t j = 0; j < N; ++j) {
+        double a = 0.0, b = 0.0;
+        int64_t st = 0;
+        for (int64_t ch = 0; ch < job.nchunk; ++ch) {
+            a += job.psum[j * job.nchunk + ch];
+            b += job.psq[j * job.nchunk + ch];
+            st += job.pst[j * job.nchunk + ch];
+        }
+        double mean = a / (double)n;
+        double var = (b - a * a / (double)n) / (double)(n - 1);
+        if (var < 0.0) var = 0.0;
+        if (cont) cont[j] = mean;
+        if (se) se[j] = sqrt(var / (double)n);
+        if (steps) steps[j] = st;
+        if (sum) sum[j] = a;
+        if (sumsq) sumsq[j] = b;
+    }
+    pthread_mutex_destroy(&job.lock);
+    free(job.psum); free(job.psq); free(job.pst); free(L);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* CMC training points: independent Brownian components B, drawn at T and
+ * bridged backward date by date (Sections 3.2-3.3):
+ *   B_T = sqrt(T) Z,
+ *   B_{t_m} = (t_m / t_{m+1}) B_{t_{m+1}} + sqrt(t_m (t_{m+1} - t_m) / t_{m+1}) Z,
+ *   x_i = S0_i exp((r - delta_i - sigma_i^2/2) t_m + sigma_i (L B_{t_m})_i).
+ * Z of point j at date m: OUTER stream, key date m, counters (b, 0, j, 0). */
+
+static void outer_normals(int d, uint32_t seed, int date, uint32_t j, double *z)
+{
+    int nblk = (d + 3) / 4;
+    uint32_t k1 = key_hi(ORC_STREAM_OUTER, date);
+    for (int b = 0; b < nblk; ++b) {
+        uint32_t ctr[4] = {(uint32_t)b, 0u, j, 0u};
+        double blk[4];
+        orc_normal_block(seed, k1, ctr, blk);
+        for (int w = 0; w < 4 && 4 * b + w < d; ++w) z[4 * b + w] = blk[w];
+    }
+}
+
+static void bridge_endpoint(const orc_spec *s, int64_t N, uint32_t seed, double *B)
+{
+    int d = s->d, NT = s->n_dates;
+    double z[64];
+    double tN = date_of(s, NT);
+    for (int64_t j = 0; j < N; ++j) {
+        outer_normals(d, seed, NT, (uint32_t)j, z);
+        for (int i = 0; i < d; ++i) B[(size_t)i * N + j] = sqrt(tN) * z[i];
+    }
+}
+
+/* B holds date m+1 on entry and date m on exit. */
+static void bridge_back(const orc_spec *s, int m, int64_t N, uint32_t seed, double *B)
+{
+    int d = s->d;
+    double z[64];
+    double t0 = date_of(s, m), t1 = date_of(s, m + 1);
+    double mean_f = t0 / t1;
+    double sd = sqrt(t0 * (t1 - t0) / t1);
+    for (int64_t j = 0; j < N; ++j) {
+        outer_normals(d, seed, m, (uint32_t)j, z);
+        for (int i = 0; i < d; ++i)
+            B[(size_t)i * N + j] = mean_f * B[(size_t)i * N + j] + sd * z[i];
+    }
+}
+
+static void points_from_bridge(const orc_spec *s, const double *L, int m, int64_t N,
+                               const double *B, double *x)
+{
+    int d = s->d;
+    double tm = date_of(s, m);
+    for (int64_t j = 0; j < N; ++j) {
+        for (int i = 0; i < d; ++i) {
+            double w = 0.0;
+            for (int l = 0; l <= i; ++l) w += L[i * d + l] * B[(size_t)l * N + j];
+            double drift = s->r - s->delta[i] - 0.5 * s->sigma[i] * s->sigma[i];
+            x[(size_t)i * N + j] = s->S0[i] * exp(drift * tm + s->sigma[i] * w);
+        }
+    }
+}
+
+int orc_points_cmc(const orc_spec *s, int m, int64_t N, uint32_t seed, double *x)
+{
+    int rc = check_spec(s);
+    if (rc) return rc;
+    if (m < 1 || m > s->n_dates || N < 1) return ORC_EINVAL;
+    int d = s->d;
+    double *L = malloc(sizeof(double) * d * d);
+    double *B = malloc(sizeof(double) * d * N);
+    if (!L || !B) { free(L); free(B); return ORC_ENOMEM; }
+    rc = orc_cholesky(d, s->rho, L);
+    if (!rc) {
+        bridge_endpoint(s, N, seed, B);
+        for (int mm = s->n_dates - 1; mm >= m; --mm) bridge_back(s, mm, N, seed, B);
+        points_from_bridge(s, L, m, N, B, x);
+    }
+    free(L); free(B);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* I&Z lattice points [glp] (Section 2.3).  The paper takes them from SSJ or
+ * quantization files; here a rank-1 Korobov lattice in the q = d-1 free
+ * coordinates, u_j = frac((j g + 1/2) / J) with g = (1, a, a^2, ...) mod J,
+ * whose generator a maximises the minimal toroidal distance (ties: smallest
+ * a).  Coordinates map to prices through the lognormal quantile of S_{t_m}. */
+
+int64_t orc_korobov(int64_t J, int q)
+{
+    if (q <= 1 || J <= 2) return 1;
+    int64_t best_a = 1, best = -1;
+    int64_t g[64];
+    for (int64_t a = 1; a < J; ++a) {
+        g[0] = 1;
+        for (int i = 1; i < q; ++i) g[i] = (g[i - 1] * a) % J;
+        int64_t dmin = INT64_MAX;
+        for (int64_t jj = 1; jj < J && dmin > best; ++jj) {
+            int64_t dist = 0;
+            for (int i = 0; i < q; ++i) {
+                int64_t v = (jj * g[i]) % J;
+                if (J - v < v) v = J - v;
+                dist += v * v;
+            }
+            if (dist < dmin) dmin = dist;
+        }
+        if (dmin > best) { best = dmin; best_a = a; }
+    }
+    return best_a;
+}
+
+static double norm_cdf(double x)
+{
+    return 0.5 * erfc(-x / sqrt(2.0));
+}
+
+/* Inverse standard normal CDF by bisection on the CDF. */
+static double norm_inv(double u)
+{
+    double lo = -40.0, hi = 40.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (norm_cdf(mid) < u) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+int orc_points_iz(const orc_spec *s, int m, int64_t J, double *x)
+{
+    int rc = check_spec(s);
+    if (rc) return rc;
+    if (m < 1 || m > s->n_dates || J < 1) return ORC_EINVAL;
+    int d = s->d, q = d - 1;
+    double tm = date_of(s, m);
+    int64_t a = orc_korobov(J, q);
+    int64_t g[64];
+    if (q > 0) {
+        g[0] = 1;
+        for (int i = 1; i < q; ++i) g[i] = (g[i - 1] * a) % J;
+    }
+    for (int64_t j = 0; j < J; ++j) {
+        x[j] = s->K;
+        for (int i = 0; i < q; ++i) {
+            double u = ((double)((j * g[i]) % J) + 0.5) / (double)J;
+            int asset = i + 1;
+            double drift = s->r - s->delta[asset] - 0.5 * s->sigma[asset] * s->sigma[asset];
+            x[(size_t)asset * J + j] =
+                s->S0[asset] * exp(drift * tm + s->sigma[asset] * sqrt(tm) * norm_inv(u));
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Small dense solver: Cholesky of (A + lambda I), then two triangular solves. */
+
+static int spd_solve(int p, const double *A, double lambda, const double *b, double *out)
+{
+    double *C = malloc(sizeof(double) * p * p);
+    double *y = malloc(sizeof(double) * p);
+    if (!C || !y) { free(C); free(y); return ORC_ENOMEM; }
+    for (int i = 0; i < p * p; ++i) C[i] = A[i];
+    for (int i = 0; i < p; ++i) C[i * p + i] += lambda;
+    double *L = malloc(sizeof(double) * p * p);
+    if (!L) { free(C); free(y); return ORC_ENOMEM; }
+    int rc = orc_cholesky(p, C, L);   /* generic factor; C need not have unit diagonal */
+    if (rc) { free(C); free(y); free(L); return rc; }
+    for (int i = 0; i < p; ++i) {
+        double acc = b[i];
+        for (int l = 0; l < i; ++l) acc -= L[i * p + l] * y[l];
+        y[i] = acc / L[i * p + i];
+    }
+    for (int i = p - 1; i >= 0; --i) {
+        double acc = y[i];
+        for (int l = i + 1; l < p; ++l) acc -= L[l * p + i] * out[l];
+        out[i] = acc / L[i * p + i];
+    }
+    free(C); free(y); free(L);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* CMC classification [class] (Section 3.2, Algorithm 2).  The paper uses
+ * AdaBoost or LogitBoost with parameters from the Picazo reference.  Reading:
+ * LogitBoost (Friedman, Hastie, Tibshirani 2000) with a weighted
+ * least-squares linear base learner on the standardised features, fitted on
+ * the in-the-money training points.  Label e_j = 1 iff Phi(x_j) - C_j > 0.
+ * Each round:  w = max(pi(1-pi), 1e-10),  z = clip((e - pi)/w, -4, 4),
+ *   beta = (Psi^T W Psi + lambda I)^-1 Psi^T W z,  lambda = 1e-8 tr(.)/p,
+ *   F += beta/2,  pi = 1/(1 + exp(-2F)).
+ * The standardisation is folded into the returned weights so that
+ * F(x) = sum_f w_f phi_f(x) on raw features; exercise iff Phi > 0 and F > 0. */
+
+int orc_fit_cmc(const orc_spec *s, const double *x, const double *cont,
+                int64_t N, int rounds, double *w)
+{
+    int rc = check_spec(s);
+    if (rc) return rc;
+    int d = s->d, p = orc_rule_width(ORC_CMC, d);
+    for (int f = 0; f < p; ++f) w[f] = 0.0;
+    double logS[64];
+    /* in-the-money training points */
+    int64_t nI = 0;
+    double *phi = malloc(sizeof(double) * p * N);
+    double *lab = malloc(sizeof(double) * N);
+    if (!phi || !lab) { free(phi); free(lab); return ORC_ENOMEM; }
+    for (int64_t j = 0; j < N; ++j) {
+        for (int i = 0; i < d; ++i) logS[i] = log(x[(size_t)i * N + j]);
+        double payoff = orc_payoff(s, logS);
+        if (!(payoff > 0.0)) continue;
+        cmc_features(s, logS, payoff, phi + (size_t)nI * p);
+        lab[nI] = (payoff - cont[j] > 0.0) ? 1.0 : 0.0;
+        ++nI;
+    }
+    if (nI == 0) { free(phi); free(lab); return ORC_OK; }   /* never exercise */
+    /* standardise columns 1..p-1 over the fitted points */
+    double *mu = calloc(p, sizeof(double)), *sd = calloc(p, sizeof(double));
+    for (int f = 1; f < p; ++f) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < nI; ++j) acc += phi[(size_t)j * p + f];
+        mu[f] = acc / (double)nI;
+        double v = 0.0;
+        for (int64_t j = 0; j < nI; ++j) {
+            double dv = phi[(size_t)j * p + f] - mu[f];
+            v += dv * dv;
+        }
+        sd[f] = sqrt(v / (double)nI);
+        if (!(sd[f] > 1e-12 * (1.0 + fabs(mu[f])))) sd[f] = 1.0;
+        for (int64_t j = 0; j < nI; ++j)
+            phi[(size_t)j * p + f] = (phi[(size_t)j * p + f] - mu[f]) / sd[f];
+    }
+    double *F = calloc(nI, sizeof(double)), *pi = malloc(sizeof(double) * nI);
+    double *A = malloc(sizeof(double) * p * p), *bv = malloc(sizeof(double) * p);
+    double *beta = malloc(sizeof(double) * p), *gam = calloc(p, sizeof(double));
+    for (int64_t j = 0; j < nI; ++j) pi[j] = 0.5;
+    rc = ORC_OK;
+    for (int round = 0; round < rounds; ++round) {
+        for (int f = 0; f < p * p; ++f) A[f] = 0.0;
+        for (int f = 0; f < p; ++f) bv[f] = 0.0;
+        for (int64_t j = 0; j < nI; ++j) {
+            double wj = pi[j] * (1.0 - pi[j]);
+            if (wj < 1e-10) wj = 1e-10;
+            double zj = (lab[j] - pi[j]) / wj;
+            if (zj > 4.0) zj = 4.0;
+            if (zj < -4.0) zj = -4.0;
+            const double *ps = phi + (size_t)j * p;
+            for (int a = 0; a < p; ++a) {
+                bv[a] += wj * zj * ps[a];
+                for (int b = 0; b < p; ++b) A[a * p + b] += wj * ps[a] * ps[b];
+            }
+        }
+        double tr = 0.0;
+        for (int a = 0; a < p; ++a) tr += A[a * p + a];
+        rc = spd_solve(p, A, 1e-8 * tr / p, bv, beta);
+        if (rc) break;
+        for (int a = 0; a < p; ++a) gam[a] += 0.5 * beta[a];
+        for (int64_t j = 0; j < nI; ++j) {
+            double dF = 0.0;
+            for (int a = 0; a < p; ++a) dF += beta[a] * phi[(size_t)j * p + a];
+            F[j] += 0.5 * dF;
+            pi[j] = 1.0 / (1.0 + exp(-2.0 * F[j]));
+        }
+    }
+    if (!rc) {
+        double w0 = gam[0];
+        for (int f = 1; f < p; ++f) {
+            w[f] = gam[f] / sd[f];
+            w0 -= gam[f] * mu[f] / sd[f];
+        }
+        w[0] = w0;
+    }
+    free(phi); free(lab); free(mu); free(sd); free(F); free(pi);
+    free(A); free(bv); free(beta); free(gam);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* I&Z boundary-point search (Section 2.1 eq. (1), Section 2.4): start the
+ * searched coordinate at K and iterate s <- Phi_1^{-1}(C(s)) with the same
+ * inner paths each time (common random numbers), until |s' - s| < eps.
+ * Phi_1^{-1}(c) is the first-asset price whose payoff equals c:
+ *   geometric put      (K - c)^d / prod_{i>=2} x_i,
+ *   arithmetic put     d (K - c) - sum_{i>=2} x_i,
+ *   one-asset call     K + c.
+ * A non-positive inverse drops the point. */
+
+static double iz_invert(const orc_spec *s, const double *x_other, double c)
+{
+    int d = s->d;
+    if (s->payoff == ORC_CALL_MAX) return s->K + c;
+    if (!(s->K - c > 0.0)) return -1.0;
+    if (s->payoff == ORC_PUT_GEO || d == 1) {
+        double prod = 1.0;
+        for (int i = 1; i < d; ++i) prod *= x_other[i];
+        return pow(s->K - c, (double)d) / prod;
+    }
+    double rest = 0.0;
+    for (int i = 1; i < d; ++i) rest += x_other[i];
+    return (double)d * (s->K - c) - rest;
+}
+
+typedef struct {
+    const path_ctx *c;
+    const double *x;
+    int64_t J, n;
+    double eps;
+    int max_iter;
+    double *s_out;
+    int32_t *iters;
+    int64_t *steps;
+    int64_t next;
+    pthread_mutex_t lock;
+} iz_job;
+
+static void *iz_worker(void *arg)
+{
+    iz_job *job = (iz_job *)arg;
+    const orc_spec *s = job->c->s;
+    int d = s->d;
+    double xo[64], logx[64];
+    for (;;) {
+        pthread_mutex_lock(&job->lock);
+        int64_t j = job->next++;
+        pthread_mutex_unlock(&job->lock);
+        if (j >= job->J) break;
+        for (int i = 0; i < d; ++i) xo[i] = job->x[(size_t)i * job->J + j];
+        double sv = s->K, result = -1.0;
+        int it = 0;
+        int64_t st = 0;
+        while (it < job->max_iter) {
+            logx[0] = log(sv);
+            for (int i = 1; i < d; ++i) logx[i] = log(xo[i]);
+            double sum = 0.0, sq = 0.0;
+            run_paths(job->c, logx, (uint32_t)j, 0, job->n, &sum, &sq, &st);
+            double cval = sum / (double)job->n;
+            double snew = iz_invert(s, xo, cval);
+            ++it;
+            if (!(snew > 0.0) || !isfinite(snew)) break;
+            if (fabs(snew - sv) < job->eps) { result = snew; break; }
+            sv = snew;
+        }
+        job->s_out[j] = result;
+        job->iters[j] = it;
+        job->steps[j] = st;
+    }
+    return NULL;
+}
+
+int orc_iz_search(const orc_spec *s, const double *rules, int m, const double *x,
+                  int64_t J, int64_t n, uint32_t seed, double eps, int max_iter,
+                  int nthreads, double *s_out, int32_t *iters, int64_t *steps_total)
+{
+    int rc = check_spec(s);
+    if (rc) return rc;
+    if (m < 1 || m >= s->n_dates || J < 1 || n < 2 || max_iter < 1 || !(eps > 0.0))
+        return ORC_EINVAL;
+    if (s->payoff == ORC_CALL_MAX && s->d > 1) return ORC_EUNSUPPORTED;
+    int d = s->d;
+    double *L = malloc(sizeof(double) * d * d);
+    int64_t *st = calloc(J, sizeof(int64_t));
+    if (!L || !st) { free(L); free(st); return ORC_ENOMEM; }
+    rc = orc_cholesky(d, s->rho, L);
+    if (rc) { free(L); free(st); return rc; }
+    path_ctx c = {s, ORC_IZ, rules, orc_rule_width(ORC_IZ, d), m, L, seed,
+                  key_hi(ORC_STREAM_INNER, m)};
+    iz_job job = {&c, x, J, n, eps, max_iter, s_out, iters, st, 0};
+    pthread_mutex_init(&job.lock, NULL);
+    int nt = resolve_threads(nthreads);
+    if (nt > J) nt = (int)J;
+    pthread_t *th = malloc(sizeof(pthread_t) * nt);
+    for (int t = 0; t < nt; ++t) pthread_create(&th[t], NULL, iz_worker, &job);
+    for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+    free(th);
+    int64_t tot = 0;
+    for (int64_t j = 0; j < J; ++j) tot += st[j];
+    if (steps_total) *steps_total = tot;
+    pthread_mutex_destroy(&job.lock);
+    free(L); free(st);
+    return ORC_OK;
+}
+
+/* [reg] (Section 2.3): least squares of ln s*_j on the full quadratic in the
+ * log-moneyness of the other assets, over the converged points, through the
+ * normal equations with a ridge of 1e-10 tr/p.  No converged point: never
+ * exercise. */
+int orc_fit_iz(const orc_spec *s, const double *x, const double *sstar,
+               int64_t J, double *b)
+{
+    int rc = check_spec(s);
+    if (rc) return rc;
+    int d = s->d, p = orc_rule_width(ORC_IZ, d);
+    double *A = calloc((size_t)p * p, sizeof(double)), *bv = calloc(p, sizeof(double));
+    double xi[1 + 63 + 63 * 64 / 2], logS[64];
+    int64_t cnt = 0;
+    for (int64_t j = 0; j < J; ++j) {
+        if (!(sstar[j] > 0.0)) continue;
+        for (int i = 0; i < d; ++i) logS[i] = log(x[(size_t)i * J + j]);
+        iz_features(s, logS, xi);
+        double y = log(sstar[j]);
+        for (int a = 0; a < p; ++a) {
+            bv[a] += xi[a] * y;
+            for (int c = 0; c < p; ++c) A[a * p + c] += xi[a] * xi[c];
+        }
+        ++cnt;
+    }
+    for (int f = 0; f < p; ++f) b[f] = 0.0;
+    if (cnt == 0) {
+        b[0] = iz_direction_is_call(s) ? IZ_NEVER : -IZ_NEVER;
+    } else {
+        double tr = 0.0;
+        for (int a = 0; a < p; ++a) tr += A[a * p + a];
+        rc = spd_solve(p, A, 1e-10 * tr / p, bv, b);
+    }
+    free(A); free(bv);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Whole pricer: backward sweep over the dates, then final pricing with an
+ * independent stream; price, sample variance, standard error and the 95%
+ * half-width 1.96 se (the reading under which the CI column of Table 4 is
+ * consistent). */
+
+int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_final,
+              uint32_t seed, int rounds, double eps, int max_iter, int nthreads,
+              double *rules_out, double *result)
+{
+    int rc = check_spec(s);
+    if (rc) return rc;
+    if (N < 2 || n < 2 || n_final < 2 || (method != ORC_CMC && method != ORC_IZ))
+        return ORC_EINVAL;
+    if (method == ORC_IZ && s->payoff == ORC_CALL_MAX && s->d > 1) return ORC_EUNSUPPORTED;
+    int d = s->d, NT = s->n_dates, width = orc_rule_width(method, d);
+    double *rules = calloc((size_t)(NT + 1) * width, sizeof(double));
+    double *L = malloc(sizeof(double) * d * d);
+    double *x = malloc(sizeof(double) * d * N);
+    double *B = malloc(sizeof(double) * d * N);
+    double *cont = malloc(sizeof(double) * N);
+    int64_t *steps = malloc(sizeof(int64_t) * N);
+    int32_t *iters = malloc(sizeof(int32_t) * N);
+    if (!rules || !L || !x || !B || !cont || !steps || !iters) { rc = ORC_ENOMEM; goto done; }
+    rc = orc_cholesky(d, s->rho, L);
+    if (rc) goto done;
+    int64_t inner = 0, unconv = 0, iz_it = 0;
+    if (method == ORC_CMC) {
+        bridge_endpoint(s, N, seed, B);
+        for (int m = NT - 1; m >= 1; --m) {
+            bridge_back(s, m, N, seed, B);
+            points_from_bridge(s, L, m, N, B, x);
+            rc = orc_continuation(s, method, rules, m, x, N, n, seed, ORC_STREAM_INNER,
+                                  nthreads, cont, NULL, steps, NULL, NULL);
+            if (rc) goto done;
+            for (int64_t j = 0; j < N; ++j) inner += steps[j];
+            rc = orc_fit_cmc(s, x, cont, N, rounds, rules + (size_t)m * width);
+            if (rc) goto done;
+        }
+    } else {
+        for (int m = NT - 1; m >= 1; --m) {
+            rc = orc_points_iz(s, m, N, x);
+            if (rc) goto done;
+            int64_t st = 0;
+            rc = orc_iz_search(s, rules, m, x, N, n, seed, eps, max_iter, nthreads,
+                               cont, iters, &st);
+            if (rc) goto done;
+            inner += st;
+            for (int64_t j = 0; j < N; ++j) {
+                iz_it += iters[j];
+                if (!(cont[j] > 0.0)) ++unconv;
+            }
+            rc = orc_fit_iz(s, x, cont, N, rules + (size_t)m * width);
+            if (rc) goto done;
+        }
+    }
+    {
+        double sum = 0.0, sq = 0.0;
+        int64_t fsteps = 0;
+        rc = orc_continuation(s, method, rules, 0, s->S0, 1, n_final, seed, ORC_STREAM_FINAL,
+                              nthreads, NULL, NULL, &fsteps, &sum, &sq);
+        if (rc) goto done;
+        double price = sum / (double)n_final;
+        double var = (sq - sum * sum / (double)n_final) / (double)(n_final - 1);
+        if (var < 0.0) var = 0.0;
+        double se = sqrt(var / (double)n_final);
+        result[0] = price;
+        result[1] = var;
+        result[2] = se;
+        result[3] = 1.96 * se;
+        result[4] = (double)inner;
+        result[5] = (double)fsteps;
+        result[6] = (double)unconv;
+        result[7] = (double)iz_it;
+    }
+    if (rules_out) memcpy(rules_out, rules, sizeof(double) * (NT + 1) * width);
+done:
+    free(rules); free(L); free(x); free(B); free(cont); free(steps); free(iters);
+    return rc;
+}

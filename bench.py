@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the nested continuation-value Monte Carlo on one MI355X.
+
+One step = one whole pricing pass of the 5-asset geometric-average Bermudan
+put (S0_i = K = 100, r = 0.05, sigma_i = 0.2, pairwise rho = 0.3, T = 1,
+10 dates) by the CMC pricer with N = 4096 training points per date,
+n = 4096 inner paths per point and 1e6 final-pricing paths: sample points,
+continuation estimates (the hot kernel), labels and boosting fit at every
+date, then final pricing.  Inputs are synthetic and generated on the device.
+
+Prints ONE JSON line: inner path-steps per second of the FP32 form (float
+stepping, double accumulation), with the plain FP64 form, prices and their
+distance in standard errors, per-step latency percentiles, the hot kernel's
+VALU roofline and the CPU oracle's rate on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz -> VALU issue slots per second
+# (one full-rate operation per lane per cycle; FP32 FMA 78.6 TFLOP/s unpacked).
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+
+# Issue cost (full-rate slots) of the operations of one inner path-step.
+# Quarter-rate classes: 32x32->64 integer multiply and the FP32
+# transcendentals (log2, exp2, sqrt, sin, cos); everything else full rate.
+COST = {"mul64": 4.0, "trans": 4.0, "alu": 1.0}
+
+
+def slots_per_step_fp32(d: int, payoff: int, method: int) -> float:
+    """Algorithmic VALU issue slots of one inner path-step (FP32 form).
+
+    Philox4x32-10 block: 10 rounds x (2 wide multiplies + 2 three-input xors).
+    Box-Muller pair: 2 word->float conversions and 2 scalings, log2, one
+    multiply, sqrt, sin, cos, 2 multiplies.  Step: sqrt(dt) z (d), the
+    lower-triangular correlation d(d+1)/2 FMAs, the drift d FMAs.  Payoff:
+    max-call / geometric one exp (plus d-1 max/adds and 3 ops), arithmetic
+    basket d exps.  CMC rule: d subtractions + 2d FMAs + 3 for g; I&Z
+    boundary: 1 + q + q(q+1)/2 FMAs + q(q+1)/2 products.  Per path (amortised
+    over the executed steps, ignored here): the FP64 accumulation.
+    """
+    blocks = (d + 3) // 4
+    pairs = (d + 1) // 2
+    philox = blocks * 10 * (2 * COST["mul64"] + 2 * COST["alu"])
+    bm = pairs * (4 * COST["alu"] + COST["trans"] + COST["alu"] + COST["trans"] + 2 * COST["trans"]
+                  + 2 * COST["alu"])
+    step = d + d * (d + 1) / 2 + d
+    if payoff == 0:
+        pay = d * (COST["trans"] + 2) + 3
+    else:
+        pay = (d - 1) + COST["trans"] + 4
+    if method == 0:
+        rule = 3 * d + 4
+    else:
+        q = d - 1
+        rule = 1 + q + q * (q + 1)
+    return philox + bm + step + pay + rule
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=float), q))
+
+
+def cpu_baseline(spec, N, n, seed, target_seconds: float) -> dict:
+    """The FP64 oracle timed on this host: the inner-path continuation
+    estimates of a subset of the CMC training points, at every date, with the
+    same draws as the GPU run (rules: never exercise)."""
+    from oracle import oracle as orc
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    rules = orc.empty_rules(spec, orc.CMC)
+    pts = {m: orc.points_cmc(spec, m, N, seed) for m in range(1, spec.n_dates)}
+
+    def run(k):
+        steps = 0
+        t0 = time.perf_counter()
+        for m in range(1, spec.n_dates):
+            ids = np.arange(k, dtype=np.uint32)
+            r = orc.continuation(spec, orc.CMC, rules, m, pts[m][:, :k], n, seed, nthreads=threads, ids=ids)
+            steps += int(r["steps"].sum())
+        return steps, time.perf_counter() - t0
+
+    k = max(threads, 16)
+    steps, dt = run(k)
+    if dt < target_seconds:
+        k = int(min(N, max(k, k * target_seconds / max(dt, 1e-3))))
+        steps, dt = run(k)
+    return {"value": steps / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"continuation estimates of {k} of the {N} training points at each of the "
+                      f"{spec.n_dates - 1} dates, n = {n} inner paths, FP64 ({steps} path-steps in {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--N", type=int, default=4096)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--n-final", type=int, default=1_000_000)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline (0 disables it)")
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the pricer runs on a single device and this build has no "
+              "multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0805_1827_amd import bmc, inputs
+
+    spec = inputs.geometric_put5()
+    ctx = bmc.Context(0)
+    kw = dict(N=args.N, n=args.n, n_final=args.n_final, seed=args.seed)
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            bmc.bmc_price(ctx, spec, bmc.CMC, prec, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [bmc.bmc_price(ctx, spec, bmc.CMC, prec, **kw) for _ in range(steps)]
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - t0
+
+    res32, t32 = timed(bmc.FP32, args.steps, args.warmup)
+    fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(2, args.steps // 2)
+    res64, t64 = timed(bmc.FP64, fp64_steps, 1)
+
+    inner32 = sum(r["inner_path_steps"] for r in res32)
+    inner64 = sum(r["inner_path_steps"] for r in res64)
+    calc32 = sum(r["calc_seconds"] for r in res32)
+    calc64 = sum(r["calc_seconds"] for r in res64)
+    launches32 = args.steps * (spec.n_dates - 1)
+    p32, p64 = res32[-1], res64[-1]
+    se = p64["std_err"]
+
+    slots = slots_per_step_fp32(spec.d, spec.payoff, bmc.CMC)
+    achieved = slots * inner32 / calc32
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                "kernel": "k_cont<5, float> (continuation, FP32 stepping)",
+                "slots_per_path_step": slots,
+                "avg_launch_ms": 1e3 * calc32 / launches32, "launches": launches32}
+
+    out = {
+        "metric": "inner path-steps/s (FP32 stepping, FP64 accumulation)",
+        "value": inner32 / t32,
+        "unit": "path-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "5-asset geometric-average Bermudan put, CMC, N=n=4096, 10 dates, "
+                               "1e6 final paths, seed 1",
+                   "d": spec.d, "dates": spec.n_dates, "N": args.N, "n": args.n, "n_final": args.n_final,
+                   "method": "CMC"},
+        "kernel_path_steps_per_s": inner32 / calc32,
+        "fp64": {"value": inner64 / t64, "ms_per_step": 1e3 * t64 / fp64_steps,
+                 "kernel_path_steps_per_s": inner64 / calc64, "steps": fp64_steps},
+        "fp32_over_fp64": (inner32 / t32) / (inner64 / t64),
+        "price_fp32": p32["price"], "price_fp64": p64["price"], "std_err": se,
+        "fp32_error_in_std_err": abs(p32["price"] - p64["price"]) / se,
+        "latency_ms": {"p50": 1e3 * percentile([r["seconds"] for r in res32], 50),
+                       "p99": 1e3 * percentile([r["seconds"] for r in res32], 99)},
+        "phase_ms": {"calc": 1e3 * calc32 / args.steps,
+                     "fit": 1e3 * sum(r["fit_seconds"] for r in res32) / args.steps,
+                     "final": 1e3 * sum(r["final_seconds"] for r in res32) / args.steps},
+        "inner_path_steps_per_price": inner32 // args.steps,
+        "roofline": roofline,
+    }
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(spec, args.N, args.n, args.seed, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

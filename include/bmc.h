@@ -1,0 +1,197 @@
+/*
+ * bmc.h - C ABI of the MI355X (gfx950) nested continuation-value Monte Carlo
+ * for multi-asset Bermudan options: the data-generation phase shared by the
+ * two pricers of Doan, Gaikwad, Bossy, Baude & Stokes-Rees, "Parallel Pricing
+ * Algorithms for Multi-Dimensional Bermudan/American Options using Monte Carlo
+ * methods" (INRIA RR-6530, 2008), around which sit the rule fits (I&Z boundary
+ * regression, CMC boosting classifier) and the final pricing pass.
+ *
+ * Conventions
+ *  - Every entry point returns a bmc_status and never throws.  On error the
+ *    outputs are untouched and bmc_last_error() returns a thread-local message.
+ *  - Spec arrays (bmc_spec) are HOST memory owned by the caller and read only
+ *    during the call.
+ *  - Arrays documented as "device" are HIP device memory owned by the caller
+ *    (e.g. torch tensors' data_ptr()).  Calls taking device arrays are
+ *    asynchronous on the context's stream unless stated otherwise; the caller
+ *    synchronises (bmc_sync or its own stream sync) before reading outputs.
+ *  - Point sets are structure-of-arrays FP64: x[i*N + j] is asset i of point j.
+ *  - bmc_ctx and bmc_rules are opaque, library-owned, freed by their destroy
+ *    calls.  A context is not thread-safe; use one per host thread.
+ *  - Random numbers: Philox4x32-10 keyed by (seed, stream << 16 | date), with
+ *    counters (step-block, path, point, 0); seeds must fit in 32 bits.
+ */
+#ifndef BMC_H
+#define BMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BMC_D_MAX 64      /* assets */
+#define BMC_NT_MAX 512    /* exercise dates */
+
+typedef enum {
+    BMC_OK = 0,
+    BMC_EINVAL = -1,        /* invalid argument or spec */
+    BMC_ENOTSPD = -2,       /* correlation matrix not positive definite */
+    BMC_ENOMEM = -3,        /* device allocation failed or budget exceeded */
+    BMC_EDEVICE = -4,       /* HIP runtime error */
+    BMC_EUNSUPPORTED = -5,  /* combination not supported */
+    BMC_ENOCONV = -6,       /* reserved (I&Z drops and counts non-converged points) */
+    BMC_EBUSY = -7          /* request not finished yet */
+} bmc_status;
+
+/* Payoffs (Section 2.1-2.2, Section 3.2): arithmetic-basket put
+ * (K - mean S)^+, call on the maximum (max S - K)^+, geometric-average put
+ * (K - (prod S)^(1/d))^+.  For d = 1 the two puts coincide. */
+typedef enum { BMC_PUT_BASKET = 0, BMC_CALL_MAX = 1, BMC_PUT_GEO = 2 } bmc_payoff;
+
+/* Pricers: Classification-Monte Carlo (Section 3) and Ibanez-Zapatero
+ * boundary computation (Section 2). */
+typedef enum { BMC_CMC = 0, BMC_IZ = 1 } bmc_method;
+
+/* Arithmetic of the inner paths.  FP64: everything in double.  FP32: path
+ * stepping, exp and the uniform-to-normal map in float, per-lane payoff sums
+ * in double.  FP32_KAHAN: as FP32 with per-lane Kahan-compensated float sums
+ * merged in double.  Rule fits, Cholesky and final reductions are always FP64. */
+typedef enum { BMC_FP64 = 0, BMC_FP32 = 1, BMC_FP32_KAHAN = 2 } bmc_precision;
+
+/* Random-number streams (second key word, high half). */
+typedef enum { BMC_STREAM_OUTER = 1, BMC_STREAM_INNER = 2, BMC_STREAM_FINAL = 3 } bmc_stream;
+
+/* Market model of Section 2.2 / 3.2: d assets under risk-neutral GBM with
+ * rate r, dividend yields delta_i, volatilities sigma_i, correlation rho, and
+ * N_T exercise dates 0 < t_1 < ... < t_NT = T (t_0 = 0 is not a date). */
+typedef struct {
+    int32_t d;              /* 1..BMC_D_MAX */
+    const double *S0;       /* [d] spot prices, > 0 */
+    const double *delta;    /* [d] dividend yields */
+    const double *sigma;    /* [d] volatilities, >= 0 */
+    const double *rho;      /* [d*d] row-major, symmetric, unit diagonal, SPD */
+    double K, r, T;         /* strike > 0, rate, maturity > 0 */
+    int32_t n_dates;        /* N_T, 1..BMC_NT_MAX */
+    const double *dates;    /* [n_dates] strictly increasing, last == T */
+    int32_t payoff;         /* bmc_payoff */
+} bmc_spec;
+
+typedef struct {
+    int32_t method;         /* bmc_method */
+    int32_t precision;      /* bmc_precision */
+    int64_t N;              /* sample points per date (CMC training points, I&Z lattice points) */
+    int64_t n;              /* inner paths per point */
+    int64_t n_final;        /* final-pricing paths */
+    uint64_t seed;          /* < 2^32 */
+    int32_t cls_rounds;     /* CMC boosting rounds (default 8 when 0) */
+    int32_t iz_max_iter;    /* I&Z iteration cap (default 100 when 0) */
+    double iz_eps;          /* I&Z tolerance in price units (default 0.01 when 0) */
+} bmc_opts;
+
+typedef struct {
+    double price, variance, std_err, ci95;   /* ci95 = 1.96 std_err */
+    int64_t inner_path_steps;                /* executed continuation path-steps */
+    int64_t final_path_steps;                /* executed final-pricing path-steps */
+    int64_t iz_unconverged;                  /* I&Z points dropped or not converged */
+    int64_t iz_iterations;                   /* I&Z continuation evaluations per point, summed */
+    double seconds;                          /* wall time of the call */
+    double calc_seconds;                     /* continuation (data generation) */
+    double fit_seconds;                      /* rule fits */
+    double final_seconds;                    /* final pricing */
+} bmc_result;
+
+typedef struct bmc_ctx bmc_ctx;
+typedef struct bmc_rules bmc_rules;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t bmc_version(void);
+/* Message of the last failing call on this thread ("" if none). */
+const char *bmc_last_error(void);
+
+/* Context on HIP device `device`, issuing work on `hip_stream` (a
+ * hipStream_t; NULL = the default stream).  Owns scratch memory. */
+bmc_status bmc_ctx_create(int32_t device, void *hip_stream, bmc_ctx **out);
+void bmc_ctx_destroy(bmc_ctx *ctx);
+/* Blocks until all work issued through ctx has finished. */
+bmc_status bmc_sync(bmc_ctx *ctx);
+
+/* Whole pricer, synchronous (Algorithm 1 for BMC_IZ, Algorithm 2 for BMC_CMC):
+ * backward sweep over the dates (sample points, continuation estimates, rule
+ * fit), then final pricing on an independent stream.  If rules_out is not
+ * NULL it receives the learned rules (caller destroys them). */
+bmc_status bmc_price(bmc_ctx *ctx, const bmc_spec *spec, const bmc_opts *opts,
+                     bmc_rules **rules_out, bmc_result *out);
+
+/* Exercise-rule table of one spec and method: one row of width w per date
+ * (rows 1..N_T-1 used).  CMC (Section 3.2): F(x) = sum_f w_f phi_f(x) with
+ * phi = [1, u_1..u_d, u_1^2..u_d^2, g, g^2], u_i = ln(S_i/K), g = Phi(S)/K;
+ * exercise iff Phi > 0 and F > 0.  I&Z (Section 2.2): boundary
+ * b(x) = sum_f w_f xi_f with xi = [1, v_2..v_d, v_a v_b (a <= b)],
+ * v_i = ln(S_i/K); puts exercise iff Phi > 0 and ln S_1 < b, the one-asset
+ * call iff ln S_1 > b.  A new table never exercises. */
+bmc_status bmc_rules_create(bmc_ctx *ctx, const bmc_spec *spec, int32_t method, bmc_rules **out);
+void bmc_rules_destroy(bmc_rules *rules);
+int32_t bmc_rules_width(const bmc_rules *rules);
+/* Row `date` (1..N_T-1) from/to host memory (synchronous). */
+bmc_status bmc_rules_set(bmc_rules *rules, int32_t date, const double *w_host);
+bmc_status bmc_rules_get(const bmc_rules *rules, int32_t date, double *w_host);
+/* Serialised form (header + FP64 rows).  *bytes: in = capacity, out = size;
+ * buf = NULL queries the size. */
+bmc_status bmc_rules_export(const bmc_rules *rules, void *buf, size_t *bytes);
+bmc_status bmc_rules_import(bmc_ctx *ctx, const void *buf, size_t bytes, bmc_rules **out);
+
+/* Sample points at `date` (1..N_T) into device x[d*N].  CMC: training points
+ * from the Brownian bridge run back from T (Section 3.2-3.3).  I&Z: rank-1
+ * lattice points (Section 2.3, [glp]) with asset 1 set to K. */
+bmc_status bmc_sample_points(bmc_ctx *ctx, const bmc_spec *spec, int32_t method, int32_t date,
+                             int64_t N, uint64_t seed, double *x);
+
+/* Continuation values at `date` m (0..N_T-1) of the N device points x: n inner
+ * paths per point from t_m to T under the rules of later dates (Section 3.2,
+ * the "small BA option"; Section 2.3 [calc]).  Writes device cont[N],
+ * std_err[N] and, if not NULL, steps[N] (executed path-steps).  m = 0 with a
+ * single point is the final-pricing pass (use bmc_final_price). */
+bmc_status bmc_estimate_continuation(bmc_ctx *ctx, const bmc_spec *spec, const bmc_rules *rules,
+                                     int32_t date, const double *x, int64_t N, int64_t n,
+                                     uint64_t seed, int32_t precision,
+                                     double *cont, double *std_err, int64_t *steps);
+
+/* Fits the rule row of `date` from N device points.  CMC: values = device
+ * continuation estimates; boosting on the in-the-money points (Section 3.2
+ * [class]).  I&Z: x[0*N + j] holds the converged boundary coordinate s*_j
+ * (<= 0 marks a dropped point) and values is ignored; quadratic least squares
+ * of ln s* (Section 2.3 [reg]).  rounds: CMC boosting rounds (0 = 8). */
+bmc_status bmc_fit_rule(bmc_ctx *ctx, const bmc_spec *spec, bmc_rules *rules, int32_t date,
+                        const double *x, const double *values, int64_t N, int32_t rounds);
+
+/* I&Z boundary-point search at `date` (Section 2.1 eq. (1), Section 2.4):
+ * for each of the J device points x (asset 1 ignored) iterate
+ * s <- Phi_1^{-1}(C(s)) from s = K with common random numbers until
+ * |s' - s| < eps or max_iter.  Writes device s_out[J] (<= 0: dropped or not
+ * converged) and iters[J]; *steps (host, may be NULL) receives the executed
+ * path-steps.  Synchronous. */
+bmc_status bmc_iz_search(bmc_ctx *ctx, const bmc_spec *spec, const bmc_rules *rules, int32_t date,
+                         const double *x, int64_t J, int64_t n, uint64_t seed, int32_t precision,
+                         double eps, int32_t max_iter, double *s_out, int32_t *iters,
+                         int64_t *steps);
+
+/* Final pricing [mc] (Algorithms 1-2): n_final paths from S0 on the FINAL
+ * stream under the rules; FP64 merge to price, sample variance, standard
+ * error and 95% half-width.  Synchronous. */
+bmc_status bmc_final_price(bmc_ctx *ctx, const bmc_spec *spec, const bmc_rules *rules,
+                           int64_t n_final, uint64_t seed, int32_t precision, bmc_result *out);
+
+/* Raw generator access for verification: M Philox4x32-10 blocks at device
+ * counters ctr[4*M] -> device out[4*M]; and the four Box-Muller normals of
+ * each block in the given precision (FP32 results widened to double). */
+bmc_status bmc_philox(bmc_ctx *ctx, uint32_t k0, uint32_t k1, const uint32_t *ctr, int64_t M,
+                      uint32_t *out);
+bmc_status bmc_normals(bmc_ctx *ctx, uint32_t k0, uint32_t k1, const uint32_t *ctr, int64_t M,
+                       int32_t precision, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BMC_H */

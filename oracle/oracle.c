@@ -315,6 +315,7 @@ enum { CHUNK = 4096 };
 typedef struct {
     const path_ctx *c;
     const double *x;
+    const uint32_t *ids;
     int64_t N, n, nchunk;
     double *psum, *psq;
     int64_t *pst;
@@ -337,7 +338,8 @@ static void *cont_worker(void *arg)
         int64_t lo = ch * CHUNK, hi = lo + CHUNK < job->n ? lo + CHUNK : job->n;
         double sum = 0.0, sq = 0.0;
         int64_t st = 0;
-        run_paths(job->c, logx, (uint32_t)j, lo, hi, &sum, &sq, &st);
+        uint32_t jid = job->ids ? job->ids[j] : (uint32_t)j;
+        run_paths(job->c, logx, jid, lo, hi, &sum, &sq, &st);
         job->psum[item] = sum;
         job->psq[item] = sq;
         job->pst[item] = st;
@@ -346,8 +348,8 @@ static void *cont_worker(void *arg)
 }
 
 int orc_continuation(const orc_spec *s, int method, const double *rules, int m,
-                     const double *x, int64_t N, int64_t n, uint32_t seed,
-                     int stream, int nthreads, double *cont, double *se,
+                     const double *x, int64_t N, const uint32_t *ids, int64_t n,
+                     uint32_t seed, int stream, int nthreads, double *cont, double *se,
                      int64_t *steps, double *sum, double *sumsq)
 {
     int rc = check_spec(s);
@@ -361,7 +363,7 @@ int orc_continuation(const orc_spec *s, int method, const double *rules, int m,
     if (rc) { free(L); return rc; }
     path_ctx c = {s, method, rules, orc_rule_width(method, d), m, L, seed, key_hi(stream, m)};
     cont_job job;
-    job.c = &c; job.x = x; job.N = N; job.n = n;
+    job.c = &c; job.x = x; job.ids = ids; job.N = N; job.n = n;
     job.nchunk = (n + CHUNK - 1) / CHUNK;
     job.psum = malloc(sizeof(double) * N * job.nchunk);
     job.psq = malloc(sizeof(double) * N * job.nchunk);
@@ -849,7 +851,7 @@ int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_fin
         for (int m = NT - 1; m >= 1; --m) {
             bridge_back(s, m, N, seed, B);
             points_from_bridge(s, L, m, N, B, x);
-            rc = orc_continuation(s, method, rules, m, x, N, n, seed, ORC_STREAM_INNER,
+            rc = orc_continuation(s, method, rules, m, x, N, NULL, n, seed, ORC_STREAM_INNER,
                                   nthreads, cont, NULL, steps, NULL, NULL);
             if (rc) goto done;
             for (int64_t j = 0; j < N; ++j) inner += steps[j];
@@ -876,8 +878,8 @@ int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_fin
     {
         double sum = 0.0, sq = 0.0;
         int64_t fsteps = 0;
-        rc = orc_continuation(s, method, rules, 0, s->S0, 1, n_final, seed, ORC_STREAM_FINAL,
-                              nthreads, NULL, NULL, &fsteps, &sum, &sq);
+        rc = orc_continuation(s, method, rules, 0, s->S0, 1, NULL, n_final, seed,
+                              ORC_STREAM_FINAL, nthreads, NULL, NULL, &fsteps, &sum, &sq);
         if (rc) goto done;
         double price = sum / (double)n_final;
         double var = (sq - sum * sum / (double)n_final) / (double)(n_final - 1);

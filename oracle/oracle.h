@@ -66,11 +66,14 @@ int orc_points_iz(const orc_spec *s, int m, int64_t J, double *x);
  * Continuation estimate at date m (0 <= m < N_T) for N points x, n inner paths
  * each, under the rule table `rules` ([(N_T+1) * width], row k = date k).
  * m = 0 with stream FINAL and the single point S0 is the final pricing pass.
+ * ids (may be NULL) gives each point's index in the random-number counters
+ * (default: its position j), so that a subset of a larger point set can be
+ * re-evaluated with its original draws.
  * Outputs cont[N], se[N], steps[N] (executed path-steps), sum[N], sumsq[N].
  */
 int orc_continuation(const orc_spec *s, int method, const double *rules, int m,
-                     const double *x, int64_t N, int64_t n, uint32_t seed,
-                     int stream, int nthreads, double *cont, double *se,
+                     const double *x, int64_t N, const uint32_t *ids, int64_t n,
+                     uint32_t seed, int stream, int nthreads, double *cont, double *se,
                      int64_t *steps, double *sum, double *sumsq);
 
 /* CMC LogitBoost fit of the exercise rule at one date (folded weights). */

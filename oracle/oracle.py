@@ -64,7 +64,7 @@ def lib():
         L.orc_korobov.argtypes = [C.c_int64, C.c_int]
         L.orc_korobov.restype = C.c_int64
         L.orc_points_iz.argtypes = [sp, C.c_int, C.c_int64, dp]
-        L.orc_continuation.argtypes = [sp, C.c_int, dp, C.c_int, dp, C.c_int64, C.c_int64,
+        L.orc_continuation.argtypes = [sp, C.c_int, dp, C.c_int, dp, C.c_int64, u32p, C.c_int64,
                                        C.c_uint32, C.c_int, C.c_int, dp, dp, i64p, dp, dp]
         L.orc_fit_cmc.argtypes = [sp, dp, dp, C.c_int64, C.c_int, dp]
         L.orc_iz_search.argtypes = [sp, dp, C.c_int, dp, C.c_int64, C.c_int64, C.c_uint32,
@@ -165,14 +165,19 @@ def empty_rules(spec, method: int) -> np.ndarray:
 
 
 def continuation(spec, method: int, rules, m: int, x: np.ndarray, n: int, seed: int,
-                 stream: int = STREAM_INNER, nthreads: int = 0) -> dict:
+                 stream: int = STREAM_INNER, nthreads: int = 0, ids=None) -> dict:
+    """ids: optional point indices used in the random-number counters."""
     h = _SpecHolder(spec)
     x = np.ascontiguousarray(x, dtype=np.float64)
     N = x.shape[1]
+    idp = None
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.uint32).reshape(N)
+        idp = ids.ctypes.data_as(C.POINTER(C.c_uint32))
     rules = np.ascontiguousarray(rules, dtype=np.float64)
     cont, se, sm, sq = (np.zeros(N) for _ in range(4))
     steps = np.zeros(N, dtype=np.int64)
-    _check(lib().orc_continuation(h.ptr, method, _dp(rules), m, _dp(x), N, n, seed, stream,
+    _check(lib().orc_continuation(h.ptr, method, _dp(rules), m, _dp(x), N, idp, n, seed, stream,
                                   nthreads, _dp(cont), _dp(se),
                                   steps.ctypes.data_as(C.POINTER(C.c_int64)), _dp(sm), _dp(sq)),
            "continuation")

@@ -1,0 +1,707 @@
+// C ABI of the gfx950 nested continuation-value Monte Carlo: contexts, rule
+// tables, spec validation/upload and the pricer drivers.  Declarations and
+// contracts are in include/bmc.h.
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bmc.h"
+#include "internal.hpp"
+#include "runtime.hpp"
+
+using namespace bmc;
+
+// ---------------------------------------------------------------------------
+// Errors
+
+static thread_local std::string g_last_error;
+
+bmc_status bmc::fail(bmc_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+bmc_status bmc::hip_fail(hipError_t e, const char* where)
+{
+    return fail(BMC_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+extern "C" const char* bmc_last_error(void) { return g_last_error.c_str(); }
+extern "C" int32_t bmc_version(void) { return 10000; }
+
+// ---------------------------------------------------------------------------
+// Device buffers
+
+hipError_t DBuf::ensure(size_t n)
+{
+    if (n <= bytes) return hipSuccess;
+    if (ptr) {
+        hipError_t e = hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+        if (e != hipSuccess) return e;
+    }
+    size_t want = n < 256 ? 256 : n;
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return e;
+    }
+    bytes = want;
+    return hipSuccess;
+}
+
+void DBuf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Spec validation and upload
+
+bmc_status bmc::validate_spec(const bmc_spec* s)
+{
+    if (!s) return fail(BMC_EINVAL, "spec is NULL");
+    if (s->d < 1 || s->d > BMC_D_MAX) return fail(BMC_EINVAL, "d = %d outside 1..%d", s->d, BMC_D_MAX);
+    if (s->n_dates < 1 || s->n_dates > BMC_NT_MAX)
+        return fail(BMC_EINVAL, "n_dates = %d outside 1..%d", s->n_dates, BMC_NT_MAX);
+    if (!s->S0 || !s->delta || !s->sigma || !s->rho || !s->dates)
+        return fail(BMC_EINVAL, "spec array pointer is NULL");
+    if (!(s->K > 0.0) || !std::isfinite(s->K)) return fail(BMC_EINVAL, "K must be > 0");
+    if (!(s->T > 0.0) || !std::isfinite(s->T)) return fail(BMC_EINVAL, "T must be > 0");
+    if (!std::isfinite(s->r)) return fail(BMC_EINVAL, "r must be finite");
+    if (s->payoff < BMC_PUT_BASKET || s->payoff > BMC_PUT_GEO)
+        return fail(BMC_EINVAL, "unknown payoff %d", s->payoff);
+    double prev = 0.0;
+    for (int k = 0; k < s->n_dates; ++k) {
+        if (!(s->dates[k] > prev) || !std::isfinite(s->dates[k]))
+            return fail(BMC_EINVAL, "dates must be strictly increasing in (0, T]");
+        prev = s->dates[k];
+    }
+    if (std::fabs(prev - s->T) > 1e-12 * s->T) return fail(BMC_EINVAL, "last date must equal T");
+    const int d = s->d;
+    for (int i = 0; i < d; ++i) {
+        if (!(s->S0[i] > 0.0) || !std::isfinite(s->S0[i])) return fail(BMC_EINVAL, "S0[%d] must be > 0", i);
+        if (!(s->sigma[i] >= 0.0) || !std::isfinite(s->sigma[i]))
+            return fail(BMC_EINVAL, "sigma[%d] must be >= 0", i);
+        if (!std::isfinite(s->delta[i])) return fail(BMC_EINVAL, "delta[%d] must be finite", i);
+        if (std::fabs(s->rho[i * d + i] - 1.0) > 1e-12) return fail(BMC_EINVAL, "rho must have a unit diagonal");
+        for (int j = 0; j < i; ++j) {
+            const double a = s->rho[i * d + j], b = s->rho[j * d + i];
+            if (!std::isfinite(a) || std::fabs(a - b) > 1e-12 || std::fabs(a) > 1.0)
+                return fail(BMC_EINVAL, "rho must be symmetric with entries in [-1, 1]");
+        }
+    }
+    return BMC_OK;
+}
+
+static void pack_spec(const bmc_spec* s, HostSpecPack* p)
+{
+    std::memset(p, 0, sizeof(*p));
+    p->d = s->d;
+    p->n_dates = s->n_dates;
+    p->payoff = s->payoff;
+    p->K = s->K;
+    p->r = s->r;
+    p->T = s->T;
+    for (int i = 0; i < s->d; ++i) {
+        p->S0[i] = s->S0[i];
+        p->delta[i] = s->delta[i];
+        p->sigma[i] = s->sigma[i];
+    }
+    std::memcpy(p->rho, s->rho, sizeof(double) * s->d * s->d);
+    std::memcpy(p->dates, s->dates, sizeof(double) * s->n_dates);
+}
+
+// Uploads and derives a spec into the context's spec slot; checks the
+// Cholesky status (one stream synchronisation).
+bmc_status bmc::upload_spec(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot)
+{
+    bmc_status st = validate_spec(s);
+    if (st) return st;
+    hipError_t e = slot.ensure(sizeof(DevSpec));
+    if (e) return hip_fail(e, "spec allocation");
+    if ((e = ctx->pack_dev.ensure(sizeof(HostSpecPack)))) return hip_fail(e, "spec staging");
+    if ((e = hipStreamSynchronize(ctx->stream))) return hip_fail(e, "stream sync");
+    pack_spec(s, ctx->pack_host);
+    if ((e = hipMemcpyAsync(ctx->pack_dev.ptr, ctx->pack_host, sizeof(HostSpecPack),
+                            hipMemcpyHostToDevice, ctx->stream)))
+        return hip_fail(e, "spec upload");
+    if ((e = launch_setup((const HostSpecPack*)ctx->pack_dev.ptr, (DevSpec*)slot.ptr, ctx->stream)))
+        return hip_fail(e, "setup launch");
+    int32_t status = 0;
+    if ((e = hipMemcpyAsync(&status, (char*)slot.ptr + offsetof(DevSpec, status), sizeof(int32_t),
+                            hipMemcpyDeviceToHost, ctx->stream)))
+        return hip_fail(e, "status read");
+    if ((e = hipStreamSynchronize(ctx->stream))) return hip_fail(e, "stream sync");
+    if (status != 0) return fail(BMC_ENOTSPD, "correlation matrix is not positive definite");
+    return BMC_OK;
+}
+
+const double* bmc::dev_S0(const void* devspec)
+{
+    return (const double*)((const char*)devspec + offsetof(DevSpec, f64) + offsetof(SpecT<double>, S0));
+}
+
+// ---------------------------------------------------------------------------
+// Context
+
+extern "C" bmc_status bmc_ctx_create(int32_t device, void* hip_stream, bmc_ctx** out)
+{
+    if (!out) return fail(BMC_EINVAL, "out is NULL");
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return fail(BMC_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= count) return fail(BMC_EINVAL, "device %d outside 0..%d", device, count - 1);
+    if ((e = hipSetDevice(device))) return hip_fail(e, "hipSetDevice");
+    bmc_ctx* c = new bmc_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if ((e = hipHostMalloc((void**)&c->pack_host, sizeof(HostSpecPack), hipHostMallocDefault))) {
+        delete c;
+        return hip_fail(e, "pinned staging");
+    }
+    if ((e = hipHostMalloc((void**)&c->host_io, 4096, hipHostMallocDefault))) {
+        (void)hipHostFree(c->pack_host);
+        delete c;
+        return hip_fail(e, "pinned staging");
+    }
+    *out = c;
+    return BMC_OK;
+}
+
+bmc_ctx::~bmc_ctx()
+{
+    for (DBuf* b : {&spec, &spec2, &pack_dev, &part, &B, &x, &x2, &cont, &se, &steps, &fit, &iz,
+                    &counters, &korobov})
+        b->release();
+    if (pack_host) (void)hipHostFree(pack_host);
+    if (host_io) (void)hipHostFree(host_io);
+}
+
+extern "C" void bmc_ctx_destroy(bmc_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+}
+
+extern "C" bmc_status bmc_sync(bmc_ctx* ctx)
+{
+    if (!ctx) return fail(BMC_EINVAL, "ctx is NULL");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(e, "stream sync");
+    return BMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Rules
+
+static double never_value(int method, int payoff)
+{
+    if (method == BMC_CMC) return 0.0;
+    return payoff == BMC_CALL_MAX ? 1e300 : -1e300;
+}
+
+static bmc_status rules_alloc(bmc_ctx* ctx, int method, int d, int n_dates, int payoff,
+                              bmc_rules** out)
+{
+    bmc_rules* r = new bmc_rules();
+    r->ctx = ctx;
+    r->method = method;
+    r->d = d;
+    r->n_dates = n_dates;
+    r->payoff = payoff;
+    r->width = rule_width(method, d);
+    const size_t rows = (size_t)(n_dates + 1) * r->width;
+    hipError_t e;
+    if ((e = hipMalloc((void**)&r->w64, sizeof(double) * rows)) ||
+        (e = hipMalloc((void**)&r->w32, sizeof(float) * rows))) {
+        if (r->w64) (void)hipFree(r->w64);
+        delete r;
+        return fail(BMC_ENOMEM, "rule table allocation: %s", hipGetErrorString(e));
+    }
+    std::vector<double> h(rows, 0.0);
+    std::vector<float> hf(rows, 0.0f);
+    const double nv = never_value(method, payoff);
+    for (int k = 0; k <= n_dates; ++k) {
+        h[(size_t)k * r->width] = nv;
+        hf[(size_t)k * r->width] = (float)nv;
+    }
+    if ((e = hipMemcpy(r->w64, h.data(), sizeof(double) * rows, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(r->w32, hf.data(), sizeof(float) * rows, hipMemcpyHostToDevice))) {
+        bmc_rules_destroy(r);
+        return hip_fail(e, "rule table init");
+    }
+    *out = r;
+    return BMC_OK;
+}
+
+extern "C" bmc_status bmc_rules_create(bmc_ctx* ctx, const bmc_spec* spec, int32_t method,
+                                       bmc_rules** out)
+{
+    if (!ctx || !out) return fail(BMC_EINVAL, "NULL argument");
+    bmc_status st = validate_spec(spec);
+    if (st) return st;
+    if (method != BMC_CMC && method != BMC_IZ) return fail(BMC_EINVAL, "unknown method %d", method);
+    if (method == BMC_IZ && spec->d > IZ_D_MAX)
+        return fail(BMC_EUNSUPPORTED, "I&Z supports d <= %d", IZ_D_MAX);
+    if (method == BMC_IZ && spec->payoff == BMC_CALL_MAX && spec->d > 1)
+        return fail(BMC_EUNSUPPORTED, "I&Z for the max-call needs d boundaries (not provided)");
+    (void)hipSetDevice(ctx->device);
+    return rules_alloc(ctx, method, spec->d, spec->n_dates, spec->payoff, out);
+}
+
+extern "C" void bmc_rules_destroy(bmc_rules* r)
+{
+    if (!r) return;
+    if (r->w64) (void)hipFree(r->w64);
+    if (r->w32) (void)hipFree(r->w32);
+    delete r;
+}
+
+extern "C" int32_t bmc_rules_width(const bmc_rules* r) { return r ? r->width : 0; }
+
+extern "C" bmc_status bmc_rules_set(bmc_rules* r, int32_t date, const double* w)
+{
+    if (!r || !w) return fail(BMC_EINVAL, "NULL argument");
+    if (date < 1 || date >= r->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, r->n_dates - 1);
+    (void)hipSetDevice(r->ctx->device);
+    std::vector<float> wf(r->width);
+    for (int f = 0; f < r->width; ++f) wf[f] = (float)w[f];
+    hipError_t e;
+    if ((e = hipStreamSynchronize(r->ctx->stream)) ||
+        (e = hipMemcpy(r->w64 + (size_t)date * r->width, w, sizeof(double) * r->width, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(r->w32 + (size_t)date * r->width, wf.data(), sizeof(float) * r->width, hipMemcpyHostToDevice)))
+        return hip_fail(e, "rule upload");
+    return BMC_OK;
+}
+
+extern "C" bmc_status bmc_rules_get(const bmc_rules* r, int32_t date, double* w)
+{
+    if (!r || !w) return fail(BMC_EINVAL, "NULL argument");
+    if (date < 0 || date > r->n_dates) return fail(BMC_EINVAL, "date %d outside 0..%d", date, r->n_dates);
+    (void)hipSetDevice(r->ctx->device);
+    hipError_t e;
+    if ((e = hipStreamSynchronize(r->ctx->stream)) ||
+        (e = hipMemcpy(w, r->w64 + (size_t)date * r->width, sizeof(double) * r->width, hipMemcpyDeviceToHost)))
+        return hip_fail(e, "rule download");
+    return BMC_OK;
+}
+
+struct RulesHeader {
+    char magic[4];
+    int32_t version, method, d, n_dates, width, payoff, pad;
+};
+
+extern "C" bmc_status bmc_rules_export(const bmc_rules* r, void* buf, size_t* bytes)
+{
+    if (!r || !bytes) return fail(BMC_EINVAL, "NULL argument");
+    const size_t rows = (size_t)(r->n_dates + 1) * r->width;
+    const size_t need = sizeof(RulesHeader) + sizeof(double) * rows;
+    if (!buf) {
+        *bytes = need;
+        return BMC_OK;
+    }
+    if (*bytes < need) return fail(BMC_EINVAL, "buffer too small: %zu < %zu", *bytes, need);
+    RulesHeader h;
+    std::memcpy(h.magic, "BMCR", 4);
+    h.version = 1;
+    h.method = r->method;
+    h.d = r->d;
+    h.n_dates = r->n_dates;
+    h.width = r->width;
+    h.payoff = r->payoff;
+    h.pad = 0;
+    std::memcpy(buf, &h, sizeof(h));
+    (void)hipSetDevice(r->ctx->device);
+    hipError_t e;
+    if ((e = hipStreamSynchronize(r->ctx->stream)) ||
+        (e = hipMemcpy((char*)buf + sizeof(h), r->w64, sizeof(double) * rows, hipMemcpyDeviceToHost)))
+        return hip_fail(e, "rule export");
+    *bytes = need;
+    return BMC_OK;
+}
+
+extern "C" bmc_status bmc_rules_import(bmc_ctx* ctx, const void* buf, size_t bytes, bmc_rules** out)
+{
+    if (!ctx || !buf || !out) return fail(BMC_EINVAL, "NULL argument");
+    RulesHeader h;
+    if (bytes < sizeof(h)) return fail(BMC_EINVAL, "buffer too small");
+    std::memcpy(&h, buf, sizeof(h));
+    if (std::memcmp(h.magic, "BMCR", 4) != 0 || h.version != 1) return fail(BMC_EINVAL, "not a rule table");
+    if (h.d < 1 || h.d > BMC_D_MAX || h.n_dates < 1 || h.n_dates > BMC_NT_MAX ||
+        (h.method != BMC_CMC && h.method != BMC_IZ) || h.width != rule_width(h.method, h.d))
+        return fail(BMC_EINVAL, "corrupt rule table header");
+    const size_t rows = (size_t)(h.n_dates + 1) * h.width;
+    if (bytes < sizeof(h) + sizeof(double) * rows) return fail(BMC_EINVAL, "truncated rule table");
+    (void)hipSetDevice(ctx->device);
+    bmc_rules* r = nullptr;
+    bmc_status st = rules_alloc(ctx, h.method, h.d, h.n_dates, h.payoff, &r);
+    if (st) return st;
+    std::vector<double> w(rows);
+    std::memcpy(w.data(), (const char*)buf + sizeof(h), sizeof(double) * rows);
+    std::vector<float> wf(rows);
+    for (size_t i = 0; i < rows; ++i) wf[i] = (float)w[i];
+    hipError_t e;
+    if ((e = hipMemcpy(r->w64, w.data(), sizeof(double) * rows, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(r->w32, wf.data(), sizeof(float) * rows, hipMemcpyHostToDevice))) {
+        bmc_rules_destroy(r);
+        return hip_fail(e, "rule import");
+    }
+    *out = r;
+    return BMC_OK;
+}
+
+static bmc_status check_rules(const bmc_rules* r, const bmc_spec* s)
+{
+    if (!r) return fail(BMC_EINVAL, "rules is NULL");
+    if (r->d != s->d || r->n_dates != s->n_dates)
+        return fail(BMC_EINVAL, "rule table (d=%d, dates=%d) does not match the spec (d=%d, dates=%d)",
+                    r->d, r->n_dates, s->d, s->n_dates);
+    return BMC_OK;
+}
+
+static bmc_status check_prec(int32_t prec)
+{
+    if (prec < BMC_FP64 || prec > BMC_FP32_KAHAN) return fail(BMC_EINVAL, "unknown precision %d", prec);
+    return BMC_OK;
+}
+
+static bmc_status check_seed(uint64_t seed)
+{
+    if (seed > 0xFFFFFFFFull) return fail(BMC_EINVAL, "seed must fit in 32 bits");
+    return BMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Continuation launches
+
+uint32_t bmc::choose_ppt(int64_t points, int64_t n, const Tuning* tune)
+{
+    if (tune && tune->ppt > 0) return (uint32_t)tune->ppt;
+    // enough lanes to fill 256 CUs x 2048 resident lanes, then longer chunks
+    const double lanes = 256.0 * 2048.0;
+    const double per_lane = (double)points * (double)n / lanes;
+    uint32_t ppt = 1;
+    while (ppt < 16 && (double)(ppt * 2) <= per_lane) ppt *= 2;
+    return ppt;
+}
+
+bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int method,
+                         int width, const void* rules64, const void* rules32, int prec, int m,
+                         const double* x, int64_t N, const int32_t* ids, const int32_t* n_ids,
+                         uint32_t n, uint32_t k0, uint32_t k1, double* cont, double* se,
+                         int64_t* steps, double* sums, unsigned long long* steps_total,
+                         const Tuning* tune)
+{
+    const int block = (tune && tune->block > 0) ? tune->block : 256;
+    const uint32_t ppt = choose_ppt(N, n, tune);
+    const uint32_t per_wg = (uint32_t)block * ppt;
+    const uint32_t nchunk = (n + per_wg - 1) / per_wg;
+    const size_t part_bytes = sizeof(double) * 3 * (size_t)N * nchunk;
+    hipError_t e = ctx->part.ensure(part_bytes);
+    if (e) return hip_fail(e, "partials allocation");
+    const size_t lds = cont_lds_bytes(prec, n_dates, width);
+    if (lds > 64 * 1024) return fail(BMC_EUNSUPPORTED, "rule table too large for LDS (%zu bytes)", lds);
+    const int64_t grid = (int64_t)N * nchunk;
+    if (grid > 0x7FFFFFFF) return fail(BMC_EINVAL, "too many jobs in one launch");
+    ContArgs a;
+    a.spec = (const DevSpec*)devspec;
+    a.rules = prec == BMC_FP64 ? rules64 : rules32;
+    a.x = x;
+    a.N = N;
+    a.ids = ids;
+    a.n_ids = n_ids;
+    a.n = n;
+    a.m = m;
+    a.method = method;
+    a.width = width;
+    a.paths_per_wg = per_wg;
+    a.nchunk = nchunk;
+    a.k0 = k0;
+    a.k1 = k1;
+    a.part = (double*)ctx->part.ptr;
+    if ((e = launch_cont(d, prec, a, (int)grid, block, lds, ctx->stream))) return hip_fail(e, "continuation launch");
+    if ((e = launch_finalize(a.part, nchunk, n, N, ids, n_ids, cont, se, steps, sums, steps_total,
+                             ctx->stream)))
+        return hip_fail(e, "finalize launch");
+    return BMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Entry points on device arrays
+
+extern "C" bmc_status bmc_estimate_continuation(bmc_ctx* ctx, const bmc_spec* spec, const bmc_rules* rules,
+                                                int32_t date, const double* x, int64_t N, int64_t n,
+                                                uint64_t seed, int32_t precision, double* cont,
+                                                double* std_err, int64_t* steps)
+{
+    if (!ctx || !x || !cont || !std_err) return fail(BMC_EINVAL, "NULL argument");
+    (void)hipSetDevice(ctx->device);
+    bmc_status st;
+    if ((st = upload_spec(ctx, spec, ctx->spec))) return st;
+    if ((st = check_rules(rules, spec)) || (st = check_prec(precision)) || (st = check_seed(seed))) return st;
+    if (date < 0 || date >= spec->n_dates) return fail(BMC_EINVAL, "date %d outside 0..%d", date, spec->n_dates - 1);
+    if (N < 1 || N > 0x7FFFFFFF) return fail(BMC_EINVAL, "N = %lld out of range", (long long)N);
+    if (n < 2 || n > 0x7FFFFFFF) return fail(BMC_EINVAL, "n = %lld out of range", (long long)n);
+    return run_cont(ctx, ctx->spec.ptr, spec->d, spec->n_dates, rules->method, rules->width, rules->w64,
+                    rules->w32, precision, date, x, N, nullptr, nullptr, (uint32_t)n, (uint32_t)seed,
+                    key_hi(BMC_STREAM_INNER, date), cont, std_err, steps, nullptr, nullptr, nullptr);
+}
+
+bmc_status bmc::fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rules* rules, int date,
+                              const double* x, const double* values, int64_t N, int rounds)
+{
+    hipError_t e;
+    double* row64 = rules->w64 + (size_t)date * rules->width;
+    float* row32 = rules->w32 + (size_t)date * rules->width;
+    if (rules->method == BMC_CMC) {
+        const int p = rules->width;
+        if ((e = ctx->fit.ensure(sizeof(double) * fit_scratch_doubles(N, p, rounds))))
+            return hip_fail(e, "fit scratch");
+        FitScratch fs;
+        fit_scratch_carve((double*)ctx->fit.ptr, N, p, rounds, &fs);
+        if ((e = launch_fit_cmc((const DevSpec*)devspec, d, x, values, N, rounds, fs, row64, row32, ctx->stream)))
+            return hip_fail(e, "fit launch");
+    } else {
+        if ((e = ctx->fit.ensure(sizeof(double) * fitiz_scratch_doubles(N, rules->width))))
+            return hip_fail(e, "fit scratch");
+        if ((e = launch_fit_iz((const DevSpec*)devspec, d, x, N, (double*)ctx->fit.ptr, row64, row32,
+                               ctx->stream)))
+            return hip_fail(e, "fit launch");
+    }
+    return BMC_OK;
+}
+
+extern "C" bmc_status bmc_fit_rule(bmc_ctx* ctx, const bmc_spec* spec, bmc_rules* rules, int32_t date,
+                                   const double* x, const double* values, int64_t N, int32_t rounds)
+{
+    if (!ctx || !x) return fail(BMC_EINVAL, "NULL argument");
+    (void)hipSetDevice(ctx->device);
+    bmc_status st;
+    if ((st = upload_spec(ctx, spec, ctx->spec))) return st;
+    if ((st = check_rules(rules, spec))) return st;
+    if (date < 1 || date >= spec->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, spec->n_dates - 1);
+    if (N < 1 || N > 0x7FFFFFFF) return fail(BMC_EINVAL, "N out of range");
+    if (rules->method == BMC_CMC && !values) return fail(BMC_EINVAL, "CMC fit needs continuation values");
+    if (rounds <= 0) rounds = 8;
+    if (rounds > 64) return fail(BMC_EINVAL, "rounds must be <= 64");
+    return fit_rule_impl(ctx, ctx->spec.ptr, spec->d, rules, date, x, values, N, rounds);
+}
+
+bmc_status bmc::sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, int method,
+                                   int date, int64_t N, uint32_t seed, double* x, double* Bbuf)
+{
+    hipError_t e;
+    const DevSpec* ds = (const DevSpec*)devspec;
+    const int d = spec->d, NT = spec->n_dates;
+    if (method == BMC_CMC) {
+        if ((e = launch_bridge_end(ds, d, N, seed, Bbuf, ctx->stream))) return hip_fail(e, "bridge");
+        for (int mm = NT - 1; mm >= date; --mm)
+            if ((e = launch_bridge_back(ds, d, mm, N, seed, Bbuf, nullptr, 1, ctx->stream)))
+                return hip_fail(e, "bridge");
+        if ((e = launch_bridge_back(ds, d, date, N, seed, Bbuf, x, 0, ctx->stream))) return hip_fail(e, "points");
+    } else {
+        const unsigned long long* best = nullptr;
+        if (d - 1 >= 2 && N > 2) {
+            if ((e = ctx->korobov.ensure(sizeof(unsigned long long)))) return hip_fail(e, "korobov");
+            if ((e = hipMemsetAsync(ctx->korobov.ptr, 0, sizeof(unsigned long long), ctx->stream)))
+                return hip_fail(e, "korobov");
+            if ((e = launch_korobov(N, d - 1, (unsigned long long*)ctx->korobov.ptr, ctx->stream)))
+                return hip_fail(e, "korobov");
+            best = (const unsigned long long*)ctx->korobov.ptr;
+        }
+        if ((e = launch_lattice(ds, d, date, N, best, x, ctx->stream))) return hip_fail(e, "lattice");
+    }
+    return BMC_OK;
+}
+
+extern "C" bmc_status bmc_sample_points(bmc_ctx* ctx, const bmc_spec* spec, int32_t method, int32_t date,
+                                        int64_t N, uint64_t seed, double* x)
+{
+    if (!ctx || !x) return fail(BMC_EINVAL, "NULL argument");
+    (void)hipSetDevice(ctx->device);
+    bmc_status st;
+    if ((st = upload_spec(ctx, spec, ctx->spec)) || (st = check_seed(seed))) return st;
+    if (method != BMC_CMC && method != BMC_IZ) return fail(BMC_EINVAL, "unknown method %d", method);
+    if (date < 1 || date > spec->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, spec->n_dates);
+    if (N < 1 || N > 0x7FFFFFFF) return fail(BMC_EINVAL, "N out of range");
+    if (method == BMC_IZ && (spec->d > IZ_D_MAX || N > 65536))
+        return fail(BMC_EUNSUPPORTED, "I&Z lattice supports d <= %d and J <= 65536", IZ_D_MAX);
+    hipError_t e = ctx->B.ensure(sizeof(double) * spec->d * N);
+    if (e) return hip_fail(e, "bridge buffer");
+    return sample_points_impl(ctx, ctx->spec.ptr, spec, method, date, N, (uint32_t)seed, x, (double*)ctx->B.ptr);
+}
+
+bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, const bmc_rules* rules,
+                               int date, const double* x, int64_t J, uint32_t n, uint32_t seed, int prec,
+                               double eps, int max_iter, double* s_out, int32_t* iters, int64_t* steps_out,
+                               const Tuning* tune)
+{
+    const int d = spec->d;
+    hipError_t e;
+    // x_work [d][J], s_cur, cont [J], steps [J], steps_acc [J], ids x2, counters
+    const size_t need = sizeof(double) * ((size_t)d * J + 3 * J) + sizeof(unsigned long long) * J +
+                        sizeof(int32_t) * 2 * J + 64;
+    if ((e = ctx->iz.ensure(need))) return hip_fail(e, "search buffers");
+    if ((e = ctx->counters.ensure(64))) return hip_fail(e, "counters");
+    char* c = (char*)ctx->iz.ptr;
+    double* x_work = (double*)c; c += sizeof(double) * d * J;
+    double* s_cur = (double*)c; c += sizeof(double) * J;
+    double* cont = (double*)c; c += sizeof(double) * J;
+    int64_t* stp = (int64_t*)c; c += sizeof(int64_t) * J;
+    unsigned long long* acc = (unsigned long long*)c; c += sizeof(unsigned long long) * J;
+    int32_t* ids_a = (int32_t*)c; c += sizeof(int32_t) * J;
+    int32_t* ids_b = (int32_t*)c;
+    // counters buffer: [0,8) step total, [16,40) final sums/steps, [48,56) active counts
+    int32_t* cnt = (int32_t*)((char*)ctx->counters.ptr + 48);
+    const DevSpec* ds = (const DevSpec*)devspec;
+    if ((e = launch_iz_init(ds, x, d, J, x_work, s_cur, s_out, iters, ids_a, &cnt[0], acc, ctx->stream)))
+        return hip_fail(e, "search init");
+    const uint32_t k1 = key_hi(BMC_STREAM_INNER, date);
+    for (int it = 0; it < max_iter; ++it) {
+        int32_t* ids_in = (it & 1) ? ids_b : ids_a;
+        int32_t* ids_out = (it & 1) ? ids_a : ids_b;
+        int32_t* n_in = &cnt[it & 1];
+        int32_t* n_out = &cnt[1 - (it & 1)];
+        if ((e = hipMemsetAsync(n_out, 0, sizeof(int32_t), ctx->stream))) return hip_fail(e, "search");
+        bmc_status st = run_cont(ctx, devspec, d, spec->n_dates, rules->method, rules->width, rules->w64,
+                                 rules->w32, prec, date, x_work, J, ids_in, n_in, n, seed, k1, cont,
+                                 nullptr, stp, nullptr, nullptr, tune);
+        if (st) return st;
+        if ((e = launch_iz_update(ds, d, J, cont, stp, ids_in, n_in, ids_out, n_out, s_cur, x_work, s_out,
+                                  iters, acc, eps, max_iter, it, ctx->stream)))
+            return hip_fail(e, "search update");
+        if ((it & 3) == 3 || it == max_iter - 1) {
+            int32_t left = 0;
+            if ((e = hipMemcpyAsync(&left, n_out, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream)) ||
+                (e = hipStreamSynchronize(ctx->stream)))
+                return hip_fail(e, "search progress");
+            if (left == 0) break;
+        }
+    }
+    if (steps_out) {
+        std::vector<unsigned long long> h(J);
+        if ((e = hipMemcpyAsync(h.data(), acc, sizeof(unsigned long long) * J, hipMemcpyDeviceToHost,
+                                ctx->stream)) ||
+            (e = hipStreamSynchronize(ctx->stream)))
+            return hip_fail(e, "search steps");
+        unsigned long long tot = 0;
+        for (int64_t j = 0; j < J; ++j) tot += h[j];
+        *steps_out = (int64_t)tot;
+    }
+    return BMC_OK;
+}
+
+extern "C" bmc_status bmc_iz_search(bmc_ctx* ctx, const bmc_spec* spec, const bmc_rules* rules, int32_t date,
+                                    const double* x, int64_t J, int64_t n, uint64_t seed, int32_t precision,
+                                    double eps, int32_t max_iter, double* s_out, int32_t* iters, int64_t* steps)
+{
+    if (!ctx || !x || !s_out || !iters) return fail(BMC_EINVAL, "NULL argument");
+    (void)hipSetDevice(ctx->device);
+    bmc_status st;
+    if ((st = upload_spec(ctx, spec, ctx->spec))) return st;
+    if ((st = check_rules(rules, spec)) || (st = check_prec(precision)) || (st = check_seed(seed))) return st;
+    if (rules->method != BMC_IZ) return fail(BMC_EINVAL, "I&Z search needs an I&Z rule table");
+    if (date < 1 || date >= spec->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, spec->n_dates - 1);
+    if (J < 1 || J > 0x7FFFFFFF || n < 2 || n > 0x7FFFFFFF) return fail(BMC_EINVAL, "J or n out of range");
+    if (!(eps > 0.0) || max_iter < 1) return fail(BMC_EINVAL, "eps must be > 0 and max_iter >= 1");
+    st = iz_search_impl(ctx, ctx->spec.ptr, spec, rules, date, x, J, (uint32_t)n, (uint32_t)seed, precision, eps,
+                        max_iter, s_out, iters, steps, nullptr);
+    if (st) return st;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(e, "stream sync");
+    return BMC_OK;
+}
+
+bmc_status bmc::final_price_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, const bmc_rules* rules,
+                                 int64_t n_final, uint32_t seed, int prec, double* host_sums,
+                                 const Tuning* tune)
+{
+    hipError_t e;
+    if ((e = ctx->counters.ensure(64))) return hip_fail(e, "counters");
+    double* sums = (double*)((char*)ctx->counters.ptr + 16);   // [2]
+    int64_t* fsteps = (int64_t*)((char*)ctx->counters.ptr + 32);
+    bmc_status st = run_cont(ctx, devspec, spec->d, spec->n_dates, rules->method, rules->width, rules->w64,
+                             rules->w32, prec, 0, dev_S0(devspec), 1, nullptr, nullptr, (uint32_t)n_final,
+                             seed, key_hi(BMC_STREAM_FINAL, 0), nullptr, nullptr, fsteps, sums, nullptr, tune);
+    if (st) return st;
+    if ((e = hipMemcpyAsync(ctx->host_io, sums, 16, hipMemcpyDeviceToHost, ctx->stream)) ||
+        (e = hipMemcpyAsync((char*)ctx->host_io + 16, fsteps, 8, hipMemcpyDeviceToHost, ctx->stream)) ||
+        (e = hipStreamSynchronize(ctx->stream)))
+        return hip_fail(e, "final read");
+    std::memcpy(host_sums, ctx->host_io, 16);
+    int64_t fs;
+    std::memcpy(&fs, (char*)ctx->host_io + 16, 8);
+    host_sums[2] = (double)fs;
+    return BMC_OK;
+}
+
+void bmc::fill_price(const double* sums, int64_t n_final, bmc_result* out)
+{
+    const double s = sums[0], q = sums[1], nn = (double)n_final;
+    double var = (q - s * s / nn) / (nn - 1.0);
+    if (var < 0.0) var = 0.0;
+    out->price = s / nn;
+    out->variance = var;
+    out->std_err = std::sqrt(var / nn);
+    out->ci95 = 1.96 * out->std_err;
+    out->final_path_steps = (int64_t)sums[2];
+}
+
+extern "C" bmc_status bmc_final_price(bmc_ctx* ctx, const bmc_spec* spec, const bmc_rules* rules,
+                                      int64_t n_final, uint64_t seed, int32_t precision, bmc_result* out)
+{
+    if (!ctx || !out) return fail(BMC_EINVAL, "NULL argument");
+    (void)hipSetDevice(ctx->device);
+    auto t0 = std::chrono::steady_clock::now();
+    bmc_status st;
+    if ((st = upload_spec(ctx, spec, ctx->spec))) return st;
+    if ((st = check_rules(rules, spec)) || (st = check_prec(precision)) || (st = check_seed(seed))) return st;
+    if (n_final < 2 || n_final > 0x7FFFFFFF) return fail(BMC_EINVAL, "n_final out of range");
+    double sums[3];
+    if ((st = final_price_impl(ctx, ctx->spec.ptr, spec, rules, n_final, (uint32_t)seed, precision, sums, nullptr)))
+        return st;
+    bmc_result r;
+    std::memset(&r, 0, sizeof(r));
+    fill_price(sums, n_final, &r);
+    r.seconds = r.final_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = r;
+    return BMC_OK;
+}
+
+extern "C" bmc_status bmc_philox(bmc_ctx* ctx, uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t M,
+                                 uint32_t* out)
+{
+    if (!ctx || !ctr || !out || M < 0) return fail(BMC_EINVAL, "bad argument");
+    (void)hipSetDevice(ctx->device);
+    if (M == 0) return BMC_OK;
+    hipError_t e = launch_philox(k0, k1, ctr, M, out, ctx->stream);
+    return e ? hip_fail(e, "philox launch") : BMC_OK;
+}
+
+extern "C" bmc_status bmc_normals(bmc_ctx* ctx, uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t M,
+                                  int32_t precision, double* out)
+{
+    if (!ctx || !ctr || !out || M < 0) return fail(BMC_EINVAL, "bad argument");
+    bmc_status st = check_prec(precision);
+    if (st) return st;
+    (void)hipSetDevice(ctx->device);
+    if (M == 0) return BMC_OK;
+    hipError_t e = launch_normals(k0, k1, ctr, M, precision == BMC_FP64 ? 0 : 1, out, ctx->stream);
+    return e ? hip_fail(e, "normals launch") : BMC_OK;
+}

@@ -1,0 +1,6 @@
+// Continuation kernel instantiation for dimension bound 4.
+#include "cont_kernel.hpp"
+
+namespace bmc {
+template hipError_t launch_cont_d<4, true>(int, const ContArgs&, int, int, size_t, hipStream_t);
+}  // namespace bmc

@@ -1,0 +1,207 @@
+// Device building blocks of the nested continuation-value Monte Carlo on
+// gfx950: Philox4x32-10 counter generator, uniform-to-normal map, spec tables,
+// payoffs and exercise-rule tests.  FP64 and FP32 variants share templates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bmc {
+
+constexpr int D_MAX = 64;
+constexpr int NT_MAX = 512;
+
+enum { PUT_BASKET = 0, CALL_MAX = 1, PUT_GEO = 2 };
+enum { CMC = 0, IZ = 1 };
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP32_KAHAN = 2 };
+enum { STREAM_OUTER = 1, STREAM_INNER = 2, STREAM_FINAL = 3 };
+
+// Per-spec constants in one precision.  A = diag(sigma) L (row-major, lower),
+// drift_i = r - delta_i - sigma_i^2 / 2, t[0] = 0, dt[k] = t_k - t_{k-1},
+// sdt[k] = sqrt(dt[k]).
+template <class R>
+struct SpecT {
+    int32_t d, n_dates, payoff, pad;
+    R K, lnK, invK, r, inv_d;
+    R S0[D_MAX], drift[D_MAX], sigma[D_MAX];
+    R A[D_MAX * D_MAX];
+    R t[NT_MAX + 1], dt[NT_MAX + 1], sdt[NT_MAX + 1];
+};
+
+struct DevSpec {
+    SpecT<double> f64;
+    SpecT<float> f32;
+    double L[D_MAX * D_MAX];   // Cholesky factor of rho
+    int32_t status;            // 0 or -2 (not positive definite)
+};
+
+template <class R> __device__ __forceinline__ const SpecT<R>& spec_of(const DevSpec* s);
+template <> __device__ __forceinline__ const SpecT<double>& spec_of<double>(const DevSpec* s) { return s->f64; }
+template <> __device__ __forceinline__ const SpecT<float>& spec_of<float>(const DevSpec* s) { return s->f32; }
+
+__host__ __device__ __forceinline__ uint32_t key_hi(int stream, int date)
+{
+    return ((uint32_t)stream << 16) | ((uint32_t)date & 0xFFFFu);
+}
+
+struct Words { uint32_t w[4]; };
+
+// Philox4x32-10: ten rounds of two 32x32->64 products (multipliers
+// 0xD2511F53 on counter word 0, 0xCD9E8D57 on word 2), the high halves
+// xor-ed with the other words and the key, the key advanced by the Weyl
+// increments 0x9E3779B9 / 0xBB67AE85 between rounds.  Key words that are
+// uniform across the wavefront stay in scalar registers.
+__device__ __forceinline__ Words philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
+                                        uint32_t c2, uint32_t c3)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t a = (uint64_t)0xD2511F53u * c0;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t x0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+        const uint32_t x2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = x0;
+        c2 = x2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Words o;
+    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+    return o;
+}
+
+// Box-Muller on one word pair: u = (x + 1/2) 2^-32 in (0, 1),
+// z0 = sqrt(-2 ln u_a) cos(2 pi u_b), z1 = sqrt(-2 ln u_a) sin(2 pi u_b).
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1)
+{
+    const double ua = ((double)a + 0.5) * 0x1p-32;   // exact
+    const double ub = ((double)b + 0.5) * 0x1p-32;
+    const double rad = sqrt(-2.0 * log(ua));
+    double s, c;
+    sincospi(2.0 * ub, &s, &c);
+    z0 = rad * c;
+    z1 = rad * s;
+}
+
+// FP32 form on the hardware transcendental unit: v_log_f32 is log2,
+// v_sin_f32 / v_cos_f32 take their argument in revolutions.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1)
+{
+    const float ua = fmaf((float)a, 0x1p-32f, 0x1p-33f);
+    const float ub = fmaf((float)b, 0x1p-32f, 0x1p-33f);
+    const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));
+    z0 = rad * __builtin_amdgcn_cosf(ub);
+    z1 = rad * __builtin_amdgcn_sinf(ub);
+}
+
+__device__ __forceinline__ double fexp(double x) { return exp(x); }
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+
+// The d normals of one step: block b of step k has counter (k*nb + b, p, j, 0);
+// asset i takes normal (i mod 4) of block i/4.  D is the compile-time bound,
+// d the runtime dimension (d <= D).
+template <int D, class R>
+__device__ __forceinline__ void step_normals(int d, uint32_t k0, uint32_t k1, uint32_t c0,
+                                             uint32_t p, uint32_t j, R (&z)[D])
+{
+    constexpr int NB = (D + 3) / 4;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (4 * b < d) {
+            const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, 0u);
+            R z0, z1, z2, z3;
+            box_muller(w.w[0], w.w[1], z0, z1);
+            if (4 * b + 0 < D) z[4 * b + 0] = z0;
+            if (4 * b + 1 < D) z[4 * b + 1] = z1;
+            if (4 * b + 2 < D && 4 * b + 2 < d) {
+                box_muller(w.w[2], w.w[3], z2, z3);
+                z[4 * b + 2] = z2;
+                if (4 * b + 3 < D) z[4 * b + 3] = z3;
+            }
+        }
+    }
+}
+
+// Payoff from log-prices.  Max-call and geometric put need one exp.
+template <int D, class R>
+__device__ __forceinline__ R payoff(int kind, int d, R K, R inv_d, const R (&x)[D])
+{
+    R v;
+    if (kind == CALL_MAX) {
+        R mx = x[0];
+#pragma unroll
+        for (int i = 1; i < D; ++i)
+            if (i < d) mx = fmax(mx, x[i]);
+        v = fexp(mx) - K;
+    } else if (kind == PUT_GEO) {
+        R s = x[0];
+#pragma unroll
+        for (int i = 1; i < D; ++i)
+            if (i < d) s += x[i];
+        v = K - fexp(s * inv_d);
+    } else {
+        R s = fexp(x[0]);
+#pragma unroll
+        for (int i = 1; i < D; ++i)
+            if (i < d) s += fexp(x[i]);
+        v = K - s * inv_d;
+    }
+    return v > R(0) ? v : R(0);
+}
+
+// CMC classifier value F = w . [1, u, u^2, g, g^2] with u_i = ln S_i - ln K.
+template <int D, class R>
+__device__ __forceinline__ R cmc_score(int d, const R* __restrict__ w, R lnK, R g, const R (&x)[D])
+{
+    R F = w[0];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        if (i < d) {
+            const R u = x[i] - lnK;
+            F += (w[1 + i] + w[1 + d + i] * u) * u;
+        }
+    }
+    F += (w[1 + 2 * d] + w[2 + 2 * d] * g) * g;
+    return F;
+}
+
+// I&Z boundary b = w . [1, v_2..v_d, v_a v_b (a <= b)], v_i = ln S_i - ln K.
+template <int D, class R>
+__device__ __forceinline__ R iz_boundary(int d, const R* __restrict__ w, R lnK, const R (&x)[D])
+{
+    const int q = d - 1;
+    R v[D > 1 ? D - 1 : 1];
+    R b = w[0];
+#pragma unroll
+    for (int a = 0; a + 1 < D; ++a) {
+        if (a < q) {
+            v[a] = x[a + 1] - lnK;
+            b += w[1 + a] * v[a];
+        }
+    }
+    int f = 1 + q;
+#pragma unroll
+    for (int a = 0; a + 1 < D; ++a) {
+        if (a < q) {
+#pragma unroll
+            for (int c = a; c + 1 < D; ++c) {
+                if (c < q) {
+                    b += w[f] * (v[a] * v[c]);
+                    ++f;
+                }
+            }
+        }
+    }
+    return b;
+}
+
+__host__ __device__ __forceinline__ int rule_width(int method, int d)
+{
+    if (method == CMC) return 2 * d + 3;
+    const int q = d - 1;
+    return 1 + q + q * (q + 1) / 2;
+}
+
+}  // namespace bmc

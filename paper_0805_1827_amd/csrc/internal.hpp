@@ -1,0 +1,97 @@
+// Internal launch interface between the C ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace bmc {
+
+// Spec as uploaded from the host, before the device-side setup kernel derives
+// the Cholesky factor and the per-precision tables.
+struct HostSpecPack {
+    int32_t d, n_dates, payoff, pad;
+    double K, r, T;
+    double S0[D_MAX], delta[D_MAX], sigma[D_MAX];
+    double rho[D_MAX * D_MAX];
+    double dates[NT_MAX];
+};
+
+// One continuation launch: points (ids or 0..N-1) x chunks of paths.
+struct ContArgs {
+    const DevSpec* spec;
+    const void* rules;        // R[(NT+1) * width], row k = date k
+    const double* x;          // SoA points [d][N]
+    int64_t N;                // row stride of x
+    const int32_t* ids;       // active point ids, or null for 0..N-1
+    const int32_t* n_ids;     // device count of ids, or null
+    uint32_t n;               // paths per point
+    int32_t m;                // start date
+    int32_t method;           // CMC / IZ
+    int32_t width;            // rule row width
+    uint32_t paths_per_wg;    // paths of one workgroup (a chunk)
+    uint32_t nchunk;          // chunks per point
+    uint32_t k0, k1;          // Philox key
+    double* part;             // [N * nchunk * 3]: sum, sum of squares, steps
+};
+
+struct LaunchCfg {
+    int block = 256;          // threads per workgroup
+    int ppt = 4;              // paths per thread per chunk
+};
+
+// Kernels (kernels.hip).  All enqueue on `st` and return hipError_t.
+hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, hipStream_t st);
+hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, size_t lds,
+                       hipStream_t st);
+size_t cont_lds_bytes(int prec, int n_dates, int width);
+hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int64_t N,
+                           const int32_t* ids, const int32_t* n_ids, double* cont, double* se,
+                           int64_t* steps, double* sums, unsigned long long* steps_total,
+                           hipStream_t st);
+hipError_t launch_bridge_end(const DevSpec* s, int d, int64_t N, uint32_t seed, double* B,
+                             hipStream_t st);
+hipError_t launch_bridge_back(const DevSpec* s, int d, int m, int64_t N, uint32_t seed, double* B,
+                              double* x, int bridge, hipStream_t st);
+hipError_t launch_korobov(int64_t J, int q, unsigned long long* best, hipStream_t st);
+hipError_t launch_lattice(const DevSpec* s, int d, int m, int64_t J, const unsigned long long* best,
+                          double* x, hipStream_t st);
+hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int64_t J, double* x_work,
+                          double* s_cur, double* s_out, int32_t* iters, int32_t* ids,
+                          int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st);
+hipError_t launch_iz_update(const DevSpec* s, int d, int64_t J, const double* cont,
+                            const int64_t* steps, const int32_t* ids_in, const int32_t* n_in,
+                            int32_t* ids_out, int32_t* n_out, double* s_cur, double* x_work,
+                            double* s_out, int32_t* iters, unsigned long long* steps_acc,
+                            double eps, int max_iter, int it, hipStream_t st);
+hipError_t launch_rules_narrow(const double* w64, float* w32, int64_t count, hipStream_t st);
+
+// CMC boosting fit (FP64) of rule row m.
+struct FitScratch {
+    double* phi;     // [p][N] raw features
+    double* lab;     // [N]
+    double* msk;     // [N]
+    double* F;       // [N]
+    double* pi;      // [N]
+    double* part1;   // [tiles][p+1]
+    double* part2;   // [tiles][p]
+    double* partA;   // [2][tiles][npairs + p]
+    double* beta;    // [rounds][p]
+};
+size_t fit_scratch_doubles(int64_t N, int p, int rounds);
+void fit_scratch_carve(double* base, int64_t N, int p, int rounds, FitScratch* fs);
+hipError_t launch_fit_cmc(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
+                          int rounds, const FitScratch& fs, double* row64, float* row32,
+                          hipStream_t st);
+// I&Z quadratic regression of rule row m; x[0*J + j] = s*_j.
+size_t fitiz_scratch_doubles(int64_t J, int p);
+hipError_t launch_fit_iz(const DevSpec* s, int d, const double* x, int64_t J, double* scratch,
+                         double* row64, float* row32, hipStream_t st);
+
+hipError_t launch_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t M, uint32_t* out,
+                         hipStream_t st);
+hipError_t launch_normals(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t M, int prec,
+                          double* out, hipStream_t st);
+
+}  // namespace bmc

@@ -1,0 +1,178 @@
+// Whole-pricer driver (Algorithm 1 for I&Z, Algorithm 2 for CMC): backward
+// sweep over the exercise dates on the device, then the final pricing pass.
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+#include "runtime.hpp"
+
+using namespace bmc;
+
+namespace {
+
+// Phase timers on the context stream, summed after the closing sync.
+struct PhaseTimer {
+    hipStream_t st;
+    std::vector<hipEvent_t> evs;
+    std::vector<int> phase;
+    explicit PhaseTimer(hipStream_t s) : st(s) {}
+    ~PhaseTimer()
+    {
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    }
+    void mark(int ph)
+    {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        (void)hipEventRecord(e, st);
+        evs.push_back(e);
+        phase.push_back(ph);
+    }
+    // Time from each mark to the next, credited to the earlier mark's phase.
+    void totals(double* sec) const
+    {
+        for (size_t i = 0; i + 1 < evs.size(); ++i) {
+            float ms = 0.f;
+            if (phase[i] >= 0 && hipEventElapsedTime(&ms, evs[i], evs[i + 1]) == hipSuccess)
+                sec[phase[i]] += ms * 1e-3;
+        }
+    }
+};
+
+enum { PH_CALC = 0, PH_FIT = 1, PH_FINAL = 2 };
+
+}  // namespace
+
+bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* opts, bmc_rules** rules_out,
+                          bmc_result* out, const Tuning* tune)
+{
+    auto t_start = std::chrono::steady_clock::now();
+    if (!ctx || !opts || !out) return fail(BMC_EINVAL, "NULL argument");
+    (void)hipSetDevice(ctx->device);
+    const int method = opts->method, prec = opts->precision;
+    if (method != BMC_CMC && method != BMC_IZ) return fail(BMC_EINVAL, "unknown method %d", method);
+    if (prec < BMC_FP64 || prec > BMC_FP32_KAHAN) return fail(BMC_EINVAL, "unknown precision %d", prec);
+    if (opts->N < 2 || opts->N > 0x7FFFFFFF || opts->n < 2 || opts->n > 0x7FFFFFFF || opts->n_final < 2 ||
+        opts->n_final > 0x7FFFFFFF)
+        return fail(BMC_EINVAL, "N, n and n_final must be in 2..2^31-1");
+    if (opts->seed > 0xFFFFFFFFull) return fail(BMC_EINVAL, "seed must fit in 32 bits");
+    const int rounds = opts->cls_rounds > 0 ? opts->cls_rounds : 8;
+    const int max_iter = opts->iz_max_iter > 0 ? opts->iz_max_iter : 100;
+    const double eps = opts->iz_eps > 0.0 ? opts->iz_eps : 0.01;
+    if (rounds > 64) return fail(BMC_EINVAL, "cls_rounds must be <= 64");
+    bmc_status st = upload_spec(ctx, spec, ctx->spec);
+    if (st) return st;
+    if (method == BMC_IZ && opts->N > 65536) return fail(BMC_EUNSUPPORTED, "I&Z supports N <= 65536 lattice points");
+    bmc_rules* rules = nullptr;
+    if ((st = bmc_rules_create(ctx, spec, method, &rules))) return st;
+
+    const int d = spec->d, NT = spec->n_dates;
+    const int64_t N = opts->N;
+    const uint32_t n = (uint32_t)opts->n, seed = (uint32_t)opts->seed;
+    const void* ds = ctx->spec.ptr;
+    hipError_t e;
+    PhaseTimer timer(ctx->stream);
+    int64_t unconv = 0, iz_iters = 0, iz_steps = 0;
+    if ((e = ctx->counters.ensure(64)) || (e = ctx->x.ensure(sizeof(double) * d * N)) ||
+        (e = ctx->cont.ensure(sizeof(double) * N)) || (e = ctx->B.ensure(sizeof(double) * d * N)) ||
+        (e = ctx->steps.ensure(sizeof(int64_t) * N + sizeof(int32_t) * N))) {
+        bmc_rules_destroy(rules);
+        return fail(BMC_ENOMEM, "device buffers: %s", hipGetErrorString(e));
+    }
+    unsigned long long* steps_total = (unsigned long long*)ctx->counters.ptr;
+    double* x = (double*)ctx->x.ptr;
+    double* cont = (double*)ctx->cont.ptr;
+    double* B = (double*)ctx->B.ptr;
+    if ((e = hipMemsetAsync(steps_total, 0, sizeof(unsigned long long), ctx->stream))) {
+        bmc_rules_destroy(rules);
+        return hip_fail(e, "counter reset");
+    }
+
+    if (method == BMC_CMC) {
+        if ((e = launch_bridge_end((const DevSpec*)ds, d, N, seed, B, ctx->stream))) st = hip_fail(e, "bridge");
+        for (int m = NT - 1; m >= 1 && !st; --m) {
+            if ((e = launch_bridge_back((const DevSpec*)ds, d, m, N, seed, B, x, 1, ctx->stream))) {
+                st = hip_fail(e, "bridge");
+                break;
+            }
+            timer.mark(PH_CALC);
+            st = run_cont(ctx, ds, d, NT, method, rules->width, rules->w64, rules->w32, prec, m, x, N, nullptr,
+                          nullptr, n, seed, key_hi(BMC_STREAM_INNER, m), cont, nullptr, nullptr, nullptr,
+                          steps_total, tune);
+            if (st) break;
+            timer.mark(PH_FIT);
+            st = fit_rule_impl(ctx, ds, d, rules, m, x, cont, N, rounds);
+            timer.mark(-1);
+        }
+    } else {
+        double* s_out = cont;
+        int32_t* iters = (int32_t*)((char*)ctx->steps.ptr + sizeof(int64_t) * N);
+        std::vector<double> hs(N);
+        std::vector<int32_t> hi(N);
+        for (int m = NT - 1; m >= 1 && !st; --m) {
+            if ((st = sample_points_impl(ctx, ds, spec, BMC_IZ, m, N, seed, x, B))) break;
+            timer.mark(PH_CALC);
+            int64_t stp = 0;
+            st = iz_search_impl(ctx, ds, spec, rules, m, x, N, n, seed, prec, eps, max_iter, s_out, iters, &stp,
+                                tune);
+            if (st) break;
+            iz_steps += stp;
+            timer.mark(PH_FIT);
+            if ((e = hipMemcpyAsync(x, s_out, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream))) {
+                st = hip_fail(e, "boundary copy");
+                break;
+            }
+            if ((st = fit_rule_impl(ctx, ds, d, rules, m, x, nullptr, N, rounds))) break;
+            timer.mark(-1);
+            if ((e = hipMemcpyAsync(hs.data(), s_out, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream)) ||
+                (e = hipMemcpyAsync(hi.data(), iters, sizeof(int32_t) * N, hipMemcpyDeviceToHost, ctx->stream)) ||
+                (e = hipStreamSynchronize(ctx->stream))) {
+                st = hip_fail(e, "search results");
+                break;
+            }
+            for (int64_t j = 0; j < N; ++j) {
+                if (!(hs[j] > 0.0)) ++unconv;
+                iz_iters += hi[j];
+            }
+        }
+    }
+    double sums[3] = {0, 0, 0};
+    if (!st) {
+        timer.mark(PH_FINAL);
+        st = final_price_impl(ctx, ds, spec, rules, opts->n_final, seed, prec, sums, tune);
+        timer.mark(-1);
+    }
+    unsigned long long inner = 0;
+    if (!st) {
+        if ((e = hipMemcpyAsync(&inner, steps_total, sizeof(inner), hipMemcpyDeviceToHost, ctx->stream)) ||
+            (e = hipStreamSynchronize(ctx->stream)))
+            st = hip_fail(e, "result read");
+    }
+    if (st) {
+        bmc_rules_destroy(rules);
+        return st;
+    }
+    bmc_result r;
+    std::memset(&r, 0, sizeof(r));
+    fill_price(sums, opts->n_final, &r);
+    r.inner_path_steps = method == BMC_CMC ? (int64_t)inner : iz_steps;
+    r.iz_unconverged = unconv;
+    r.iz_iterations = iz_iters;
+    double sec[3] = {0, 0, 0};
+    timer.totals(sec);
+    r.calc_seconds = sec[PH_CALC];
+    r.fit_seconds = sec[PH_FIT];
+    r.final_seconds = sec[PH_FINAL];
+    r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    *out = r;
+    if (rules_out) *rules_out = rules;
+    else bmc_rules_destroy(rules);
+    return BMC_OK;
+}
+
+extern "C" bmc_status bmc_price(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* opts, bmc_rules** rules_out,
+                                bmc_result* out)
+{
+    return bmc_price_impl(ctx, spec, opts, rules_out, out, nullptr);
+}

@@ -1,0 +1,75 @@
+// Host-side runtime structures shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "bmc.h"
+
+namespace bmc {
+
+struct HostSpecPack;
+
+constexpr int IZ_D_MAX = 16;
+
+// Grow-only device allocation.
+struct DBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t n);
+    void release();
+};
+
+// Launch shape of the continuation kernel (0 = automatic).
+struct Tuning {
+    int block = 0;
+    int ppt = 0;
+};
+
+bmc_status fail(bmc_status st, const char* fmt, ...);
+bmc_status hip_fail(hipError_t e, const char* where);
+bmc_status validate_spec(const bmc_spec* s);
+
+}  // namespace bmc
+
+struct bmc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bmc::HostSpecPack* pack_host = nullptr;   // pinned staging
+    void* host_io = nullptr;                  // pinned 4 KB for small results
+    bmc::DBuf spec, spec2, pack_dev, part, B, x, x2, cont, se, steps, fit, iz, counters, korobov;
+    ~bmc_ctx();
+};
+
+struct bmc_rules {
+    bmc_ctx* ctx = nullptr;
+    int method = 0, d = 0, n_dates = 0, width = 0, payoff = 0;
+    double* w64 = nullptr;   // device [(n_dates+1) * width]
+    float* w32 = nullptr;    // device, same rows in float
+};
+
+namespace bmc {
+
+bmc_status upload_spec(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot);
+const double* dev_S0(const void* devspec);
+uint32_t choose_ppt(int64_t points, int64_t n, const Tuning* tune);
+bmc_status run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int method, int width,
+                    const void* rules64, const void* rules32, int prec, int m, const double* x,
+                    int64_t N, const int32_t* ids, const int32_t* n_ids, uint32_t n, uint32_t k0,
+                    uint32_t k1, double* cont, double* se, int64_t* steps, double* sums,
+                    unsigned long long* steps_total, const Tuning* tune);
+bmc_status fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rules* rules, int date,
+                         const double* x, const double* values, int64_t N, int rounds);
+bmc_status sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, int method,
+                              int date, int64_t N, uint32_t seed, double* x, double* Bbuf);
+bmc_status iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec,
+                          const bmc_rules* rules, int date, const double* x, int64_t J, uint32_t n,
+                          uint32_t seed, int prec, double eps, int max_iter, double* s_out,
+                          int32_t* iters, int64_t* steps_out, const Tuning* tune);
+bmc_status final_price_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec,
+                            const bmc_rules* rules, int64_t n_final, uint32_t seed, int prec,
+                            double* host_sums, const Tuning* tune);
+void fill_price(const double* sums, int64_t n_final, bmc_result* out);
+
+}  // namespace bmc

@@ -1,0 +1,407 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle
+on identical seeded inputs.
+
+Bars: integer outputs (Philox words, executed path-steps, I&Z iteration
+counts) bit-exact; FP64 values |a - b| <= 1e-10 max(|a|, |b|) + 1e-12 K;
+FP32 mode within 0.1 of the Monte Carlo standard error of the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from conftest import cpu_threads
+
+pytestmark = pytest.mark.gpu
+NT_CPU = cpu_threads()
+REL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bmc(torch_mod):
+    from paper_0805_1827_amd import bmc as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(bmc):
+    c = bmc.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch_mod, a, dtype=None):
+    dtype = dtype or torch_mod.float64
+    return torch_mod.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def assert_close(a, b, K, rel=REL, what=""):
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    tol = rel * np.maximum(np.abs(a), np.abs(b)) + 1e-12 * K
+    bad = np.abs(a - b) > tol
+    assert not bad.any(), f"{what}: {bad.sum()} mismatches, worst {np.max(np.abs(a - b) / (tol + 1e-300)):.3g}x tol; " \
+                          f"first idx {np.argmax(bad)} gpu {a.flat[np.argmax(bad)]!r} oracle {b.flat[np.argmax(bad)]!r}"
+
+
+def cmc_scores(spec, table_rows, x):
+    """F = w . [1, u, u^2, g, g^2] of each rule row at the points x (columns)."""
+    u = np.log(x) - np.log(spec.K)
+    if spec.payoff == 1:
+        pay = np.maximum(x.max(axis=0) - spec.K, 0.0)
+    elif spec.payoff == 2:
+        pay = np.maximum(spec.K - np.exp(np.log(x).mean(axis=0)), 0.0)
+    else:
+        pay = np.maximum(spec.K - x.mean(axis=0), 0.0)
+    g = pay / spec.K
+    phi = np.column_stack([np.ones(x.shape[1]), u.T, (u ** 2).T, g, g * g])
+    return np.atleast_2d(table_rows) @ phi.T
+
+
+def assert_same_rule(spec, w_gpu, w_ref, x, what=""):
+    """The learned exercise rules agree where they are used: the classifier
+    values at the points agree (individual weights of nearly collinear
+    features are not determined to full precision)."""
+    Fg, Fr = cmc_scores(spec, w_gpu, x), cmc_scores(spec, w_ref, x)
+    assert np.all(np.abs(Fg - Fr) <= 1e-6 * (1.0 + np.abs(Fr))), f"{what}: max |dF| {np.max(np.abs(Fg - Fr)):.3g}"
+
+
+def gpu_rules(bmc, ctx, spec, method, table):
+    r = bmc.bmc_rules_create(ctx, spec, method)
+    bmc.set_rules_table(r, table)
+    return r
+
+
+def cont_parity(bmc, ctx, orc, torch_mod, spec, method, table, m, x, n, seed, ids=None, prec=None):
+    rules = gpu_rules(bmc, ctx, spec, method, table)
+    c, se, st = bmc.bmc_estimate_continuation(ctx, spec, rules, m, dev(torch_mod, x), n, seed,
+                                              bmc.FP64 if prec is None else prec)
+    torch_mod.cuda.synchronize()
+    ref = orc.continuation(spec, method, table, m, x, n, seed, nthreads=NT_CPU, ids=ids)
+    return host(c), host(se), host(st), ref
+
+
+# --- random numbers -------------------------------------------------------
+
+def test_philox_bit_exact(bmc, ctx, orc, torch_mod):
+    rng = np.random.default_rng(5)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:8] = [[0, 0, 0, 0], [1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1],
+               [0xFFFFFFFF] * 4, [9, 499, 123, 0], [3, 7, 11, 13]]
+    for k0, k1 in ((1, (2 << 16) | 9), (0xDEADBEEF, 0x12345678)):
+        out = host(bmc.bmc_philox(ctx, k0, k1, dev(torch_mod, ctr.view(np.int32), torch_mod.int32)))
+        ref = np.stack([orc.philox(k0, k1, c) for c in ctr])
+        assert np.array_equal(out.view(np.uint32), ref)
+
+
+def test_normals_fp64_and_fp32(bmc, ctx, orc, torch_mod):
+    rng = np.random.default_rng(6)
+    ctr = rng.integers(0, 2 ** 32, size=(8192, 4), dtype=np.uint64).astype(np.uint32)
+    dctr = dev(torch_mod, ctr.view(np.int32), torch_mod.int32)
+    ref = np.stack([orc.normal_block(77, 99, c) for c in ctr])
+    z64 = host(bmc.bmc_normals(ctx, 77, 99, dctr, bmc.FP64))
+    assert np.max(np.abs(z64 - ref)) < 1e-13
+    z32 = host(bmc.bmc_normals(ctx, 77, 99, dctr, bmc.FP32))
+    err = np.abs(z32 - ref)
+    assert err.max() < 5e-4 and err.mean() < 2e-6
+
+
+# --- sample points ----------------------------------------------------------
+
+def test_cmc_points_parity(bmc, ctx, orc, torch_mod, inputs):
+    for spec, N in ((inputs.geometric_put5(), 1000), (inputs.one_asset_put(), 333),
+                    (inputs.max_call(3, 90.0), 517)):
+        for m in sorted({1, spec.n_dates // 2, spec.n_dates - 1, spec.n_dates}):
+            x = host(bmc.bmc_sample_points(ctx, spec, bmc.CMC, m, N, 7))
+            assert_close(x, orc.points_cmc(spec, m, N, 7), spec.K, rel=1e-12, what=f"points m={m}")
+
+
+def test_iz_lattice_parity(bmc, ctx, orc, torch_mod, inputs):
+    for spec, J in ((inputs.geometric_put5(), 256), (inputs.one_asset_put(), 8),
+                    (inputs.basket(3, 100.0, 100.0, 0.05, 0.0, 0.25, 0.2, 1.0, 6, inputs.PUT_BASKET), 97)):
+        for m in (1, spec.n_dates - 1):
+            x = host(bmc.bmc_sample_points(ctx, spec, bmc.IZ, m, J, 1))
+            assert_close(x, orc.points_iz(spec, m, J), spec.K, rel=1e-12, what=f"lattice m={m}")
+
+
+# --- continuation estimates -------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c1_rules(orc, inputs):
+    spec = inputs.one_asset_put()
+    return spec, orc.price(spec, orc.CMC, 500, 500, 1000, 1, nthreads=NT_CPU)["rules"]
+
+
+def test_continuation_c1_every_date(bmc, ctx, orc, torch_mod, c1_rules):
+    """1-asset put, N = n = 500 (ragged chunks), every date, oracle's rules."""
+    spec, table = c1_rules
+    for m in range(1, spec.n_dates):
+        x = orc.points_cmc(spec, m, 500, 1)
+        c, se, st, ref = cont_parity(bmc, ctx, orc, torch_mod, spec, bmc.CMC, table, m, x, 500, 1)
+        assert_close(c, ref["cont"], spec.K, what=f"cont m={m}")
+        assert_close(se, ref["se"], spec.K, rel=1e-8, what=f"se m={m}")
+        assert np.array_equal(st, ref["steps"]), m
+
+
+def _small_rules(orc, spec, method=0, N=128, n=128):
+    return orc.price(spec, method, N, n, 256, 11, nthreads=NT_CPU)["rules"]
+
+
+@pytest.mark.parametrize("case", ["geo5", "maxcall3", "basket4"])
+def test_continuation_multi_asset(bmc, ctx, orc, torch_mod, inputs, case):
+    spec = {"geo5": inputs.geometric_put5(), "maxcall3": inputs.max_call(3, 100.0),
+            "basket4": inputs.basket(4, [95, 100, 105, 110], 100.0, 0.05, [0.0, 0.01, 0.02, 0.0],
+                                     [0.2, 0.25, 0.3, 0.15], 0.4, 1.0, 8, inputs.PUT_BASKET)}[case]
+    table = _small_rules(orc, spec)
+    for m, n in ((1, 1000), (spec.n_dates // 2, 4096), (spec.n_dates - 1, 777)):
+        x = orc.points_cmc(spec, m, 48, 3)
+        c, se, st, ref = cont_parity(bmc, ctx, orc, torch_mod, spec, bmc.CMC, table, m, x, n, 5)
+        assert_close(c, ref["cont"], spec.K, what=f"{case} m={m}")
+        assert np.array_equal(st, ref["steps"])
+
+
+@pytest.mark.parametrize("d,payoff", [(12, 0), (20, 1), (40, 2)])
+def test_continuation_large_d(bmc, ctx, orc, torch_mod, inputs, d, payoff):
+    """Dimension buckets (runtime d below the compiled bound), Wishart correlation."""
+    rng = np.random.default_rng(d)
+    sigma = rng.uniform(0.1, 0.4, size=d)
+    rho = inputs.wishart_corr(d, rng)
+    T, delta = (3.0, 0.1) if payoff == 1 else (1.0, 0.0)
+    spec = inputs.basket(d, 100.0, 100.0, 0.05, delta, sigma, rho, T, 6, payoff)
+    table = _small_rules(orc, spec, N=96, n=64)
+    for m in (1, 5):
+        x = orc.points_cmc(spec, m, 24, 2)
+        c, se, st, ref = cont_parity(bmc, ctx, orc, torch_mod, spec, bmc.CMC, table, m, x, 600, 9)
+        assert_close(c, ref["cont"], spec.K, what=f"d={d} m={m}")
+        assert np.array_equal(st, ref["steps"])
+
+
+def test_continuation_under_iz_rules(bmc, ctx, orc, torch_mod, inputs):
+    spec = inputs.geometric_put5()
+    table = orc.price(spec, orc.IZ, 32, 400, 256, 4, nthreads=NT_CPU)["rules"]
+    for m in (1, 4, 8):
+        x = orc.points_cmc(spec, m, 40, 3)
+        c, se, st, ref = cont_parity(bmc, ctx, orc, torch_mod, spec, bmc.IZ, table, m, x, 2000, 6)
+        assert_close(c, ref["cont"], spec.K, what=f"iz rules m={m}")
+        assert np.array_equal(st, ref["steps"])
+
+
+def test_continuation_single_point_two_paths(bmc, ctx, orc, torch_mod, c1_rules):
+    spec, table = c1_rules
+    x = np.array([[97.5]])
+    c, se, st, ref = cont_parity(bmc, ctx, orc, torch_mod, spec, bmc.CMC, table, 3, x, 2, 1)
+    assert_close(c, ref["cont"], spec.K)
+    assert np.array_equal(st, ref["steps"])
+
+
+def test_continuation_deep_out_of_the_money_is_zero(bmc, ctx, orc, torch_mod, c1_rules):
+    spec, table = c1_rules
+    x = np.array([[400.0, 1000.0]])
+    c, se, st, ref = cont_parity(bmc, ctx, orc, torch_mod, spec, bmc.CMC, table, 8, x, 300, 1)
+    assert np.all(c == 0.0) and np.all(ref["cont"] == 0.0)
+
+
+# --- rule fits -----------------------------------------------------------------
+
+def test_cmc_fit_parity(bmc, ctx, orc, torch_mod, inputs, c1_rules):
+    cases = [(c1_rules[0], c1_rules[1], 5, 500), (inputs.geometric_put5(), None, 6, 700),
+             (inputs.max_call(3, 110.0), None, 4, 900)]
+    for spec, table, m, N in cases:
+        if table is None:
+            table = _small_rules(orc, spec)
+        x = orc.points_cmc(spec, m, N, 1)
+        cont = orc.continuation(spec, orc.CMC, table, m, x, 300, 1, nthreads=NT_CPU)["cont"]
+        w_ref = orc.fit_cmc(spec, x, cont, rounds=8)
+        rules = bmc.bmc_rules_create(ctx, spec, bmc.CMC)
+        bmc.bmc_fit_rule(ctx, spec, rules, m, dev(torch_mod, x), dev(torch_mod, cont), rounds=8)
+        w = bmc.bmc_rules_get(rules, m)
+        assert_same_rule(spec, w, w_ref, x, what=f"fit d={spec.d}")
+        assert_same_rule(spec, w, w_ref, orc.points_cmc(spec, m, 2000, 99), what=f"fit d={spec.d} fresh")
+
+
+def test_iz_fit_parity(bmc, ctx, orc, torch_mod, inputs):
+    spec = inputs.geometric_put5()
+    m = 7
+    x = orc.points_iz(spec, m, 200)
+    rng = np.random.default_rng(1)
+    sstar = 90.0 * np.exp(rng.normal(0, 0.05, 200))
+    sstar[::17] = -1.0                     # dropped points
+    b_ref = orc.fit_iz(spec, x, sstar)
+    xs = x.copy()
+    xs[0] = sstar
+    rules = bmc.bmc_rules_create(ctx, spec, bmc.IZ)
+    bmc.bmc_fit_rule(ctx, spec, rules, m, dev(torch_mod, xs))
+    assert np.allclose(bmc.bmc_rules_get(rules, m), b_ref, rtol=1e-9, atol=1e-11)
+
+
+def test_iz_fit_without_points_never_exercises(bmc, ctx, orc, torch_mod, inputs):
+    spec = inputs.geometric_put5()
+    x = orc.points_iz(spec, 3, 16)
+    sstar = -np.ones(16)
+    xs = x.copy()
+    xs[0] = sstar
+    rules = bmc.bmc_rules_create(ctx, spec, bmc.IZ)
+    bmc.bmc_fit_rule(ctx, spec, rules, 3, dev(torch_mod, xs))
+    assert np.array_equal(bmc.bmc_rules_get(rules, 3), orc.fit_iz(spec, x, sstar))
+
+
+# --- I&Z search -------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["put1", "geo5"])
+def test_iz_search_parity(bmc, ctx, orc, torch_mod, inputs, case):
+    spec = inputs.one_asset_put() if case == "put1" else inputs.geometric_put5()
+    J, n = (8, 3000) if case == "put1" else (40, 1500)
+    table = orc.empty_rules(spec, orc.IZ)
+    if case == "geo5":
+        table = orc.price(spec, orc.IZ, 16, 300, 256, 2, nthreads=NT_CPU)["rules"]
+    for m in (spec.n_dates - 1, 3):
+        x = orc.points_iz(spec, m, J)
+        rules = gpu_rules(bmc, ctx, spec, bmc.IZ, table)
+        s, it, steps = bmc.bmc_iz_search(ctx, spec, rules, m, dev(torch_mod, x), n, 2)
+        ref = orc.iz_search(spec, table, m, x, n, 2, nthreads=NT_CPU)
+        assert np.array_equal(host(it), ref["iters"])
+        assert_close(host(s), ref["s"], spec.K, what=f"s* m={m}")
+        assert steps == ref["steps"]
+
+
+# --- final pricing and the whole pricer ----------------------------------------------
+
+def test_final_price_parity(bmc, ctx, orc, torch_mod, c1_rules):
+    spec, table = c1_rules
+    rules = gpu_rules(bmc, ctx, spec, bmc.CMC, table)
+    r = bmc.bmc_final_price(ctx, spec, rules, 100000, 1)
+    ref = orc.final_price(spec, orc.CMC, table, 100000, 1, nthreads=NT_CPU)
+    assert_close(r["price"], ref["price"], spec.K)
+    assert_close(r["std_err"], ref["std_err"], spec.K, rel=1e-8)
+    assert r["final_path_steps"] == ref["final_steps"]
+
+
+@pytest.mark.parametrize("case", ["c1_cmc", "c1_iz", "geo5_cmc", "geo5_iz", "maxcall3_cmc"])
+def test_price_end_to_end_fp64(bmc, ctx, orc, torch_mod, inputs, case):
+    spec = {"c1": inputs.one_asset_put(), "geo5": inputs.geometric_put5(),
+            "maxcall3": inputs.max_call(3, 100.0)}[case.split("_")[0]]
+    method = bmc.CMC if case.endswith("cmc") else bmc.IZ
+    N, n, nf = {"c1_cmc": (500, 500, 100000), "c1_iz": (16, 500, 100000), "geo5_cmc": (512, 512, 100000),
+                "geo5_iz": (48, 400, 50000), "maxcall3_cmc": (400, 300, 50000)}[case]
+    res, rules = bmc.bmc_price(ctx, spec, method, bmc.FP64, N=N, n=n, n_final=nf, seed=1, want_rules=True)
+    ref = orc.price(spec, method, N, n, nf, 1, nthreads=NT_CPU)
+    assert_close(res["price"], ref["price"], spec.K, what="price")
+    table = bmc.rules_table(rules)
+    for m in range(1, spec.n_dates):
+        if method == bmc.CMC:
+            assert_same_rule(spec, table[m], ref["rules"][m], orc.points_cmc(spec, m, 1000, 5), what=f"m={m}")
+        else:
+            assert np.allclose(table[m], ref["rules"][m], rtol=1e-8, atol=1e-10)
+    assert res["inner_path_steps"] == ref["inner_path_steps"]
+    assert res["final_path_steps"] == ref["final_path_steps"]
+    if method == bmc.IZ:
+        assert res["iz_iterations"] == ref["iz_iterations"]
+        assert res["iz_unconverged"] == ref["iz_unconverged"]
+
+
+@pytest.mark.parametrize("prec", ["FP32", "FP32_KAHAN"])
+@pytest.mark.parametrize("case", ["c1_cmc", "geo5_cmc", "geo5_iz"])
+def test_price_fp32_within_tenth_of_std_err(bmc, ctx, orc, torch_mod, inputs, case, prec):
+    spec = inputs.one_asset_put() if case.startswith("c1") else inputs.geometric_put5()
+    method = bmc.CMC if case.endswith("cmc") else bmc.IZ
+    N, n = (500, 500) if method == bmc.CMC else (256, 1000)
+    res = bmc.bmc_price(ctx, spec, method, getattr(bmc, prec), N=N, n=n, n_final=200000, seed=1)
+    ref = orc.price(spec, method, N, n, 200000, 1, nthreads=NT_CPU)
+    assert abs(res["price"] - ref["price"]) <= 0.1 * ref["std_err"], (res["price"], ref["price"], ref["std_err"])
+
+
+def test_fp32_continuation_within_tenth_of_std_err(bmc, ctx, orc, torch_mod, c1_rules):
+    spec, table = c1_rules
+    x = orc.points_cmc(spec, 4, 500, 1)
+    for prec in (bmc.FP32, bmc.FP32_KAHAN):
+        c, se, st, ref = cont_parity(bmc, ctx, orc, torch_mod, spec, bmc.CMC, table, 4, x, 500, 1, prec=prec)
+        assert np.all(np.abs(c - ref["cont"]) <= 0.1 * ref["se"] + 1e-12)
+
+
+# --- full-size workload, sampled ----------------------------------------------------
+
+def test_full_size_geometric_put_sampled(bmc, ctx, orc, torch_mod, inputs):
+    """5-asset geometric put at N = n = 4096 (the benchmark's shape): every point
+    on the GPU, a sample of points re-evaluated by the oracle."""
+    spec = inputs.geometric_put5()
+    table = _small_rules(orc, spec, N=256, n=256)
+    m = 5
+    N, n = 4096, 4096
+    x = orc.points_cmc(spec, m, N, 1)
+    rules = gpu_rules(bmc, ctx, spec, bmc.CMC, table)
+    for prec in (bmc.FP64, bmc.FP32):
+        c, se, st = bmc.bmc_estimate_continuation(ctx, spec, rules, m, dev(torch_mod, x), n, 1, prec)
+        c, se, st = host(c), host(se), host(st)
+        ids = np.array([0, 1, 2, 1023, 2047, 2048, 3000, 4094, 4095])
+        ref = orc.continuation(spec, orc.CMC, table, m, x[:, ids], n, 1, nthreads=NT_CPU, ids=ids)
+        if prec == bmc.FP64:
+            assert_close(c[ids], ref["cont"], spec.K, what="full-size cont")
+            assert np.array_equal(st[ids], ref["steps"])
+        else:
+            assert np.all(np.abs(c[ids] - ref["cont"]) <= 0.1 * ref["se"] + 1e-12)
+        assert np.all(c >= 0) and np.all(np.isfinite(se))
+
+
+def test_full_size_final_pricing(bmc, ctx, orc, torch_mod, inputs):
+    spec = inputs.geometric_put5()
+    table = _small_rules(orc, spec, N=256, n=256)
+    rules = gpu_rules(bmc, ctx, spec, bmc.CMC, table)
+    r = bmc.bmc_final_price(ctx, spec, rules, 1000000, 1)
+    ref = orc.final_price(spec, orc.CMC, table, 1000000, 1, nthreads=NT_CPU)
+    assert_close(r["price"], ref["price"], spec.K)
+    assert r["final_path_steps"] == ref["final_steps"]
+
+
+# --- determinism, errors, serialisation --------------------------------------------
+
+def test_repeat_is_bit_identical(bmc, ctx, torch_mod, inputs):
+    spec = inputs.geometric_put5()
+    a = bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP32, N=256, n=256, n_final=20000, seed=4)
+    b = bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP32, N=256, n=256, n_final=20000, seed=4)
+    assert a["price"] == b["price"] and a["inner_path_steps"] == b["inner_path_steps"]
+
+
+def test_error_statuses(bmc, ctx, torch_mod, inputs):
+    spec = inputs.geometric_put5()
+    bad = inputs.basket(3, 100.0, 100.0, 0.05, 0.0, 0.2, 0.0, 1.0, 4, inputs.PUT_GEO)
+    bad.rho = np.array([[1.0, 0.9, 0.9], [0.9, 1.0, -0.9], [0.9, -0.9, 1.0]])
+    with pytest.raises(bmc.BmcError) as e:
+        bmc.bmc_price(ctx, bad, N=8, n=8, n_final=8)
+    assert e.value.status == bmc.ENOTSPD
+    late = inputs.geometric_put5()
+    late.dates = late.dates[::-1].copy()
+    with pytest.raises(bmc.BmcError) as e:
+        bmc.bmc_price(ctx, late, N=8, n=8, n_final=8)
+    assert e.value.status == bmc.EINVAL
+    with pytest.raises(bmc.BmcError) as e:
+        bmc.bmc_price(ctx, spec, N=8, n=8, n_final=8, seed=2 ** 32)
+    assert e.value.status == bmc.EINVAL
+    with pytest.raises(bmc.BmcError) as e:
+        bmc.bmc_rules_create(ctx, inputs.max_call(3, 100.0), bmc.IZ)
+    assert e.value.status == bmc.EUNSUPPORTED
+    other = bmc.bmc_rules_create(ctx, inputs.one_asset_put(), bmc.CMC)
+    with pytest.raises(bmc.BmcError) as e:
+        bmc.bmc_final_price(ctx, spec, other, 100, 1)
+    assert e.value.status == bmc.EINVAL
+    assert "does not match" in bmc.load().bmc_last_error().decode()
+
+
+def test_rules_export_import_roundtrip(bmc, ctx, torch_mod, inputs):
+    spec = inputs.geometric_put5()
+    res, rules = bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP64, N=256, n=128, n_final=10000, seed=2,
+                               want_rules=True)
+    blob = bmc.bmc_rules_export(rules)
+    back = bmc.bmc_rules_import(ctx, blob)
+    assert np.array_equal(bmc.rules_table(back), bmc.rules_table(rules))
+    a = bmc.bmc_final_price(ctx, spec, rules, 10000, 2)
+    b = bmc.bmc_final_price(ctx, spec, back, 10000, 2)
+    assert a["price"] == b["price"] == res["price"]

@@ -136,7 +136,10 @@ def main():
 
     res32, t32 = timed(bmc.FP32, args.steps, args.warmup)
     fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(2, args.steps // 2)
-    res64, t64 = timed(bmc.FP64, fp64_steps, 1)
+    if fp64_steps > 0:
+        res64, t64 = timed(bmc.FP64, fp64_steps, 1)
+    else:   # profiling runs of the FP32 form only
+        res64, t64, fp64_steps = res32, t32, args.steps
 
     inner32 = sum(r["inner_path_steps"] for r in res32)
     inner64 = sum(r["inner_path_steps"] for r in res64)

@@ -61,8 +61,24 @@ def build(jobs: int | None = None, verbose: bool = False) -> Path:
     return LIB
 
 
+def build_calib() -> list[Path]:
+    """Builds the VALU-rate and copy probes (roofline calibration) into calib/bin/."""
+    out = PKG / "calib" / "bin"
+    out.mkdir(parents=True, exist_ok=True)
+    exes = []
+    for src in sorted((PKG / "calib").glob("*.hip")):
+        exe = out / src.stem
+        subprocess.run([HIPCC, "--offload-arch=" + ARCH, "-O3", "-Xclang", "-target-feature", "-Xclang",
+                        "-packed-fp32-ops", str(src), "-o", str(exe)], check=True, capture_output=True)
+        exes.append(exe)
+    return exes
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--calib", action="store_true", help="also build the calibration probes")
     args = ap.parse_args()
     build(args.jobs, verbose=True)
+    if args.calib:
+        build_calib()

@@ -1,0 +1,438 @@
+// Device arithmetic of the FP64 rule fits, shared by the one-launch
+// (cooperative) and multi-launch forms so that both give identical rules.
+// Reductions are deterministic: a tile is reduced sequentially by one thread
+// per output quantity; tiles are merged in tile order.
+#pragma once
+
+#include "internal.hpp"
+
+namespace bmc {
+
+// Points per tile (= threads per block) of the fits.
+__host__ __device__ __forceinline__ int fit_tile(int p)
+{
+    if (p <= 15) return 256;
+    if (p <= 48) return 128;
+    if (p <= 96) return 64;
+    return 32;
+}
+
+__device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
+
+// q-th entry of a packed lower triangle -> (row i, column l <= i).
+__device__ __forceinline__ void pair_of(int q, int& i, int& l)
+{
+    i = 0;
+    while (q >= i + 1) {
+        q -= i + 1;
+        ++i;
+    }
+    l = q;
+}
+
+// Solves (A + lam I) x = b for the packed lower triangle A (overwritten by
+// its Cholesky factor; b is overwritten too).  Whole block; false if a pivot
+// is not positive.  Right-looking, column-parallel: every entry still
+// subtracts its terms in increasing column order, as the sequential
+// left-looking factorisation and substitutions do.
+__device__ inline bool block_spd_solve(int p, double* A, double lam, double* b, double* x, int* flag)
+{
+    const int tid = threadIdx.x, T = blockDim.x;
+    if (tid == 0) *flag = 0;
+    for (int i = tid; i < p; i += T) A[tri(i, i)] += lam;
+    __syncthreads();
+    for (int c = 0; c < p; ++c) {
+        if (tid == 0) {
+            double v = A[tri(c, c)];
+            if (!(v > 0.0)) {
+                *flag = 1;
+                v = 1.0;
+            }
+            A[tri(c, c)] = sqrt(v);
+        }
+        __syncthreads();
+        const double lcc = A[tri(c, c)];
+        for (int i = c + 1 + tid; i < p; i += T) A[tri(i, c)] /= lcc;
+        __syncthreads();
+        // trailing update A_il -= L_ic L_lc for c < l <= i
+        const int m = p - c - 1;
+        for (int e = tid; e < m * (m + 1) / 2; e += T) {
+            int ii, ll;
+            pair_of(e, ii, ll);
+            const int i = c + 1 + ii, l = c + 1 + ll;
+            A[tri(i, l)] -= A[tri(i, c)] * A[tri(l, c)];
+        }
+        __syncthreads();
+    }
+    // forward substitution L y = b (y in b), then L^T x = y
+    for (int c = 0; c < p; ++c) {
+        if (tid == 0) b[c] /= A[tri(c, c)];
+        __syncthreads();
+        for (int i = c + 1 + tid; i < p; i += T) b[i] -= A[tri(i, c)] * b[c];
+        __syncthreads();
+    }
+    for (int c = p - 1; c >= 0; --c) {
+        if (tid == 0) x[c] = b[c] / A[tri(c, c)];
+        __syncthreads();
+        for (int i = tid; i < c; i += T) b[i] -= A[tri(c, i)] * x[c];
+        __syncthreads();
+    }
+    return *flag == 0;
+}
+
+// Value of v in lane src (uniform src), through the scalar unit.
+__device__ __forceinline__ double bcast_lane(double v, int src)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// The same factorisation and substitutions by one wavefront (the calling
+// threads must be lanes 0..63 of one wave, all active): lane i keeps row i
+// of the factor in registers and the columns travel by lane broadcasts,
+// with no block barrier.  Same per-entry subtraction order as above.
+// Returns false (on every lane) if a pivot is not positive.
+template <int P>
+__device__ bool wave_spd_solve(int p, const double* A, double lam, const double* b, double* x)
+{
+    const int lane = threadIdx.x & 63;
+    double row[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        row[k] = (lane < p && k <= lane) ? A[tri(lane, k)] : 0.0;
+        if (k == lane) row[k] += lam;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        if (c < p) {
+            double dc = bcast_lane(row[c], c);
+            if (!(dc > 0.0)) {
+                ok = false;
+                dc = 1.0;
+            }
+            const double lcc = sqrt(dc);
+            if (lane == c) row[c] = lcc;
+            else if (lane > c) row[c] = row[c] / lcc;
+#pragma unroll
+            for (int l = c + 1; l < P; ++l) {
+                if (l < p) {
+                    const double llc = bcast_lane(row[c], l);
+                    if (lane >= l) row[l] -= row[c] * llc;
+                }
+            }
+        }
+    }
+    double y = lane < p ? b[lane] : 0.0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        if (c < p) {
+            const double yc = bcast_lane(y, c) / bcast_lane(row[c], c);
+            if (lane == c) y = yc;
+            else if (lane > c) y -= row[c] * yc;
+        }
+    }
+    double xv = 0.0;
+#pragma unroll
+    for (int c = P - 1; c >= 0; --c) {
+        if (c < p) {
+            const double xc = bcast_lane(y, c) / bcast_lane(row[c], c);
+            if (lane == c) xv = xc;
+            double lci = 0.0;
+#pragma unroll
+            for (int k = 0; k < c; ++k) {
+                const double t = bcast_lane(row[k], c);
+                if (lane == k) lci = t;
+            }
+            if (lane < c) y -= lci * xc;
+        }
+    }
+    if (lane < p) x[lane] = xv;
+    return ok;
+}
+
+// Dispatch for a whole block: one wavefront solves small systems in
+// registers, larger ones use the block form.  A and b are scratch.
+__device__ inline bool spd_solve(int p, double* A, double lam, double* b, double* x, int* flag)
+{
+    if (p <= 32) {
+        if (threadIdx.x < 64) {
+            const bool ok = p <= 16 ? wave_spd_solve<16>(p, A, lam, b, x) : wave_spd_solve<32>(p, A, lam, b, x);
+            if (threadIdx.x == 0) *flag = ok ? 0 : 1;
+        }
+        __syncthreads();
+        return *flag == 0;
+    }
+    return block_spd_solve(p, A, lam, b, x, flag);
+}
+
+// Payoff of point j from its log-prices (FP64, runtime d).
+__device__ inline double point_payoff(const SpecT<double>& S, const double* __restrict__ x, int64_t N, int64_t j)
+{
+    const int d = S.d;
+    double v;
+    if (S.payoff == CALL_MAX) {
+        double mx = log(x[j]);
+        for (int i = 1; i < d; ++i) mx = fmax(mx, log(x[i * N + j]));
+        v = exp(mx) - S.K;
+    } else if (S.payoff == PUT_GEO) {
+        double sl = 0.0;
+        for (int i = 0; i < d; ++i) sl += log(x[i * N + j]);
+        v = S.K - exp(sl * S.inv_d);
+    } else {
+        double sm = 0.0;
+        for (int i = 0; i < d; ++i) sm += exp(log(x[i * N + j]));
+        v = S.K - sm * S.inv_d;
+    }
+    return v > 0.0 ? v : 0.0;
+}
+
+// CMC training data of point j: raw features phi = [1, u, u^2, g, g^2]
+// (column f at phi[f*N + j]), label e = [Phi - C > 0], in-the-money mask.
+__device__ inline void fit_prep_point(const SpecT<double>& S, const double* __restrict__ x,
+                                      const double* __restrict__ cont, int64_t N, int64_t j, double* phi,
+                                      double* lab, double* msk)
+{
+    if (j >= N) return;
+    const int d = S.d;
+    const double pay = point_payoff(S, x, N, j);
+    msk[j] = pay > 0.0 ? 1.0 : 0.0;
+    lab[j] = (pay - cont[j] > 0.0) ? 1.0 : 0.0;
+    phi[j] = 1.0;
+    for (int i = 0; i < d; ++i) {
+        const double u = log(x[i * N + j]) - S.lnK;
+        phi[(1 + i) * N + j] = u;
+        phi[(1 + d + i) * N + j] = u * u;
+    }
+    const double g = pay / S.K;
+    phi[(1 + 2 * d) * N + j] = g;
+    phi[(2 + 2 * d) * N + j] = g * g;
+}
+
+// out[f] = sum over the tile of msk * phi_f (f < p), out[p] = sum of msk.
+__device__ inline void fit_tile_feature_sums(const double* phi, const double* msk, int64_t N, int p,
+                                             int64_t j0, int T, double* out)
+{
+    const int64_t j1 = min(N, j0 + (int64_t)T);
+    for (int f = threadIdx.x; f <= p; f += blockDim.x) {
+        double acc = 0.0;
+        for (int64_t jj = j0; jj < j1; ++jj) acc += (f < p) ? msk[jj] * phi[f * N + jj] : msk[jj];
+        out[f] = acc;
+    }
+}
+
+// out[f] = sum over the tile of msk * (phi_f - mu_f)^2.
+__device__ inline void fit_tile_var_sums(const double* phi, const double* msk, int64_t N, int p, int64_t j0,
+                                         int T, const double* mu, double* out)
+{
+    const int64_t j1 = min(N, j0 + (int64_t)T);
+    for (int f = threadIdx.x; f < p; f += blockDim.x) {
+        double acc = 0.0;
+        for (int64_t jj = j0; jj < j1; ++jj) {
+            const double dv = phi[f * N + jj] - mu[f];
+            acc += msk[jj] * dv * dv;
+        }
+        out[f] = acc;
+    }
+}
+
+// Standardisation of column f from the merged sums; the constant column and
+// a (numerically) constant feature keep scale 1.
+__device__ __forceinline__ void fit_mu_sd(int f, double cnt, double sf, double sv, double* mu, double* sd)
+{
+    double m = 0.0, s = 1.0;
+    if (f > 0 && cnt > 0.0) {
+        m = sf / cnt;
+        s = sqrt(sv / cnt);
+        if (!(s > 1e-12 * (1.0 + fabs(m)))) s = 1.0;
+    }
+    *mu = m;
+    *sd = s;
+}
+
+// One boosting round at point j (tile row tl = threadIdx.x): standardised
+// features into psi, F += beta_prev . psi / 2 (if beta_prev), pi = 1/(1 +
+// exp(-2F)), weight w = max(pi(1-pi), 1e-10) (masked) and working response
+// z = clip((e - pi)/w, -4, 4) into wz.
+__device__ inline void fit_round_point(const double* phi, const double* lab, const double* msk, int64_t N, int p,
+                                       const double* mu, const double* sd, const double* beta_prev, int64_t j,
+                                       double* F, double* pi, double* psi, double* wz)
+{
+    const int tl = threadIdx.x;
+    if (j < N) {
+        for (int f = 0; f < p; ++f) psi[tl * p + f] = f == 0 ? 1.0 : (phi[f * N + j] - mu[f]) / sd[f];
+        double Fj, pj;
+        if (!beta_prev) {
+            Fj = 0.0;
+            pj = 0.5;
+        } else {
+            double dF = 0.0;
+            for (int f = 0; f < p; ++f) dF += beta_prev[f] * psi[tl * p + f];
+            Fj = F[j] + 0.5 * dF;
+            pj = 1.0 / (1.0 + exp(-2.0 * Fj));
+        }
+        F[j] = Fj;
+        pi[j] = pj;
+        double w = pj * (1.0 - pj);
+        if (w < 1e-10) w = 1e-10;
+        double z = (lab[j] - pj) / w;
+        if (z > 4.0) z = 4.0;
+        if (z < -4.0) z = -4.0;
+        wz[2 * tl] = w * msk[j];
+        wz[2 * tl + 1] = z;
+    } else {
+        for (int f = 0; f < p; ++f) psi[tl * p + f] = 0.0;
+        wz[2 * tl] = 0.0;
+        wz[2 * tl + 1] = 0.0;
+    }
+}
+
+// Weighted normal equations of the tile: out[q] = sum w psi_a psi_b for the
+// packed pair q = (a, b), then out[npairs + a] = sum w z psi_a.
+__device__ inline void fit_tile_normal_eqs(const double* psi, const double* wz, int p, int nt, double* out)
+{
+    const int npairs = p * (p + 1) / 2;
+    for (int q = threadIdx.x; q < npairs + p; q += blockDim.x) {
+        double acc = 0.0;
+        if (q < npairs) {
+            int a, b;
+            pair_of(q, a, b);
+#pragma unroll 8
+            for (int t = 0; t < nt; ++t) acc += wz[2 * t] * psi[t * p + a] * psi[t * p + b];
+        } else {
+            const int a = q - npairs;
+#pragma unroll 8
+            for (int t = 0; t < nt; ++t) acc += wz[2 * t] * wz[2 * t + 1] * psi[t * p + a];
+        }
+        out[q] = acc;
+    }
+}
+
+// gamma = sum_r beta_r / 2 folded through the standardisation onto the raw
+// features: w_f = gamma_f / sd_f, w_0 = gamma_0 - sum_f gamma_f mu_f / sd_f.
+__device__ inline void fit_fold(int p, int rounds, const double* musd, const double* beta, double* row64,
+                                float* row32)
+{
+    if (threadIdx.x != 0) return;
+    const bool any = musd[2 * p] > 0.0;
+    double w0 = 0.0;
+    for (int f = 0; f < p; ++f) {
+        double g = 0.0;
+        if (any)
+            for (int r = 0; r < rounds; ++r) g += 0.5 * beta[r * p + f];
+        if (f == 0) {
+            w0 += g;
+        } else {
+            const double wf = g / musd[p + f];
+            w0 -= g * musd[f] / musd[p + f];
+            row64[f] = wf;
+            row32[f] = (float)wf;
+        }
+    }
+    row64[0] = w0;
+    row32[0] = (float)w0;
+}
+
+// Tile reduction of nq quantities over the nt tile points, value(q, t), in
+// two fixed levels: SUB runs of consecutive points per quantity, each summed
+// in order by one thread, then the runs summed in order.  red: LDS [nq*SUB].
+constexpr int TILE_SUB = 16;
+
+template <class F>
+__device__ inline void tile_sum2(int nq, int nt, F value, double* red, double* out)
+{
+    const int T = blockDim.x;
+    const int run = (nt + TILE_SUB - 1) / TILE_SUB;
+    for (int e = threadIdx.x; e < nq * TILE_SUB; e += T) {
+        const int q = e / TILE_SUB, s = e % TILE_SUB;
+        const int t0 = s * run, t1 = min(nt, t0 + run);
+        double acc = 0.0;
+        for (int t = t0; t < t1; ++t) acc += value(q, t);
+        red[e] = acc;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nq; q += T) {
+        double acc = 0.0;
+        for (int s = 0; s < TILE_SUB; ++s) acc += red[q * TILE_SUB + s];
+        out[q] = acc;
+    }
+    __syncthreads();
+}
+
+// Boosting round at point j for the matrix-core path (p <= 15): as
+// fit_round_point, but the tile row has stride 16 and holds
+// [psi_0..psi_{p-1}, z, 0...]; w goes to wz[2 tl].
+__device__ inline void fit_round_point16(const double* phi, const double* lab, const double* msk, int64_t N,
+                                         int p, const double* mu, const double* sd, const double* beta_prev,
+                                         int64_t j, double* F, double* pi, double* psi16, double* wz)
+{
+    const int tl = threadIdx.x;
+    double* row = psi16 + 16 * tl;
+    if (j < N) {
+        for (int f = 0; f < p; ++f) row[f] = f == 0 ? 1.0 : (phi[f * N + j] - mu[f]) / sd[f];
+        double Fj, pj;
+        if (!beta_prev) {
+            Fj = 0.0;
+            pj = 0.5;
+        } else {
+            double dF = 0.0;
+            for (int f = 0; f < p; ++f) dF += beta_prev[f] * row[f];
+            Fj = F[j] + 0.5 * dF;
+            pj = 1.0 / (1.0 + exp(-2.0 * Fj));
+        }
+        F[j] = Fj;
+        pi[j] = pj;
+        double w = pj * (1.0 - pj);
+        if (w < 1e-10) w = 1e-10;
+        double z = (lab[j] - pj) / w;
+        if (z > 4.0) z = 4.0;
+        if (z < -4.0) z = -4.0;
+        row[p] = z;
+        for (int f = p + 1; f < 16; ++f) row[f] = 0.0;
+        wz[2 * tl] = w * msk[j];
+    } else {
+        for (int f = 0; f < 16; ++f) row[f] = 0.0;
+        wz[2 * tl] = 0.0;
+    }
+}
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Weighted Gram matrix of the tile on the matrix cores: G = sum_t w_t
+// r_t r_t^T with r_t = [psi, z, 0..] (16 wide), one 16x16x4 FP64 MFMA per
+// four points; wave k covers points 64k..64k+63 and the waves' partial G are
+// merged in wave order.  Writes the packed normal equations (A, then the
+// right-hand side G[a][p]) like fit_tile_normal_eqs.  aux: LDS [waves*256].
+__device__ inline void fit_tile_normal_eqs_mfma(const double* psi16, const double* wz, int p, int nt, double* aux,
+                                                double* out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = wave * 64; k0 < wave * 64 + 64; k0 += 4) {
+        const int t = k0 + (lane >> 4);   // point of this lane's k
+        const int c = lane & 15;          // row of A / column of B
+        const double r = t < nt ? psi16[16 * t + c] : 0.0;
+        const double w = t < nt ? wz[2 * t] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(w * r, r, acc, 0, 0, 0);
+    }
+    // D[i][j] sits in lane j + 16 (i % 4), element i / 4
+    for (int e = 0; e < 4; ++e) aux[wave * 256 + (4 * e + (lane >> 4)) * 16 + (lane & 15)] = acc[e];
+    __syncthreads();
+    const int npairs = p * (p + 1) / 2;
+    for (int q = threadIdx.x; q < npairs + p; q += blockDim.x) {
+        int i, l;
+        if (q < npairs) pair_of(q, i, l);
+        else { i = q - npairs; l = p; }
+        double s = 0.0;
+        for (int k = 0; k < waves; ++k) s += aux[k * 256 + i * 16 + l];
+        out[q] = s;
+    }
+}
+
+bool fit_coop_supported(int p);
+hipError_t launch_fit_cmc_coop(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
+                               int rounds, const FitScratch& fs, double* row64, float* row32, hipStream_t st);
+
+}  // namespace bmc

@@ -1,0 +1,236 @@
+// One-launch CMC boosting fit (cooperative grid): the tiles of training
+// points are spread over the blocks; each boosting round ends with one grid
+// barrier, after which every block merges the tile partials (in tile order)
+// and solves the small system itself, so the coefficients never leave the
+// block between rounds.  Used for p <= 40 (the LDS budget); wider rules use
+// the multi-launch form in fit.hip.  For p <= 15 the tile's weighted normal
+// equations run on the FP64 matrix cores.
+#include <hip/hip_cooperative_groups.h>
+
+#include "fit_common.hpp"
+
+namespace cg = cooperative_groups;
+
+namespace bmc {
+
+// Optional phase timestamps of block 0 (compiled out unless BMC_FIT_TRACE).
+#ifdef BMC_FIT_TRACE
+__device__ unsigned long long g_fit_trace[256];
+#define FIT_MARK(i) do { if (blockIdx.x == 0 && threadIdx.x == 0) g_fit_trace[i] = wall_clock64(); } while (0)
+#else
+#define FIT_MARK(i) do { } while (0)
+#endif
+
+struct FitCoopArgs {
+    const DevSpec* s;
+    const double* x;
+    const double* cont;
+    int64_t N;
+    int p, rounds, ntiles;
+    FitScratch fs;
+    double* musd;
+    double* row64;
+    float* row32;
+};
+
+__host__ __device__ inline int coop_psi_width(int p) { return p <= 15 ? 16 : p; }
+__host__ __device__ inline int coop_aux(int p, int T)
+{
+    const int a = TILE_SUB * (p + 1), b = (T / 64) * 256;
+    return a > b ? a : b;
+}
+
+// Sum over tiles, in tile order, of the Q columns of a [ntiles][Q] array,
+// staged through LDS in chunks with coalesced loads by the whole block;
+// out[Q] in LDS.  Same order as a sequential merge from zero.
+__device__ void merge_tiles(const double* __restrict__ part, int ntiles, int Q, double* stage, int cap,
+                            double* out)
+{
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int chunk = cap / Q;   // >= 1 by construction of the LDS layout
+    for (int q = tid; q < Q; q += T) out[q] = 0.0;
+    for (int t0 = 0; t0 < ntiles; t0 += chunk) {
+        const int nt = min(chunk, ntiles - t0);
+        __syncthreads();
+        for (int e = tid; e < nt * Q; e += T) stage[e] = part[(size_t)t0 * Q + e];
+        __syncthreads();
+        for (int q = tid; q < Q; q += T) {
+            double acc = out[q];
+            for (int t = 0; t < nt; ++t) acc += stage[t * Q + q];
+            out[q] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// Raw features and mask of tile points j0.. into LDS: stage[f*T + t], m[t].
+__device__ void stage_tile(const double* __restrict__ phi, const double* __restrict__ msk, int64_t N, int p,
+                           int64_t j0, double* stage, double* m)
+{
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int64_t j = j0 + tid;
+    for (int f = 0; f < p; ++f) stage[f * T + tid] = j < N ? phi[f * N + j] : 0.0;
+    m[tid] = j < N ? msk[j] : 0.0;
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_fit_cmc_coop(FitCoopArgs a)
+{
+    cg::grid_group grid = cg::this_grid();
+    extern __shared__ double sh[];
+    __shared__ int flag;
+    __shared__ double lam, cnt_s;
+    const int p = a.p, T = blockDim.x, npairs = p * (p + 1) / 2, Q = npairs + p;
+    const int tid = threadIdx.x;
+    const bool mfma = p <= 15;
+    double* psi = sh;                                   // [T][psi width]; also the staging area
+    double* wz = psi + (size_t)T * coop_psi_width(p);  // [T][2]
+    double* aux = wz + 2 * T;                           // two-level sums / per-wave Gram matrices
+    double* A = aux + coop_aux(p, T);                   // [npairs] packed lower triangle, then bv
+    double* bv = A + npairs;                            // [p]
+    double* beta = bv + p;                              // [p]
+    double* mu = beta + p;                              // [p]
+    double* sd = mu + p;                                // [p]
+    const int cap = T * coop_psi_width(p);
+    const SpecT<double>& S = a.s->f64;
+    const FitScratch& fs = a.fs;
+    const int64_t N = a.N;
+
+    FIT_MARK(0);
+    // features, labels, in-the-money mask; tile sums of features and count
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const int64_t j0 = (int64_t)t * T;
+        fit_prep_point(S, a.x, a.cont, N, j0 + tid, fs.phi, fs.lab, fs.msk);
+        __syncthreads();
+        stage_tile(fs.phi, fs.msk, N, p, j0, psi, wz);
+        const int nt = (int)min((int64_t)T, N - j0);
+        tile_sum2(p + 1, nt, [&](int f, int q) { return f < p ? wz[q] * psi[f * T + q] : wz[q]; }, aux,
+                  fs.part1 + (size_t)t * (p + 1));
+    }
+    FIT_MARK(1);
+    grid.sync();
+    FIT_MARK(2);
+    // means (every block), tile sums of squared deviations
+    merge_tiles(fs.part1, a.ntiles, p + 1, psi, cap, A);
+    if (tid == 0) cnt_s = A[p];
+    __syncthreads();
+    const double cnt = cnt_s;
+    for (int f = tid; f < p; f += T) mu[f] = cnt > 0.0 ? A[f] / cnt : 0.0;
+    __syncthreads();
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const int64_t j0 = (int64_t)t * T;
+        stage_tile(fs.phi, fs.msk, N, p, j0, psi, wz);
+        const int nt = (int)min((int64_t)T, N - j0);
+        tile_sum2(p, nt,
+                  [&](int f, int q) {
+                      const double dv = psi[f * T + q] - mu[f];
+                      return wz[q] * dv * dv;
+                  },
+                  aux, fs.part2 + (size_t)t * p);
+    }
+    FIT_MARK(3);
+    grid.sync();
+    FIT_MARK(4);
+    merge_tiles(fs.part1, a.ntiles, p + 1, psi, cap, A);          // feature sums
+    merge_tiles(fs.part2, a.ntiles, p, psi, cap, A + (p + 1));    // squared deviations
+    for (int f = tid; f < p; f += T) {
+        fit_mu_sd(f, cnt, A[f], A[p + 1 + f], &mu[f], &sd[f]);
+        if (blockIdx.x == 0) {
+            a.musd[f] = mu[f];
+            a.musd[p + f] = sd[f];
+        }
+    }
+    if (blockIdx.x == 0 && tid == 0) a.musd[2 * p] = cnt;
+    __syncthreads();
+    if (!(cnt > 0.0)) {   // no in-the-money point: never exercise (same in every block)
+        if (blockIdx.x == 0)
+            for (int f = tid; f < p; f += T) { a.row64[f] = 0.0; a.row32[f] = 0.0f; }
+        return;
+    }
+    // Round r's tile partials go to buffer r % 2: a block writes round r+2's
+    // partials only after the barrier of round r+1, which every block passes
+    // after reading round r's, so one barrier per round suffices.
+    const size_t part_stride = (size_t)a.ntiles * Q;
+    for (int r = 0; r < a.rounds; ++r) {
+        double* partA = fs.partA + (size_t)(r & 1) * part_stride;
+        FIT_MARK(8 + 8 * r);
+        for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+            const int64_t j0 = (int64_t)t * T;
+            const int nt = (int)min((int64_t)T, N - j0);
+            if (mfma) {
+                fit_round_point16(fs.phi, fs.lab, fs.msk, N, p, mu, sd, r > 0 ? beta : nullptr, j0 + tid, fs.F,
+                                  fs.pi, psi, wz);
+                __syncthreads();
+                FIT_MARK(9 + 8 * r);
+                fit_tile_normal_eqs_mfma(psi, wz, p, nt, aux, partA + (size_t)t * Q);
+            } else {
+                fit_round_point(fs.phi, fs.lab, fs.msk, N, p, mu, sd, r > 0 ? beta : nullptr, j0 + tid, fs.F,
+                                fs.pi, psi, wz);
+                __syncthreads();
+                FIT_MARK(9 + 8 * r);
+                fit_tile_normal_eqs(psi, wz, p, nt, partA + (size_t)t * Q);
+            }
+            __syncthreads();
+        }
+        FIT_MARK(10 + 8 * r);
+        grid.sync();
+        FIT_MARK(11 + 8 * r);
+        merge_tiles(partA, a.ntiles, Q, psi, cap, A);   // A then bv
+        FIT_MARK(12 + 8 * r);
+        if (tid == 0) {
+            double tr = 0.0;
+            for (int i = 0; i < p; ++i) tr += A[tri(i, i)];
+            lam = 1e-8 * tr / p;
+        }
+        __syncthreads();
+        if (!spd_solve(p, A, lam, bv, beta, &flag))
+            for (int f = tid; f < p; f += T) beta[f] = 0.0;
+        __syncthreads();
+        FIT_MARK(13 + 8 * r);
+        if (blockIdx.x == 0)
+            for (int f = tid; f < p; f += T) fs.beta[(size_t)r * p + f] = beta[f];
+    }
+    FIT_MARK(200);
+    if (blockIdx.x == 0) {
+        __syncthreads();
+        fit_fold(p, a.rounds, a.musd, fs.beta, a.row64, a.row32);
+    }
+}
+
+bool fit_coop_supported(int p) { return p <= 40; }
+
+hipError_t launch_fit_cmc_coop(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
+                               int rounds, const FitScratch& fs, double* row64, float* row32,
+                               hipStream_t st)
+{
+    FitCoopArgs a;
+    a.s = s;
+    a.x = x;
+    a.cont = cont;
+    a.N = N;
+    a.p = rule_width(CMC, d);
+    a.rounds = rounds;
+    const int T = fit_tile(a.p);
+    a.ntiles = (int)((N + T - 1) / T);
+    a.fs = fs;
+    a.musd = fs.beta + (size_t)rounds * a.p;
+    a.row64 = row64;
+    a.row32 = row32;
+    const int npairs = a.p * (a.p + 1) / 2;
+    const size_t lds = sizeof(double) * ((size_t)T * coop_psi_width(a.p) + 2 * T + coop_aux(a.p, T) + npairs +
+                                         4 * a.p);
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev))) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_fit_cmc_coop),
+                                                          T, lds)))
+        return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    const int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)per_cu * cus);
+    void* args[] = {&a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_fit_cmc_coop), dim3(grid), dim3(T), args,
+                                      (unsigned)lds, st);
+}
+
+}  // namespace bmc

@@ -111,9 +111,26 @@ hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, 
     return launch_cont_d<64, false>(prec, a, grid, block, lds, st);
 }
 
-// Per point: merge the chunk partials in chunk order into the continuation
-// estimate C = sum/n and its standard error sqrt(var/n), var = (sumsq -
-// sum^2/n)/(n-1).
+// Continuation estimate C = sum/n and its standard error sqrt(var/n), with
+// var = (sumsq - sum^2/n)/(n-1), from a point's merged sums.
+__device__ __forceinline__ void finalize_point(int64_t j, double s, double q, double c, uint32_t n, double* cont,
+                                               double* se, int64_t* steps, double* sums,
+                                               unsigned long long* steps_total)
+{
+    const double nn = (double)n;
+    double var = (q - s * s / nn) / (nn - 1.0);
+    if (var < 0.0) var = 0.0;
+    if (cont) cont[j] = s / nn;
+    if (se) se[j] = sqrt(var / nn);
+    if (steps) steps[j] = (int64_t)c;
+    if (sums) {
+        sums[2 * j] = s;
+        sums[2 * j + 1] = q;
+    }
+    if (steps_total) atomicAdd(steps_total, (unsigned long long)c);
+}
+
+// Per point: merge the chunk partials in chunk order.
 __global__ void k_finalize(const double* __restrict__ part, uint32_t nchunk, uint32_t n, int64_t N,
                            const int32_t* __restrict__ ids, const int32_t* __restrict__ n_ids,
                            double* cont, double* se, int64_t* steps, double* sums,
@@ -134,14 +151,40 @@ __global__ void k_finalize(const double* __restrict__ part, uint32_t nchunk, uin
         q += o[1];
         c += o[2];
     }
-    const double nn = (double)n;
-    double var = (q - s * s / nn) / (nn - 1.0);
-    if (var < 0.0) var = 0.0;
-    if (cont) cont[j] = s / nn;
-    if (se) se[j] = sqrt(var / nn);
-    if (steps) steps[j] = (int64_t)c;
-    if (sums) { sums[2 * j] = s; sums[2 * j + 1] = q; }
-    if (steps_total) atomicAdd(steps_total, (unsigned long long)c);
+    finalize_point(j, s, q, c, n, cont, se, steps, sums, steps_total);
+}
+
+// Same merge for points with many chunks (final pricing): one block per
+// point, each thread merges a contiguous run of chunks in order, then a
+// fixed-shape tree over the threads.
+__global__ void __launch_bounds__(256) k_finalize_wide(const double* __restrict__ part, uint32_t nchunk,
+                                                       uint32_t n, double* cont, double* se, int64_t* steps,
+                                                       double* sums, unsigned long long* steps_total)
+{
+    __shared__ double red[3][256];
+    const int64_t j = blockIdx.x;
+    const uint32_t T = blockDim.x, t = threadIdx.x;
+    const uint32_t lo = (uint32_t)(((uint64_t)nchunk * t) / T), hi = (uint32_t)(((uint64_t)nchunk * (t + 1)) / T);
+    double s = 0.0, q = 0.0, c = 0.0;
+    for (uint32_t ch = lo; ch < hi; ++ch) {
+        const double* o = part + ((size_t)j * nchunk + ch) * 3;
+        s += o[0];
+        q += o[1];
+        c += o[2];
+    }
+    red[0][t] = s;
+    red[1][t] = q;
+    red[2][t] = c;
+    __syncthreads();
+    for (uint32_t w = T / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] += red[0][t + w];
+            red[1][t] += red[1][t + w];
+            red[2][t] += red[2][t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) finalize_point(j, red[0][0], red[1][0], red[2][0], n, cont, se, steps, sums, steps_total);
 }
 
 hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int64_t N,
@@ -149,6 +192,11 @@ hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int6
                            int64_t* steps, double* sums, unsigned long long* steps_total,
                            hipStream_t st)
 {
+    if (!ids && nchunk >= 64 && N <= 4096) {
+        hipLaunchKernelGGL(k_finalize_wide, dim3((unsigned)N), dim3(256), 0, st, part, nchunk, n, cont, se, steps,
+                           sums, steps_total);
+        return hipGetLastError();
+    }
     const int grid = (int)((N + 255) / 256);
     hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, st, part, nchunk, n, N, ids, n_ids,
                        cont, se, steps, sums, steps_total);
@@ -377,453 +425,6 @@ hipError_t launch_rules_narrow(const double* w64, float* w32, int64_t count, hip
 {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_narrow, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, w64, w32, count);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// FP64 rule fits.  Reductions are deterministic: a block reduces its tile
-// sequentially (one thread per output quantity), and tiles are merged in tile
-// order.  The small SPD systems are factorised by a block-parallel Cholesky.
-
-__device__ __forceinline__ void pair_of(int q, int& i, int& l)
-{
-    i = 0;
-    while (q >= i + 1) { q -= i + 1; ++i; }
-    l = q;
-}
-
-__device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
-
-// Solves (A + lam I) x = b for packed lower-triangular A (overwritten by L).
-// Returns false if a pivot is not positive.  Called by a whole block.
-__device__ bool block_spd_solve(int p, double* A, double lam, const double* b, double* x,
-                                int* flag)
-{
-    const int tid = threadIdx.x;
-    if (tid == 0) *flag = 0;
-    __syncthreads();
-    for (int c = 0; c < p; ++c) {
-        if (tid == 0) {
-            double acc = A[tri(c, c)] + lam;
-            for (int l = 0; l < c; ++l) acc -= A[tri(c, l)] * A[tri(c, l)];
-            if (!(acc > 0.0)) { *flag = 1; acc = 1.0; }
-            A[tri(c, c)] = sqrt(acc);
-        }
-        __syncthreads();
-        for (int i = c + 1 + tid; i < p; i += blockDim.x) {
-            double acc = A[tri(i, c)];
-            for (int l = 0; l < c; ++l) acc -= A[tri(i, l)] * A[tri(c, l)];
-            A[tri(i, c)] = acc / A[tri(c, c)];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        for (int i = 0; i < p; ++i) {
-            double acc = b[i];
-            for (int l = 0; l < i; ++l) acc -= A[tri(i, l)] * x[l];
-            x[i] = acc / A[tri(i, i)];
-        }
-        for (int i = p - 1; i >= 0; --i) {
-            double acc = x[i];
-            for (int l = i + 1; l < p; ++l) acc -= A[tri(l, i)] * x[l];
-            x[i] = acc / A[tri(i, i)];
-        }
-    }
-    __syncthreads();
-    return *flag == 0;
-}
-
-// Payoff of point j from its log-prices (FP64, runtime d).
-__device__ double point_payoff(const SpecT<double>& S, const double* __restrict__ x, int64_t N,
-                               int64_t j)
-{
-    const int d = S.d;
-    double v;
-    if (S.payoff == CALL_MAX) {
-        double mx = log(x[j]);
-        for (int i = 1; i < d; ++i) mx = fmax(mx, log(x[i * N + j]));
-        v = exp(mx) - S.K;
-    } else if (S.payoff == PUT_GEO) {
-        double sl = 0.0;
-        for (int i = 0; i < d; ++i) sl += log(x[i * N + j]);
-        v = S.K - exp(sl * S.inv_d);
-    } else {
-        double sm = 0.0;
-        for (int i = 0; i < d; ++i) sm += exp(log(x[i * N + j]));
-        v = S.K - sm * S.inv_d;
-    }
-    return v > 0.0 ? v : 0.0;
-}
-
-// Raw features phi = [1, u, u^2, g, g^2], labels e = [Phi - C > 0] and the
-// in-the-money mask; tile sums of masked features and the count.
-__global__ void k_fit_prep(const DevSpec* __restrict__ s, const double* __restrict__ x,
-                           const double* __restrict__ cont, int64_t N, int p, double* phi,
-                           double* lab, double* msk, double* part1)
-{
-    const SpecT<double>& S = s->f64;
-    const int d = S.d;
-    const int64_t j0 = (int64_t)blockIdx.x * blockDim.x;
-    const int64_t j = j0 + threadIdx.x;
-    if (j < N) {
-        const double pay = point_payoff(S, x, N, j);
-        const bool itm = pay > 0.0;
-        msk[j] = itm ? 1.0 : 0.0;
-        lab[j] = (pay - cont[j] > 0.0) ? 1.0 : 0.0;
-        phi[j] = 1.0;
-        for (int i = 0; i < d; ++i) {
-            const double u = log(x[i * N + j]) - S.lnK;
-            phi[(1 + i) * N + j] = u;
-            phi[(1 + d + i) * N + j] = u * u;
-        }
-        const double g = pay / S.K;
-        phi[(1 + 2 * d) * N + j] = g;
-        phi[(2 + 2 * d) * N + j] = g * g;
-    }
-    __syncthreads();
-    const int64_t j1 = min(N, j0 + (int64_t)blockDim.x);
-    for (int f = threadIdx.x; f <= p; f += blockDim.x) {
-        double acc = 0.0;
-        for (int64_t jj = j0; jj < j1; ++jj) acc += (f < p) ? msk[jj] * phi[f * N + jj] : msk[jj];
-        part1[(size_t)blockIdx.x * (p + 1) + f] = acc;
-    }
-}
-
-// Tile sums of masked squared deviations from the means.
-__global__ void k_fit_var(const double* __restrict__ phi, const double* __restrict__ msk, int64_t N,
-                          int p, int ntiles, const double* __restrict__ part1, double* part2)
-{
-    const int64_t j0 = (int64_t)blockIdx.x * blockDim.x;
-    const int64_t j1 = min(N, j0 + (int64_t)blockDim.x);
-    for (int f = threadIdx.x; f < p; f += blockDim.x) {
-        double sf = 0.0, cnt = 0.0;
-        for (int t = 0; t < ntiles; ++t) {
-            sf += part1[(size_t)t * (p + 1) + f];
-            cnt += part1[(size_t)t * (p + 1) + p];
-        }
-        const double mu = cnt > 0.0 ? sf / cnt : 0.0;
-        double acc = 0.0;
-        for (int64_t jj = j0; jj < j1; ++jj) {
-            const double dv = phi[f * N + jj] - mu;
-            acc += msk[jj] * dv * dv;
-        }
-        part2[(size_t)blockIdx.x * p + f] = acc;
-    }
-}
-
-// Means and standard deviations (columns 1..p-1; a constant column keeps
-// scale 1), and the fitted-point count, into musd[2p + 1].
-__global__ void k_fit_musd(int p, int ntiles, const double* __restrict__ part1,
-                           const double* __restrict__ part2, double* musd)
-{
-    for (int f = threadIdx.x; f < p; f += blockDim.x) {
-        double sf = 0.0, sv = 0.0, cnt = 0.0;
-        for (int t = 0; t < ntiles; ++t) {
-            sf += part1[(size_t)t * (p + 1) + f];
-            sv += part2[(size_t)t * p + f];
-            cnt += part1[(size_t)t * (p + 1) + p];
-        }
-        double mu = 0.0, sd = 1.0;
-        if (f > 0 && cnt > 0.0) {
-            mu = sf / cnt;
-            sd = sqrt(sv / cnt);
-            if (!(sd > 1e-12 * (1.0 + fabs(mu)))) sd = 1.0;
-        }
-        musd[f] = mu;
-        musd[p + f] = sd;
-        if (f == 0) musd[2 * p] = cnt;
-    }
-}
-
-// One boosting round on a tile: apply the previous round's coefficients to
-// F and pi, then accumulate this round's weighted normal equations.
-__global__ void k_fit_step(const double* __restrict__ phi, const double* __restrict__ lab,
-                           const double* __restrict__ msk, int64_t N, int p,
-                           const double* __restrict__ musd, const double* __restrict__ beta_prev,
-                           int round, int rounds, double* F, double* pi, double* partA)
-{
-    extern __shared__ double sh[];
-    const double cnt = musd[2 * p];
-    if (!(cnt > 0.0)) return;
-    const int T = blockDim.x;
-    double* psi = sh;              // [T][p]
-    double* wz = psi + (size_t)T * p;   // [T][2]
-    const int64_t j0 = (int64_t)blockIdx.x * T;
-    const int64_t j = j0 + threadIdx.x;
-    const int tl = threadIdx.x;
-    if (j < N) {
-        for (int f = 0; f < p; ++f)
-            psi[tl * p + f] = f == 0 ? 1.0 : (phi[f * N + j] - musd[f]) / musd[p + f];
-        double Fj, pj;
-        if (round == 0) {
-            Fj = 0.0;
-            pj = 0.5;
-        } else {
-            double dF = 0.0;
-            for (int f = 0; f < p; ++f) dF += beta_prev[f] * psi[tl * p + f];
-            Fj = F[j] + 0.5 * dF;
-            pj = 1.0 / (1.0 + exp(-2.0 * Fj));
-        }
-        F[j] = Fj;
-        pi[j] = pj;
-        double w = pj * (1.0 - pj);
-        if (w < 1e-10) w = 1e-10;
-        double z = (lab[j] - pj) / w;
-        if (z > 4.0) z = 4.0;
-        if (z < -4.0) z = -4.0;
-        wz[2 * tl] = w * msk[j];
-        wz[2 * tl + 1] = z;
-    } else {
-        for (int f = 0; f < p; ++f) psi[tl * p + f] = 0.0;
-        wz[2 * tl] = 0.0;
-        wz[2 * tl + 1] = 0.0;
-    }
-    __syncthreads();
-    if (round >= rounds) return;
-    const int npairs = p * (p + 1) / 2;
-    const int nt = (int)min((int64_t)T, N - j0);
-    for (int q = threadIdx.x; q < npairs + p; q += T) {
-        double acc = 0.0;
-        if (q < npairs) {
-            int a, b;
-            pair_of(q, a, b);
-            for (int t = 0; t < nt; ++t) acc += wz[2 * t] * psi[t * p + a] * psi[t * p + b];
-        } else {
-            const int a = q - npairs;
-            for (int t = 0; t < nt; ++t) acc += wz[2 * t] * wz[2 * t + 1] * psi[t * p + a];
-        }
-        partA[(size_t)blockIdx.x * (npairs + p) + q] = acc;
-    }
-}
-
-// Merges the tile normal equations of one round and solves them.
-__global__ void k_fit_solve(int p, int ntiles, const double* __restrict__ partA,
-                            const double* __restrict__ musd, double lam_rel, double* Awork,
-                            double* beta_out)
-{
-    __shared__ int flag;
-    __shared__ double lam;
-    if (!(musd[2 * p] > 0.0)) return;
-    const int npairs = p * (p + 1) / 2;
-    double* A = Awork;            // [npairs]
-    double* b = Awork + npairs;   // [p]
-    for (int q = threadIdx.x; q < npairs + p; q += blockDim.x) {
-        double acc = 0.0;
-        for (int t = 0; t < ntiles; ++t) acc += partA[(size_t)t * (npairs + p) + q];
-        Awork[q] = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double tr = 0.0;
-        for (int i = 0; i < p; ++i) tr += A[tri(i, i)];
-        lam = lam_rel * tr / p;
-    }
-    __syncthreads();
-    if (!block_spd_solve(p, A, lam, b, beta_out, &flag)) {
-        for (int f = threadIdx.x; f < p; f += blockDim.x) beta_out[f] = 0.0;
-    }
-}
-
-// gamma = sum_r beta_r / 2, folded through the standardisation onto raw
-// features: w_f = gamma_f / sd_f, w_0 = gamma_0 - sum_f gamma_f mu_f / sd_f.
-__global__ void k_fit_fold(int p, int rounds, const double* __restrict__ musd,
-                           const double* __restrict__ beta, double* row64, float* row32)
-{
-    if (threadIdx.x != 0) return;
-    const bool any = musd[2 * p] > 0.0;
-    double w0 = 0.0;
-    for (int f = 0; f < p; ++f) {
-        double g = 0.0;
-        if (any)
-            for (int r = 0; r < rounds; ++r) g += 0.5 * beta[r * p + f];
-        if (f == 0) {
-            w0 += g;
-        } else {
-            const double wf = g / musd[p + f];
-            w0 -= g * musd[f] / musd[p + f];
-            row64[f] = wf;
-            row32[f] = (float)wf;
-        }
-    }
-    row64[0] = w0;
-    row32[0] = (float)w0;
-}
-
-static int fit_tile(int p)
-{
-    if (p <= 48) return 128;
-    if (p <= 96) return 64;
-    return 32;
-}
-
-size_t fit_scratch_doubles(int64_t N, int p, int rounds)
-{
-    const int T = fit_tile(p);
-    const int64_t tiles = (N + T - 1) / T;
-    const int64_t npairs = (int64_t)p * (p + 1) / 2;
-    return (size_t)(p * N + 4 * N + tiles * (p + 1) + tiles * p + tiles * (npairs + p) +
-                    (int64_t)rounds * p + (2 * p + 1) + (npairs + p) + 64);
-}
-
-void fit_scratch_carve(double* base, int64_t N, int p, int rounds, FitScratch* fs)
-{
-    const int T = fit_tile(p);
-    const int64_t tiles = (N + T - 1) / T;
-    const int64_t npairs = (int64_t)p * (p + 1) / 2;
-    double* c = base;
-    fs->phi = c; c += p * N;
-    fs->lab = c; c += N;
-    fs->msk = c; c += N;
-    fs->F = c; c += N;
-    fs->pi = c; c += N;
-    fs->part1 = c; c += tiles * (p + 1);
-    fs->part2 = c; c += tiles * p;
-    fs->partA = c; c += tiles * (npairs + p);
-    fs->beta = c; c += (int64_t)rounds * p;
-    (void)c;
-}
-
-hipError_t launch_fit_cmc(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
-                          int rounds, const FitScratch& fs, double* row64, float* row32,
-                          hipStream_t st)
-{
-    const int p = rule_width(CMC, d);
-    const int T = fit_tile(p);
-    const int tiles = (int)((N + T - 1) / T);
-    const int npairs = p * (p + 1) / 2;
-    double* musd = fs.beta + (size_t)rounds * p;
-    double* Awork = musd + 2 * p + 1;
-    hipLaunchKernelGGL(k_fit_prep, dim3(tiles), dim3(T), 0, st, s, x, cont, N, p, fs.phi, fs.lab,
-                       fs.msk, fs.part1);
-    hipLaunchKernelGGL(k_fit_var, dim3(tiles), dim3(T), 0, st, fs.phi, fs.msk, N, p, tiles, fs.part1,
-                       fs.part2);
-    hipLaunchKernelGGL(k_fit_musd, dim3(1), dim3(256), 0, st, p, tiles, fs.part1, fs.part2, musd);
-    const size_t lds = sizeof(double) * ((size_t)T * p + 2 * T);
-    for (int r = 0; r < rounds; ++r) {
-        const double* bprev = r > 0 ? fs.beta + (size_t)(r - 1) * p : nullptr;
-        hipLaunchKernelGGL(k_fit_step, dim3(tiles), dim3(T), lds, st, fs.phi, fs.lab, fs.msk, N, p,
-                           musd, bprev, r, rounds, fs.F, fs.pi, fs.partA);
-        hipLaunchKernelGGL(k_fit_solve, dim3(1), dim3(256), 0, st, p, tiles, fs.partA, musd, 1e-8,
-                           Awork, fs.beta + (size_t)r * p);
-    }
-    (void)npairs;
-    hipLaunchKernelGGL(k_fit_fold, dim3(1), dim3(64), 0, st, p, rounds, musd, fs.beta, row64, row32);
-    return hipGetLastError();
-}
-
-// I&Z regression: tile normal equations of ln s* on xi = [1, v, v_a v_b].
-__global__ void k_fitiz_part(const DevSpec* __restrict__ s, const double* __restrict__ x, int64_t J,
-                             int p, double* part)
-{
-    extern __shared__ double sh[];
-    const SpecT<double>& S = s->f64;
-    const int d = S.d, q = d - 1;
-    const int T = blockDim.x;
-    double* xi = sh;                     // [T][p]
-    double* ym = xi + (size_t)T * p;     // [T][2]
-    const int64_t j0 = (int64_t)blockIdx.x * T;
-    const int64_t j = j0 + threadIdx.x;
-    const int tl = threadIdx.x;
-    const double sst = j < J ? x[j] : -1.0;
-    if (sst > 0.0) {
-        xi[tl * p] = 1.0;
-        for (int a = 0; a < q; ++a) xi[tl * p + 1 + a] = log(x[(a + 1) * J + j]) - S.lnK;
-        int f = 1 + q;
-        for (int a = 0; a < q; ++a)
-            for (int c = a; c < q; ++c) {
-                xi[tl * p + f] = xi[tl * p + 1 + a] * xi[tl * p + 1 + c];
-                ++f;
-            }
-        ym[2 * tl] = log(sst);
-        ym[2 * tl + 1] = 1.0;
-    } else {
-        for (int f = 0; f < p; ++f) xi[tl * p + f] = 0.0;
-        ym[2 * tl] = 0.0;
-        ym[2 * tl + 1] = 0.0;
-    }
-    __syncthreads();
-    const int npairs = p * (p + 1) / 2;
-    const int nt = (int)min((int64_t)T, J - j0);
-    for (int qq = threadIdx.x; qq <= npairs + p; qq += T) {
-        double acc = 0.0;
-        if (qq < npairs) {
-            int a, b;
-            pair_of(qq, a, b);
-            for (int t = 0; t < nt; ++t) acc += xi[t * p + a] * xi[t * p + b];
-        } else if (qq < npairs + p) {
-            const int a = qq - npairs;
-            for (int t = 0; t < nt; ++t) acc += xi[t * p + a] * ym[2 * t];
-        } else {
-            for (int t = 0; t < nt; ++t) acc += ym[2 * t + 1];
-        }
-        part[(size_t)blockIdx.x * (npairs + p + 1) + qq] = acc;
-    }
-}
-
-__global__ void k_fitiz_solve(const DevSpec* __restrict__ s, int p, int ntiles,
-                              const double* __restrict__ part, double* Awork, double* row64,
-                              float* row32)
-{
-    __shared__ int flag;
-    __shared__ double lam, cnt;
-    // no converged point: a boundary no price crosses (puts below, the call above)
-    const double dir_never = s->f64.payoff == CALL_MAX ? 1e300 : -1e300;
-    const int npairs = p * (p + 1) / 2;
-    double* A = Awork;
-    double* b = Awork + npairs;
-    double* sol = b + p;
-    for (int q = threadIdx.x; q <= npairs + p; q += blockDim.x) {
-        double acc = 0.0;
-        for (int t = 0; t < ntiles; ++t) acc += part[(size_t)t * (npairs + p + 1) + q];
-        if (q < npairs + p) Awork[q] = acc;
-        else cnt = acc;
-    }
-    __syncthreads();
-    if (!(cnt > 0.0)) {
-        for (int f = threadIdx.x; f < p; f += blockDim.x) {
-            const double v = f == 0 ? dir_never : 0.0;
-            row64[f] = v;
-            row32[f] = (float)v;
-        }
-        return;
-    }
-    if (threadIdx.x == 0) {
-        double tr = 0.0;
-        for (int i = 0; i < p; ++i) tr += A[tri(i, i)];
-        lam = 1e-10 * tr / p;
-    }
-    __syncthreads();
-    const bool ok = block_spd_solve(p, A, lam, b, sol, &flag);
-    for (int f = threadIdx.x; f < p; f += blockDim.x) {
-        const double v = ok ? sol[f] : (f == 0 ? dir_never : 0.0);
-        row64[f] = v;
-        row32[f] = (float)v;
-    }
-}
-
-static int fitiz_tile(int p) { return p <= 48 ? 128 : 64; }
-
-size_t fitiz_scratch_doubles(int64_t J, int p)
-{
-    const int T = fitiz_tile(p);
-    const int64_t tiles = (J + T - 1) / T;
-    const int64_t npairs = (int64_t)p * (p + 1) / 2;
-    return (size_t)(tiles * (npairs + p + 1) + npairs + 2 * p + 64);
-}
-
-hipError_t launch_fit_iz(const DevSpec* s, int d, const double* x, int64_t J, double* scratch,
-                         double* row64, float* row32, hipStream_t st)
-{
-    const int p = rule_width(IZ, d);
-    const int T = fitiz_tile(p);
-    const int tiles = (int)((J + T - 1) / T);
-    const int npairs = p * (p + 1) / 2;
-    double* part = scratch;
-    double* Awork = scratch + (size_t)tiles * (npairs + p + 1);
-    const size_t lds = sizeof(double) * ((size_t)T * p + 2 * T);
-    hipLaunchKernelGGL(k_fitiz_part, dim3(tiles), dim3(T), lds, st, s, x, J, p, part);
-    hipLaunchKernelGGL(k_fitiz_solve, dim3(1), dim3(256), 0, st, s, p, tiles, part, Awork, row64,
-                       row32);
     return hipGetLastError();
 }
 

@@ -28,48 +28,68 @@ import numpy as np
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz -> VALU issue slots per second
-# (one full-rate operation per lane per cycle; FP32 FMA 78.6 TFLOP/s unpacked).
+# MI355X VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz, in FP32-FMA
+# issue slots per second (= 78.6 TFLOP/s of unpacked FP32 FMA).
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
-# Issue cost (full-rate slots) of the operations of one inner path-step.
-# Quarter-rate classes: 32x32->64 integer multiply and the FP32
-# transcendentals (log2, exp2, sqrt, sin, cos); everything else full rate.
-COST = {"mul64": 4.0, "trans": 4.0, "alu": 1.0}
+# Issue cost of one lane-operation of each class, in FP32-FMA slots, measured
+# on gfx950 by paper_0805_1827_amd/calib/valu_rates.hip (8 independent chains
+# of one instruction class per lane, 8 waves per SIMD on all 256 CUs):
+# 2-input integer/logic 0.6, v_mad_u64_u32 (32x32->64 multiply) 1.15, FP32
+# transcendental (v_log/v_exp/v_sin/v_cos/v_sqrt) 1.9, FP32 FMA/add/mul 1.0.
+COST = {"int": 0.6, "mul64": 1.15, "trans": 1.9, "f32": 1.0}
 
 
 def slots_per_step_fp32(d: int, payoff: int, method: int) -> float:
     """Algorithmic VALU issue slots of one inner path-step (FP32 form).
 
-    Philox4x32-10 block: 10 rounds x (2 wide multiplies + 2 three-input xors).
-    Box-Muller pair: 2 word->float conversions and 2 scalings, log2, one
-    multiply, sqrt, sin, cos, 2 multiplies.  Step: sqrt(dt) z (d), the
-    lower-triangular correlation d(d+1)/2 FMAs, the drift d FMAs.  Payoff:
-    max-call / geometric one exp (plus d-1 max/adds and 3 ops), arithmetic
-    basket d exps.  CMC rule: d subtractions + 2d FMAs + 3 for g; I&Z
-    boundary: 1 + q + q(q+1)/2 FMAs + q(q+1)/2 products.  Per path (amortised
-    over the executed steps, ignored here): the FP64 accumulation.
+    Philox4x32-10 block: 10 rounds x (2 wide multiplies + 4 two-input xors;
+    the key schedule is scalar).  Box-Muller pair: 2 word->float conversions
+    and 2 scalings, log2, a multiply, sqrt, sin, cos, 2 multiplies.  Step:
+    sqrt(dt) z (d), the lower-triangular correlation d(d+1)/2 FMAs, the drift
+    d FMAs.  Payoff: max-call / geometric one exp plus d+3 simple ops;
+    arithmetic basket d exps plus d+3.  CMC rule: d subtractions, 2d FMAs, 4
+    more for g and the comparison; I&Z boundary: q + q(q+1)/2 FMAs and
+    q(q+1)/2 products (q = d-1).  Per path (amortised over its steps and left
+    out): the FP64 accumulation of the payoff.
     """
     blocks = (d + 3) // 4
     pairs = (d + 1) // 2
-    philox = blocks * 10 * (2 * COST["mul64"] + 2 * COST["alu"])
-    bm = pairs * (4 * COST["alu"] + COST["trans"] + COST["alu"] + COST["trans"] + 2 * COST["trans"]
-                  + 2 * COST["alu"])
-    step = d + d * (d + 1) / 2 + d
+    philox = blocks * 10 * (2 * COST["mul64"] + 4 * COST["int"])
+    bm = pairs * (4 * COST["f32"] + COST["trans"] + COST["f32"] + COST["trans"] + 2 * COST["trans"]
+                  + 2 * COST["f32"])
+    step = (d + d * (d + 1) / 2 + d) * COST["f32"]
     if payoff == 0:
-        pay = d * (COST["trans"] + 2) + 3
+        pay = d * COST["trans"] + (d + 3) * COST["f32"]
     else:
-        pay = (d - 1) + COST["trans"] + 4
+        pay = COST["trans"] + (d + 3) * COST["f32"]
     if method == 0:
-        rule = 3 * d + 4
+        rule = (3 * d + 4) * COST["f32"]
     else:
         q = d - 1
-        rule = 1 + q + q * (q + 1)
+        rule = (1 + q + q * (q + 1)) * COST["f32"]
     return philox + bm + step + pay + rule
 
 
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q))
+
+
+TRAFFIC_FILE = ROOT / "profiles" / "k_cont_geo5_fp32_traffic.json"
+KERNEL_SOURCES = ("cont_kernel.hpp", "device.hpp", "internal.hpp")
+
+
+def measured_traffic():
+    """HBM bytes per date launch of the continuation kernel from the committed
+    FETCH_SIZE / WRITE_SIZE runs (scaled by a copy kernel), or None when the
+    kernel's sources have changed since those counters were taken."""
+    import hashlib
+    if not TRAFFIC_FILE.exists():
+        return None
+    rec = json.loads(TRAFFIC_FILE.read_text())
+    csrc = ROOT / "paper_0805_1827_amd" / "csrc"
+    h = hashlib.sha256(b"".join((csrc / f).read_bytes() for f in KERNEL_SOURCES)).hexdigest()
+    return rec["hbm_bytes_per_launch"] if rec.get("src_sha256") == h else None
 
 
 def cpu_baseline(spec, N, n, seed, target_seconds: float) -> dict:
@@ -152,7 +172,7 @@ def main():
     slots = slots_per_step_fp32(spec.d, spec.payoff, bmc.CMC)
     achieved = slots * inner32 / calc32
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(),
                 "kernel": "k_cont<5, float> (continuation, FP32 stepping)",
                 "slots_per_path_step": slots,
                 "avg_launch_ms": 1e3 * calc32 / launches32, "launches": launches32}

@@ -124,6 +124,21 @@ bmc_status bmc_sync(bmc_ctx *ctx);
 bmc_status bmc_price(bmc_ctx *ctx, const bmc_spec *spec, const bmc_opts *opts,
                      bmc_rules **rules_out, bmc_result *out);
 
+/* Many options priced together by the CMC pricer (Algorithm 2 for each),
+ * synchronous.  specs[count], opts[count] (host; method must be BMC_CMC; each
+ * option has its own d, dates, N, n, n_final, seed and precision) and
+ * results[count] (host).  The options share every launch: round r learns
+ * date N_T - 1 - r of each option that has one (bridge step, one persistent
+ * continuation launch per dimension bucket and precision carrying the
+ * (option, point, path-chunk) jobs, the boosting fits one block per option),
+ * and an option's final pricing joins the round after its last date.  Each
+ * result, and each rule table, is bit-identical to bmc_price on the same
+ * spec and options.  seconds and the phase times are those of the whole
+ * batch.  If rules_out is not NULL it receives count rule tables (caller
+ * destroys them).  On error nothing is written. */
+bmc_status bmc_price_batch(bmc_ctx *ctx, int32_t count, const bmc_spec *specs, const bmc_opts *opts,
+                           bmc_rules **rules_out, bmc_result *results);
+
 /* Exercise-rule table of one spec and method: one row of width w per date
  * (rows 1..N_T-1 used).  CMC (Section 3.2): F(x) = sum_f w_f phi_f(x) with
  * phi = [1, u_1..u_d, u_1^2..u_d^2, g, g^2], u_i = ln(S_i/K), g = Phi(S)/K;

@@ -26,7 +26,7 @@ SYMBOLS = [
     "bmc_version", "bmc_last_error", "bmc_ctx_create", "bmc_ctx_destroy", "bmc_sync", "bmc_price",
     "bmc_rules_create", "bmc_rules_destroy", "bmc_rules_width", "bmc_rules_set", "bmc_rules_get",
     "bmc_rules_export", "bmc_rules_import", "bmc_sample_points", "bmc_estimate_continuation",
-    "bmc_fit_rule", "bmc_iz_search", "bmc_final_price", "bmc_philox", "bmc_normals",
+    "bmc_fit_rule", "bmc_iz_search", "bmc_final_price", "bmc_philox", "bmc_normals", "bmc_price_batch",
 ]
 
 
@@ -82,6 +82,7 @@ def load():
     L.bmc_ctx_destroy.restype = None
     L.bmc_sync.argtypes = [vp]
     L.bmc_price.argtypes = [vp, sp, C.POINTER(bmc_opts), C.POINTER(vp), C.POINTER(bmc_result)]
+    L.bmc_price_batch.argtypes = [vp, C.c_int32, sp, C.POINTER(bmc_opts), C.POINTER(vp), C.POINTER(bmc_result)]
     L.bmc_rules_create.argtypes = [vp, sp, C.c_int32, C.POINTER(vp)]
     L.bmc_rules_destroy.argtypes = [vp]
     L.bmc_rules_destroy.restype = None
@@ -215,6 +216,30 @@ def bmc_price(ctx: Context, spec, method: int = CMC, precision: int = FP64, N: i
     out = res.as_dict()
     if want_rules:
         return out, Rules(rh, s.n_dates)
+    return out
+
+
+def bmc_price_batch(ctx: Context, specs, opts, want_rules: bool = False):
+    """Prices many options in shared launches.  specs: option specs; opts:
+    one dict per option with keys of bmc_price (method, precision, N, n,
+    n_final, seed, cls_rounds).  Returns the list of result dicts (and the
+    list of Rules with want_rules)."""
+    ss = [as_spec(s) for s in specs]
+    count = len(ss)
+    if count != len(opts):
+        raise ValueError("specs and opts differ in length")
+    sarr = (bmc_spec * count)(*[s.c for s in ss])
+    oarr = (bmc_opts * count)()
+    for i, o in enumerate(opts):
+        oarr[i] = bmc_opts(o.get("method", CMC), o.get("precision", FP64), o.get("N", 500), o.get("n", 500),
+                           o.get("n_final", 100000), o.get("seed", 1), o.get("cls_rounds", 0),
+                           o.get("iz_max_iter", 0), o.get("iz_eps", 0.0))
+    res = (bmc_result * count)()
+    rh = (C.c_void_p * count)()
+    _check(load().bmc_price_batch(ctx.h, count, sarr, oarr, rh if want_rules else None, res))
+    out = [r.as_dict() for r in res]
+    if want_rules:
+        return out, [Rules(C.c_void_p(rh[i]), ss[i].n_dates) for i in range(count)]
     return out
 
 

@@ -32,8 +32,15 @@ def sources() -> list[Path]:
     return sorted(CSRC.glob("*.hip"))
 
 
-def _compile(src: Path) -> Path:
+def _headers_mtime() -> float:
+    hdrs = list(CSRC.glob("*.hpp")) + list((ROOT / "include").glob("*.h"))
+    return max(h.stat().st_mtime for h in hdrs)
+
+
+def _compile(src: Path, incremental: bool = False) -> Path:
     obj = OBJ / (src.stem + ".o")
+    if incremental and obj.exists() and obj.stat().st_mtime > max(src.stat().st_mtime, _headers_mtime()):
+        return obj
     cmd = [HIPCC, *FLAGS, "-c", str(src), "-o", str(obj)]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -41,7 +48,7 @@ def _compile(src: Path) -> Path:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> Path:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> Path:
     OBJ.mkdir(exist_ok=True)
     srcs = sources()
     jobs = jobs or max(1, min(len(srcs), len(os.sched_getaffinity(0)), 16))
@@ -49,7 +56,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> Path:
     order = sorted(srcs, key=lambda p: (0 if p.stem.startswith("cont_d") and int(p.stem[6:]) > 8 else 1,
                                         -(int(p.stem[6:]) if p.stem.startswith("cont_d") else 0)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, order))
+        objs = list(ex.map(lambda s: _compile(s, incremental), order))
     tmp = LIB.with_suffix(".so.tmp")
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *map(str, objs), "-o", str(tmp)]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -78,7 +85,9 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--calib", action="store_true", help="also build the calibration probes")
+    ap.add_argument("--incremental", action="store_true",
+                    help="skip objects newer than their source and every header")
     args = ap.parse_args()
-    build(args.jobs, verbose=True)
+    build(args.jobs, verbose=True, incremental=args.incremental)
     if args.calib:
         build_calib()

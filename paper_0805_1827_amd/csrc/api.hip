@@ -107,7 +107,7 @@ bmc_status bmc::validate_spec(const bmc_spec* s)
     return BMC_OK;
 }
 
-static void pack_spec(const bmc_spec* s, HostSpecPack* p)
+void bmc::pack_spec(const bmc_spec* s, HostSpecPack* p)
 {
     std::memset(p, 0, sizeof(*p));
     p->d = s->d;
@@ -139,7 +139,7 @@ bmc_status bmc::upload_spec(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot)
     if ((e = hipMemcpyAsync(ctx->pack_dev.ptr, ctx->pack_host, sizeof(HostSpecPack),
                             hipMemcpyHostToDevice, ctx->stream)))
         return hip_fail(e, "spec upload");
-    if ((e = launch_setup((const HostSpecPack*)ctx->pack_dev.ptr, (DevSpec*)slot.ptr, ctx->stream)))
+    if ((e = launch_setup((const HostSpecPack*)ctx->pack_dev.ptr, (DevSpec*)slot.ptr, 1, ctx->stream)))
         return hip_fail(e, "setup launch");
     int32_t status = 0;
     if ((e = hipMemcpyAsync(&status, (char*)slot.ptr + offsetof(DevSpec, status), sizeof(int32_t),
@@ -185,9 +185,10 @@ extern "C" bmc_status bmc_ctx_create(int32_t device, void* hip_stream, bmc_ctx**
 bmc_ctx::~bmc_ctx()
 {
     for (DBuf* b : {&spec, &spec2, &pack_dev, &part, &B, &x, &x2, &cont, &se, &steps, &fit, &iz,
-                    &counters, &korobov})
+                    &counters, &korobov, &bspec, &barena, &btab})
         b->release();
     if (pack_host) (void)hipHostFree(pack_host);
+    if (bhost) (void)hipHostFree(bhost);
     if (host_io) (void)hipHostFree(host_io);
 }
 

@@ -36,12 +36,13 @@ struct KahanAcc {
     __device__ double sumsq() const { return (double)q - (double)cq; }
 };
 
+// One (point j, chunk) job of a continuation launch, run by a whole block;
+// lds: the dynamic table area, red: [3][16] wave partials.
 template <int D, bool EXACT, class R, class ACC>
-__global__ void __launch_bounds__(256) k_cont(const ContArgs a)
+__device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, const uint32_t chunk, double* lds,
+                                         double (*red)[16])
 {
-    extern __shared__ double lds[];
-    __shared__ double red[3][16];
-    const SpecT<R>& S = spec_of<R>(a.spec);
+    const_as<SpecT<R>>& S = *as_const(&spec_of<R>(a.spec));
     const int d = EXACT ? D : S.d;
     const int NT = S.n_dates;
     const int m = a.m;
@@ -52,13 +53,8 @@ __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
     R* sdtv = dtv + NT + 1;
     R* wt = sdtv + NT + 1;
 
-    const uint32_t slot = blockIdx.x / a.nchunk;
-    const uint32_t chunk = blockIdx.x - slot * a.nchunk;
-    if (a.n_ids && slot >= (uint32_t)*a.n_ids) return;   // retired job (whole block)
-    const uint32_t j = a.ids ? (uint32_t)a.ids[slot] : slot;
-
-    const double* t64 = a.spec->f64.t;
-    const double r64 = a.spec->f64.r;
+    const_as<double>* t64 = as_const(a.spec)->f64.t;
+    const double r64 = as_const(a.spec)->f64.r;
     const double tm = t64[m];
     for (int k = threadIdx.x; k <= NT; k += blockDim.x) {
         disc[k] = exp(-r64 * (t64[k] - tm));
@@ -167,6 +163,44 @@ __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
     }
 }
 
+// One launch per (spec, date): block = one (point, chunk) job.
+template <int D, bool EXACT, class R, class ACC>
+__global__ void __launch_bounds__(256) k_cont(const ContArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double red[3][16];
+    const uint32_t slot = blockIdx.x / a.nchunk;
+    const uint32_t chunk = blockIdx.x - slot * a.nchunk;
+    if (a.n_ids && slot >= (uint32_t)*a.n_ids) return;   // retired job (whole block)
+    const uint32_t j = a.ids ? (uint32_t)a.ids[slot] : slot;
+    cont_job<D, EXACT, R, ACC>(a, j, chunk, lds, red);
+}
+
+// One launch over the jobs of many tasks (options at their own dates): block
+// b runs job job0 + b, mapped to (task, point, chunk) through the exclusive
+// prefix sums of the tasks' job counts.  Every job writes its own partial
+// sums, so results do not depend on the launch it ran in.  The task table and
+// prefix sums are read through the scalar unit (uniform loads).
+template <int D, bool EXACT, class R, class ACC>
+__global__ void __launch_bounds__(256) k_cont_multi(const ContArgs* __restrict__ tasks,
+                                                    const uint32_t* __restrict__ prefix, int ntasks, uint32_t job0)
+{
+    extern __shared__ double lds[];
+    __shared__ double red[3][16];
+    const_as<uint32_t>* pre = as_const(prefix);
+    const uint32_t job = job0 + blockIdx.x;
+    int lo = 0, hi = ntasks;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= job) lo = mid;
+        else hi = mid;
+    }
+    const ContArgs a = load_const(tasks + lo);
+    const uint32_t local = job - pre[lo];
+    const uint32_t slot = local / a.nchunk;
+    cont_job<D, EXACT, R, ACC>(a, slot, local - slot * a.nchunk, lds, red);
+}
+
 template <int D, bool EXACT>
 hipError_t launch_cont_d(int prec, const ContArgs& a, int grid, int block, size_t lds,
                                 hipStream_t st)
@@ -177,6 +211,22 @@ hipError_t launch_cont_d(int prec, const ContArgs& a, int grid, int block, size_
         hipLaunchKernelGGL((k_cont<D, EXACT, float, Acc<double>>), dim3(grid), dim3(block), lds, st, a);
     else
         hipLaunchKernelGGL((k_cont<D, EXACT, float, KahanAcc>), dim3(grid), dim3(block), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int D, bool EXACT>
+hipError_t launch_cont_multi_d(int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks, uint32_t job0,
+                               uint32_t jobs, int block, size_t lds, hipStream_t st)
+{
+    if (prec == PREC_FP64)
+        hipLaunchKernelGGL((k_cont_multi<D, EXACT, double, Acc<double>>), dim3(jobs), dim3(block), lds, st, tasks,
+                           prefix, ntasks, job0);
+    else if (prec == PREC_FP32)
+        hipLaunchKernelGGL((k_cont_multi<D, EXACT, float, Acc<double>>), dim3(jobs), dim3(block), lds, st, tasks,
+                           prefix, ntasks, job0);
+    else
+        hipLaunchKernelGGL((k_cont_multi<D, EXACT, float, KahanAcc>), dim3(jobs), dim3(block), lds, st, tasks,
+                           prefix, ntasks, job0);
     return hipGetLastError();
 }
 

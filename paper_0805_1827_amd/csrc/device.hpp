@@ -35,6 +35,25 @@ struct DevSpec {
     int32_t status;            // 0 or -2 (not positive definite)
 };
 
+// Read-only views in the constant address space: a kernel never writes the
+// spec or its task tables, so uniform loads from them go through the scalar
+// unit into SGPRs even in kernels that store to global memory in a loop.
+#define BMC_CONST_AS __attribute__((address_space(4)))
+template <class T> using const_as = const BMC_CONST_AS T;
+template <class T> __device__ __forceinline__ const_as<T>* as_const(const T* p) { return (const_as<T>*)p; }
+// Copy of a read-only struct through the scalar unit (word by word; the
+// compiler merges the words into wide scalar loads when the address is uniform).
+template <class T> __device__ __forceinline__ T load_const(const T* p)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
+    T out;
+    const_as<uint32_t>* src = (const_as<uint32_t>*)p;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+    return out;
+}
+
 template <class R> __device__ __forceinline__ const SpecT<R>& spec_of(const DevSpec* s);
 template <> __device__ __forceinline__ const SpecT<double>& spec_of<double>(const DevSpec* s) { return s->f64; }
 template <> __device__ __forceinline__ const SpecT<float>& spec_of<float>(const DevSpec* s) { return s->f32; }

@@ -8,15 +8,6 @@
 
 namespace bmc {
 
-// Points per tile (= threads per block) of the fits.
-__host__ __device__ __forceinline__ int fit_tile(int p)
-{
-    if (p <= 15) return 256;
-    if (p <= 48) return 128;
-    if (p <= 96) return 64;
-    return 32;
-}
-
 __device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
 
 // q-th entry of a packed lower triangle -> (row i, column l <= i).

@@ -2,8 +2,8 @@
 // points are spread over the blocks; each boosting round ends with one grid
 // barrier, after which every block merges the tile partials (in tile order)
 // and solves the small system itself, so the coefficients never leave the
-// block between rounds.  Used for p <= 40 (the LDS budget); wider rules use
-// the multi-launch form in fit.hip.  For p <= 15 the tile's weighted normal
+// block between rounds.  Used while the block's LDS layout fits in 64 KB
+// (p <= 46); wider rules use the multi-launch form in fit.hip.  For p <= 15 the tile's weighted normal
 // equations run on the FP64 matrix cores.
 #include <hip/hip_cooperative_groups.h>
 
@@ -20,18 +20,6 @@ __device__ unsigned long long g_fit_trace[256];
 #else
 #define FIT_MARK(i) do { } while (0)
 #endif
-
-struct FitCoopArgs {
-    const DevSpec* s;
-    const double* x;
-    const double* cont;
-    int64_t N;
-    int p, rounds, ntiles;
-    FitScratch fs;
-    double* musd;
-    double* row64;
-    float* row32;
-};
 
 __host__ __device__ inline int coop_psi_width(int p) { return p <= 15 ? 16 : p; }
 __host__ __device__ inline int coop_aux(int p, int T)
@@ -74,9 +62,25 @@ __device__ void stage_tile(const double* __restrict__ phi, const double* __restr
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) k_fit_cmc_coop(FitCoopArgs a)
+// The fit runs on a group of blocks: the whole cooperative grid, or one
+// block (many options fitted side by side, one per block).  Tile t belongs
+// to group member t mod size; every member merges all tiles in tile order,
+// so the result does not depend on the group size.
+struct GridGroup {
+    cg::grid_group g;
+    __device__ int rank() const { return blockIdx.x; }
+    __device__ int size() const { return gridDim.x; }
+    __device__ void sync() { g.sync(); }
+};
+struct BlockGroup {
+    __device__ int rank() const { return 0; }
+    __device__ int size() const { return 1; }
+    __device__ void sync() { __syncthreads(); }
+};
+
+template <class G>
+__device__ void fit_cmc_body(const FitTask& a, G grp)
 {
-    cg::grid_group grid = cg::this_grid();
     extern __shared__ double sh[];
     __shared__ int flag;
     __shared__ double lam, cnt_s;
@@ -98,7 +102,7 @@ __global__ void __launch_bounds__(256) k_fit_cmc_coop(FitCoopArgs a)
 
     FIT_MARK(0);
     // features, labels, in-the-money mask; tile sums of features and count
-    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    for (int t = grp.rank(); t < a.ntiles; t += grp.size()) {
         const int64_t j0 = (int64_t)t * T;
         fit_prep_point(S, a.x, a.cont, N, j0 + tid, fs.phi, fs.lab, fs.msk);
         __syncthreads();
@@ -108,7 +112,7 @@ __global__ void __launch_bounds__(256) k_fit_cmc_coop(FitCoopArgs a)
                   fs.part1 + (size_t)t * (p + 1));
     }
     FIT_MARK(1);
-    grid.sync();
+    grp.sync();
     FIT_MARK(2);
     // means (every block), tile sums of squared deviations
     merge_tiles(fs.part1, a.ntiles, p + 1, psi, cap, A);
@@ -117,7 +121,7 @@ __global__ void __launch_bounds__(256) k_fit_cmc_coop(FitCoopArgs a)
     const double cnt = cnt_s;
     for (int f = tid; f < p; f += T) mu[f] = cnt > 0.0 ? A[f] / cnt : 0.0;
     __syncthreads();
-    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    for (int t = grp.rank(); t < a.ntiles; t += grp.size()) {
         const int64_t j0 = (int64_t)t * T;
         stage_tile(fs.phi, fs.msk, N, p, j0, psi, wz);
         const int nt = (int)min((int64_t)T, N - j0);
@@ -129,21 +133,21 @@ __global__ void __launch_bounds__(256) k_fit_cmc_coop(FitCoopArgs a)
                   aux, fs.part2 + (size_t)t * p);
     }
     FIT_MARK(3);
-    grid.sync();
+    grp.sync();
     FIT_MARK(4);
     merge_tiles(fs.part1, a.ntiles, p + 1, psi, cap, A);          // feature sums
     merge_tiles(fs.part2, a.ntiles, p, psi, cap, A + (p + 1));    // squared deviations
     for (int f = tid; f < p; f += T) {
         fit_mu_sd(f, cnt, A[f], A[p + 1 + f], &mu[f], &sd[f]);
-        if (blockIdx.x == 0) {
+        if (grp.rank() == 0) {
             a.musd[f] = mu[f];
             a.musd[p + f] = sd[f];
         }
     }
-    if (blockIdx.x == 0 && tid == 0) a.musd[2 * p] = cnt;
+    if (grp.rank() == 0 && tid == 0) a.musd[2 * p] = cnt;
     __syncthreads();
     if (!(cnt > 0.0)) {   // no in-the-money point: never exercise (same in every block)
-        if (blockIdx.x == 0)
+        if (grp.rank() == 0)
             for (int f = tid; f < p; f += T) { a.row64[f] = 0.0; a.row32[f] = 0.0f; }
         return;
     }
@@ -154,7 +158,7 @@ __global__ void __launch_bounds__(256) k_fit_cmc_coop(FitCoopArgs a)
     for (int r = 0; r < a.rounds; ++r) {
         double* partA = fs.partA + (size_t)(r & 1) * part_stride;
         FIT_MARK(8 + 8 * r);
-        for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        for (int t = grp.rank(); t < a.ntiles; t += grp.size()) {
             const int64_t j0 = (int64_t)t * T;
             const int nt = (int)min((int64_t)T, N - j0);
             if (mfma) {
@@ -173,7 +177,7 @@ __global__ void __launch_bounds__(256) k_fit_cmc_coop(FitCoopArgs a)
             __syncthreads();
         }
         FIT_MARK(10 + 8 * r);
-        grid.sync();
+        grp.sync();
         FIT_MARK(11 + 8 * r);
         merge_tiles(partA, a.ntiles, Q, psi, cap, A);   // A then bv
         FIT_MARK(12 + 8 * r);
@@ -187,23 +191,37 @@ __global__ void __launch_bounds__(256) k_fit_cmc_coop(FitCoopArgs a)
             for (int f = tid; f < p; f += T) beta[f] = 0.0;
         __syncthreads();
         FIT_MARK(13 + 8 * r);
-        if (blockIdx.x == 0)
+        if (grp.rank() == 0)
             for (int f = tid; f < p; f += T) fs.beta[(size_t)r * p + f] = beta[f];
     }
     FIT_MARK(200);
-    if (blockIdx.x == 0) {
+    if (grp.rank() == 0) {
         __syncthreads();
         fit_fold(p, a.rounds, a.musd, fs.beta, a.row64, a.row32);
     }
 }
 
-bool fit_coop_supported(int p) { return p <= 40; }
+__global__ void __launch_bounds__(256) k_fit_cmc_coop(FitTask a) { fit_cmc_body(a, GridGroup{cg::this_grid()}); }
 
-hipError_t launch_fit_cmc_coop(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
-                               int rounds, const FitScratch& fs, double* row64, float* row32,
-                               hipStream_t st)
+// One option per block.
+__global__ void __launch_bounds__(256) k_fit_cmc_multi(const FitTask* __restrict__ tasks)
 {
-    FitCoopArgs a;
+    const FitTask a = tasks[blockIdx.x];
+    fit_cmc_body(a, BlockGroup{});
+}
+
+size_t fit_task_lds(int p)
+{
+    const int T = fit_tile(p), npairs = p * (p + 1) / 2;
+    return sizeof(double) * ((size_t)T * coop_psi_width(p) + 2 * T + coop_aux(p, T) + npairs + 4 * p);
+}
+
+bool fit_coop_supported(int p) { return fit_task_lds(p) <= 64 * 1024; }
+
+FitTask fit_task_make(const DevSpec* s, int d, const double* x, const double* cont, int64_t N, int rounds,
+                      const FitScratch& fs, double* row64, float* row32)
+{
+    FitTask a;
     a.s = s;
     a.x = x;
     a.cont = cont;
@@ -216,9 +234,16 @@ hipError_t launch_fit_cmc_coop(const DevSpec* s, int d, const double* x, const d
     a.musd = fs.beta + (size_t)rounds * a.p;
     a.row64 = row64;
     a.row32 = row32;
-    const int npairs = a.p * (a.p + 1) / 2;
-    const size_t lds = sizeof(double) * ((size_t)T * coop_psi_width(a.p) + 2 * T + coop_aux(a.p, T) + npairs +
-                                         4 * a.p);
+    return a;
+}
+
+hipError_t launch_fit_cmc_coop(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
+                               int rounds, const FitScratch& fs, double* row64, float* row32,
+                               hipStream_t st)
+{
+    FitTask a = fit_task_make(s, d, x, cont, N, rounds, fs, row64, row32);
+    const int T = fit_tile(a.p);
+    const size_t lds = fit_task_lds(a.p);
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e;
     if ((e = hipGetDevice(&dev))) return e;
@@ -231,6 +256,12 @@ hipError_t launch_fit_cmc_coop(const DevSpec* s, int d, const double* x, const d
     void* args[] = {&a};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_fit_cmc_coop), dim3(grid), dim3(T), args,
                                       (unsigned)lds, st);
+}
+
+hipError_t launch_fit_cmc_multi(const FitTask* tasks, int ntasks, int T, size_t lds, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fit_cmc_multi, dim3(ntasks), dim3(T), lds, st, tasks);
+    return hipGetLastError();
 }
 
 }  // namespace bmc

@@ -36,16 +36,54 @@ struct ContArgs {
     double* part;             // [N * nchunk * 3]: sum, sum of squares, steps
 };
 
+// Finalize of one task inside a multi-task launch (see launch_finalize).
+struct FinTask {
+    const double* part;
+    double* cont;
+    double* se;
+    int64_t* steps;
+    double* sums;
+    unsigned long long* steps_total;
+    int64_t N;
+    uint32_t nchunk, n;
+    int32_t wide;
+    int32_t pad;
+};
+
+// Bridge step of one option inside a multi-task launch.
+struct BridgeTask {
+    const DevSpec* s;
+    double* B;
+    double* x;
+    int64_t N;
+    uint32_t seed;
+    int32_t m;
+};
+
 struct LaunchCfg {
     int block = 256;          // threads per workgroup
     int ppt = 4;              // paths per thread per chunk
 };
 
 // Kernels (kernels.hip).  All enqueue on `st` and return hipError_t.
-hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, hipStream_t st);
+hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st);
 hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, size_t lds,
                        hipStream_t st);
 size_t cont_lds_bytes(int prec, int n_dates, int width);
+// Template bucket of dimension d (exact for d <= 8).
+int cont_bucket(int d);
+// One launch over jobs job0 .. job0+jobs-1 of many tasks of one bucket;
+// prefix[t] is the first job of task t, prefix[ntasks] the total.
+hipError_t launch_cont_multi(int bucket, int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks,
+                             uint32_t job0, uint32_t jobs, int block, size_t lds, hipStream_t st);
+bool finalize_is_wide(uint32_t nchunk, int64_t N, bool has_ids);
+// prefix: first block of each task (wide: N blocks, else ceil(N/256)).
+hipError_t launch_finalize_multi(const FinTask* tasks, const uint32_t* prefix, int ntasks, uint32_t blocks,
+                                 hipStream_t st);
+// end = 1: draw B at maturity; end = 0: bridge back to date m and write x.
+// prefix: first block of each task (ceil(N/256) blocks each).
+hipError_t launch_bridge_multi(const BridgeTask* tasks, const uint32_t* prefix, int ntasks, uint32_t blocks,
+                               int end, hipStream_t st);
 hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int64_t N,
                            const int32_t* ids, const int32_t* n_ids, double* cont, double* se,
                            int64_t* steps, double* sums, unsigned long long* steps_total,
@@ -79,6 +117,34 @@ struct FitScratch {
     double* partA;   // [2][tiles][npairs + p]
     double* beta;    // [rounds][p]
 };
+// Points per tile (= threads per block) of the fits.
+__host__ __device__ __forceinline__ int fit_tile(int p)
+{
+    if (p <= 15) return 256;
+    if (p <= 48) return 128;
+    if (p <= 96) return 64;
+    return 32;
+}
+
+// One CMC fit as run by the cooperative grid or by one block of a
+// multi-option launch.
+struct FitTask {
+    const DevSpec* s;
+    const double* x;
+    const double* cont;
+    int64_t N;
+    int p, rounds, ntiles;
+    FitScratch fs;
+    double* musd;
+    double* row64;
+    float* row32;
+};
+FitTask fit_task_make(const DevSpec* s, int d, const double* x, const double* cont, int64_t N, int rounds,
+                      const FitScratch& fs, double* row64, float* row32);
+size_t fit_task_lds(int p);
+bool fit_coop_supported(int p);
+// One block per task; all tasks share the tile size T = fit_tile(p).
+hipError_t launch_fit_cmc_multi(const FitTask* tasks, int ntasks, int T, size_t lds, hipStream_t st);
 size_t fit_scratch_doubles(int64_t N, int p, int rounds);
 void fit_scratch_carve(double* base, int64_t N, int p, int rounds, FitScratch* fs);
 hipError_t launch_fit_cmc(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,

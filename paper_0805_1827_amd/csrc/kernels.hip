@@ -14,6 +14,8 @@ __global__ void __launch_bounds__(256) k_setup(const HostSpecPack* __restrict__ 
 {
     __shared__ double L[D_MAX * D_MAX];
     __shared__ int bad;
+    in += blockIdx.x;   // one block per spec
+    out += blockIdx.x;
     const int d = in->d, NT = in->n_dates, tid = threadIdx.x;
     if (tid == 0) bad = 0;
     for (int i = tid; i < D_MAX * D_MAX; i += blockDim.x) L[i] = 0.0;
@@ -69,10 +71,23 @@ __global__ void __launch_bounds__(256) k_setup(const HostSpecPack* __restrict__ 
     }
 }
 
-hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, hipStream_t st)
+hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, in, out);
+    hipLaunchKernelGGL(k_setup, dim3(count), dim3(256), 0, st, in, out);
     return hipGetLastError();
+}
+
+// Task of a multi-task launch whose blocks are numbered through the
+// exclusive prefix sums of the tasks' block counts.
+__device__ __forceinline__ int task_of_block(const uint32_t* __restrict__ prefix, int ntasks, uint32_t b)
+{
+    int lo = 0, hi = ntasks;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -111,6 +126,45 @@ hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, 
     return launch_cont_d<64, false>(prec, a, grid, block, lds, st);
 }
 
+template <int D, bool EXACT>
+hipError_t launch_cont_multi_d(int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks, uint32_t job0,
+                               uint32_t jobs, int block, size_t lds, hipStream_t st);
+
+int cont_bucket(int d)
+{
+    if (d <= 8) return d;
+    if (d <= 12) return 12;
+    if (d <= 16) return 16;
+    if (d <= 24) return 24;
+    if (d <= 32) return 32;
+    if (d <= 40) return 40;
+    return 64;
+}
+
+hipError_t launch_cont_multi(int bucket, int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks,
+                             uint32_t job0, uint32_t jobs, int block, size_t lds, hipStream_t st)
+{
+#define BMC_MULTI(DD, EX) return launch_cont_multi_d<DD, EX>(prec, tasks, prefix, ntasks, job0, jobs, block, lds, st)
+    switch (bucket) {
+    case 1: BMC_MULTI(1, true);
+    case 2: BMC_MULTI(2, true);
+    case 3: BMC_MULTI(3, true);
+    case 4: BMC_MULTI(4, true);
+    case 5: BMC_MULTI(5, true);
+    case 6: BMC_MULTI(6, true);
+    case 7: BMC_MULTI(7, true);
+    case 8: BMC_MULTI(8, true);
+    case 12: BMC_MULTI(12, false);
+    case 16: BMC_MULTI(16, false);
+    case 24: BMC_MULTI(24, false);
+    case 32: BMC_MULTI(32, false);
+    case 40: BMC_MULTI(40, false);
+    case 64: BMC_MULTI(64, false);
+    default: return hipErrorInvalidValue;
+    }
+#undef BMC_MULTI
+}
+
 // Continuation estimate C = sum/n and its standard error sqrt(var/n), with
 // var = (sumsq - sum^2/n)/(n-1), from a point's merged sums.
 __device__ __forceinline__ void finalize_point(int64_t j, double s, double q, double c, uint32_t n, double* cont,
@@ -131,6 +185,52 @@ __device__ __forceinline__ void finalize_point(int64_t j, double s, double q, do
 }
 
 // Per point: merge the chunk partials in chunk order.
+__device__ __forceinline__ void merge_serial(const double* __restrict__ part, uint32_t nchunk, int64_t j, double& s,
+                                             double& q, double& c)
+{
+    s = 0.0;
+    q = 0.0;
+    c = 0.0;
+    for (uint32_t ch = 0; ch < nchunk; ++ch) {
+        const double* o = part + ((size_t)j * nchunk + ch) * 3;
+        s += o[0];
+        q += o[1];
+        c += o[2];
+    }
+}
+
+// Same merge for points with many chunks (final pricing), by a 256-thread
+// block: each thread merges a contiguous run of chunks in order, then a
+// fixed-shape tree over the threads; the result is valid in thread 0.
+__device__ __forceinline__ void merge_wide(const double* __restrict__ part, uint32_t nchunk, int64_t j,
+                                           double (*red)[256], double& s, double& q, double& c)
+{
+    const uint32_t T = blockDim.x, t = threadIdx.x;
+    const uint32_t lo = (uint32_t)(((uint64_t)nchunk * t) / T), hi = (uint32_t)(((uint64_t)nchunk * (t + 1)) / T);
+    double s_ = 0.0, q_ = 0.0, c_ = 0.0;
+    for (uint32_t ch = lo; ch < hi; ++ch) {
+        const double* o = part + ((size_t)j * nchunk + ch) * 3;
+        s_ += o[0];
+        q_ += o[1];
+        c_ += o[2];
+    }
+    red[0][t] = s_;
+    red[1][t] = q_;
+    red[2][t] = c_;
+    __syncthreads();
+    for (uint32_t w = T / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] += red[0][t + w];
+            red[1][t] += red[1][t + w];
+            red[2][t] += red[2][t + w];
+        }
+        __syncthreads();
+    }
+    s = red[0][0];
+    q = red[1][0];
+    c = red[2][0];
+}
+
 __global__ void k_finalize(const double* __restrict__ part, uint32_t nchunk, uint32_t n, int64_t N,
                            const int32_t* __restrict__ ids, const int32_t* __restrict__ n_ids,
                            double* cont, double* se, int64_t* steps, double* sums,
@@ -144,47 +244,50 @@ __global__ void k_finalize(const double* __restrict__ part, uint32_t nchunk, uin
     } else if (slot >= N) {
         return;
     }
-    double s = 0.0, q = 0.0, c = 0.0;
-    for (uint32_t ch = 0; ch < nchunk; ++ch) {
-        const double* o = part + ((size_t)j * nchunk + ch) * 3;
-        s += o[0];
-        q += o[1];
-        c += o[2];
-    }
+    double s, q, c;
+    merge_serial(part, nchunk, j, s, q, c);
     finalize_point(j, s, q, c, n, cont, se, steps, sums, steps_total);
 }
 
-// Same merge for points with many chunks (final pricing): one block per
-// point, each thread merges a contiguous run of chunks in order, then a
-// fixed-shape tree over the threads.
 __global__ void __launch_bounds__(256) k_finalize_wide(const double* __restrict__ part, uint32_t nchunk,
                                                        uint32_t n, double* cont, double* se, int64_t* steps,
                                                        double* sums, unsigned long long* steps_total)
 {
     __shared__ double red[3][256];
     const int64_t j = blockIdx.x;
-    const uint32_t T = blockDim.x, t = threadIdx.x;
-    const uint32_t lo = (uint32_t)(((uint64_t)nchunk * t) / T), hi = (uint32_t)(((uint64_t)nchunk * (t + 1)) / T);
-    double s = 0.0, q = 0.0, c = 0.0;
-    for (uint32_t ch = lo; ch < hi; ++ch) {
-        const double* o = part + ((size_t)j * nchunk + ch) * 3;
-        s += o[0];
-        q += o[1];
-        c += o[2];
+    double s, q, c;
+    merge_wide(part, nchunk, j, red, s, q, c);
+    if (threadIdx.x == 0) finalize_point(j, s, q, c, n, cont, se, steps, sums, steps_total);
+}
+
+// Finalize of many tasks in one launch: a wide task has one block per point,
+// a narrow one a block per 256 points.
+__global__ void __launch_bounds__(256) k_finalize_multi(const FinTask* __restrict__ tasks,
+                                                        const uint32_t* __restrict__ prefix, int ntasks)
+{
+    __shared__ double red[3][256];
+    const int ti = task_of_block(prefix, ntasks, blockIdx.x);
+    const FinTask& f = tasks[ti];
+    const uint32_t local = blockIdx.x - prefix[ti];
+    double s, q, c;
+    if (f.wide) {
+        merge_wide(f.part, f.nchunk, local, red, s, q, c);
+        if (threadIdx.x == 0) finalize_point(local, s, q, c, f.n, f.cont, f.se, f.steps, f.sums, f.steps_total);
+    } else {
+        const int64_t j = (int64_t)local * blockDim.x + threadIdx.x;
+        if (j >= f.N) return;
+        merge_serial(f.part, f.nchunk, j, s, q, c);
+        finalize_point(j, s, q, c, f.n, f.cont, f.se, f.steps, f.sums, f.steps_total);
     }
-    red[0][t] = s;
-    red[1][t] = q;
-    red[2][t] = c;
-    __syncthreads();
-    for (uint32_t w = T / 2; w > 0; w >>= 1) {
-        if (t < w) {
-            red[0][t] += red[0][t + w];
-            red[1][t] += red[1][t + w];
-            red[2][t] += red[2][t + w];
-        }
-        __syncthreads();
-    }
-    if (t == 0) finalize_point(j, red[0][0], red[1][0], red[2][0], n, cont, se, steps, sums, steps_total);
+}
+
+bool finalize_is_wide(uint32_t nchunk, int64_t N, bool has_ids) { return !has_ids && nchunk >= 64 && N <= 4096; }
+
+hipError_t launch_finalize_multi(const FinTask* tasks, const uint32_t* prefix, int ntasks, uint32_t blocks,
+                                 hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finalize_multi, dim3(blocks), dim3(256), 0, st, tasks, prefix, ntasks);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int64_t N,
@@ -192,7 +295,7 @@ hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int6
                            int64_t* steps, double* sums, unsigned long long* steps_total,
                            hipStream_t st)
 {
-    if (!ids && nchunk >= 64 && N <= 4096) {
+    if (finalize_is_wide(nchunk, N, ids != nullptr)) {
         hipLaunchKernelGGL(k_finalize_wide, dim3((unsigned)N), dim3(256), 0, st, part, nchunk, n, cont, se, steps,
                            sums, steps_total);
         return hipGetLastError();
@@ -214,10 +317,9 @@ __device__ __forceinline__ void outer_block(uint32_t seed, uint32_t k1, uint32_t
     if (4 * (int)b + 2 < d) box_muller(w.w[2], w.w[3], z[2], z[3]);
 }
 
-__global__ void k_bridge_end(const DevSpec* __restrict__ s, int64_t N, uint32_t seed, double* B)
+__device__ __forceinline__ void bridge_end_point(const DevSpec* __restrict__ s, int64_t N, uint32_t seed, double* B,
+                                                 int64_t j)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
     const SpecT<double>& S = s->f64;
     const int d = S.d, NT = S.n_dates;
     const uint32_t k1 = key_hi(STREAM_OUTER, NT);
@@ -231,11 +333,9 @@ __global__ void k_bridge_end(const DevSpec* __restrict__ s, int64_t N, uint32_t 
 
 // B holds date m+1 on entry and date m on exit (bridge = 1); with bridge = 0
 // B already holds date m.  x (optional) receives the points at date m.
-__global__ void k_bridge_back(const DevSpec* __restrict__ s, int m, int64_t N, uint32_t seed,
-                              double* B, double* x, int bridge)
+__device__ __forceinline__ void bridge_back_point(const DevSpec* __restrict__ s, int m, int64_t N, uint32_t seed,
+                                                  double* B, double* x, int bridge, int64_t j)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
     const SpecT<double>& S = s->f64;
     const int d = S.d;
     const uint32_t k1 = key_hi(STREAM_OUTER, m);
@@ -259,6 +359,31 @@ __global__ void k_bridge_back(const DevSpec* __restrict__ s, int m, int64_t N, u
     }
 }
 
+__global__ void k_bridge_end(const DevSpec* __restrict__ s, int64_t N, uint32_t seed, double* B)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < N) bridge_end_point(s, N, seed, B, j);
+}
+
+__global__ void k_bridge_back(const DevSpec* __restrict__ s, int m, int64_t N, uint32_t seed,
+                              double* B, double* x, int bridge)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < N) bridge_back_point(s, m, N, seed, B, x, bridge, j);
+}
+
+// Bridge steps of many options in one launch (256 points per block).
+__global__ void k_bridge_multi(const BridgeTask* __restrict__ tasks, const uint32_t* __restrict__ prefix, int ntasks,
+                               int end)
+{
+    const int ti = task_of_block(prefix, ntasks, blockIdx.x);
+    const BridgeTask& t = tasks[ti];
+    const int64_t j = (int64_t)(blockIdx.x - prefix[ti]) * blockDim.x + threadIdx.x;
+    if (j >= t.N) return;
+    if (end) bridge_end_point(t.s, t.N, t.seed, t.B, j);
+    else bridge_back_point(t.s, t.m, t.N, t.seed, t.B, t.x, 1, j);
+}
+
 hipError_t launch_bridge_end(const DevSpec* s, int d, int64_t N, uint32_t seed, double* B,
                              hipStream_t st)
 {
@@ -273,6 +398,13 @@ hipError_t launch_bridge_back(const DevSpec* s, int d, int m, int64_t N, uint32_
     (void)d;
     hipLaunchKernelGGL(k_bridge_back, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, s, m, N,
                        seed, B, x, bridge);
+    return hipGetLastError();
+}
+
+hipError_t launch_bridge_multi(const BridgeTask* tasks, const uint32_t* prefix, int ntasks, uint32_t blocks,
+                               int end, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bridge_multi, dim3(blocks), dim3(256), 0, st, tasks, prefix, ntasks, end);
     return hipGetLastError();
 }
 

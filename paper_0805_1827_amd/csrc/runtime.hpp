@@ -39,6 +39,10 @@ struct bmc_ctx {
     bmc::HostSpecPack* pack_host = nullptr;   // pinned staging
     void* host_io = nullptr;                  // pinned 4 KB for small results
     bmc::DBuf spec, spec2, pack_dev, part, B, x, x2, cont, se, steps, fit, iz, counters, korobov;
+    // batched pricing: device specs, per-option arena, task tables; pinned staging
+    bmc::DBuf bspec, barena, btab;
+    void* bhost = nullptr;
+    size_t bhost_bytes = 0;
     ~bmc_ctx();
 };
 
@@ -52,6 +56,7 @@ struct bmc_rules {
 namespace bmc {
 
 bmc_status upload_spec(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot);
+void pack_spec(const bmc_spec* s, HostSpecPack* p);
 const double* dev_S0(const void* devspec);
 uint32_t choose_ppt(int64_t points, int64_t n, const Tuning* tune);
 bmc_status run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int method, int width,

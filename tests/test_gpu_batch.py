@@ -1,0 +1,112 @@
+"""Batched pricing (bmc_price_batch): many options of uneven dimension, date
+count, path counts and precision in shared launches.
+
+Bars: every option's result and rule table bit-identical to its standalone
+bmc_price run (same chunking, tile and merge orders); FP64 prices against the
+FP64 oracle at the parity tolerance; results independent of the batch's
+composition and order.
+"""
+import numpy as np
+import pytest
+
+from conftest import cpu_threads
+
+pytestmark = pytest.mark.gpu
+NT_CPU = cpu_threads()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bmc(torch_mod):
+    from paper_0805_1827_amd import bmc as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(bmc):
+    c = bmc.Context(0)
+    yield c
+    c.close()
+
+
+# (d, dates, n, N, precision name): every template bucket kind (exact d,
+# runtime d inside a bucket), a single-date option (final pricing only),
+# ragged N against the fit tiles and n against the path chunks.
+SHAPES = [(1, 6, 1024, 96, "FP64"), (2, 4, 1000, 130, "FP32"), (3, 9, 4096, 64, "FP32_KAHAN"),
+          (5, 10, 1024, 200, "FP64"), (7, 5, 4096, 96, "FP32"), (9, 7, 1024, 64, "FP64"),
+          (13, 4, 1500, 72, "FP32"), (20, 6, 1024, 80, "FP64"), (4, 1, 1024, 64, "FP64"),
+          (5, 12, 2048, 300, "FP32"), (16, 3, 512, 257, "FP32_KAHAN"), (1, 2, 333, 50, "FP32")]
+
+
+def make_batch(bmc, inputs, shapes=SHAPES, first_seed=40, n_final=20000):
+    specs, opts = [], []
+    for k, (d, nd, n, N, prec) in enumerate(shapes):
+        specs.append(inputs.random_option(first_seed + k, d_range=(d, d), dates_range=(nd, nd), n_choices=(n,)))
+        opts.append(dict(method=bmc.CMC, precision=getattr(bmc, prec), N=N, n=n, n_final=n_final,
+                         seed=first_seed + k))
+    return specs, opts
+
+
+def test_batch_bit_identical_to_standalone(bmc, ctx, inputs):
+    specs, opts = make_batch(bmc, inputs)
+    res, rules = bmc.bmc_price_batch(ctx, specs, opts, want_rules=True)
+    for k, (s, o) in enumerate(zip(specs, opts)):
+        alone, ar = bmc.bmc_price(ctx, s, want_rules=True, **o)
+        for key in ("price", "variance", "std_err", "inner_path_steps", "final_path_steps"):
+            assert res[k][key] == alone[key], (k, SHAPES[k], key, res[k][key], alone[key])
+        assert np.array_equal(bmc.rules_table(rules[k]), bmc.rules_table(ar)), (k, SHAPES[k])
+        assert res[k]["inner_path_steps"] > 0 or s.n_dates == 1
+
+
+def test_batch_independent_of_composition(bmc, ctx, inputs):
+    specs, opts = make_batch(bmc, inputs)
+    full = bmc.bmc_price_batch(ctx, specs, opts)
+    again = bmc.bmc_price_batch(ctx, specs, opts)
+    perm = np.random.default_rng(3).permutation(len(specs))
+    part = perm[: len(perm) // 2]
+    sub = bmc.bmc_price_batch(ctx, [specs[i] for i in part], [opts[i] for i in part])
+    for k in range(len(specs)):
+        assert full[k]["price"] == again[k]["price"]
+    for j, i in enumerate(part):
+        assert sub[j]["price"] == full[i]["price"] and sub[j]["inner_path_steps"] == full[i]["inner_path_steps"]
+
+
+def test_batch_fp64_against_oracle(bmc, ctx, orc, inputs):
+    shapes = [(1, 5, 256, 64, "FP64"), (3, 4, 300, 48, "FP64"), (5, 4, 256, 40, "FP64"), (2, 1, 256, 8, "FP64")]
+    specs, opts = make_batch(bmc, inputs, shapes, first_seed=7, n_final=30000)
+    res = bmc.bmc_price_batch(ctx, specs, opts)
+    for k, (s, o) in enumerate(zip(specs, opts)):
+        ref = orc.price(s, orc.CMC, o["N"], o["n"], o["n_final"], o["seed"], nthreads=NT_CPU)
+        tol = 1e-10 * max(abs(res[k]["price"]), abs(ref["price"])) + 1e-12 * s.K
+        assert abs(res[k]["price"] - ref["price"]) <= tol, (k, res[k]["price"], ref["price"])
+        assert res[k]["inner_path_steps"] == ref["inner_path_steps"]
+        assert res[k]["final_path_steps"] == ref["final_path_steps"]
+
+
+def test_batch_errors(bmc, ctx, inputs):
+    specs, opts = make_batch(bmc, inputs, SHAPES[:3])
+    bad = [dict(o) for o in opts]
+    bad[1]["method"] = bmc.IZ
+    with pytest.raises(bmc.BmcError) as ei:
+        bmc.bmc_price_batch(ctx, specs, bad)
+    assert ei.value.status == bmc.EUNSUPPORTED
+    bad = [dict(o) for o in opts]
+    bad[2]["n"] = 1
+    with pytest.raises(bmc.BmcError) as ei:
+        bmc.bmc_price_batch(ctx, specs, bad)
+    assert ei.value.status == bmc.EINVAL
+    s = inputs.basket(2, 100.0, 100.0, 0.05, 0.0, 0.2, 0.0, 1.0, 4, inputs.PUT_BASKET)
+    s.rho = np.array([[1.0, 1.2], [1.2, 1.0]])
+    with pytest.raises(bmc.BmcError) as ei:
+        bmc.bmc_price_batch(ctx, [specs[0], s], [opts[0], opts[0]])
+    assert ei.value.status == bmc.ENOTSPD
+    # the context still works after the failed calls
+    ok = bmc.bmc_price_batch(ctx, specs[:1], opts[:1])
+    assert ok[0]["price"] == bmc.bmc_price(ctx, specs[0], **opts[0])["price"]

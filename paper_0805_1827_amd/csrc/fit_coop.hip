@@ -2,8 +2,9 @@
 // points are spread over the blocks; each boosting round ends with one grid
 // barrier, after which every block merges the tile partials (in tile order)
 // and solves the small system itself, so the coefficients never leave the
-// block between rounds.  Used while the block's LDS layout fits in 64 KB
-// (p <= 46); wider rules use the multi-launch form in fit.hip.  For p <= 15 the tile's weighted normal
+// block between rounds.  Used while the block's LDS layout fits the
+// device's per-workgroup LDS (every p up to d = 64 on gfx950's 160 KB); the
+// multi-launch form in fit.hip is the fallback for smaller LDS.  For p <= 15 the tile's weighted normal
 // equations run on the FP64 matrix cores.
 #include <hip/hip_cooperative_groups.h>
 
@@ -216,7 +217,36 @@ size_t fit_task_lds(int p)
     return sizeof(double) * ((size_t)T * coop_psi_width(p) + 2 * T + coop_aux(p, T) + npairs + 4 * p);
 }
 
-bool fit_coop_supported(int p) { return fit_task_lds(p) <= 64 * 1024; }
+// Dynamic LDS the fit kernels may use on the current device: the
+// per-workgroup maximum (160 KB on gfx950) less their static LDS.  Falls
+// back to 64 KB if the runtime refuses the larger size.
+static size_t fit_lds_limit()
+{
+    static size_t limit = 0;
+    if (limit == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 64 * 1024;
+        size_t lim = (size_t)v;
+        for (const void* f : {reinterpret_cast<const void*>(k_fit_cmc_coop),
+                              reinterpret_cast<const void*>(k_fit_cmc_multi)}) {
+            hipFuncAttributes fa;
+            size_t dyn = 64 * 1024 - 256;
+            if (hipFuncGetAttributes(&fa, f) == hipSuccess && fa.sharedSizeBytes < (size_t)v) {
+                const size_t want = (size_t)v - fa.sharedSizeBytes;
+                if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess)
+                    dyn = want;
+            }
+            lim = std::min(lim, dyn);
+        }
+        (void)hipGetLastError();   // a refused attribute must not surface at the next launch check
+        limit = lim;
+    }
+    return limit;
+}
+
+bool fit_coop_supported(int p) { return fit_task_lds(p) <= fit_lds_limit(); }
 
 FitTask fit_task_make(const DevSpec* s, int d, const double* x, const double* cont, int64_t N, int rounds,
                       const FitScratch& fs, double* row64, float* row32)

@@ -38,11 +38,13 @@ def ctx(bmc):
 
 # (d, dates, n, N, precision name): every template bucket kind (exact d,
 # runtime d inside a bucket), a single-date option (final pricing only),
-# ragged N against the fit tiles and n against the path chunks.
+# ragged N against the fit tiles and n against the path chunks, wide rules
+# (d = 40: p = 83 with 64-point fit tiles).
 SHAPES = [(1, 6, 1024, 96, "FP64"), (2, 4, 1000, 130, "FP32"), (3, 9, 4096, 64, "FP32_KAHAN"),
           (5, 10, 1024, 200, "FP64"), (7, 5, 4096, 96, "FP32"), (9, 7, 1024, 64, "FP64"),
           (13, 4, 1500, 72, "FP32"), (20, 6, 1024, 80, "FP64"), (4, 1, 1024, 64, "FP64"),
-          (5, 12, 2048, 300, "FP32"), (16, 3, 512, 257, "FP32_KAHAN"), (1, 2, 333, 50, "FP32")]
+          (5, 12, 2048, 300, "FP32"), (16, 3, 512, 257, "FP32_KAHAN"), (1, 2, 333, 50, "FP32"),
+          (40, 3, 512, 70, "FP64"), (27, 4, 700, 65, "FP32")]
 
 
 def make_batch(bmc, inputs, shapes=SHAPES, first_seed=40, n_final=20000):
@@ -102,8 +104,8 @@ def test_batch_errors(bmc, ctx, inputs):
     with pytest.raises(bmc.BmcError) as ei:
         bmc.bmc_price_batch(ctx, specs, bad)
     assert ei.value.status == bmc.EINVAL
-    s = inputs.basket(2, 100.0, 100.0, 0.05, 0.0, 0.2, 0.0, 1.0, 4, inputs.PUT_BASKET)
-    s.rho = np.array([[1.0, 1.2], [1.2, 1.0]])
+    s = inputs.basket(3, 100.0, 100.0, 0.05, 0.0, 0.2, 0.0, 1.0, 4, inputs.PUT_BASKET)
+    s.rho = np.array([[1.0, 0.9, -0.9], [0.9, 1.0, 0.9], [-0.9, 0.9, 1.0]])   # symmetric, not PSD
     with pytest.raises(bmc.BmcError) as ei:
         bmc.bmc_price_batch(ctx, [specs[0], s], [opts[0], opts[0]])
     assert ei.value.status == bmc.ENOTSPD

@@ -120,6 +120,44 @@ def cpu_baseline(spec, N, n, seed, target_seconds: float) -> dict:
                       f"{spec.n_dates - 1} dates, n = {n} inner paths, FP64 ({steps} path-steps in {dt:.1f} s)"}
 
 
+def batch_form(ctx, bmc, inputs, count: int, N: int, n_final: int) -> dict:
+    """The uneven-instance batch (count options: d in 1..20, 4..50 dates, n in
+    {1k, 4k, 16k}, Wishart correlations, three payoffs, seeds 0..count-1),
+    priced by bmc_price_batch in FP32 and FP64, with the FP32 slot roofline
+    over the batch's executed path-steps and the FP32-FP64 price distance."""
+    import torch
+    specs = inputs.uneven_batch(count)
+
+    def opts(prec):
+        return [dict(method=bmc.CMC, precision=prec, N=N, n=s.meta["n"], n_final=n_final, seed=s.meta["seed"])
+                for s in specs]
+
+    bmc.bmc_price_batch(ctx, specs[:4], opts(bmc.FP32)[:4])   # warm-up (module load, buffers)
+    out = {}
+    for name, prec in (("fp32", bmc.FP32), ("fp64", bmc.FP64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = bmc.bmc_price_batch(ctx, specs, opts(prec))
+        dt = time.perf_counter() - t0
+        out[name] = (res, dt)
+    r32, t32 = out["fp32"]
+    r64, t64 = out["fp64"]
+    steps32 = sum(r["inner_path_steps"] for r in r32)
+    steps64 = sum(r["inner_path_steps"] for r in r64)
+    slots = sum(slots_per_step_fp32(s.d, s.payoff, bmc.CMC) * r["inner_path_steps"] for s, r in zip(specs, r32))
+    calc = r32[0]["calc_seconds"]
+    dist = np.array([abs(a["price"] - b["price"]) / b["std_err"] for a, b in zip(r32, r64)])
+    return {"workload": f"{count} uneven options (d 1-20, 4-50 dates, n in 1k/4k/16k, Wishart rho, "
+                        f"3 payoffs, seeds 0-{count - 1}), CMC, N={N}, n_final={n_final}",
+            "fp32": {"value": steps32 / t32, "seconds": t32, "inner_path_steps": steps32,
+                     "phase_s": {"calc": calc, "fit": r32[0]["fit_seconds"], "final": r32[0]["final_seconds"]}},
+            "fp64": {"value": steps64 / t64, "seconds": t64, "inner_path_steps": steps64},
+            "unit": "path-steps/s",
+            "fp32_slot_frac_of_peak": slots / calc / PEAK_SLOTS,
+            "fp32_vs_fp64_price_in_std_err": {"median": float(np.median(dist)), "max": float(dist.max()),
+                                              "frac_within_0.1": float(np.mean(dist <= 0.1))}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +170,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline (0 disables it)")
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--batch", type=int, default=256, help="options in the batched form (0 disables it)")
+    ap.add_argument("--batch-N", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the pricer runs on a single device and this build has no "
@@ -208,6 +248,8 @@ def main():
         "inner_path_steps_per_price": inner32 // args.steps,
         "roofline": roofline,
     }
+    if args.batch > 0:
+        out["batch"] = batch_form(ctx, bmc, inputs, args.batch, args.batch_N, 100_000)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(spec, args.N, args.n, args.seed, args.cpu_seconds)
     print(json.dumps(out), flush=True)

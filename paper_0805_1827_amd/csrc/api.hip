@@ -416,8 +416,8 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
     const size_t part_bytes = sizeof(double) * 3 * (size_t)N * nchunk;
     hipError_t e = ctx->part.ensure(part_bytes);
     if (e) return hip_fail(e, "partials allocation");
-    const size_t lds = cont_lds_bytes(prec, n_dates, width);
-    if (lds > 64 * 1024) return fail(BMC_EUNSUPPORTED, "rule table too large for LDS (%zu bytes)", lds);
+    const size_t lds = cont_lds_bytes(prec, d, n_dates, width);
+    if (lds > cont_lds_limit()) return fail(BMC_EUNSUPPORTED, "rule table too large for LDS (%zu bytes)", lds);
     const int64_t grid = (int64_t)N * nchunk;
     if (grid > 0x7FFFFFFF) return fail(BMC_EINVAL, "too many jobs in one launch");
     ContArgs a;

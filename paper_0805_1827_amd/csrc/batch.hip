@@ -116,8 +116,8 @@ extern "C" bmc_status bmc_price_batch(bmc_ctx* ctx, int32_t count, const bmc_spe
         q.nchunk = (q.n + q.per_wg - 1) / q.per_wg;
         q.fper_wg = 256u * choose_ppt(1, q.n_final, nullptr);
         q.fnchunk = (q.n_final + q.fper_wg - 1) / q.fper_wg;
-        q.lds = cont_lds_bytes(q.prec, q.NT, q.p);
-        if (q.lds > 64 * 1024) return fail(BMC_EUNSUPPORTED, "option %d: rule table too large for LDS", i);
+        q.lds = cont_lds_bytes(q.prec, q.d, q.NT, q.p);
+        if (q.lds > cont_lds_limit()) return fail(BMC_EUNSUPPORTED, "option %d: rule table too large for LDS", i);
         if ((uint64_t)q.N * q.nchunk > 0x7FFFFFFFull) return fail(BMC_EINVAL, "option %d: too many jobs", i);
         q.ow64 = rules64_bytes;
         rules64_bytes += align_up(sizeof(double) * (size_t)(q.NT + 1) * q.p);

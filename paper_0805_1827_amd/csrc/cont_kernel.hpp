@@ -36,22 +36,73 @@ struct KahanAcc {
     __device__ double sumsq() const { return (double)q - (double)cq; }
 };
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Correlated increment ls += A (s z) for the FP32 buckets on the matrix cores:
+// v_mfma_f32_4x4x1_16b_f32 gives element i of lane L the product
+// a[4 (L/4) + i] b[L], so with b = the lane's own s z_l and a = A[4c + L%4][l]
+// (lanes of a group of four hold the four rows of asset chunk c), element i
+// of every lane accumulates A[4c+i][l] s z_l for its own path.  arow is A
+// row-major [D][D], zero-padded; a quad of columns is one 16-byte LDS read.
+// Only the lower block triangle (chunks c >= column quad t) is visited.
+template <int D>
+__device__ __forceinline__ void corr_mfma(const float* __restrict__ arow, const float (&zs)[D], float (&ls)[D])
+{
+    constexpr int NC = D / 4;
+    const int r = threadIdx.x & 3;
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+#pragma unroll
+        for (int ch = t; ch < NC; ++ch) {
+            const f32x4 a = *reinterpret_cast<const f32x4*>(arow + (4 * ch + r) * D + 4 * t);
+            f32x4 v = {ls[4 * ch], ls[4 * ch + 1], ls[4 * ch + 2], ls[4 * ch + 3]};
+            v = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, zs[4 * t], v, 0, 0, 0);
+            v = __builtin_amdgcn_mfma_f32_4x4x1f32(a.y, zs[4 * t + 1], v, 0, 0, 0);
+            v = __builtin_amdgcn_mfma_f32_4x4x1f32(a.z, zs[4 * t + 2], v, 0, 0, 0);
+            v = __builtin_amdgcn_mfma_f32_4x4x1f32(a.w, zs[4 * t + 3], v, 0, 0, 0);
+            ls[4 * ch] = v.x;
+            ls[4 * ch + 1] = v.y;
+            ls[4 * ch + 2] = v.z;
+            ls[4 * ch + 3] = v.w;
+        }
+    }
+}
+
+template <int D, class R> constexpr bool uses_mfma() { return D >= 12 && sizeof(R) == 4; }
+template <int D> constexpr bool uses_lds_coef() { return D >= 12; }
+
 // One (point j, chunk) job of a continuation launch, run by a whole block;
 // lds: the dynamic table area, red: [3][16] wave partials.
 template <int D, bool EXACT, class R, class ACC>
 __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, const uint32_t chunk, double* lds,
                                          double (*red)[16])
 {
+    constexpr bool MF = uses_mfma<D, R>();
+    constexpr bool LC = uses_lds_coef<D>();
+    // Bucket kernels (d < D possible) pad the path state to D entries with
+    // neutral values, so that every per-asset loop runs to D without tests:
+    // zero coefficients and drifts, log-prices 0 (geometric put) or -1e30
+    // (max-call and arithmetic basket: no effect on a maximum or a sum of
+    // exponentials), zero classifier weights.
+    constexpr bool PAD = !EXACT;
     const_as<SpecT<R>>& S = *as_const(&spec_of<R>(a.spec));
     const int d = EXACT ? D : S.d;
+    if (!EXACT) __builtin_assume(d > dim_floor(D) && d <= D);
     const int NT = S.n_dates;
     const int m = a.m;
     const int W = a.width;
+    const bool padw = PAD && a.method == CMC;   // classifier rows padded to 2D+3
+    const int WL = cont_rule_stride(D, W);
     double* disc = lds;
     R* lx = reinterpret_cast<R*>(disc + NT + 1);
     R* dtv = lx + D_MAX;
     R* sdtv = dtv + NT + 1;
     R* wt = sdtv + NT + 1;
+    size_t coef_off = 0;
+    (void)cont_lds_layout(sizeof(R), D, NT, W, &coef_off);
+    const int payk = S.payoff;
+    R* coef = reinterpret_cast<R*>(reinterpret_cast<char*>(lds) + coef_off);   // [D][D]
+    R* drift = coef + D * D;                                                   // [D]
 
     const_as<double>* t64 = as_const(a.spec)->f64.t;
     const double r64 = as_const(a.spec)->f64.r;
@@ -62,58 +113,117 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
         sdtv[k] = S.sdt[k];
     }
     const R* __restrict__ rules = reinterpret_cast<const R*>(a.rules);
-    for (int i = (m + 1) * W + threadIdx.x; i < NT * W; i += blockDim.x) wt[i] = rules[i];
-    if ((int)threadIdx.x < d) lx[threadIdx.x] = (R)log(a.x[(int64_t)threadIdx.x * a.N + j]);
+    if (padw) {
+        // [1, u_1..u_d, uu_1..uu_d, g, gg] -> [1, u_1..u_D, uu_1..uu_D, g, gg]
+        for (int e = (m + 1) * WL + threadIdx.x; e < NT * WL; e += blockDim.x) {
+            const int k = e / WL, f = e - k * WL;
+            int src;
+            if (f == 0) src = 0;
+            else if (f <= D) src = f - 1 < d ? f : -1;
+            else if (f <= 2 * D) src = f - 1 - D < d ? f - D + d : -1;
+            else src = f - 2 * D + 2 * d;
+            wt[e] = src >= 0 ? rules[k * W + src] : R(0);
+        }
+    } else {
+        for (int i = (m + 1) * W + threadIdx.x; i < NT * W; i += blockDim.x) wt[i] = rules[i];
+    }
+    if ((int)threadIdx.x < D)
+        lx[threadIdx.x] = (int)threadIdx.x < d ? (R)log(a.x[(int64_t)threadIdx.x * a.N + j])
+                                                : (payk == PUT_GEO ? R(0) : R(-1e30));
+    if constexpr (LC) {
+        // FP32: row-major A[i][l] (matrix-core operand rows); FP64: column-major
+        // A[l][i] (consecutive rows of one column in one read).  Zero beyond d.
+        for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+            const int i = MF ? e / D : e % D, l = MF ? e % D : e / D;
+            coef[e] = (i < d && l <= i) ? S.A[i * D_MAX + l] : R(0);
+        }
+        for (int i = threadIdx.x; i < D; i += blockDim.x) drift[i] = i < d ? S.drift[i] : R(0);
+    }
     __syncthreads();
 
     const uint32_t lo = chunk * a.paths_per_wg;
     const uint32_t hi = min(a.n, lo + a.paths_per_wg);
     const uint32_t nb = (uint32_t)(d + 3) >> 2;
     const uint32_t k0 = a.k0, k1 = a.k1;
-    const int payk = S.payoff;
     const bool call_dir = payk == CALL_MAX;
     const R K = S.K, lnK = S.lnK, invK = S.invK, inv_d = S.inv_d;
 
+    // dp: the extent of the per-asset loops (D for padded buckets)
+    const int dp = PAD ? D : d;
     R ls[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) ls[i] = (i < d) ? lx[i] : R(0);
+    for (int i = 0; i < D; ++i) ls[i] = (i < dp) ? lx[i] : R(0);
 
     ACC acc;
     uint32_t steps = 0;
     uint32_t p = lo + threadIdx.x;
     int k = m + 1;
-    while (p < hi) {
+    // Matrix-core steps need every lane of the wavefront (operands come from
+    // neighbouring lanes): the loop runs while any lane has a path, and lanes
+    // without one step through dummy paths whose payoffs are not counted.
+    auto more = [&]() { return MF ? __any(p < hi) != 0 : p < hi; };
+    while (more()) {
+        const bool live = MF ? p < hi : true;
         const R dtk = dtv[k], sk = sdtv[k];
+        // Opaque per-iteration offset: keeps the coefficient loads inside the
+        // loop instead of hoisted into registers.
+        uint32_t opq = 0;
+        if constexpr (LC) asm volatile("" : "+v"(opq));
+        const R* cf = coef + (opq & ~3u);
+        const R* dr = drift + (opq & ~3u);
 #pragma unroll
-        for (int i = 0; i < D; ++i)
-            if (i < d) ls[i] += S.drift[i] * dtk;
+        for (int i = 0; i < D; ++i) {
+            if (i < dp) {
+                if constexpr (LC) ls[i] += dr[i] * dtk;
+                else ls[i] += S.drift[i] * dtk;
+            }
+        }
         const uint32_t c0 = (uint32_t)k * nb;
+        if constexpr (MF) {
+            R zs[D];
 #pragma unroll
-        for (int b = 0; b < (D + 3) / 4; ++b) {
-            if (4 * b < d) {
-                const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, 0u);
+            for (int b = 0; b < D / 4; ++b) {
                 R z[4];
+                const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, 0u);
                 box_muller(w.w[0], w.w[1], z[0], z[1]);
-                if (4 * b + 2 < d) box_muller(w.w[2], w.w[3], z[2], z[3]);
-                else { z[2] = R(0); z[3] = R(0); }
+                box_muller(w.w[2], w.w[3], z[2], z[3]);
 #pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    const int l = 4 * b + h;
-                    if (l < D && l < d) {
-                        const R zl = sk * z[h];
+                for (int h = 0; h < 4; ++h) zs[4 * b + h] = sk * z[h];
+            }
+            corr_mfma<D>(reinterpret_cast<const float*>(cf), reinterpret_cast<const float(&)[D]>(zs),
+                         reinterpret_cast<float(&)[D]>(ls));
+        } else {
 #pragma unroll
-                        for (int i = l; i < D; ++i)
-                            if (i < d) ls[i] += S.A[i * D_MAX + l] * zl;
+            for (int b = 0; b < (D + 3) / 4; ++b) {
+                if (4 * b < dp) {
+                    const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, 0u);
+                    R z[4];
+                    box_muller(w.w[0], w.w[1], z[0], z[1]);
+                    if (4 * b + 2 < dp) box_muller(w.w[2], w.w[3], z[2], z[3]);
+                    else { z[2] = R(0); z[3] = R(0); }
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const int l = 4 * b + h;
+                        if (l < D && l < dp) {
+                            const R zl = sk * z[h];
+#pragma unroll
+                            for (int i = l; i < D; ++i) {
+                                if (i < dp) {
+                                    if constexpr (LC) ls[i] += cf[l * D + i] * zl;
+                                    else ls[i] += S.A[i * D_MAX + l] * zl;
+                                }
+                            }
+                        }
                     }
                 }
             }
         }
-        const R phi = payoff<D, R>(payk, d, K, inv_d, ls);
+        const R phi = payoff<D, R>(payk, dp, K, inv_d, ls);
         bool stop = (k == NT);
         if (!stop && phi > R(0)) {
-            const R* w = wt + k * W;
+            const R* w = wt + k * WL;
             if (a.method == CMC) {
-                stop = cmc_score<D, R>(d, w, lnK, phi * invK, ls) > R(0);
+                stop = cmc_score<D, R>(dp, w, lnK, phi * invK, ls) > R(0);
             } else {
                 if constexpr (D <= 16) {
                     const R bnd = iz_boundary<D, R>(d, w, lnK, ls);
@@ -122,13 +232,15 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
             }
         }
         if (stop) {
-            acc.add((double)phi * disc[k]);
-            steps += (uint32_t)(k - m);
+            if (live) {
+                acc.add((double)phi * disc[k]);
+                steps += (uint32_t)(k - m);
+            }
             p += blockDim.x;
             k = m + 1;
 #pragma unroll
             for (int i = 0; i < D; ++i)
-                if (i < d) ls[i] = lx[i];
+                if (i < dp) ls[i] = lx[i];
         } else {
             ++k;
         }
@@ -167,7 +279,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 template <int D, bool EXACT, class R, class ACC>
 __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
 {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     __shared__ double red[3][16];
     const uint32_t slot = blockIdx.x / a.nchunk;
     const uint32_t chunk = blockIdx.x - slot * a.nchunk;
@@ -185,7 +297,7 @@ template <int D, bool EXACT, class R, class ACC>
 __global__ void __launch_bounds__(256) k_cont_multi(const ContArgs* __restrict__ tasks,
                                                     const uint32_t* __restrict__ prefix, int ntasks, uint32_t job0)
 {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     __shared__ double red[3][16];
     const_as<uint32_t>* pre = as_const(prefix);
     const uint32_t job = job0 + blockIdx.x;
@@ -201,10 +313,28 @@ __global__ void __launch_bounds__(256) k_cont_multi(const ContArgs* __restrict__
     cont_job<D, EXACT, R, ACC>(a, slot, local - slot * a.nchunk, lds, red);
 }
 
+// Lets every kernel of bound D use the device's whole LDS (done once).
+template <int D, bool EXACT>
+bool cont_allow_lds()
+{
+    const int v = (int)cont_lds_limit();
+    const void* ks[] = {reinterpret_cast<const void*>(k_cont<D, EXACT, double, Acc<double>>),
+                        reinterpret_cast<const void*>(k_cont<D, EXACT, float, Acc<double>>),
+                        reinterpret_cast<const void*>(k_cont<D, EXACT, float, KahanAcc>),
+                        reinterpret_cast<const void*>(k_cont_multi<D, EXACT, double, Acc<double>>),
+                        reinterpret_cast<const void*>(k_cont_multi<D, EXACT, float, Acc<double>>),
+                        reinterpret_cast<const void*>(k_cont_multi<D, EXACT, float, KahanAcc>)};
+    for (const void* f : ks) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    (void)hipGetLastError();   // a refused attribute must not surface at the next launch check
+    return true;
+}
+
 template <int D, bool EXACT>
 hipError_t launch_cont_d(int prec, const ContArgs& a, int grid, int block, size_t lds,
                                 hipStream_t st)
 {
+    static const bool lds_ok = cont_allow_lds<D, EXACT>();
+    (void)lds_ok;
     if (prec == PREC_FP64)
         hipLaunchKernelGGL((k_cont<D, EXACT, double, Acc<double>>), dim3(grid), dim3(block), lds, st, a);
     else if (prec == PREC_FP32)
@@ -218,6 +348,8 @@ template <int D, bool EXACT>
 hipError_t launch_cont_multi_d(int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks, uint32_t job0,
                                uint32_t jobs, int block, size_t lds, hipStream_t st)
 {
+    static const bool lds_ok = cont_allow_lds<D, EXACT>();
+    (void)lds_ok;
     if (prec == PREC_FP64)
         hipLaunchKernelGGL((k_cont_multi<D, EXACT, double, Acc<double>>), dim3(jobs), dim3(block), lds, st, tasks,
                            prefix, ntasks, job0);

@@ -69,9 +69,36 @@ struct LaunchCfg {
 hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st);
 hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, size_t lds,
                        hipStream_t st);
-size_t cont_lds_bytes(int prec, int n_dates, int width);
-// Template bucket of dimension d (exact for d <= 8).
+// Dimension buckets: d <= 8 has its own instantiation (correlation
+// coefficients in scalar registers); larger d share a bound D with
+// dim_floor(D) < d <= D (multiples of 4 up to 40, then of 8), keep the
+// coefficient tables in LDS, and in FP32 run the correlation on the matrix
+// cores.
+__host__ __device__ constexpr int dim_floor(int D) { return D <= 8 ? D - 1 : (D <= 40 ? D - 4 : D - 8); }
 int cont_bucket(int d);
+
+// LDS bytes of a continuation job: discount table (double), then in the
+// stepping precision: log-point [D_MAX], dt and sqrt(dt) [NT+1], rule rows
+// [(NT+1) W], and for D >= 12 the correlation coefficients [D][D] (16-byte
+// aligned, at *coef_off) and the drifts [D].
+// Row stride of the rule rows in LDS: bucket kernels pad classifier rows to
+// 2D+3 (zero weights for the padded assets).
+__host__ __device__ inline int cont_rule_stride(int D, int width)
+{
+    return D >= 12 && width < 2 * D + 3 ? 2 * D + 3 : width;
+}
+__host__ __device__ inline size_t cont_lds_layout(size_t rsize, int D, int n_dates, int width, size_t* coef_off)
+{
+    size_t off = sizeof(double) * (n_dates + 1) +
+                 rsize * (D_MAX + 2 * (size_t)(n_dates + 1) + (size_t)(n_dates + 1) * cont_rule_stride(D, width));
+    off = (off + 15) & ~(size_t)15;
+    if (coef_off) *coef_off = off;
+    if (D >= 12) off += rsize * ((size_t)D * D + D);
+    return off + 16;
+}
+size_t cont_lds_bytes(int prec, int d, int n_dates, int width);
+// Dynamic LDS a continuation workgroup may use on the current device.
+size_t cont_lds_limit();
 // One launch over jobs job0 .. job0+jobs-1 of many tasks of one bucket;
 // prefix[t] is the first job of task t, prefix[ntasks] the total.
 hipError_t launch_cont_multi(int bucket, int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks,

@@ -97,72 +97,63 @@ template <int D, bool EXACT>
 hipError_t launch_cont_d(int prec, const ContArgs& a, int grid, int block, size_t lds,
                          hipStream_t st);
 
-size_t cont_lds_bytes(int prec, int n_dates, int width)
+int cont_bucket(int d)
+{
+    if (d <= 8) return d;
+    if (d <= 40) return (d + 3) / 4 * 4;
+    return (d + 7) / 8 * 8;
+}
+
+size_t cont_lds_bytes(int prec, int d, int n_dates, int width)
 {
     const size_t rs = prec == PREC_FP64 ? sizeof(double) : sizeof(float);
-    return sizeof(double) * (n_dates + 1) +
-           rs * (D_MAX + 2 * (size_t)(n_dates + 1) + (size_t)(n_dates + 1) * width) + 16;
+    return cont_lds_layout(rs, cont_bucket(d), n_dates, width, nullptr);
 }
+
+size_t cont_lds_limit()
+{
+    static size_t limit = 0;
+    if (limit == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 64 * 1024;
+        limit = (size_t)v - 1024;   // the kernels' static LDS (wave partials) stays below 1 KB
+    }
+    return limit;
+}
+
+#define BMC_BUCKETS(X)                                                                                    \
+    X(1, true) X(2, true) X(3, true) X(4, true) X(5, true) X(6, true) X(7, true) X(8, true) X(12, false)   \
+    X(16, false) X(20, false) X(24, false) X(28, false) X(32, false) X(36, false) X(40, false) X(48, false) \
+    X(56, false) X(64, false)
 
 hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, size_t lds,
                        hipStream_t st)
 {
-    switch (d) {
-    case 1: return launch_cont_d<1, true>(prec, a, grid, block, lds, st);
-    case 2: return launch_cont_d<2, true>(prec, a, grid, block, lds, st);
-    case 3: return launch_cont_d<3, true>(prec, a, grid, block, lds, st);
-    case 4: return launch_cont_d<4, true>(prec, a, grid, block, lds, st);
-    case 5: return launch_cont_d<5, true>(prec, a, grid, block, lds, st);
-    case 6: return launch_cont_d<6, true>(prec, a, grid, block, lds, st);
-    case 7: return launch_cont_d<7, true>(prec, a, grid, block, lds, st);
-    case 8: return launch_cont_d<8, true>(prec, a, grid, block, lds, st);
-    default: break;
+#define BMC_ONE(DD, EX) \
+    case DD: return launch_cont_d<DD, EX>(prec, a, grid, block, lds, st);
+    switch (cont_bucket(d)) {
+        BMC_BUCKETS(BMC_ONE)
+    default: return hipErrorInvalidValue;
     }
-    if (d <= 12) return launch_cont_d<12, false>(prec, a, grid, block, lds, st);
-    if (d <= 16) return launch_cont_d<16, false>(prec, a, grid, block, lds, st);
-    if (d <= 24) return launch_cont_d<24, false>(prec, a, grid, block, lds, st);
-    if (d <= 32) return launch_cont_d<32, false>(prec, a, grid, block, lds, st);
-    if (d <= 40) return launch_cont_d<40, false>(prec, a, grid, block, lds, st);
-    return launch_cont_d<64, false>(prec, a, grid, block, lds, st);
+#undef BMC_ONE
 }
 
 template <int D, bool EXACT>
 hipError_t launch_cont_multi_d(int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks, uint32_t job0,
                                uint32_t jobs, int block, size_t lds, hipStream_t st);
 
-int cont_bucket(int d)
-{
-    if (d <= 8) return d;
-    if (d <= 12) return 12;
-    if (d <= 16) return 16;
-    if (d <= 24) return 24;
-    if (d <= 32) return 32;
-    if (d <= 40) return 40;
-    return 64;
-}
-
 hipError_t launch_cont_multi(int bucket, int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks,
                              uint32_t job0, uint32_t jobs, int block, size_t lds, hipStream_t st)
 {
-#define BMC_MULTI(DD, EX) return launch_cont_multi_d<DD, EX>(prec, tasks, prefix, ntasks, job0, jobs, block, lds, st)
+#define BMC_ONE(DD, EX) \
+    case DD: return launch_cont_multi_d<DD, EX>(prec, tasks, prefix, ntasks, job0, jobs, block, lds, st);
     switch (bucket) {
-    case 1: BMC_MULTI(1, true);
-    case 2: BMC_MULTI(2, true);
-    case 3: BMC_MULTI(3, true);
-    case 4: BMC_MULTI(4, true);
-    case 5: BMC_MULTI(5, true);
-    case 6: BMC_MULTI(6, true);
-    case 7: BMC_MULTI(7, true);
-    case 8: BMC_MULTI(8, true);
-    case 12: BMC_MULTI(12, false);
-    case 16: BMC_MULTI(16, false);
-    case 24: BMC_MULTI(24, false);
-    case 32: BMC_MULTI(32, false);
-    case 40: BMC_MULTI(40, false);
-    case 64: BMC_MULTI(64, false);
+        BMC_BUCKETS(BMC_ONE)
     default: return hipErrorInvalidValue;
     }
-#undef BMC_MULTI
+#undef BMC_ONE
 }
 
 // Continuation estimate C = sum/n and its standard error sqrt(var/n), with

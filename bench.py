@@ -40,6 +40,20 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 COST = {"int": 0.6, "mul64": 1.15, "trans": 1.9, "f32": 1.0}
 
 
+# FP32 dense matrix-core peak of MI355X (TFLOP/s).
+PEAK_MFMA_F32 = 157.3e12
+
+
+def uses_mfma(d: int) -> bool:
+    """FP32 kernels for d > 8 run the correlation on the matrix cores."""
+    return d > 8
+
+
+def mfma_flops_per_step(d: int) -> float:
+    """Algorithmic flops of the correlation product A (s z) per path-step."""
+    return float(d * (d + 1))
+
+
 def slots_per_step_fp32(d: int, payoff: int, method: int) -> float:
     """Algorithmic VALU issue slots of one inner path-step (FP32 form).
 
@@ -51,14 +65,17 @@ def slots_per_step_fp32(d: int, payoff: int, method: int) -> float:
     arithmetic basket d exps plus d+3.  CMC rule: d subtractions, 2d FMAs, 4
     more for g and the comparison; I&Z boundary: q + q(q+1)/2 FMAs and
     q(q+1)/2 products (q = d-1).  Per path (amortised over its steps and left
-    out): the FP64 accumulation of the payoff.
+    out): the FP64 accumulation of the payoff.  For d > 8 the correlation
+    runs on the matrix cores and is left out of the VALU count (reported as
+    matrix-core flops, mfma_flops_per_step).
     """
     blocks = (d + 3) // 4
     pairs = (d + 1) // 2
     philox = blocks * 10 * (2 * COST["mul64"] + 4 * COST["int"])
     bm = pairs * (4 * COST["f32"] + COST["trans"] + COST["f32"] + COST["trans"] + 2 * COST["trans"]
                   + 2 * COST["f32"])
-    step = (d + d * (d + 1) / 2 + d) * COST["f32"]
+    corr = 0 if uses_mfma(d) else d * (d + 1) / 2
+    step = (d + corr + d) * COST["f32"]
     if payoff == 0:
         pay = d * COST["trans"] + (d + 3) * COST["f32"]
     else:
@@ -145,6 +162,7 @@ def batch_form(ctx, bmc, inputs, count: int, N: int, n_final: int) -> dict:
     steps32 = sum(r["inner_path_steps"] for r in r32)
     steps64 = sum(r["inner_path_steps"] for r in r64)
     slots = sum(slots_per_step_fp32(s.d, s.payoff, bmc.CMC) * r["inner_path_steps"] for s, r in zip(specs, r32))
+    mflops = sum(mfma_flops_per_step(s.d) * r["inner_path_steps"] for s, r in zip(specs, r32) if uses_mfma(s.d))
     calc = r32[0]["calc_seconds"]
     dist = np.array([abs(a["price"] - b["price"]) / b["std_err"] for a, b in zip(r32, r64)])
     return {"workload": f"{count} uneven options (d 1-20, 4-50 dates, n in 1k/4k/16k, Wishart rho, "
@@ -153,7 +171,9 @@ def batch_form(ctx, bmc, inputs, count: int, N: int, n_final: int) -> dict:
                      "phase_s": {"calc": calc, "fit": r32[0]["fit_seconds"], "final": r32[0]["final_seconds"]}},
             "fp64": {"value": steps64 / t64, "seconds": t64, "inner_path_steps": steps64},
             "unit": "path-steps/s",
-            "fp32_slot_frac_of_peak": slots / calc / PEAK_SLOTS,
+            "fp32_valu_slot_frac_of_peak": slots / calc / PEAK_SLOTS,
+            "fp32_mfma_tflops": mflops / calc / 1e12,
+            "fp32_mfma_frac_of_peak": mflops / calc / PEAK_MFMA_F32,
             "fp32_vs_fp64_price_in_std_err": {"median": float(np.median(dist)), "max": float(dist.max()),
                                               "frac_within_0.1": float(np.mean(dist <= 0.1))}}
 

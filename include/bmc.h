@@ -139,6 +139,18 @@ bmc_status bmc_price(bmc_ctx *ctx, const bmc_spec *spec, const bmc_opts *opts,
 bmc_status bmc_price_batch(bmc_ctx *ctx, int32_t count, const bmc_spec *specs, const bmc_opts *opts,
                            bmc_rules **rules_out, bmc_result *results);
 
+/* Launch shape of the continuation kernel: each workgroup job takes 256*ppt
+ * paths of one point (ppt = paths per lane, 1..64).  The shape fixes the
+ * order of the floating-point sums, so prices with different shapes agree to
+ * the parity tolerance but not bit for bit; every call on a context uses
+ * the context's table, so a price is the same alone and in a batch.
+ * bmc_tuning_set keys an entry by dimension bucket (d = 0: any), precision
+ * (-1: any) and n rounded up to a power of two (n = 0: any); ppt = 0 removes
+ * the entry.  Without an entry a heuristic picks ppt from N and n.
+ * bmc_tuning_get returns the shape a call with (d, precision, N, n) uses. */
+bmc_status bmc_tuning_set(bmc_ctx *ctx, int32_t d, int32_t precision, int64_t n, int32_t ppt);
+bmc_status bmc_tuning_get(bmc_ctx *ctx, int32_t d, int32_t precision, int64_t N, int64_t n, int32_t *ppt);
+
 /* Exercise-rule table of one spec and method: one row of width w per date
  * (rows 1..N_T-1 used).  CMC (Section 3.2): F(x) = sum_f w_f phi_f(x) with
  * phi = [1, u_1..u_d, u_1^2..u_d^2, g, g^2], u_i = ln(S_i/K), g = Phi(S)/K;

@@ -27,6 +27,7 @@ SYMBOLS = [
     "bmc_rules_create", "bmc_rules_destroy", "bmc_rules_width", "bmc_rules_set", "bmc_rules_get",
     "bmc_rules_export", "bmc_rules_import", "bmc_sample_points", "bmc_estimate_continuation",
     "bmc_fit_rule", "bmc_iz_search", "bmc_final_price", "bmc_philox", "bmc_normals", "bmc_price_batch",
+    "bmc_tuning_set", "bmc_tuning_get",
 ]
 
 
@@ -83,6 +84,8 @@ def load():
     L.bmc_sync.argtypes = [vp]
     L.bmc_price.argtypes = [vp, sp, C.POINTER(bmc_opts), C.POINTER(vp), C.POINTER(bmc_result)]
     L.bmc_price_batch.argtypes = [vp, C.c_int32, sp, C.POINTER(bmc_opts), C.POINTER(vp), C.POINTER(bmc_result)]
+    L.bmc_tuning_set.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int32]
+    L.bmc_tuning_get.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.POINTER(C.c_int32)]
     L.bmc_rules_create.argtypes = [vp, sp, C.c_int32, C.POINTER(vp)]
     L.bmc_rules_destroy.argtypes = [vp]
     L.bmc_rules_destroy.restype = None
@@ -241,6 +244,16 @@ def bmc_price_batch(ctx: Context, specs, opts, want_rules: bool = False):
     if want_rules:
         return out, [Rules(C.c_void_p(rh[i]), ss[i].n_dates) for i in range(count)]
     return out
+
+
+def bmc_tuning_set(ctx: Context, d: int = 0, precision: int = -1, n: int = 0, ppt: int = 0) -> None:
+    _check(load().bmc_tuning_set(ctx.h, d, precision, n, ppt))
+
+
+def bmc_tuning_get(ctx: Context, d: int, precision: int, N: int, n: int) -> int:
+    v = C.c_int32(0)
+    _check(load().bmc_tuning_get(ctx.h, d, precision, N, n, C.byref(v)))
+    return int(v.value)
 
 
 def bmc_rules_create(ctx: Context, spec, method: int) -> Rules:

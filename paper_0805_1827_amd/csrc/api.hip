@@ -391,15 +391,58 @@ static bmc_status check_seed(uint64_t seed)
 // ---------------------------------------------------------------------------
 // Continuation launches
 
-uint32_t bmc::choose_ppt(int64_t points, int64_t n, const Tuning* tune)
+int bmc::n_class(int64_t n)
+{
+    int c = 0;
+    while (c < 40 && ((int64_t)1 << c) < n) ++c;
+    return c + 1;   // 1 + ceil(log2 n); 0 is the wildcard
+}
+
+uint64_t bmc::ppt_key(int bucket, int prec_plus1, int nclass)
+{
+    return ((uint64_t)(uint32_t)bucket << 32) | ((uint64_t)(uint32_t)prec_plus1 << 16) | (uint64_t)(uint32_t)nclass;
+}
+
+uint32_t bmc::choose_ppt(const bmc_ctx* ctx, int d, int prec, int64_t points, int64_t n, const Tuning* tune)
 {
     if (tune && tune->ppt > 0) return (uint32_t)tune->ppt;
+    if (ctx && !ctx->ppt_table.empty()) {
+        const int b = cont_bucket(d), pr = prec + 1, c = n_class(n);
+        for (int mask = 0; mask < 8; ++mask) {   // exact key first, then wildcards
+            const uint64_t k = ppt_key(mask & 4 ? 0 : b, mask & 2 ? 0 : pr, mask & 1 ? 0 : c);
+            auto it = ctx->ppt_table.find(k);
+            if (it != ctx->ppt_table.end()) return (uint32_t)it->second;
+        }
+    }
     // enough lanes to fill 256 CUs x 2048 resident lanes, then longer chunks
     const double lanes = 256.0 * 2048.0;
     const double per_lane = (double)points * (double)n / lanes;
     uint32_t ppt = 1;
     while (ppt < 16 && (double)(ppt * 2) <= per_lane) ppt *= 2;
     return ppt;
+}
+
+extern "C" bmc_status bmc_tuning_set(bmc_ctx* ctx, int32_t d, int32_t precision, int64_t n, int32_t ppt)
+{
+    if (!ctx) return fail(BMC_EINVAL, "NULL argument");
+    if (d < 0 || d > BMC_D_MAX) return fail(BMC_EINVAL, "d = %d outside 0..%d", d, BMC_D_MAX);
+    if (precision < -1 || precision > BMC_FP32_KAHAN) return fail(BMC_EINVAL, "unknown precision %d", precision);
+    if (n < 0 || n > 0x7FFFFFFF) return fail(BMC_EINVAL, "n out of range");
+    if (ppt < 0 || ppt > 64) return fail(BMC_EINVAL, "ppt = %d outside 0..64", ppt);
+    const uint64_t k = ppt_key(d ? cont_bucket(d) : 0, precision + 1, n ? n_class(n) : 0);
+    if (ppt == 0) ctx->ppt_table.erase(k);
+    else ctx->ppt_table[k] = ppt;
+    return BMC_OK;
+}
+
+extern "C" bmc_status bmc_tuning_get(bmc_ctx* ctx, int32_t d, int32_t precision, int64_t N, int64_t n, int32_t* ppt)
+{
+    if (!ctx || !ppt) return fail(BMC_EINVAL, "NULL argument");
+    if (d < 1 || d > BMC_D_MAX) return fail(BMC_EINVAL, "d = %d outside 1..%d", d, BMC_D_MAX);
+    if (precision < BMC_FP64 || precision > BMC_FP32_KAHAN) return fail(BMC_EINVAL, "unknown precision %d", precision);
+    if (N < 1 || n < 1) return fail(BMC_EINVAL, "N and n must be positive");
+    *ppt = (int32_t)choose_ppt(ctx, d, precision, N, n, nullptr);
+    return BMC_OK;
 }
 
 bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int method,
@@ -410,7 +453,7 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
                          const Tuning* tune)
 {
     const int block = (tune && tune->block > 0) ? tune->block : 256;
-    const uint32_t ppt = choose_ppt(N, n, tune);
+    const uint32_t ppt = choose_ppt(ctx, d, prec, N, n, tune);
     const uint32_t per_wg = (uint32_t)block * ppt;
     const uint32_t nchunk = (n + per_wg - 1) / per_wg;
     const size_t part_bytes = sizeof(double) * 3 * (size_t)N * nchunk;

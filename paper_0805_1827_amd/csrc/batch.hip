@@ -112,9 +112,9 @@ extern "C" bmc_status bmc_price_batch(bmc_ctx* ctx, int32_t count, const bmc_spe
         q.n = (uint32_t)opts[i].n;
         q.n_final = (uint32_t)opts[i].n_final;
         q.seed = (uint32_t)opts[i].seed;
-        q.per_wg = 256u * choose_ppt(q.N, q.n, nullptr);
+        q.per_wg = 256u * choose_ppt(ctx, q.d, q.prec, q.N, q.n, nullptr);
         q.nchunk = (q.n + q.per_wg - 1) / q.per_wg;
-        q.fper_wg = 256u * choose_ppt(1, q.n_final, nullptr);
+        q.fper_wg = 256u * choose_ppt(ctx, q.d, q.prec, 1, q.n_final, nullptr);
         q.fnchunk = (q.n_final + q.fper_wg - 1) / q.fper_wg;
         q.lds = cont_lds_bytes(q.prec, q.d, q.NT, q.p);
         if (q.lds > cont_lds_limit()) return fail(BMC_EUNSUPPORTED, "option %d: rule table too large for LDS", i);

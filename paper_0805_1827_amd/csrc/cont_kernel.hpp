@@ -68,8 +68,8 @@ __device__ __forceinline__ void corr_mfma(const float* __restrict__ arow, const 
     }
 }
 
-template <int D, class R> constexpr bool uses_mfma() { return D >= 12 && sizeof(R) == 4; }
-template <int D> constexpr bool uses_lds_coef() { return D >= 12; }
+template <int D, class R> constexpr bool uses_mfma() { return D >= 9 && sizeof(R) == 4; }
+template <int D> constexpr bool uses_lds_coef() { return D >= 9; }
 
 // One (point j, chunk) job of a continuation launch, run by a whole block;
 // lds: the dynamic table area, red: [3][16] wave partials.
@@ -79,12 +79,14 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 {
     constexpr bool MF = uses_mfma<D, R>();
     constexpr bool LC = uses_lds_coef<D>();
+    constexpr int D4 = (D + 3) & ~3;   // matrix-core chunks of four assets
     // Bucket kernels (d < D possible) pad the path state to D entries with
     // neutral values, so that every per-asset loop runs to D without tests:
     // zero coefficients and drifts, log-prices 0 (geometric put) or -1e30
     // (max-call and arithmetic basket: no effect on a maximum or a sum of
     // exponentials), zero classifier weights.
     constexpr bool PAD = !EXACT;
+    static_assert(EXACT || D % 4 == 0, "padded bounds are multiples of four");
     const_as<SpecT<R>>& S = *as_const(&spec_of<R>(a.spec));
     const int d = EXACT ? D : S.d;
     if (!EXACT) __builtin_assume(d > dim_floor(D) && d <= D);
@@ -101,8 +103,8 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
     size_t coef_off = 0;
     (void)cont_lds_layout(sizeof(R), D, NT, W, &coef_off);
     const int payk = S.payoff;
-    R* coef = reinterpret_cast<R*>(reinterpret_cast<char*>(lds) + coef_off);   // [D][D]
-    R* drift = coef + D * D;                                                   // [D]
+    R* coef = reinterpret_cast<R*>(reinterpret_cast<char*>(lds) + coef_off);   // [D4][D4]
+    R* drift = coef + D4 * D4;                                                 // [D4]
 
     const_as<double>* t64 = as_const(a.spec)->f64.t;
     const double r64 = as_const(a.spec)->f64.r;
@@ -133,11 +135,11 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
     if constexpr (LC) {
         // FP32: row-major A[i][l] (matrix-core operand rows); FP64: column-major
         // A[l][i] (consecutive rows of one column in one read).  Zero beyond d.
-        for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
-            const int i = MF ? e / D : e % D, l = MF ? e % D : e / D;
+        for (int e = threadIdx.x; e < D4 * D4; e += blockDim.x) {
+            const int i = MF ? e / D4 : e % D4, l = MF ? e % D4 : e / D4;
             coef[e] = (i < d && l <= i) ? S.A[i * D_MAX + l] : R(0);
         }
-        for (int i = threadIdx.x; i < D; i += blockDim.x) drift[i] = i < d ? S.drift[i] : R(0);
+        for (int i = threadIdx.x; i < D4; i += blockDim.x) drift[i] = i < d ? S.drift[i] : R(0);
     }
     __syncthreads();
 
@@ -150,9 +152,9 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 
     // dp: the extent of the per-asset loops (D for padded buckets)
     const int dp = PAD ? D : d;
-    R ls[D];
+    R ls[D4];
 #pragma unroll
-    for (int i = 0; i < D; ++i) ls[i] = (i < dp) ? lx[i] : R(0);
+    for (int i = 0; i < D4; ++i) ls[i] = (i < dp) ? lx[i] : R(0);
 
     ACC acc;
     uint32_t steps = 0;
@@ -180,18 +182,18 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
         }
         const uint32_t c0 = (uint32_t)k * nb;
         if constexpr (MF) {
-            R zs[D];
+            R zs[D4];
 #pragma unroll
-            for (int b = 0; b < D / 4; ++b) {
-                R z[4];
+            for (int b = 0; b < D4 / 4; ++b) {
+                R z[4] = {R(0), R(0), R(0), R(0)};
                 const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, 0u);
                 box_muller(w.w[0], w.w[1], z[0], z[1]);
-                box_muller(w.w[2], w.w[3], z[2], z[3]);
+                if (4 * b + 2 < dp) box_muller(w.w[2], w.w[3], z[2], z[3]);
 #pragma unroll
-                for (int h = 0; h < 4; ++h) zs[4 * b + h] = sk * z[h];
+                for (int h = 0; h < 4; ++h) zs[4 * b + h] = 4 * b + h < dp ? sk * z[h] : R(0);
             }
-            corr_mfma<D>(reinterpret_cast<const float*>(cf), reinterpret_cast<const float(&)[D]>(zs),
-                         reinterpret_cast<float(&)[D]>(ls));
+            corr_mfma<D4>(reinterpret_cast<const float*>(cf), reinterpret_cast<const float(&)[D4]>(zs),
+                          reinterpret_cast<float(&)[D4]>(ls));
         } else {
 #pragma unroll
             for (int b = 0; b < (D + 3) / 4; ++b) {
@@ -209,7 +211,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 #pragma unroll
                             for (int i = l; i < D; ++i) {
                                 if (i < dp) {
-                                    if constexpr (LC) ls[i] += cf[l * D + i] * zl;
+                                    if constexpr (LC) ls[i] += cf[l * D4 + i] * zl;
                                     else ls[i] += S.A[i * D_MAX + l] * zl;
                                 }
                             }
@@ -218,15 +220,15 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
                 }
             }
         }
-        const R phi = payoff<D, R>(payk, dp, K, inv_d, ls);
+        const R phi = payoff<D4, R>(payk, dp, K, inv_d, ls);
         bool stop = (k == NT);
         if (!stop && phi > R(0)) {
             const R* w = wt + k * WL;
             if (a.method == CMC) {
-                stop = cmc_score<D, R>(dp, w, lnK, phi * invK, ls) > R(0);
+                stop = cmc_score<D4, R>(dp, w, lnK, phi * invK, ls) > R(0);
             } else {
                 if constexpr (D <= 16) {
-                    const R bnd = iz_boundary<D, R>(d, w, lnK, ls);
+                    const R bnd = iz_boundary<D4, R>(d, w, lnK, ls);
                     stop = call_dir ? (ls[0] > bnd) : (ls[0] < bnd);
                 }
             }

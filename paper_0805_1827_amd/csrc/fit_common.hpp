@@ -82,62 +82,71 @@ __device__ __forceinline__ double bcast_lane(double v, int src)
 // The same factorisation and substitutions by one wavefront (the calling
 // threads must be lanes 0..63 of one wave, all active): lane i keeps row i
 // of the factor in registers and the columns travel by lane broadcasts,
-// with no block barrier.  Same per-entry subtraction order as above.
+// with no block barrier.  Same per-entry subtraction order as above; the
+// divisions by a pivot become products with its reciprocal (one division
+// per column).  A (packed, in LDS) is overwritten with the factor.
 // Returns false (on every lane) if a pivot is not positive.
 template <int P>
-__device__ bool wave_spd_solve(int p, const double* A, double lam, const double* b, double* x)
+__device__ bool wave_spd_solve(int p, double* A, double lam, const double* b, double* x)
 {
     const int lane = threadIdx.x & 63;
+    // lane i holds row i of A + lam I; rows p..P-1 are the identity, so every
+    // column runs without tests
     double row[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-        row[k] = (lane < p && k <= lane) ? A[tri(lane, k)] : 0.0;
-        if (k == lane) row[k] += lam;
+        double v = (lane < p && k <= lane) ? A[tri(lane, k)] : 0.0;
+        if (k == lane) v += lane < p ? lam : 1.0;
+        row[k] = v;
     }
     bool ok = true;
+    double invd = 1.0;   // lane c: 1 / L_cc
 #pragma unroll
     for (int c = 0; c < P; ++c) {
-        if (c < p) {
-            double dc = bcast_lane(row[c], c);
-            if (!(dc > 0.0)) {
-                ok = false;
-                dc = 1.0;
-            }
-            const double lcc = sqrt(dc);
-            if (lane == c) row[c] = lcc;
-            else if (lane > c) row[c] = row[c] / lcc;
+        double dc = bcast_lane(row[c], c);
+        if (!(dc > 0.0)) {
+            ok = false;
+            dc = 1.0;
+        }
+        const double lcc = sqrt(dc);
+        const double inv = 1.0 / lcc;
+        if (lane == c) {
+            row[c] = lcc;
+            invd = inv;
+        } else if (lane > c) {
+            row[c] *= inv;
+        }
 #pragma unroll
-            for (int l = c + 1; l < P; ++l) {
-                if (l < p) {
-                    const double llc = bcast_lane(row[c], l);
-                    if (lane >= l) row[l] -= row[c] * llc;
-                }
-            }
+        for (int l = c + 1; l < P; ++l) {
+            const double llc = bcast_lane(row[c], l);
+            if (lane >= l) row[l] -= row[c] * llc;
         }
     }
+    // forward substitution L y = b
     double y = lane < p ? b[lane] : 0.0;
 #pragma unroll
     for (int c = 0; c < P; ++c) {
-        if (c < p) {
-            const double yc = bcast_lane(y, c) / bcast_lane(row[c], c);
-            if (lane == c) y = yc;
-            else if (lane > c) y -= row[c] * yc;
-        }
+        const double yc = bcast_lane(y, c) * bcast_lane(invd, c);
+        if (lane == c) y = yc;
+        else if (lane > c) y -= row[c] * yc;
     }
+    // L back into the packed triangle; each lane then reads its column, so
+    // that the back substitution L^T x = y needs no per-entry broadcasts
+    if (lane < p) {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            if (k <= lane) A[tri(lane, k)] = row[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+    double col[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) col[c] = (lane < p && c >= lane && c < p) ? A[tri(c, lane)] : 0.0;
     double xv = 0.0;
 #pragma unroll
     for (int c = P - 1; c >= 0; --c) {
-        if (c < p) {
-            const double xc = bcast_lane(y, c) / bcast_lane(row[c], c);
-            if (lane == c) xv = xc;
-            double lci = 0.0;
-#pragma unroll
-            for (int k = 0; k < c; ++k) {
-                const double t = bcast_lane(row[k], c);
-                if (lane == k) lci = t;
-            }
-            if (lane < c) y -= lci * xc;
-        }
+        const double xc = bcast_lane(y, c) * bcast_lane(invd, c);
+        if (lane == c) xv = xc;
+        if (lane < c) y -= col[c] * xc;
     }
     if (lane < p) x[lane] = xv;
     return ok;

@@ -69,31 +69,35 @@ struct LaunchCfg {
 hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st);
 hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, size_t lds,
                        hipStream_t st);
-// Dimension buckets: d <= 8 has its own instantiation (correlation
-// coefficients in scalar registers); larger d share a bound D with
-// dim_floor(D) < d <= D (multiples of 4 up to 40, then of 8), keep the
-// coefficient tables in LDS, and in FP32 run the correlation on the matrix
-// cores.
-__host__ __device__ constexpr int dim_floor(int D) { return D <= 8 ? D - 1 : (D <= 40 ? D - 4 : D - 8); }
+// Dimension buckets: every d <= 32 has its own instantiation (bucket_exact);
+// larger d share a bound D with dim_floor(D) < d <= D (36, 40, then
+// multiples of 8) and pad the path state to D.  For d >= 9 the correlation
+// coefficients live in LDS and, in FP32, the correlation runs on the matrix
+// cores in chunks of four assets.
+__host__ __device__ constexpr bool bucket_exact(int D) { return D <= 32; }
+__host__ __device__ constexpr int dim_floor(int D) { return bucket_exact(D) ? D - 1 : (D <= 40 ? D - 4 : D - 8); }
 int cont_bucket(int d);
+
+// Row stride of the rule rows in LDS: padded buckets widen classifier rows
+// to 2D+3 (zero weights for the padded assets).
+__host__ __device__ inline int cont_rule_stride(int D, int width)
+{
+    return !bucket_exact(D) && width < 2 * D + 3 ? 2 * D + 3 : width;
+}
 
 // LDS bytes of a continuation job: discount table (double), then in the
 // stepping precision: log-point [D_MAX], dt and sqrt(dt) [NT+1], rule rows
-// [(NT+1) W], and for D >= 12 the correlation coefficients [D][D] (16-byte
-// aligned, at *coef_off) and the drifts [D].
-// Row stride of the rule rows in LDS: bucket kernels pad classifier rows to
-// 2D+3 (zero weights for the padded assets).
-__host__ __device__ inline int cont_rule_stride(int D, int width)
-{
-    return D >= 12 && width < 2 * D + 3 ? 2 * D + 3 : width;
-}
+// [(NT+1) stride], and for D >= 9 the correlation coefficients [D4][D4]
+// (D4 = D rounded up to a multiple of 4; 16-byte aligned, at *coef_off)
+// and the drifts [D4].
 __host__ __device__ inline size_t cont_lds_layout(size_t rsize, int D, int n_dates, int width, size_t* coef_off)
 {
     size_t off = sizeof(double) * (n_dates + 1) +
                  rsize * (D_MAX + 2 * (size_t)(n_dates + 1) + (size_t)(n_dates + 1) * cont_rule_stride(D, width));
     off = (off + 15) & ~(size_t)15;
     if (coef_off) *coef_off = off;
-    if (D >= 12) off += rsize * ((size_t)D * D + D);
+    const size_t D4 = (size_t)((D + 3) & ~3);
+    if (D >= 9) off += rsize * (D4 * D4 + D4);
     return off + 16;
 }
 size_t cont_lds_bytes(int prec, int d, int n_dates, int width);

@@ -99,7 +99,7 @@ hipError_t launch_cont_d(int prec, const ContArgs& a, int grid, int block, size_
 
 int cont_bucket(int d)
 {
-    if (d <= 8) return d;
+    if (d <= 32) return d;
     if (d <= 40) return (d + 3) / 4 * 4;
     return (d + 7) / 8 * 8;
 }
@@ -123,10 +123,12 @@ size_t cont_lds_limit()
     return limit;
 }
 
-#define BMC_BUCKETS(X)                                                                                    \
-    X(1, true) X(2, true) X(3, true) X(4, true) X(5, true) X(6, true) X(7, true) X(8, true) X(12, false)   \
-    X(16, false) X(20, false) X(24, false) X(28, false) X(32, false) X(36, false) X(40, false) X(48, false) \
-    X(56, false) X(64, false)
+#define BMC_BUCKETS(X)  \
+    X(1, true) X(2, true) X(3, true) X(4, true) X(5, true) X(6, true) X(7, true) X(8, true) \
+     X(9, true) X(10, true) X(11, true) X(12, true) X(13, true) X(14, true) X(15, true) X(16, true) \
+     X(17, true) X(18, true) X(19, true) X(20, true) X(21, true) X(22, true) X(23, true) X(24, true) \
+     X(25, true) X(26, true) X(27, true) X(28, true) X(29, true) X(30, true) X(31, true) X(32, true) \
+     X(36, false) X(40, false) X(48, false) X(56, false) X(64, false)
 
 hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, size_t lds,
                        hipStream_t st)

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <map>
+
 #include "bmc.h"
 
 namespace bmc {
@@ -43,6 +45,9 @@ struct bmc_ctx {
     bmc::DBuf bspec, barena, btab;
     void* bhost = nullptr;
     size_t bhost_bytes = 0;
+    // continuation launch shapes (paths per lane per job) by (dimension
+    // bucket, precision, log2 n class); 0 fields are wildcards
+    std::map<uint64_t, int> ppt_table;
     ~bmc_ctx();
 };
 
@@ -58,7 +63,9 @@ namespace bmc {
 bmc_status upload_spec(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot);
 void pack_spec(const bmc_spec* s, HostSpecPack* p);
 const double* dev_S0(const void* devspec);
-uint32_t choose_ppt(int64_t points, int64_t n, const Tuning* tune);
+uint32_t choose_ppt(const bmc_ctx* ctx, int d, int prec, int64_t points, int64_t n, const Tuning* tune);
+uint64_t ppt_key(int bucket, int prec_plus1, int nclass);
+int n_class(int64_t n);
 bmc_status run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int method, int width,
                     const void* rules64, const void* rules32, int prec, int m, const double* x,
                     int64_t N, const int32_t* ids, const int32_t* n_ids, uint32_t n, uint32_t k0,

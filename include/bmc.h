@@ -151,6 +151,48 @@ bmc_status bmc_price_batch(bmc_ctx *ctx, int32_t count, const bmc_spec *specs, c
 bmc_status bmc_tuning_set(bmc_ctx *ctx, int32_t d, int32_t precision, int64_t n, int32_t ppt);
 bmc_status bmc_tuning_get(bmc_ctx *ctx, int32_t d, int32_t precision, int64_t N, int64_t n, int32_t *ppt);
 
+/* Serving loop (continuous batching).  A server owns a device arena of
+ * hbm_budget bytes and a thread that runs rounds of the batched engine: each
+ * round advances every request on the device by one stage (one date to
+ * learn, or the final pricing) in shared launches.  Between rounds, queued
+ * requests are admitted first come first served while their device
+ * footprint (points, paths' partial sums, fit scratch, rule tables) fits
+ * the arena and fewer than max_inflight are on the device; requests that
+ * arrive while others run join them as memory and slots free up.  Learned
+ * rule tables stay on the device in an LRU cache (rule_cache entries, in the
+ * arena) keyed by spec, precision, N, n, seed, boosting rounds and launch
+ * shape; a request that hits it runs only its final pricing.  Requests are
+ * CMC (bmc_opts.method = BMC_CMC).  Every result is bit-identical to
+ * bmc_price on the server's context; in a result, seconds = submission to
+ * completion and calc_seconds = time queued before admission.  The server
+ * uses ctx's device and launch-shape table (copied at creation) and its own
+ * stream; ctx stays usable.  Thread-safe: any thread may submit, poll and
+ * wait.  Destroy waits for every submitted request to finish. */
+typedef struct bmc_server bmc_server;
+typedef struct {
+    int64_t hbm_budget;     /* device bytes for requests and cached rules (0: 4 GiB) */
+    int32_t max_inflight;   /* requests on the device at once (0: 256) */
+    int32_t rule_cache;     /* learned rule tables kept (0: 256; -1: no cache) */
+} bmc_server_opts;
+typedef struct {
+    int64_t submitted, rejected, completed, failed;
+    int64_t cache_hits, cache_misses, cached_rules;
+    int64_t rounds, inner_path_steps, final_path_steps;
+    int64_t queued, inflight, hbm_in_use, hbm_peak;
+    double busy_seconds;    /* wall time of the server's rounds */
+} bmc_server_stats;
+bmc_status bmc_server_create(bmc_ctx *ctx, const bmc_server_opts *opts, bmc_server **out);
+void bmc_server_destroy(bmc_server *server);
+/* Queues a request (spec and opts are copied); BMC_ENOMEM if its footprint
+ * exceeds the whole arena.  *ticket identifies it. */
+bmc_status bmc_server_submit(bmc_server *server, const bmc_spec *spec, const bmc_opts *opts, uint64_t *ticket);
+/* BMC_EBUSY while the request is queued or running; otherwise its status
+ * (the result is written on BMC_OK) and the ticket is released. */
+bmc_status bmc_server_poll(bmc_server *server, uint64_t ticket, bmc_result *out);
+/* As poll, blocking up to timeout_s seconds (< 0: no limit). */
+bmc_status bmc_server_wait(bmc_server *server, uint64_t ticket, double timeout_s, bmc_result *out);
+bmc_status bmc_server_stats_get(bmc_server *server, bmc_server_stats *out);
+
 /* Exercise-rule table of one spec and method: one row of width w per date
  * (rows 1..N_T-1 used).  CMC (Section 3.2): F(x) = sum_f w_f phi_f(x) with
  * phi = [1, u_1..u_d, u_1^2..u_d^2, g, g^2], u_i = ln(S_i/K), g = Phi(S)/K;

@@ -27,7 +27,8 @@ SYMBOLS = [
     "bmc_rules_create", "bmc_rules_destroy", "bmc_rules_width", "bmc_rules_set", "bmc_rules_get",
     "bmc_rules_export", "bmc_rules_import", "bmc_sample_points", "bmc_estimate_continuation",
     "bmc_fit_rule", "bmc_iz_search", "bmc_final_price", "bmc_philox", "bmc_normals", "bmc_price_batch",
-    "bmc_tuning_set", "bmc_tuning_get",
+    "bmc_tuning_set", "bmc_tuning_get", "bmc_server_create", "bmc_server_destroy", "bmc_server_submit",
+    "bmc_server_poll", "bmc_server_wait", "bmc_server_stats_get",
 ]
 
 
@@ -62,6 +63,20 @@ class bmc_result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class bmc_server_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_inflight", C.c_int32), ("rule_cache", C.c_int32)]
+
+
+class bmc_server_stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "rejected", "completed", "failed", "cache_hits",
+                                          "cache_misses", "cached_rules", "rounds", "inner_path_steps",
+                                          "final_path_steps", "queued", "inflight", "hbm_in_use",
+                                          "hbm_peak")] + [("busy_seconds", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -86,6 +101,13 @@ def load():
     L.bmc_price_batch.argtypes = [vp, C.c_int32, sp, C.POINTER(bmc_opts), C.POINTER(vp), C.POINTER(bmc_result)]
     L.bmc_tuning_set.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int32]
     L.bmc_tuning_get.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.POINTER(C.c_int32)]
+    L.bmc_server_create.argtypes = [vp, C.POINTER(bmc_server_opts), C.POINTER(vp)]
+    L.bmc_server_destroy.argtypes = [vp]
+    L.bmc_server_destroy.restype = None
+    L.bmc_server_submit.argtypes = [vp, sp, C.POINTER(bmc_opts), C.POINTER(C.c_uint64)]
+    L.bmc_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(bmc_result)]
+    L.bmc_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(bmc_result)]
+    L.bmc_server_stats_get.argtypes = [vp, C.POINTER(bmc_server_stats)]
     L.bmc_rules_create.argtypes = [vp, sp, C.c_int32, C.POINTER(vp)]
     L.bmc_rules_destroy.argtypes = [vp]
     L.bmc_rules_destroy.restype = None
@@ -254,6 +276,58 @@ def bmc_tuning_get(ctx: Context, d: int, precision: int, N: int, n: int) -> int:
     v = C.c_int32(0)
     _check(load().bmc_tuning_get(ctx.h, d, precision, N, n, C.byref(v)))
     return int(v.value)
+
+
+class Server:
+    """A bmc_server: continuous-batching request loop on ctx's device."""
+
+    def __init__(self, ctx: Context, hbm_budget: int = 0, max_inflight: int = 0, rule_cache: int = 0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        o = bmc_server_opts(hbm_budget, max_inflight, rule_cache)
+        _check(load().bmc_server_create(ctx.h, C.byref(o), C.byref(h)))
+        self.h = h
+
+    def submit(self, spec, method: int = CMC, precision: int = FP64, N: int = 256, n: int = 1024,
+               n_final: int = 16384, seed: int = 1, cls_rounds: int = 0) -> int:
+        s = as_spec(spec)
+        o = bmc_opts(method, precision, N, n, n_final, seed, cls_rounds, 0, 0.0)
+        t = C.c_uint64(0)
+        _check(load().bmc_server_submit(self.h, s.ptr, C.byref(o), C.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """The result dict, or None while the request is pending."""
+        res = bmc_result()
+        st = load().bmc_server_poll(self.h, ticket, C.byref(res))
+        if st == EBUSY:
+            return None
+        _check(st)
+        return res.as_dict()
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        res = bmc_result()
+        st = load().bmc_server_wait(self.h, ticket, timeout, C.byref(res))
+        if st == EBUSY:
+            return None
+        _check(st)
+        return res.as_dict()
+
+    def stats(self) -> dict:
+        s = bmc_server_stats()
+        _check(load().bmc_server_stats_get(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().bmc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def bmc_rules_create(ctx: Context, spec, method: int) -> Rules:

@@ -66,7 +66,9 @@ struct LaunchCfg {
 };
 
 // Kernels (kernels.hip).  All enqueue on `st` and return hipError_t.
-hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st);
+// Spec setup of count packs; pack i goes to out[slots ? slots[i] : i].
+hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st,
+                        const uint32_t* slots = nullptr);
 hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, size_t lds,
                        hipStream_t st);
 // Dimension buckets: every d <= 32 has its own instantiation (bucket_exact);

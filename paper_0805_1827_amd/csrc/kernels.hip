@@ -10,12 +10,12 @@ namespace bmc {
 // Spec setup: Cholesky of rho (FP64), A = diag(sigma) L, drifts, date tables.
 
 __global__ void __launch_bounds__(256) k_setup(const HostSpecPack* __restrict__ in,
-                                               DevSpec* __restrict__ out)
+                                               DevSpec* __restrict__ out, const uint32_t* __restrict__ slots)
 {
     __shared__ double L[D_MAX * D_MAX];
     __shared__ int bad;
-    in += blockIdx.x;   // one block per spec
-    out += blockIdx.x;
+    in += blockIdx.x;   // one block per spec, written to its slot
+    out += slots ? slots[blockIdx.x] : blockIdx.x;
     const int d = in->d, NT = in->n_dates, tid = threadIdx.x;
     if (tid == 0) bad = 0;
     for (int i = tid; i < D_MAX * D_MAX; i += blockDim.x) L[i] = 0.0;
@@ -71,9 +71,9 @@ __global__ void __launch_bounds__(256) k_setup(const HostSpecPack* __restrict__ 
     }
 }
 
-hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st)
+hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st, const uint32_t* slots)
 {
-    hipLaunchKernelGGL(k_setup, dim3(count), dim3(256), 0, st, in, out);
+    hipLaunchKernelGGL(k_setup, dim3(count), dim3(256), 0, st, in, out, slots);
     return hipGetLastError();
 }
 

@@ -1,0 +1,136 @@
+"""Serving loop (bmc_server_*): continuous batching of pricing requests.
+
+Bars: every served result bit-identical to bmc_price on the same context,
+whether the request ran alone, in a mix that arrived over time, behind an
+admission limit, or from the rule cache; failures reported per request.
+"""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bmc(torch_mod):
+    from paper_0805_1827_amd import bmc as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(bmc):
+    c = bmc.Context(0)
+    yield c
+    c.close()
+
+
+# (d, dates, n, N, precision): mixed sizes, buckets and precisions
+MIX = [(1, 6, 1024, 96, "FP64"), (3, 9, 2048, 64, "FP32"), (5, 10, 1024, 128, "FP32_KAHAN"),
+       (9, 5, 512, 80, "FP64"), (14, 4, 1500, 64, "FP32"), (21, 3, 700, 70, "FP32"), (2, 1, 800, 32, "FP64"),
+       (36, 3, 512, 66, "FP32"), (7, 12, 4096, 100, "FP32")]
+
+
+def requests(bmc, inputs, shapes=MIX, first_seed=300, n_final=12000):
+    out = []
+    for k, (d, nd, n, N, prec) in enumerate(shapes):
+        s = inputs.random_option(first_seed + k, d_range=(d, d), dates_range=(nd, nd), n_choices=(n,))
+        out.append((s, dict(method=bmc.CMC, precision=getattr(bmc, prec), N=N, n=n, n_final=n_final,
+                            seed=first_seed + k)))
+    return out
+
+
+def same(a, b):
+    return all(a[k] == b[k] for k in ("price", "variance", "std_err", "final_path_steps"))
+
+
+def test_served_mix_matches_alone(bmc, ctx, inputs):
+    reqs = requests(bmc, inputs)
+    srv = bmc.Server(ctx, hbm_budget=1 << 30)
+    try:
+        # half at once, the rest while the first ones are on the device
+        tickets = [srv.submit(s, **o) for s, o in reqs[:5]]
+        time.sleep(0.02)
+        tickets += [srv.submit(s, **o) for s, o in reqs[5:]]
+        res = [srv.wait(t, 120.0) for t in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert all(r is not None for r in res)
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["cache_hits"] == 0
+    for (s, o), r in zip(reqs, res):
+        alone = bmc.bmc_price(ctx, s, **o)
+        assert same(r, alone), (s.d, s.n_dates, r["price"], alone["price"])
+        assert r["inner_path_steps"] == alone["inner_path_steps"]
+        assert r["seconds"] >= r["calc_seconds"] >= 0.0
+
+
+def test_admission_by_footprint(bmc, ctx, inputs):
+    reqs = requests(bmc, inputs, [(4, 8, 2048, 512, "FP32")] * 6, first_seed=500)
+    probe = bmc.Server(ctx, hbm_budget=1 << 30, rule_cache=-1)
+    try:
+        probe.wait(probe.submit(*reqs[0][:1], **reqs[0][1]), 120.0)
+        footprint = probe.stats()["hbm_peak"]
+    finally:
+        probe.close()
+    # room for two of these requests at a time: the others wait for memory
+    srv = bmc.Server(ctx, hbm_budget=int(2.5 * footprint), rule_cache=-1)
+    try:
+        tickets = [srv.submit(s, **o) for s, o in reqs]
+        res = [srv.wait(t, 120.0) for t in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["completed"] == 6 and st["hbm_peak"] <= 2 * footprint
+    assert st["rounds"] > 2 * 8   # the requests could not all run side by side
+    for (s, o), r in zip(reqs, res):
+        assert same(r, bmc.bmc_price(ctx, s, **o))
+
+
+def test_rule_cache_hit_runs_final_pricing_only(bmc, ctx, inputs):
+    (s, o), = requests(bmc, inputs, [(6, 7, 1024, 128, "FP32")], first_seed=700)
+    srv = bmc.Server(ctx)
+    try:
+        first = srv.wait(srv.submit(s, **o), 120.0)
+        o2 = dict(o, n_final=30000)
+        second = srv.wait(srv.submit(s, **o2), 120.0)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["cache_hits"] == 1 and st["cache_misses"] == 1 and st["cached_rules"] == 1
+    assert first["inner_path_steps"] > 0 and second["inner_path_steps"] == 0
+    assert same(first, bmc.bmc_price(ctx, s, **o))
+    assert same(second, bmc.bmc_price(ctx, s, **o2))
+
+
+def test_request_errors(bmc, ctx, inputs):
+    (s, o), = requests(bmc, inputs, [(3, 4, 1024, 64, "FP64")], first_seed=800)
+    srv = bmc.Server(ctx, hbm_budget=1 << 24)
+    try:
+        with pytest.raises(bmc.BmcError) as ei:
+            srv.submit(s, **dict(o, method=bmc.IZ))
+        assert ei.value.status == bmc.EUNSUPPORTED
+        with pytest.raises(bmc.BmcError) as ei:
+            srv.submit(s, **dict(o, N=1 << 20, n=1 << 16))   # footprint beyond the arena
+        assert ei.value.status == bmc.ENOMEM
+        bad = inputs.basket(3, 100.0, 100.0, 0.05, 0.0, 0.2, 0.0, 1.0, 4, inputs.PUT_BASKET)
+        bad.rho = np.array([[1.0, 0.9, -0.9], [0.9, 1.0, 0.9], [-0.9, 0.9, 1.0]])
+        tb = srv.submit(bad, **o)
+        tg = srv.submit(s, **o)
+        with pytest.raises(bmc.BmcError) as ei:
+            srv.wait(tb, 60.0)
+        assert ei.value.status == bmc.ENOTSPD
+        good = srv.wait(tg, 60.0)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert same(good, bmc.bmc_price(ctx, s, **o))
+    assert st["failed"] == 1 and st["rejected"] == 1

@@ -178,6 +178,62 @@ def batch_form(ctx, bmc, inputs, count: int, N: int, n_final: int) -> dict:
                                               "frac_within_0.1": float(np.mean(dist <= 0.1))}}
 
 
+def serving_form(ctx, bmc, inputs, duration: float, rate: float, precision: int, N: int = 256,
+                 seed: int = 7) -> dict:
+    """The serving loop under Poisson arrivals: requests draw from a seeded
+    catalogue of 64 specs (d in 1..40, 4..50 dates, n in {2k, 8k, 32k},
+    Wishart correlations, three payoffs), learn with N points on a rule-cache
+    miss and price with n_final = 16 n.  Latency = completion - submission."""
+    cat = inputs.serving_catalogue(64)
+    rng = np.random.default_rng(seed)
+    arrivals = inputs.poisson_arrivals(rate, duration, seed)
+    picks = rng.integers(0, len(cat), size=len(arrivals))
+    srv = bmc.Server(ctx, hbm_budget=16 << 30)
+    tickets = []
+    t0 = time.perf_counter()
+    try:
+        for t_arr, k in zip(arrivals, picks):
+            now = time.perf_counter() - t0
+            if t_arr > now:
+                time.sleep(t_arr - now)
+            s = cat[k]
+            n = s.meta["n"]
+            tickets.append(srv.submit(s, method=bmc.CMC, precision=precision, N=N, n=n, n_final=16 * n,
+                                      seed=1000 + int(k)))
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    lat = np.array([r["seconds"] for r in res])
+    steps = st["inner_path_steps"] + st["final_path_steps"]
+    return {"requests": len(res), "offered_rate": len(res) / duration, "served_rate": len(res) / wall,
+            "wall_s": wall, "cache_hit_rate": st["cache_hits"] / max(1, len(res)),
+            "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99)),
+                           "max": 1e3 * float(lat.max())},
+            "path_steps_per_s": steps / wall, "inner_path_steps": st["inner_path_steps"],
+            "final_path_steps": st["final_path_steps"], "rounds": st["rounds"],
+            "busy_frac": st["busy_seconds"] / wall, "hbm_peak_bytes": st["hbm_peak"]}
+
+
+def saturation_form(ctx, bmc, inputs, precision: int, N: int = 256) -> dict:
+    """Learning-bound rate: the 64 catalogue specs submitted at once, cold cache."""
+    cat = inputs.serving_catalogue(64)
+    srv = bmc.Server(ctx, hbm_budget=16 << 30)
+    t0 = time.perf_counter()
+    try:
+        tickets = [srv.submit(s, method=bmc.CMC, precision=precision, N=N, n=s.meta["n"],
+                              n_final=16 * s.meta["n"], seed=2000 + i) for i, s in enumerate(cat)]
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    steps = st["inner_path_steps"] + st["final_path_steps"]
+    return {"requests": len(res), "requests_per_s": len(res) / wall, "wall_s": wall,
+            "path_steps_per_s": steps / wall, "inner_path_steps": st["inner_path_steps"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)

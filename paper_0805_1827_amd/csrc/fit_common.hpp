@@ -10,15 +10,14 @@ namespace bmc {
 
 __device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
 
-// q-th entry of a packed lower triangle -> (row i, column l <= i).
+// q-th entry of a packed lower triangle -> (row i, column l <= i): the row
+// from the square root, then corrected by at most a step either way.
 __device__ __forceinline__ void pair_of(int q, int& i, int& l)
 {
-    i = 0;
-    while (q >= i + 1) {
-        q -= i + 1;
-        ++i;
-    }
-    l = q;
+    i = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+    if (i * (i + 1) / 2 > q) --i;
+    if ((i + 1) * (i + 2) / 2 <= q) ++i;
+    l = q - i * (i + 1) / 2;
 }
 
 // Solves (A + lam I) x = b for the packed lower triangle A (overwritten by
@@ -397,7 +396,79 @@ __device__ inline void fit_round_point16(const double* phi, const double* lab, c
     }
 }
 
+// Boosting round at point j for the wide matrix-core path (16 <= p <= 96): as
+// fit_round_point16 with row stride S = 16 ceil((p+1)/16).
+__device__ inline void fit_round_point_s(const double* phi, const double* lab, const double* msk, int64_t N, int p,
+                                         int S, const double* mu, const double* sd, const double* beta_prev,
+                                         int64_t j, double* F, double* pi, double* psis, double* wz)
+{
+    const int tl = threadIdx.x;
+    double* row = psis + (size_t)S * tl;
+    if (j < N) {
+        for (int f = 0; f < p; ++f) row[f] = f == 0 ? 1.0 : (phi[f * N + j] - mu[f]) / sd[f];
+        double Fj, pj;
+        if (!beta_prev) {
+            Fj = 0.0;
+            pj = 0.5;
+        } else {
+            double dF = 0.0;
+            for (int f = 0; f < p; ++f) dF += beta_prev[f] * row[f];
+            Fj = F[j] + 0.5 * dF;
+            pj = 1.0 / (1.0 + exp(-2.0 * Fj));
+        }
+        F[j] = Fj;
+        pi[j] = pj;
+        double w = pj * (1.0 - pj);
+        if (w < 1e-10) w = 1e-10;
+        double z = (lab[j] - pj) / w;
+        if (z > 4.0) z = 4.0;
+        if (z < -4.0) z = -4.0;
+        row[p] = z;
+        for (int f = p + 1; f < S; ++f) row[f] = 0.0;
+        wz[2 * tl] = w * msk[j];
+    } else {
+        for (int f = 0; f < S; ++f) row[f] = 0.0;
+        wz[2 * tl] = 0.0;
+    }
+}
+
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Weighted Gram matrix of a tile for 16 <= p <= 96 on the FP64 matrix cores:
+// the (p+1)-wide rows r_t = [psi, z, 0..] (stride S = 16 nb) give nb(nb+1)/2
+// lower 16x16 blocks G[bi][bj] = sum_t w_t r_t[16bi..] r_t[16bj..]^T; wave w
+// takes blocks w, w + waves, .., each over all points of the tile (one
+// 16x16x4 MFMA per four points), and writes its entries of the packed
+// normal equations (A, then b_J = G[p][J]) straight to out.
+__device__ inline void fit_tile_normal_eqs_mfma_wide(const double* psis, int S, const double* wz, int p, int nt,
+                                                     double* out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const int nb = S / 16, nbp = nb * (nb + 1) / 2;
+    const int npairs = p * (p + 1) / 2;
+    const int c = lane & 15, kq = lane >> 4;
+    for (int pr = wave; pr < nbp; pr += waves) {
+        int bi, bj;
+        pair_of(pr, bi, bj);
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < nt; k0 += 4) {
+            const int t = k0 + kq;
+            const bool in = t < nt;
+            const double ra = in ? psis[(size_t)S * t + 16 * bi + c] : 0.0;
+            const double rb = in ? psis[(size_t)S * t + 16 * bj + c] : 0.0;
+            const double w = in ? wz[2 * t] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(w * ra, rb, acc, 0, 0, 0);
+        }
+        // D[i][j] sits in lane j + 16 (i % 4), element i / 4
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int I = 16 * bi + 4 * e + kq, J = 16 * bj + c;
+            if (I < p && J <= I) out[tri(I, J)] = acc[e];
+            else if (I == p && J < p) out[npairs + J] = acc[e];
+        }
+    }
+}
 
 // Weighted Gram matrix of the tile on the matrix cores: G = sum_t w_t
 // r_t r_t^T with r_t = [psi, z, 0..] (16 wide), one 16x16x4 FP64 MFMA per

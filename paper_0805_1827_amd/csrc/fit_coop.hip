@@ -22,21 +22,39 @@ __device__ unsigned long long g_fit_trace[256];
 #define FIT_MARK(i) do { } while (0)
 #endif
 
-__host__ __device__ inline int coop_psi_width(int p) { return p <= 15 ? 16 : p; }
+// Normal-equation path by rule width: 1 = one 16x16 MFMA block (p <= 15),
+// 2 = 16x16 MFMA blocks (p <= 96, tiles of 64+ points), 0 = scalar.
+__host__ __device__ inline int coop_mode(int p) { return p <= 15 ? 1 : (p <= 96 ? 2 : 0); }
+__host__ __device__ inline int coop_psi_width(int p)
+{
+    const int m = coop_mode(p);
+    return m == 1 ? 16 : (m == 2 ? 16 * ((p + 16) / 16) : p);
+}
 __host__ __device__ inline int coop_aux(int p, int T)
 {
-    const int a = TILE_SUB * (p + 1), b = (T / 64) * 256;
+    const int a = TILE_SUB * (p + 1), b = coop_mode(p) == 1 ? (T / 64) * 256 : 0;
     return a > b ? a : b;
 }
 
 // Sum over tiles, in tile order, of the Q columns of a [ntiles][Q] array,
-// staged through LDS in chunks with coalesced loads by the whole block;
+// staged through LDS in chunks of whole tiles with coalesced loads by the
+// whole block (straight from memory when one tile exceeds the staging area);
 // out[Q] in LDS.  Same order as a sequential merge from zero.
 __device__ void merge_tiles(const double* __restrict__ part, int ntiles, int Q, double* stage, int cap,
                             double* out)
 {
     const int T = blockDim.x, tid = threadIdx.x;
-    const int chunk = cap / Q;   // >= 1 by construction of the LDS layout
+    const int chunk = cap / Q;
+    if (chunk < 1) {
+        __syncthreads();
+        for (int q = tid; q < Q; q += T) {
+            double acc = 0.0;
+            for (int t = 0; t < ntiles; ++t) acc += part[(size_t)t * Q + q];
+            out[q] = acc;
+        }
+        __syncthreads();
+        return;
+    }
     for (int q = tid; q < Q; q += T) out[q] = 0.0;
     for (int t0 = 0; t0 < ntiles; t0 += chunk) {
         const int nt = min(chunk, ntiles - t0);
@@ -87,7 +105,8 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
     __shared__ double lam, cnt_s;
     const int p = a.p, T = blockDim.x, npairs = p * (p + 1) / 2, Q = npairs + p;
     const int tid = threadIdx.x;
-    const bool mfma = p <= 15;
+    const int mode = coop_mode(p);
+    const int SW = coop_psi_width(p);
     double* psi = sh;                                   // [T][psi width]; also the staging area
     double* wz = psi + (size_t)T * coop_psi_width(p);  // [T][2]
     double* aux = wz + 2 * T;                           // two-level sums / per-wave Gram matrices
@@ -162,12 +181,18 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
         for (int t = grp.rank(); t < a.ntiles; t += grp.size()) {
             const int64_t j0 = (int64_t)t * T;
             const int nt = (int)min((int64_t)T, N - j0);
-            if (mfma) {
+            if (mode == 1) {
                 fit_round_point16(fs.phi, fs.lab, fs.msk, N, p, mu, sd, r > 0 ? beta : nullptr, j0 + tid, fs.F,
                                   fs.pi, psi, wz);
                 __syncthreads();
                 FIT_MARK(9 + 8 * r);
                 fit_tile_normal_eqs_mfma(psi, wz, p, nt, aux, partA + (size_t)t * Q);
+            } else if (mode == 2) {
+                fit_round_point_s(fs.phi, fs.lab, fs.msk, N, p, SW, mu, sd, r > 0 ? beta : nullptr, j0 + tid, fs.F,
+                                  fs.pi, psi, wz);
+                __syncthreads();
+                FIT_MARK(9 + 8 * r);
+                fit_tile_normal_eqs_mfma_wide(psi, SW, wz, p, nt, partA + (size_t)t * Q);
             } else {
                 fit_round_point(fs.phi, fs.lab, fs.msk, N, p, mu, sd, r > 0 ? beta : nullptr, j0 + tid, fs.F,
                                 fs.pi, psi, wz);

@@ -345,11 +345,22 @@ void bmc_server::loop()
             std::unique_lock<std::mutex> g(mu);
             cv_work.wait(g, [&] { return stop || !queue.empty() || !active.empty(); });
             if (stop && queue.empty() && active.empty()) break;
-            // admission: first come, first served, by footprint and slots
-            while (!queue.empty() && (int)active.size() < max_inflight && !free_slots.empty()) {
-                Request* r = queue.front();
+            // admission: first come, first served, by footprint and slots; a
+            // request whose rule table is being learned by an earlier one
+            // waits for it (and then runs from the cache)
+            std::unordered_map<std::string, int> learning;
+            if (cache_cap > 0)
+                for (Request* a : active)
+                    if (!a->hit && a->stage >= 1) ++learning[a->key];
+            for (auto qi = queue.begin(); qi != queue.end() && (int)active.size() < max_inflight &&
+                                          !free_slots.empty();) {
+                Request* r = *qi;
                 auto c = cache.find(r->key);
                 r->hit = c != cache.end();
+                if (!r->hit && learning.count(r->key)) {
+                    ++qi;
+                    continue;
+                }
                 size_t off;
                 bool ok = arena.alloc(r->q.bytes, &off);
                 while (!ok && evict_one()) ok = arena.alloc(r->q.bytes, &off);
@@ -358,7 +369,8 @@ void bmc_server::loop()
                     c = cache.find(r->key);   // eviction above may have removed it
                     r->hit = c != cache.end();
                 }
-                queue.pop_front();
+                qi = queue.erase(qi);
+                if (!r->hit && cache_cap > 0) ++learning[r->key];
                 r->off = off;
                 r->slot = free_slots.back();
                 free_slots.pop_back();

@@ -228,6 +228,23 @@ def test_cmc_fit_parity(bmc, ctx, orc, torch_mod, inputs, c1_rules):
         assert_same_rule(spec, w, w_ref, orc.points_cmc(spec, m, 2000, 99), what=f"fit d={spec.d} fresh")
 
 
+@pytest.mark.parametrize("d,N", [(8, 300), (10, 300), (30, 200), (50, 100)])
+def test_cmc_fit_parity_wide(bmc, ctx, orc, torch_mod, inputs, d, N):
+    """Wide rules: matrix-core normal equations in 16x16 blocks (p = 19..63,
+    ragged tiles of 128 and 64 points) and the scalar path (p = 103)."""
+    rng = np.random.default_rng(100 + d)
+    spec = inputs.basket(d, 100.0, 100.0, 0.05, 0.0, rng.uniform(0.1, 0.4, d), inputs.wishart_corr(d, rng), 1.0,
+                         6, inputs.PUT_BASKET)
+    m = 3
+    x = orc.points_cmc(spec, m, N, 2)
+    cont = orc.continuation(spec, orc.CMC, orc.empty_rules(spec, orc.CMC), m, x, 100, 2, nthreads=NT_CPU)["cont"]
+    w_ref = orc.fit_cmc(spec, x, cont, rounds=8)
+    rules = bmc.bmc_rules_create(ctx, spec, bmc.CMC)
+    bmc.bmc_fit_rule(ctx, spec, rules, m, dev(torch_mod, x), dev(torch_mod, cont), rounds=8)
+    w = bmc.bmc_rules_get(rules, m)
+    assert_same_rule(spec, w, w_ref, x, what=f"fit d={d}")
+
+
 def test_iz_fit_parity(bmc, ctx, orc, torch_mod, inputs):
     spec = inputs.geometric_put5()
     m = 7

@@ -248,6 +248,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--batch", type=int, default=256, help="options in the batched form (0 disables it)")
     ap.add_argument("--batch-N", type=int, default=256)
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the Poisson arrival window of the serving form (0 disables it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="arrival rate of the serving form (1/s)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the pricer runs on a single device and this build has no "
@@ -326,6 +329,15 @@ def main():
     }
     if args.batch > 0:
         out["batch"] = batch_form(ctx, bmc, inputs, args.batch, args.batch_N, 100_000)
+    if args.serve_seconds > 0:
+        out["serving"] = {
+            "workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s from a catalogue "
+                        "of 64 specs (d 1-40, 4-50 dates, n in 2k/8k/32k); CMC, N=256 on a rule-cache miss, "
+                        "n_final=16n",
+            "fp32": serving_form(ctx, bmc, inputs, args.serve_seconds, args.serve_rate, bmc.FP32),
+            "fp64": serving_form(ctx, bmc, inputs, args.serve_seconds, args.serve_rate, bmc.FP64),
+            "saturation_fp32": saturation_form(ctx, bmc, inputs, bmc.FP32),
+            "saturation_fp64": saturation_form(ctx, bmc, inputs, bmc.FP64)}
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(spec, args.N, args.n, args.seed, args.cpu_seconds)
     print(json.dumps(out), flush=True)

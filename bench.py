@@ -157,8 +157,21 @@ def batch_form(ctx, bmc, inputs, count: int, N: int, n_final: int) -> dict:
         res = bmc.bmc_price_batch(ctx, specs, opts(prec))
         dt = time.perf_counter() - t0
         out[name] = (res, dt)
+    # the same sweep captured as a HIP graph, then replayed
+    gctx = bmc.Context(0)
+    try:
+        bmc.bmc_ctx_set_graphs(gctx, True)
+        bmc.bmc_price_batch(gctx, specs, opts(bmc.FP32))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rg = bmc.bmc_price_batch(gctx, specs, opts(bmc.FP32))
+        t_graph = time.perf_counter() - t0
+        graph_stats = bmc.bmc_ctx_graph_stats(gctx)
+    finally:
+        gctx.close()
     r32, t32 = out["fp32"]
     r64, t64 = out["fp64"]
+    assert all(a["price"] == b["price"] for a, b in zip(rg, r32)), "graph replay differs from direct launches"
     steps32 = sum(r["inner_path_steps"] for r in r32)
     steps64 = sum(r["inner_path_steps"] for r in r64)
     slots = sum(slots_per_step_fp32(s.d, s.payoff, bmc.CMC) * r["inner_path_steps"] for s, r in zip(specs, r32))
@@ -170,6 +183,8 @@ def batch_form(ctx, bmc, inputs, count: int, N: int, n_final: int) -> dict:
             "fp32": {"value": steps32 / t32, "seconds": t32, "inner_path_steps": steps32,
                      "phase_s": {"calc": calc, "fit": r32[0]["fit_seconds"], "final": r32[0]["final_seconds"]}},
             "fp64": {"value": steps64 / t64, "seconds": t64, "inner_path_steps": steps64},
+            "fp32_graph_replay": {"value": steps32 / t_graph, "seconds": t_graph,
+                                  "captures_replays": list(graph_stats)},
             "unit": "path-steps/s",
             "fp32_valu_slot_frac_of_peak": slots / calc / PEAK_SLOTS,
             "fp32_mfma_tflops": mflops / calc / 1e12,

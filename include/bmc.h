@@ -114,6 +114,16 @@ const char *bmc_last_error(void);
  * hipStream_t; NULL = the default stream).  Owns scratch memory. */
 bmc_status bmc_ctx_create(int32_t device, void *hip_stream, bmc_ctx **out);
 void bmc_ctx_destroy(bmc_ctx *ctx);
+/* Batched date sweeps as HIP graphs (default off): bmc_price_batch captures
+ * its planned launch sequence once and replays it while the launch
+ * signature (every launch's shape and the context buffers it addresses) is
+ * unchanged; spec values, seeds and task tables are device data, so a
+ * repeated book of the same shapes replays with new inputs.  Results are
+ * identical with and without graphs; the phase times of a graph run are
+ * reported as one calc phase.  bmc_ctx_graph_stats counts captures and
+ * replays. */
+bmc_status bmc_ctx_set_graphs(bmc_ctx *ctx, int32_t enable);
+bmc_status bmc_ctx_graph_stats(bmc_ctx *ctx, int64_t *captures, int64_t *replays);
 /* Blocks until all work issued through ctx has finished. */
 bmc_status bmc_sync(bmc_ctx *ctx);
 

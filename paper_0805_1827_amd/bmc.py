@@ -28,7 +28,7 @@ SYMBOLS = [
     "bmc_rules_export", "bmc_rules_import", "bmc_sample_points", "bmc_estimate_continuation",
     "bmc_fit_rule", "bmc_iz_search", "bmc_final_price", "bmc_philox", "bmc_normals", "bmc_price_batch",
     "bmc_tuning_set", "bmc_tuning_get", "bmc_server_create", "bmc_server_destroy", "bmc_server_submit",
-    "bmc_server_poll", "bmc_server_wait", "bmc_server_stats_get",
+    "bmc_server_poll", "bmc_server_wait", "bmc_server_stats_get", "bmc_ctx_set_graphs", "bmc_ctx_graph_stats",
 ]
 
 
@@ -101,6 +101,8 @@ def load():
     L.bmc_price_batch.argtypes = [vp, C.c_int32, sp, C.POINTER(bmc_opts), C.POINTER(vp), C.POINTER(bmc_result)]
     L.bmc_tuning_set.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int32]
     L.bmc_tuning_get.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.POINTER(C.c_int32)]
+    L.bmc_ctx_set_graphs.argtypes = [vp, C.c_int32]
+    L.bmc_ctx_graph_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.bmc_server_create.argtypes = [vp, C.POINTER(bmc_server_opts), C.POINTER(vp)]
     L.bmc_server_destroy.argtypes = [vp]
     L.bmc_server_destroy.restype = None
@@ -220,6 +222,16 @@ class Rules:
             self.close()
         except Exception:
             pass
+
+
+def bmc_ctx_set_graphs(ctx: Context, enable: bool) -> None:
+    _check(load().bmc_ctx_set_graphs(ctx.h, 1 if enable else 0))
+
+
+def bmc_ctx_graph_stats(ctx: Context) -> tuple:
+    c, r = C.c_int64(0), C.c_int64(0)
+    _check(load().bmc_ctx_graph_stats(ctx.h, C.byref(c), C.byref(r)))
+    return int(c.value), int(r.value)
 
 
 def bmc_version() -> int:

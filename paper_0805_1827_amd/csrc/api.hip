@@ -189,6 +189,8 @@ bmc_ctx::~bmc_ctx()
         b->release();
     if (pack_host) (void)hipHostFree(pack_host);
     if (bhost) (void)hipHostFree(bhost);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph_stream) (void)hipStreamDestroy(graph_stream);
     if (host_io) (void)hipHostFree(host_io);
 }
 
@@ -198,6 +200,21 @@ extern "C" void bmc_ctx_destroy(bmc_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     delete ctx;
+}
+
+extern "C" bmc_status bmc_ctx_set_graphs(bmc_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return fail(BMC_EINVAL, "ctx is NULL");
+    ctx->graphs = enable != 0;
+    return BMC_OK;
+}
+
+extern "C" bmc_status bmc_ctx_graph_stats(bmc_ctx* ctx, int64_t* captures, int64_t* replays)
+{
+    if (!ctx || !captures || !replays) return fail(BMC_EINVAL, "NULL argument");
+    *captures = ctx->graph_captures;
+    *replays = ctx->graph_replays;
+    return BMC_OK;
 }
 
 extern "C" bmc_status bmc_sync(bmc_ctx* ctx)

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "engine.hpp"
@@ -14,6 +15,89 @@
 using namespace bmc;
 
 static inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Launch signature of a planned sweep: every launch's shape and table
+// offsets and the buffers they address.  Spec values, seeds and task-table
+// contents are device data, so a sweep with the same signature replays.
+static std::string sweep_signature(const std::vector<Step>& steps, const char* dtab, const char* base,
+                                   const DevSpec* dspec, size_t tab_bytes)
+{
+    std::string s;
+    auto add = [&](const void* p, size_t n) { s.append((const char*)p, n); };
+    add(&dtab, sizeof(dtab));
+    add(&base, sizeof(base));
+    add(&dspec, sizeof(dspec));
+    add(&tab_bytes, sizeof(tab_bytes));
+    for (const Step& st : steps) {
+        if (st.kind == K_MARK) continue;
+        const int64_t v[] = {st.kind, st.bucket, st.prec, st.ntasks, st.T, st.blocks, (int64_t)st.tasks,
+                             (int64_t)st.prefix, (int64_t)st.lds, st.date};
+        add(v, sizeof(v));
+        if (st.kind == K_FIT_SINGLE) {
+            add(&st.single_dev, sizeof(st.single_dev));
+            const int64_t q[] = {st.single_q.d, st.single_q.N, st.single_q.rounds};
+            add(q, sizeof(q));
+        }
+    }
+    return s;
+}
+
+// Runs the sweep as a HIP graph on the context's graph stream, ordered
+// after and before the work on st: captured when the signature is new,
+// replayed otherwise.  *ran = false (and no error) when the runtime cannot
+// capture the sweep: the caller then launches it directly.  evs receives a
+// start and an end event (one calc phase).
+static bmc_status run_graph(bmc_ctx* ctx, const std::vector<Step>& steps, const char* dtab, const char* base,
+                            const DevSpec* dspec, size_t tab_bytes, hipStream_t st, std::vector<hipEvent_t>& evs,
+                            std::vector<int>& ev_phase, bool* ran)
+{
+    hipError_t e;
+    *ran = false;
+    if (!ctx->graph_stream && (e = hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking)))
+        return hip_fail(e, "graph stream");
+    hipStream_t gs = ctx->graph_stream;
+    const std::string sig = sweep_signature(steps, dtab, base, dspec, tab_bytes);
+    if (!ctx->graph_exec || sig != ctx->graph_sig) {
+        if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+        ctx->graph_sig.clear();
+        if ((e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal))) {
+            (void)hipGetLastError();
+            return BMC_OK;
+        }
+        const hipError_t el = run_steps(steps, dtab, gs, [](int) {});
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(gs, &g);
+        hipGraphExec_t x = nullptr;
+        const hipError_t ei = (el || ec || !g) ? hipErrorUnknown : hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (el || ec || ei || !x) {
+            (void)hipGetLastError();
+            return BMC_OK;
+        }
+        ctx->graph_exec = x;
+        ctx->graph_sig = sig;
+        ++ctx->graph_captures;
+    } else {
+        ++ctx->graph_replays;
+    }
+    hipEvent_t before, t0, t1;
+    if ((e = hipEventCreate(&before)) || (e = hipEventCreate(&t0)) || (e = hipEventCreate(&t1)))
+        return hip_fail(e, "graph events");
+    evs.push_back(t0);
+    ev_phase.push_back(PH_CALC);
+    evs.push_back(t1);
+    ev_phase.push_back(-1);
+    if ((e = hipEventRecord(before, st)) || (e = hipStreamWaitEvent(gs, before, 0)) || (e = hipEventRecord(t0, gs)) ||
+        (e = hipGraphLaunch(ctx->graph_exec, gs)) || (e = hipEventRecord(t1, gs)) ||
+        (e = hipStreamWaitEvent(st, t1, 0))) {
+        (void)hipEventDestroy(before);
+        return hip_fail(e, "graph launch");
+    }
+    (void)hipEventDestroy(before);
+    *ran = true;
+    return BMC_OK;
+}
 
 extern "C" bmc_status bmc_price_batch(bmc_ctx* ctx, int32_t count, const bmc_spec* specs, const bmc_opts* opts,
                                       bmc_rules** rules_out, bmc_result* results)
@@ -98,7 +182,7 @@ extern "C" bmc_status bmc_price_batch(bmc_ctx* ctx, int32_t count, const bmc_spe
         if (((const int32_t*)(hb + status_off))[i] != 0)
             return fail(BMC_ENOTSPD, "option %d: correlation matrix is not positive definite", i);
 
-    // ---- run
+    // ---- run: direct launches with phase marks, or the captured graph
     std::vector<hipEvent_t> evs;
     std::vector<int> ev_phase;
     auto mark = [&](int phase) {
@@ -109,7 +193,11 @@ extern "C" bmc_status bmc_price_batch(bmc_ctx* ctx, int32_t count, const bmc_spe
         ev_phase.push_back(phase);
     };
     st = BMC_OK;
-    if ((e = run_steps(steps, dtab, sm, mark))) st = hip_fail(e, "batch launch");
+    bool ran = false;
+    if (ctx->graphs) {
+        if ((st = run_graph(ctx, steps, dtab, base, dspec, tab.bytes.size(), sm, evs, ev_phase, &ran))) return st;
+    }
+    if (!ran && (e = run_steps(steps, dtab, sm, mark))) st = hip_fail(e, "batch launch");
     // per-option counters [steps, sum, sum of squares, final steps]
     if (!st && (e = hipMemcpyAsync(hb + readback_off, cnt, 32 * (size_t)count, hipMemcpyDeviceToHost, sm)))
         st = hip_fail(e, "batch results");

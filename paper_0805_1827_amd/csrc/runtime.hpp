@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <map>
+#include <string>
 
 #include "bmc.h"
 
@@ -48,6 +49,13 @@ struct bmc_ctx {
     // continuation launch shapes (paths per lane per job) by (dimension
     // bucket, precision, log2 n class); 0 fields are wildcards
     std::map<uint64_t, int> ppt_table;
+    // batched date sweeps as a HIP graph: the last captured launch sequence,
+    // replayed while the signature (launch shapes and buffers) is unchanged
+    bool graphs = false;
+    std::string graph_sig;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    int64_t graph_captures = 0, graph_replays = 0;
     ~bmc_ctx();
 };
 

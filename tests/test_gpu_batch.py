@@ -112,3 +112,34 @@ def test_batch_errors(bmc, ctx, inputs):
     # the context still works after the failed calls
     ok = bmc.bmc_price_batch(ctx, specs[:1], opts[:1])
     assert ok[0]["price"] == bmc.bmc_price(ctx, specs[0], **opts[0])["price"]
+
+
+def test_batch_graph_replays_match_direct(bmc, ctx, inputs):
+    """Captured sweeps: the first call captures, calls with the same shapes
+    (new seeds, new spot prices and volatilities) replay; every replay, with
+    eager work between them, equals the direct launches and bmc_price."""
+    gctx = bmc.Context(0)
+    try:
+        bmc.bmc_ctx_set_graphs(gctx, True)
+        specs, opts = make_batch(bmc, inputs, SHAPES[:8], first_seed=60)
+        variants = [(specs, opts)]
+        for shift in (1, 2):
+            sp = []
+            for s in specs:
+                s2 = inputs.basket(s.d, s.S0 * (1.0 + 0.03 * shift), s.K, s.r, s.delta, s.sigma * (1.0 - 0.05 * shift),
+                                   s.rho, s.T, s.n_dates, s.payoff)
+                sp.append(s2)
+            variants.append((sp, [dict(o, seed=o["seed"] + 100 * shift) for o in opts]))
+        variants.append(variants[0])
+        for k, (sp, op) in enumerate(variants):
+            got = bmc.bmc_price_batch(gctx, sp, op)
+            direct = bmc.bmc_price_batch(ctx, sp, op)          # eager work between replays
+            for i in range(len(sp)):
+                assert got[i]["price"] == direct[i]["price"] and got[i]["std_err"] == direct[i]["std_err"], (k, i)
+                assert got[i]["inner_path_steps"] == direct[i]["inner_path_steps"]
+            alone = bmc.bmc_price(ctx, sp[3], **op[3])
+            assert got[3]["price"] == alone["price"]
+        captures, replays = bmc.bmc_ctx_graph_stats(gctx)
+        assert (captures, replays) == (1, 3)
+    finally:
+        gctx.close()

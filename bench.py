@@ -261,6 +261,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline (0 disables it)")
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--no-autotune", action="store_true", help="heuristic launch shapes for the headline")
     ap.add_argument("--batch", type=int, default=256, help="options in the batched form (0 disables it)")
     ap.add_argument("--batch-N", type=int, default=256)
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -278,6 +279,13 @@ def main():
     spec = inputs.geometric_put5()
     ctx = bmc.Context(0)
     kw = dict(N=args.N, n=args.n, n_final=args.n_final, seed=args.seed)
+    # launch shapes of the headline workload from the autotuner (training
+    # continuation and final pricing, both precisions)
+    tuning = {}
+    if not args.no_autotune:
+        for name, prec in (("fp32", bmc.FP32), ("fp64", bmc.FP64)):
+            tuning[name] = {"ppt": bmc.bmc_autotune(ctx, spec, prec, args.N, args.n),
+                            "final_ppt": bmc.bmc_autotune(ctx, spec, prec, 1, args.n_final)}
 
     def timed(prec, steps, warmup):
         for _ in range(warmup):
@@ -340,10 +348,13 @@ def main():
                      "fit": 1e3 * sum(r["fit_seconds"] for r in res32) / args.steps,
                      "final": 1e3 * sum(r["final_seconds"] for r in res32) / args.steps},
         "inner_path_steps_per_price": inner32 // args.steps,
+        "launch_shapes": tuning or "heuristic",
         "roofline": roofline,
     }
     if args.batch > 0:
-        out["batch"] = batch_form(ctx, bmc, inputs, args.batch, args.batch_N, 100_000)
+        bctx = bmc.Context(0)
+        out["batch"] = batch_form(bctx, bmc, inputs, args.batch, args.batch_N, 100_000)
+        bctx.close()
     if args.serve_seconds > 0:
         out["serving"] = {
             "workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s from a catalogue "

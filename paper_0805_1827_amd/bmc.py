@@ -29,6 +29,7 @@ SYMBOLS = [
     "bmc_fit_rule", "bmc_iz_search", "bmc_final_price", "bmc_philox", "bmc_normals", "bmc_price_batch",
     "bmc_tuning_set", "bmc_tuning_get", "bmc_server_create", "bmc_server_destroy", "bmc_server_submit",
     "bmc_server_poll", "bmc_server_wait", "bmc_server_stats_get", "bmc_ctx_set_graphs", "bmc_ctx_graph_stats",
+    "bmc_autotune",
 ]
 
 
@@ -101,6 +102,7 @@ def load():
     L.bmc_price_batch.argtypes = [vp, C.c_int32, sp, C.POINTER(bmc_opts), C.POINTER(vp), C.POINTER(bmc_result)]
     L.bmc_tuning_set.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int32]
     L.bmc_tuning_get.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.POINTER(C.c_int32)]
+    L.bmc_autotune.argtypes = [vp, sp, C.c_int32, C.c_int64, C.c_int64, C.POINTER(C.c_int32)]
     L.bmc_ctx_set_graphs.argtypes = [vp, C.c_int32]
     L.bmc_ctx_graph_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.bmc_server_create.argtypes = [vp, C.POINTER(bmc_server_opts), C.POINTER(vp)]
@@ -340,6 +342,13 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def bmc_autotune(ctx: Context, spec, precision: int, N: int, n: int) -> int:
+    s = as_spec(spec)
+    v = C.c_int32(0)
+    _check(load().bmc_autotune(ctx.h, s.ptr, precision, N, n, C.byref(v)))
+    return int(v.value)
 
 
 def bmc_rules_create(ctx: Context, spec, method: int) -> Rules:

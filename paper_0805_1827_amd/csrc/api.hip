@@ -1,6 +1,7 @@
 // C ABI of the gfx950 nested continuation-value Monte Carlo: contexts, rule
 // tables, spec validation/upload and the pricer drivers.  Declarations and
 // contracts are in include/bmc.h.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -449,6 +450,86 @@ extern "C" bmc_status bmc_tuning_set(bmc_ctx* ctx, int32_t d, int32_t precision,
     const uint64_t k = ppt_key(d ? cont_bucket(d) : 0, precision + 1, n ? n_class(n) : 0);
     if (ppt == 0) ctx->ppt_table.erase(k);
     else ctx->ppt_table[k] = ppt;
+    return BMC_OK;
+}
+
+// Autotuner: times the continuation kernel of this spec at its middle date
+// (CMC training points, rules that never exercise, so every path runs to
+// maturity) for each launch shape ppt = 1, 2, 4, .. up to one chunk per
+// point (at most 64), and stores the fastest per executed path-step in the
+// context's table for the spec's (dimension bucket, precision, n class).
+extern "C" bmc_status bmc_autotune(bmc_ctx* ctx, const bmc_spec* spec, int32_t precision, int64_t N, int64_t n,
+                                   int32_t* ppt_out)
+{
+    if (!ctx || !spec) return fail(BMC_EINVAL, "NULL argument");
+    if (precision < BMC_FP64 || precision > BMC_FP32_KAHAN) return fail(BMC_EINVAL, "unknown precision %d", precision);
+    if (N < 1 || N > (1 << 24) || n < 2 || n > 0x7FFFFFFF) return fail(BMC_EINVAL, "N or n out of range");
+    (void)hipSetDevice(ctx->device);
+    bmc_status st;
+    if ((st = upload_spec(ctx, spec, ctx->spec))) return st;
+    bmc_rules* rules = nullptr;
+    if ((st = bmc_rules_create(ctx, spec, BMC_CMC, &rules))) return st;
+    const int d = spec->d, NT = spec->n_dates;
+    const int m = NT >= 2 ? NT / 2 : 0;
+    hipError_t e;
+    if ((e = ctx->x.ensure(sizeof(double) * d * N)) || (e = ctx->B.ensure(sizeof(double) * d * N)) ||
+        (e = ctx->steps.ensure(sizeof(int64_t) * N)) || (e = ctx->counters.ensure(64))) {
+        bmc_rules_destroy(rules);
+        return fail(BMC_ENOMEM, "autotune buffers: %s", hipGetErrorString(e));
+    }
+    double* x = (double*)ctx->x.ptr;
+    const double* pts = x;
+    int64_t npts = N;
+    if (m >= 1) {
+        if ((st = sample_points_impl(ctx, ctx->spec.ptr, spec, BMC_CMC, m, N, 1u, x, (double*)ctx->B.ptr))) {
+            bmc_rules_destroy(rules);
+            return st;
+        }
+    } else {
+        pts = dev_S0(ctx->spec.ptr);
+        npts = 1;
+    }
+    unsigned long long* total = (unsigned long long*)ctx->counters.ptr;
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
+        bmc_rules_destroy(rules);
+        return hip_fail(e, "autotune events");
+    }
+    int best = 1;
+    double best_rate = -1.0;
+    const int64_t max_ppt = std::min<int64_t>(64, std::max<int64_t>(1, (n + 255) / 256));
+    for (int ppt = 1; ppt <= max_ppt && !st; ppt *= 2) {
+        Tuning t;
+        t.ppt = ppt;
+        double rate = 0.0;
+        for (int rep = 0; rep < 3 && !st; ++rep) {   // rep 0 warms up
+            if ((e = hipMemsetAsync(total, 0, sizeof(unsigned long long), ctx->stream)) ||
+                (e = hipEventRecord(e0, ctx->stream))) {
+                st = hip_fail(e, "autotune");
+                break;
+            }
+            st = run_cont(ctx, ctx->spec.ptr, d, NT, BMC_CMC, rules->width, rules->w64, rules->w32, precision, m, pts,
+                          npts, nullptr, nullptr, (uint32_t)n, 1u, key_hi(BMC_STREAM_INNER, m), nullptr, nullptr,
+                          nullptr, nullptr, total, &t);
+            unsigned long long steps = 0;
+            float ms = 0.f;
+            if (!st && ((e = hipEventRecord(e1, ctx->stream)) ||
+                        (e = hipMemcpyAsync(&steps, total, sizeof(steps), hipMemcpyDeviceToHost, ctx->stream)) ||
+                        (e = hipStreamSynchronize(ctx->stream)) || (e = hipEventElapsedTime(&ms, e0, e1))))
+                st = hip_fail(e, "autotune");
+            if (!st && rep > 0 && ms > 0.f) rate += (double)steps / (ms * 1e-3);
+        }
+        if (!st && rate > best_rate) {
+            best_rate = rate;
+            best = ppt;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    bmc_rules_destroy(rules);
+    if (st) return st;
+    ctx->ppt_table[ppt_key(cont_bucket(d), precision + 1, n_class(n))] = best;
+    if (ppt_out) *ppt_out = best;
     return BMC_OK;
 }
 

@@ -128,6 +128,24 @@ void bmc::pack_spec(const bmc_spec* s, HostSpecPack* p)
 
 // Uploads and derives a spec into the context's spec slot; checks the
 // Cholesky status (one stream synchronisation).
+bmc_status bmc::upload_spec_async(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot, int32_t* status_host)
+{
+    bmc_status st = validate_spec(s);
+    if (st) return st;
+    hipError_t e = slot.ensure(sizeof(DevSpec));
+    if (e) return hip_fail(e, "spec allocation");
+    if ((e = ctx->pack_dev.ensure(sizeof(HostSpecPack)))) return hip_fail(e, "spec staging");
+    if ((e = hipStreamSynchronize(ctx->stream))) return hip_fail(e, "stream sync");   // staging free
+    pack_spec(s, ctx->pack_host);
+    if ((e = hipMemcpyAsync(ctx->pack_dev.ptr, ctx->pack_host, sizeof(HostSpecPack), hipMemcpyHostToDevice,
+                            ctx->stream)) ||
+        (e = launch_setup((const HostSpecPack*)ctx->pack_dev.ptr, (DevSpec*)slot.ptr, 1, ctx->stream)) ||
+        (e = hipMemcpyAsync(status_host, (char*)slot.ptr + offsetof(DevSpec, status), sizeof(int32_t),
+                            hipMemcpyDeviceToHost, ctx->stream)))
+        return hip_fail(e, "spec upload");
+    return BMC_OK;
+}
+
 bmc_status bmc::upload_spec(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot)
 {
     bmc_status st = validate_spec(s);
@@ -190,6 +208,8 @@ bmc_ctx::~bmc_ctx()
         b->release();
     if (pack_host) (void)hipHostFree(pack_host);
     if (bhost) (void)hipHostFree(bhost);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    srules.release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph_stream) (void)hipStreamDestroy(graph_stream);
     if (host_io) (void)hipHostFree(host_io);
@@ -266,6 +286,26 @@ static bmc_status rules_alloc(bmc_ctx* ctx, int method, int d, int n_dates, int 
         return hip_fail(e, "rule table init");
     }
     *out = r;
+    return BMC_OK;
+}
+
+bmc_status bmc::scratch_rules(bmc_ctx* ctx, const bmc_spec* spec, int method, bmc_rules* r)
+{
+    r->ctx = ctx;
+    r->method = method;
+    r->d = spec->d;
+    r->n_dates = spec->n_dates;
+    r->payoff = spec->payoff;
+    r->width = rule_width(method, spec->d);
+    const size_t rows = (size_t)(spec->n_dates + 1) * r->width;
+    const size_t b64 = (sizeof(double) * rows + 255) & ~(size_t)255;
+    hipError_t e = ctx->srules.ensure(b64 + sizeof(float) * rows);
+    if (e) return hip_fail(e, "rule scratch");
+    r->w64 = (double*)ctx->srules.ptr;
+    r->w32 = (float*)((char*)ctx->srules.ptr + b64);
+    if ((e = launch_rules_fill(r->w64, r->w32, spec->n_dates + 1, r->width, never_value(method, spec->payoff),
+                               ctx->stream)))
+        return hip_fail(e, "rule scratch");
     return BMC_OK;
 }
 

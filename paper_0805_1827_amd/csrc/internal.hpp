@@ -136,6 +136,7 @@ hipError_t launch_iz_update(const DevSpec* s, int d, int64_t J, const double* co
                             int32_t* ids_out, int32_t* n_out, double* s_cur, double* x_work,
                             double* s_out, int32_t* iters, unsigned long long* steps_acc,
                             double eps, int max_iter, int it, hipStream_t st);
+hipError_t launch_rules_fill(double* w64, float* w32, int rows, int width, double nv, hipStream_t st);
 hipError_t launch_rules_narrow(const double* w64, float* w32, int64_t count, hipStream_t st);
 
 // CMC boosting fit (FP64) of rule row m.

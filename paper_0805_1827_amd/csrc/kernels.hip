@@ -546,6 +546,23 @@ __global__ void k_narrow(const double* __restrict__ a, float* b, int64_t n)
     if (i < n) b[i] = (float)a[i];
 }
 
+// Never-exercise rows: value nv in column 0 of every row, zeros elsewhere.
+__global__ void k_rules_fill(double* w64, float* w32, int rows, int width, double nv)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * width) return;
+    const double v = e % width == 0 ? nv : 0.0;
+    w64[e] = v;
+    w32[e] = (float)v;
+}
+
+hipError_t launch_rules_fill(double* w64, float* w32, int rows, int width, double nv, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rules_fill, dim3((unsigned)((rows * width + 255) / 256)), dim3(256), 0, st, w64, w32, rows,
+                       width, nv);
+    return hipGetLastError();
+}
+
 hipError_t launch_rules_narrow(const double* w64, float* w32, int64_t count, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;

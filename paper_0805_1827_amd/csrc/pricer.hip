@@ -11,21 +11,27 @@ using namespace bmc;
 
 namespace {
 
-// Phase timers on the context stream, summed after the closing sync.
+// Phase timers on the context stream, summed after the closing sync; the
+// events come from the context's pool and go back to it.
 struct PhaseTimer {
-    hipStream_t st;
+    bmc_ctx* ctx;
     std::vector<hipEvent_t> evs;
     std::vector<int> phase;
-    explicit PhaseTimer(hipStream_t s) : st(s) {}
+    explicit PhaseTimer(bmc_ctx* c) : ctx(c) {}
     ~PhaseTimer()
     {
-        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+        for (hipEvent_t e : evs) ctx->ev_pool.push_back(e);
     }
     void mark(int ph)
     {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
-        (void)hipEventRecord(e, st);
+        if (!ctx->ev_pool.empty()) {
+            e = ctx->ev_pool.back();
+            ctx->ev_pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            return;
+        }
+        (void)hipEventRecord(e, ctx->stream);
         evs.push_back(e);
         phase.push_back(ph);
     }
@@ -61,23 +67,34 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     const int max_iter = opts->iz_max_iter > 0 ? opts->iz_max_iter : 100;
     const double eps = opts->iz_eps > 0.0 ? opts->iz_eps : 0.01;
     if (rounds > 64) return fail(BMC_EINVAL, "cls_rounds must be <= 64");
-    bmc_status st = upload_spec(ctx, spec, ctx->spec);
-    if (st) return st;
     if (method == BMC_IZ && opts->N > 65536) return fail(BMC_EUNSUPPORTED, "I&Z supports N <= 65536 lattice points");
+    // spec setup status and the step total come back with the final sums (one sync)
+    int32_t* status_host = (int32_t*)((char*)ctx->host_io + 72);
+    bmc_status st = upload_spec_async(ctx, spec, ctx->spec, status_host);
+    if (st) return st;
+    bmc_rules scratch;
     bmc_rules* rules = nullptr;
-    if ((st = bmc_rules_create(ctx, spec, method, &rules))) return st;
+    if (rules_out) {
+        if ((st = bmc_rules_create(ctx, spec, method, &rules))) return st;
+    } else {
+        if ((st = scratch_rules(ctx, spec, method, &scratch))) return st;
+        rules = &scratch;
+    }
+    auto release = [&]() {
+        if (rules != &scratch) bmc_rules_destroy(rules);
+    };
 
     const int d = spec->d, NT = spec->n_dates;
     const int64_t N = opts->N;
     const uint32_t n = (uint32_t)opts->n, seed = (uint32_t)opts->seed;
     const void* ds = ctx->spec.ptr;
     hipError_t e;
-    PhaseTimer timer(ctx->stream);
+    PhaseTimer timer(ctx);
     int64_t unconv = 0, iz_iters = 0, iz_steps = 0;
     if ((e = ctx->counters.ensure(64)) || (e = ctx->x.ensure(sizeof(double) * d * N)) ||
         (e = ctx->cont.ensure(sizeof(double) * N)) || (e = ctx->B.ensure(sizeof(double) * d * N)) ||
         (e = ctx->steps.ensure(sizeof(int64_t) * N + sizeof(int32_t) * N))) {
-        bmc_rules_destroy(rules);
+        release();
         return fail(BMC_ENOMEM, "device buffers: %s", hipGetErrorString(e));
     }
     unsigned long long* steps_total = (unsigned long long*)ctx->counters.ptr;
@@ -85,7 +102,7 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     double* cont = (double*)ctx->cont.ptr;
     double* B = (double*)ctx->B.ptr;
     if ((e = hipMemsetAsync(steps_total, 0, sizeof(unsigned long long), ctx->stream))) {
-        bmc_rules_destroy(rules);
+        release();
         return hip_fail(e, "counter reset");
     }
 
@@ -138,19 +155,19 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
         }
     }
     double sums[3] = {0, 0, 0};
+    unsigned long long* inner_host = (unsigned long long*)((char*)ctx->host_io + 64);
+    if (!st && (e = hipMemcpyAsync(inner_host, steps_total, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                   ctx->stream)))
+        st = hip_fail(e, "result read");
     if (!st) {
         timer.mark(PH_FINAL);
-        st = final_price_impl(ctx, ds, spec, rules, opts->n_final, seed, prec, sums, tune);
+        st = final_price_impl(ctx, ds, spec, rules, opts->n_final, seed, prec, sums, tune);   // syncs
         timer.mark(-1);
     }
-    unsigned long long inner = 0;
-    if (!st) {
-        if ((e = hipMemcpyAsync(&inner, steps_total, sizeof(inner), hipMemcpyDeviceToHost, ctx->stream)) ||
-            (e = hipStreamSynchronize(ctx->stream)))
-            st = hip_fail(e, "result read");
-    }
+    if (!st && *status_host != 0) st = fail(BMC_ENOTSPD, "correlation matrix is not positive definite");
+    const unsigned long long inner = st ? 0 : *inner_host;
     if (st) {
-        bmc_rules_destroy(rules);
+        release();
         return st;
     }
     bmc_result r;
@@ -167,7 +184,7 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     *out = r;
     if (rules_out) *rules_out = rules;
-    else bmc_rules_destroy(rules);
+    else release();
     return BMC_OK;
 }
 

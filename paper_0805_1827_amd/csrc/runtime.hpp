@@ -7,6 +7,7 @@
 
 #include <map>
 #include <string>
+#include <vector>
 
 #include "bmc.h"
 
@@ -51,6 +52,8 @@ struct bmc_ctx {
     std::map<uint64_t, int> ppt_table;
     // batched date sweeps as a HIP graph: the last captured launch sequence,
     // replayed while the signature (launch shapes and buffers) is unchanged
+    std::vector<hipEvent_t> ev_pool;   // reusable timing events
+    bmc::DBuf srules;                  // rule table of bmc_price when the caller keeps none
     bool graphs = false;
     std::string graph_sig;
     hipGraphExec_t graph_exec = nullptr;
@@ -69,6 +72,12 @@ struct bmc_rules {
 namespace bmc {
 
 bmc_status upload_spec(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot);
+// As upload_spec without waiting: the setup status (0 or -2) is copied to
+// *status_host (pinned) on the stream; the caller checks it after a sync.
+bmc_status upload_spec_async(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot, int32_t* status_host);
+// Rule table in context scratch (rows of never-exercise values), for callers
+// that do not keep the rules; valid until the next call on the context.
+bmc_status scratch_rules(bmc_ctx* ctx, const bmc_spec* spec, int method, bmc_rules* out);
 void pack_spec(const bmc_spec* s, HostSpecPack* p);
 const double* dev_S0(const void* devspec);
 uint32_t choose_ppt(const bmc_ctx* ctx, int d, int prec, int64_t points, int64_t n, const Tuning* tune);

@@ -160,12 +160,14 @@ bmc_status bmc_price_batch(bmc_ctx *ctx, int32_t count, const bmc_spec *specs, c
  * bmc_tuning_get returns the shape a call with (d, precision, N, n) uses. */
 bmc_status bmc_tuning_set(bmc_ctx *ctx, int32_t d, int32_t precision, int64_t n, int32_t ppt);
 bmc_status bmc_tuning_get(bmc_ctx *ctx, int32_t d, int32_t precision, int64_t N, int64_t n, int32_t *ppt);
-/* Autotuner: times the continuation kernel of spec (CMC points at its middle
- * date, rules that never exercise) with N points and n paths for every
- * shape ppt = 1, 2, 4, .. up to one job per point (at most 64) and stores
- * the fastest per executed path-step in ctx's table for the spec's
- * dimension bucket, precision and n class; *ppt_out (may be NULL) receives
- * it.  Synchronous. */
+/* Autotuner: times the continuation kernel of spec with N points and n
+ * paths for every shape ppt = 1, 2, 4, .. up to one job per point (at most
+ * 64), at the first, middle and last dates (CMC points, exercise rules from
+ * a small CMC pricing of the spec: at most 4096 points, n/8 paths), and
+ * stores the shape with the most executed path-steps per
+ * second over those dates in ctx's table for the spec's dimension bucket,
+ * precision and n class; *ppt_out (may be NULL) receives it.  N = 1 tunes
+ * the final pricing (date 0).  Synchronous. */
 bmc_status bmc_autotune(bmc_ctx *ctx, const bmc_spec *spec, int32_t precision, int64_t N, int64_t n,
                         int32_t *ppt_out);
 

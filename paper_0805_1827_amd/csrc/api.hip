@@ -493,11 +493,14 @@ extern "C" bmc_status bmc_tuning_set(bmc_ctx* ctx, int32_t d, int32_t precision,
     return BMC_OK;
 }
 
-// Autotuner: times the continuation kernel of this spec at its middle date
-// (CMC training points, rules that never exercise, so every path runs to
-// maturity) for each launch shape ppt = 1, 2, 4, .. up to one chunk per
-// point (at most 64), and stores the fastest per executed path-step in the
-// context's table for the spec's (dimension bucket, precision, n class).
+// Autotuner: times the continuation kernel of this spec for each launch
+// shape ppt = 1, 2, 4, .. up to one chunk per point (at most 64), on CMC
+// training points at the first, middle and last dates under exercise rules
+// from a small CMC pricing of the same spec (N <= 4096 points, n/8 paths),
+// so that path and job lengths spread as in a real sweep, and
+// stores the shape with the largest executed path-steps per second over the
+// three dates in the context's table for the spec's (dimension bucket,
+// precision, n class).  With a single date (or N = 1) it times date 0.
 extern "C" bmc_status bmc_autotune(bmc_ctx* ctx, const bmc_spec* spec, int32_t precision, int64_t N, int64_t n,
                                    int32_t* ppt_out)
 {
@@ -506,59 +509,91 @@ extern "C" bmc_status bmc_autotune(bmc_ctx* ctx, const bmc_spec* spec, int32_t p
     if (N < 1 || N > (1 << 24) || n < 2 || n > 0x7FFFFFFF) return fail(BMC_EINVAL, "N or n out of range");
     (void)hipSetDevice(ctx->device);
     bmc_status st;
-    if ((st = upload_spec(ctx, spec, ctx->spec))) return st;
-    bmc_rules* rules = nullptr;
-    if ((st = bmc_rules_create(ctx, spec, BMC_CMC, &rules))) return st;
     const int d = spec->d, NT = spec->n_dates;
-    const int m = NT >= 2 ? NT / 2 : 0;
-    hipError_t e;
-    if ((e = ctx->x.ensure(sizeof(double) * d * N)) || (e = ctx->B.ensure(sizeof(double) * d * N)) ||
-        (e = ctx->steps.ensure(sizeof(int64_t) * N)) || (e = ctx->counters.ensure(64))) {
-        bmc_rules_destroy(rules);
-        return fail(BMC_ENOMEM, "autotune buffers: %s", hipGetErrorString(e));
+    // exercise rules close to the real ones, so that path lengths (and the
+    // spread of job lengths) are realistic: a small CMC pricing first
+    bmc_rules* learned = nullptr;
+    if (NT >= 2) {
+        bmc_opts o;
+        std::memset(&o, 0, sizeof(o));
+        o.method = BMC_CMC;
+        o.precision = precision;
+        o.N = std::min<int64_t>(std::max<int64_t>(N, 1024), 4096);
+        o.n = std::max<int64_t>(256, std::min<int64_t>(n, 4096) / 8);
+        o.n_final = 2;
+        o.seed = 7;
+        bmc_result tmp;
+        if ((st = bmc_price_impl(ctx, spec, &o, &learned, &tmp, nullptr))) return st;
     }
-    double* x = (double*)ctx->x.ptr;
-    const double* pts = x;
-    int64_t npts = N;
-    if (m >= 1) {
-        if ((st = sample_points_impl(ctx, ctx->spec.ptr, spec, BMC_CMC, m, N, 1u, x, (double*)ctx->B.ptr))) {
-            bmc_rules_destroy(rules);
-            return st;
-        }
+    if ((st = upload_spec(ctx, spec, ctx->spec))) {
+        bmc_rules_destroy(learned);
+        return st;
+    }
+    bmc_rules scratch;
+    if (!learned && (st = scratch_rules(ctx, spec, BMC_CMC, &scratch))) return st;
+    const bmc_rules& rules = learned ? *learned : scratch;
+    struct Release {
+        bmc_rules* r;
+        ~Release() { bmc_rules_destroy(r); }
+    } release_learned{learned};
+    std::vector<int> dates;
+    if (NT >= 2 && N > 1) {
+        for (int m : {1, NT / 2, NT - 1})
+            if (m >= 1 && (dates.empty() || dates.back() != m)) dates.push_back(m);
     } else {
-        pts = dev_S0(ctx->spec.ptr);
-        npts = 1;
+        dates.push_back(0);
     }
+    hipError_t e;
+    if ((e = ctx->x.ensure(sizeof(double) * d * N * dates.size())) || (e = ctx->B.ensure(sizeof(double) * d * N)) ||
+        (e = ctx->counters.ensure(64)))
+        return fail(BMC_ENOMEM, "autotune buffers: %s", hipGetErrorString(e));
+    std::vector<const double*> pts(dates.size());
+    for (size_t i = 0; i < dates.size(); ++i) {
+        if (dates[i] == 0) {
+            pts[i] = dev_S0(ctx->spec.ptr);
+            continue;
+        }
+        double* x = (double*)ctx->x.ptr + (size_t)d * N * i;
+        if ((st = sample_points_impl(ctx, ctx->spec.ptr, spec, BMC_CMC, dates[i], N, 1u, x, (double*)ctx->B.ptr)))
+            return st;
+        pts[i] = x;
+    }
+    const int64_t npts = dates[0] == 0 ? 1 : N;
     unsigned long long* total = (unsigned long long*)ctx->counters.ptr;
     hipEvent_t e0, e1;
-    if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
-        bmc_rules_destroy(rules);
-        return hip_fail(e, "autotune events");
-    }
+    if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) return hip_fail(e, "autotune events");
     int best = 1;
     double best_rate = -1.0;
     const int64_t max_ppt = std::min<int64_t>(64, std::max<int64_t>(1, (n + 255) / 256));
     for (int ppt = 1; ppt <= max_ppt && !st; ppt *= 2) {
         Tuning t;
         t.ppt = ppt;
-        double rate = 0.0;
-        for (int rep = 0; rep < 3 && !st; ++rep) {   // rep 0 warms up
-            if ((e = hipMemsetAsync(total, 0, sizeof(unsigned long long), ctx->stream)) ||
-                (e = hipEventRecord(e0, ctx->stream))) {
-                st = hip_fail(e, "autotune");
-                break;
+        double secs = 0.0, steps_all = 0.0;
+        for (int rep = 0; rep < 4 && !st; ++rep) {   // rep 0 warms up
+            for (size_t i = 0; i < dates.size() && !st; ++i) {
+                const int m = dates[i];
+                if ((e = hipMemsetAsync(total, 0, sizeof(unsigned long long), ctx->stream)) ||
+                    (e = hipEventRecord(e0, ctx->stream))) {
+                    st = hip_fail(e, "autotune");
+                    break;
+                }
+                st = run_cont(ctx, ctx->spec.ptr, d, NT, BMC_CMC, rules.width, rules.w64, rules.w32, precision, m,
+                              pts[i], npts, nullptr, nullptr, (uint32_t)n, 1u,
+                              key_hi(m == 0 ? BMC_STREAM_FINAL : BMC_STREAM_INNER, m), nullptr, nullptr, nullptr,
+                              nullptr, total, &t);
+                unsigned long long steps = 0;
+                float ms = 0.f;
+                if (!st && ((e = hipEventRecord(e1, ctx->stream)) ||
+                            (e = hipMemcpyAsync(&steps, total, sizeof(steps), hipMemcpyDeviceToHost, ctx->stream)) ||
+                            (e = hipStreamSynchronize(ctx->stream)) || (e = hipEventElapsedTime(&ms, e0, e1))))
+                    st = hip_fail(e, "autotune");
+                if (!st && rep > 0) {
+                    secs += ms * 1e-3;
+                    steps_all += (double)steps;
+                }
             }
-            st = run_cont(ctx, ctx->spec.ptr, d, NT, BMC_CMC, rules->width, rules->w64, rules->w32, precision, m, pts,
-                          npts, nullptr, nullptr, (uint32_t)n, 1u, key_hi(BMC_STREAM_INNER, m), nullptr, nullptr,
-                          nullptr, nullptr, total, &t);
-            unsigned long long steps = 0;
-            float ms = 0.f;
-            if (!st && ((e = hipEventRecord(e1, ctx->stream)) ||
-                        (e = hipMemcpyAsync(&steps, total, sizeof(steps), hipMemcpyDeviceToHost, ctx->stream)) ||
-                        (e = hipStreamSynchronize(ctx->stream)) || (e = hipEventElapsedTime(&ms, e0, e1))))
-                st = hip_fail(e, "autotune");
-            if (!st && rep > 0 && ms > 0.f) rate += (double)steps / (ms * 1e-3);
         }
+        const double rate = secs > 0.0 ? steps_all / secs : 0.0;
         if (!st && rate > best_rate) {
             best_rate = rate;
             best = ppt;
@@ -566,7 +601,6 @@ extern "C" bmc_status bmc_autotune(bmc_ctx* ctx, const bmc_spec* spec, int32_t p
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    bmc_rules_destroy(rules);
     if (st) return st;
     ctx->ppt_table[ppt_key(cont_bucket(d), precision + 1, n_class(n))] = best;
     if (ppt_out) *ppt_out = best;
@@ -812,7 +846,7 @@ extern "C" bmc_status bmc_iz_search(bmc_ctx* ctx, const bmc_spec* spec, const bm
 
 bmc_status bmc::final_price_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, const bmc_rules* rules,
                                  int64_t n_final, uint32_t seed, int prec, double* host_sums,
-                                 const Tuning* tune)
+                                 const Tuning* tune, bool sync)
 {
     hipError_t e;
     if ((e = ctx->counters.ensure(64))) return hip_fail(e, "counters");
@@ -823,14 +857,20 @@ bmc_status bmc::final_price_impl(bmc_ctx* ctx, const void* devspec, const bmc_sp
                              seed, key_hi(BMC_STREAM_FINAL, 0), nullptr, nullptr, fsteps, sums, nullptr, tune);
     if (st) return st;
     if ((e = hipMemcpyAsync(ctx->host_io, sums, 16, hipMemcpyDeviceToHost, ctx->stream)) ||
-        (e = hipMemcpyAsync((char*)ctx->host_io + 16, fsteps, 8, hipMemcpyDeviceToHost, ctx->stream)) ||
-        (e = hipStreamSynchronize(ctx->stream)))
+        (e = hipMemcpyAsync((char*)ctx->host_io + 16, fsteps, 8, hipMemcpyDeviceToHost, ctx->stream)))
         return hip_fail(e, "final read");
+    if (!sync) return BMC_OK;
+    if ((e = hipStreamSynchronize(ctx->stream))) return hip_fail(e, "final read");
+    read_final_sums(ctx, host_sums);
+    return BMC_OK;
+}
+
+void bmc::read_final_sums(const bmc_ctx* ctx, double* host_sums)
+{
     std::memcpy(host_sums, ctx->host_io, 16);
     int64_t fs;
-    std::memcpy(&fs, (char*)ctx->host_io + 16, 8);
+    std::memcpy(&fs, (const char*)ctx->host_io + 16, 8);
     host_sums[2] = (double)fs;
-    return BMC_OK;
 }
 
 void bmc::fill_price(const double* sums, int64_t n_final, bmc_result* out)

@@ -82,8 +82,9 @@ __device__ __forceinline__ double bcast_lane(double v, int src)
 // threads must be lanes 0..63 of one wave, all active): lane i keeps row i
 // of the factor in registers and the columns travel by lane broadcasts,
 // with no block barrier.  Same per-entry subtraction order as above; the
-// divisions by a pivot become products with its reciprocal (one division
-// per column).  A (packed, in LDS) is overwritten with the factor.
+// divisions by a pivot become products with its reciprocal, which comes
+// with the pivot from a refined reciprocal square root (no division).  A
+// (packed, in LDS) is overwritten with the factor.
 // Returns false (on every lane) if a pivot is not positive.
 template <int P>
 __device__ bool wave_spd_solve(int p, double* A, double lam, const double* b, double* x)
@@ -107,8 +108,12 @@ __device__ bool wave_spd_solve(int p, double* A, double lam, const double* b, do
             ok = false;
             dc = 1.0;
         }
-        const double lcc = sqrt(dc);
-        const double inv = 1.0 / lcc;
+        // 1/sqrt(dc) from the hardware estimate and two Newton steps
+        // y <- y (3 - dc y^2) / 2, then L_cc = dc / sqrt(dc)
+        double inv = __builtin_amdgcn_rsq(dc);
+        inv = inv * (1.5 - 0.5 * dc * inv * inv);
+        inv = inv * (1.5 - 0.5 * dc * inv * inv);
+        const double lcc = dc * inv;
         if (lane == c) {
             row[c] = lcc;
             invd = inv;
@@ -157,7 +162,16 @@ __device__ inline bool spd_solve(int p, double* A, double lam, double* b, double
 {
     if (p <= 32) {
         if (threadIdx.x < 64) {
-            const bool ok = p <= 16 ? wave_spd_solve<16>(p, A, lam, b, x) : wave_spd_solve<32>(p, A, lam, b, x);
+            bool ok;
+            switch (p) {   // exact widths of the CMC rules for d <= 6 (p = 2d + 3)
+            case 5: ok = wave_spd_solve<5>(p, A, lam, b, x); break;
+            case 7: ok = wave_spd_solve<7>(p, A, lam, b, x); break;
+            case 9: ok = wave_spd_solve<9>(p, A, lam, b, x); break;
+            case 11: ok = wave_spd_solve<11>(p, A, lam, b, x); break;
+            case 13: ok = wave_spd_solve<13>(p, A, lam, b, x); break;
+            case 15: ok = wave_spd_solve<15>(p, A, lam, b, x); break;
+            default: ok = p <= 16 ? wave_spd_solve<16>(p, A, lam, b, x) : wave_spd_solve<32>(p, A, lam, b, x);
+            }
             if (threadIdx.x == 0) *flag = ok ? 0 : 1;
         }
         __syncthreads();
@@ -430,6 +444,30 @@ __device__ inline void fit_round_point_s(const double* phi, const double* lab, c
         for (int f = 0; f < S; ++f) row[f] = 0.0;
         wz[2 * tl] = 0.0;
     }
+}
+
+// Later boosting rounds of a block that keeps its tile for the whole fit:
+// the standardised features are still in row[0..p) (stride SW) and F, the
+// label and the mask of its point are in registers; same arithmetic as
+// fit_round_point16 / fit_round_point_s.
+__device__ inline void fit_round_point_resident(int p, int SW, bool in, const double* beta_prev, double& F,
+                                                double lab, double msk, double* psis, double* wz)
+{
+    const int tl = threadIdx.x;
+    double* row = psis + (size_t)SW * tl;
+    if (!in) return;   // row and weight stay zero
+    double dF = 0.0;
+    for (int f = 0; f < p; ++f) dF += beta_prev[f] * row[f];
+    const double Fj = F + 0.5 * dF;
+    const double pj = 1.0 / (1.0 + exp(-2.0 * Fj));
+    F = Fj;
+    double w = pj * (1.0 - pj);
+    if (w < 1e-10) w = 1e-10;
+    double z = (lab - pj) / w;
+    if (z > 4.0) z = 4.0;
+    if (z < -4.0) z = -4.0;
+    row[p] = z;
+    wz[2 * tl] = w * msk;
 }
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));

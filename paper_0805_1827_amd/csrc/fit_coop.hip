@@ -175,13 +175,32 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
     // partials only after the barrier of round r+1, which every block passes
     // after reading round r's, so one barrier per round suffices.
     const size_t part_stride = (size_t)a.ntiles * Q;
+    // A block with (at most) one tile keeps it for the whole fit: its rows
+    // stay in psi, F, the label and the mask in registers, and the merges
+    // stage through aux instead.
+    const bool resident = mode != 0 && a.ntiles <= grp.size();
+    double F_reg = 0.0, lab_reg = 0.0, msk_reg = 0.0;
+    const int64_t j_own = (int64_t)grp.rank() * T + tid;
+    const bool own_in = grp.rank() < a.ntiles && j_own < N;
+    if (resident && own_in) {
+        lab_reg = fs.lab[j_own];
+        msk_reg = fs.msk[j_own];
+    }
+    double* mstage = resident ? aux : psi;
+    const int mcap = resident ? coop_aux(p, T) : cap;
     for (int r = 0; r < a.rounds; ++r) {
         double* partA = fs.partA + (size_t)(r & 1) * part_stride;
         FIT_MARK(8 + 8 * r);
         for (int t = grp.rank(); t < a.ntiles; t += grp.size()) {
             const int64_t j0 = (int64_t)t * T;
             const int nt = (int)min((int64_t)T, N - j0);
-            if (mode == 1) {
+            if (resident && r > 0) {
+                fit_round_point_resident(p, SW, own_in, beta, F_reg, lab_reg, msk_reg, psi, wz);
+                __syncthreads();
+                FIT_MARK(9 + 8 * r);
+                if (mode == 1) fit_tile_normal_eqs_mfma(psi, wz, p, nt, aux, partA + (size_t)t * Q);
+                else fit_tile_normal_eqs_mfma_wide(psi, SW, wz, p, nt, partA + (size_t)t * Q);
+            } else if (mode == 1) {
                 fit_round_point16(fs.phi, fs.lab, fs.msk, N, p, mu, sd, r > 0 ? beta : nullptr, j0 + tid, fs.F,
                                   fs.pi, psi, wz);
                 __syncthreads();
@@ -202,10 +221,11 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
             }
             __syncthreads();
         }
+        if (resident && r == 0 && own_in) F_reg = fs.F[j_own];   // round 0 wrote it
         FIT_MARK(10 + 8 * r);
         grp.sync();
         FIT_MARK(11 + 8 * r);
-        merge_tiles(partA, a.ntiles, Q, psi, cap, A);   // A then bv
+        merge_tiles(partA, a.ntiles, Q, mstage, mcap, A);   // A then bv
         FIT_MARK(12 + 8 * r);
         if (tid == 0) {
             double tr = 0.0;

@@ -161,8 +161,10 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
         st = hip_fail(e, "result read");
     if (!st) {
         timer.mark(PH_FINAL);
-        st = final_price_impl(ctx, ds, spec, rules, opts->n_final, seed, prec, sums, tune);   // syncs
-        timer.mark(-1);
+        st = final_price_impl(ctx, ds, spec, rules, opts->n_final, seed, prec, sums, tune, false);
+        timer.mark(-1);   // before the sync, so that every timing event has completed after it
+        if (!st && (e = hipStreamSynchronize(ctx->stream))) st = hip_fail(e, "result read");
+        if (!st) read_final_sums(ctx, sums);
     }
     if (!st && *status_host != 0) st = fail(BMC_ENOTSPD, "correlation matrix is not positive definite");
     const unsigned long long inner = st ? 0 : *inner_host;

@@ -98,7 +98,18 @@ bmc_status iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spe
                           int32_t* iters, int64_t* steps_out, const Tuning* tune);
 bmc_status final_price_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec,
                             const bmc_rules* rules, int64_t n_final, uint32_t seed, int prec,
-                            double* host_sums, const Tuning* tune);
+                            double* host_sums, const Tuning* tune, bool sync = true);
+// With sync = false the sums land in the context's pinned area at the next
+// stream sync; read_final_sums then unpacks them.
+void read_final_sums(const bmc_ctx* ctx, double* host_sums);
+
+}  // namespace bmc
+
+// Whole CMC / I&Z pricer (pricer.hip); tune forces a launch shape (or NULL).
+bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* opts, bmc_rules** rules_out,
+                          bmc_result* out, const bmc::Tuning* tune);
+
+namespace bmc {
 void fill_price(const double* sums, int64_t n_final, bmc_result* out);
 
 }  // namespace bmc

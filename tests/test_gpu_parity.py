@@ -422,3 +422,13 @@ def test_rules_export_import_roundtrip(bmc, ctx, torch_mod, inputs):
     a = bmc.bmc_final_price(ctx, spec, rules, 10000, 2)
     b = bmc.bmc_final_price(ctx, spec, back, 10000, 2)
     assert a["price"] == b["price"] == res["price"]
+
+
+def test_phase_times_are_measured(bmc, ctx, inputs):
+    """Every phase of repeated prices on one context (pooled timing events)
+    has a positive time and the phases fit inside the call's wall time."""
+    spec = inputs.geometric_put5()
+    for _ in range(4):
+        r = bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP32, N=1024, n=1024, n_final=200000, seed=2)
+        assert r["calc_seconds"] > 0 and r["fit_seconds"] > 0 and r["final_seconds"] > 0, r
+        assert r["calc_seconds"] + r["fit_seconds"] + r["final_seconds"] <= r["seconds"] * 1.001

@@ -75,6 +75,16 @@ def assert_same_rule(spec, w_gpu, w_ref, x, what=""):
     assert np.all(np.abs(Fg - Fr) <= 1e-6 * (1.0 + np.abs(Fr))), f"{what}: max |dF| {np.max(np.abs(Fg - Fr)):.3g}"
 
 
+def assert_same_labels(orc, spec, x, c_gpu, c_ref, what=""):
+    """CMC exercise labels (Phi > 0 and Phi - C > 0) from the GPU and the
+    oracle continuation values agree, except where |Phi - C| < 1e-9."""
+    phi = np.array([orc.payoff(spec, np.log(x[:, j])) for j in range(x.shape[1])])
+    y_gpu, y_ref = phi - c_gpu, phi - c_ref
+    lab_gpu, lab_ref = (phi > 0) & (y_gpu > 0), (phi > 0) & (y_ref > 0)
+    far = np.abs(y_ref) >= 1e-9
+    assert np.array_equal(lab_gpu[far], lab_ref[far]), f"{what}: {np.sum(lab_gpu[far] != lab_ref[far])} labels differ"
+
+
 def gpu_rules(bmc, ctx, spec, method, table):
     r = bmc.bmc_rules_create(ctx, spec, method)
     bmc.set_rules_table(r, table)
@@ -150,6 +160,7 @@ def test_continuation_c1_every_date(bmc, ctx, orc, torch_mod, c1_rules):
         assert_close(c, ref["cont"], spec.K, what=f"cont m={m}")
         assert_close(se, ref["se"], spec.K, rel=1e-8, what=f"se m={m}")
         assert np.array_equal(st, ref["steps"]), m
+        assert_same_labels(orc, spec, x, c, ref["cont"], what=f"labels m={m}")
 
 
 def _small_rules(orc, spec, method=0, N=128, n=128):
@@ -167,6 +178,7 @@ def test_continuation_multi_asset(bmc, ctx, orc, torch_mod, inputs, case):
         c, se, st, ref = cont_parity(bmc, ctx, orc, torch_mod, spec, bmc.CMC, table, m, x, n, 5)
         assert_close(c, ref["cont"], spec.K, what=f"{case} m={m}")
         assert np.array_equal(st, ref["steps"])
+        assert_same_labels(orc, spec, x, c, ref["cont"], what=f"{case} labels m={m}")
 
 
 @pytest.mark.parametrize("d,payoff", [(12, 0), (20, 1), (40, 2)])
@@ -363,6 +375,7 @@ def test_full_size_geometric_put_sampled(bmc, ctx, orc, torch_mod, inputs):
         if prec == bmc.FP64:
             assert_close(c[ids], ref["cont"], spec.K, what="full-size cont")
             assert np.array_equal(st[ids], ref["steps"])
+            assert_same_labels(orc, spec, x[:, ids], c[ids], ref["cont"], what="full-size labels")
         else:
             assert np.all(np.abs(c[ids] - ref["cont"]) <= 0.1 * ref["se"] + 1e-12)
         assert np.all(c >= 0) and np.all(np.isfinite(se))

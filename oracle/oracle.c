@@ -90,11 +90,11 @@ static uint32_t key_hi(int stream, int date)
  * p from point j uses B = ceil(d/4) blocks with counters (k*B + b, p, j, 0);
  * asset i takes normal i mod 4 of block i / 4. */
 static void step_normals(int d, uint32_t k0, uint32_t k1, int k, uint32_t p,
-                         uint32_t j, double *z)
+                         uint32_t j, uint32_t slot, double *z)
 {
     int nblk = (d + 3) / 4;
     for (int b = 0; b < nblk; ++b) {
-        uint32_t ctr[4] = {(uint32_t)(k * nblk + b), p, j, 0u};
+        uint32_t ctr[4] = {(uint32_t)(k * nblk + b), p, j, slot};
         double blk[4];
         orc_normal_block(k0, k1, ctr, blk);
         for (int w = 0; w < 4 && 4 * b + w < d; ++w)
@@ -185,6 +185,22 @@ int orc_rule_width(int method, int d)
     return 1 + q + q * (q + 1) / 2;
 }
 
+/* I&Z regions (Section 2.2): the call on the maximum of d assets has d
+ * exercise regions, region i where asset i is the largest, each with its own
+ * boundary in the other d - 1 assets; the put family has one boundary in
+ * assets 2..d.  A rule row holds one block of orc_rule_width(IZ, d)
+ * coefficients per region. */
+int orc_iz_regions(const orc_spec *s)
+{
+    return s->payoff == ORC_CALL_MAX ? s->d : 1;
+}
+
+int orc_rule_width_spec(const orc_spec *s, int method)
+{
+    if (method == ORC_CMC) return orc_rule_width(ORC_CMC, s->d);
+    return orc_iz_regions(s) * orc_rule_width(ORC_IZ, s->d);
+}
+
 /* CMC features (reading of Section 3.2; the paper defers the classifier's
  * inputs to the Picazo reference): with u_i = ln(S_i / K) and g = Phi(S)/K,
  *   phi(S) = [1, u_1..u_d, u_1^2..u_d^2, g, g^2]. */
@@ -203,21 +219,22 @@ static void cmc_features(const orc_spec *s, const double *logS, double payoff, d
     phi[2 + 2 * d] = g * g;
 }
 
-/* I&Z boundary features: full quadratic in v_i = ln(S_i/K) of assets 2..d,
- * ordered [1, v_2..v_d, v_a v_b for a <= b]. */
-static void iz_features(const orc_spec *s, const double *logS, double *xi)
+/* I&Z boundary features of region r: full quadratic in v = ln(S_i/K) of the
+ * assets i != r in increasing order, [1, v_1..v_q, v_a v_b for a <= b]
+ * (region 0 of the put family: assets 2..d). */
+static void iz_features(const orc_spec *s, const double *logS, int region, double *xi)
 {
     int q = s->d - 1;
     double lnK = log(s->K);
     xi[0] = 1.0;
-    for (int a = 0; a < q; ++a) xi[1 + a] = logS[1 + a] - lnK;
+    for (int a = 0; a < q; ++a) xi[1 + a] = logS[a < region ? a : a + 1] - lnK;
     int f = 1 + q;
     for (int a = 0; a < q; ++a)
         for (int b = a; b < q; ++b) xi[f++] = xi[1 + a] * xi[1 + b];
 }
 
-/* I&Z searches the first asset.  Puts exercise below the boundary; the
- * one-asset call exercises above it. */
+/* I&Z: puts search the first asset and exercise below its boundary; the
+ * max-call searches the asset of the region and exercises above it. */
 static int iz_direction_is_call(const orc_spec *s)
 {
     return s->payoff == ORC_CALL_MAX;
@@ -240,11 +257,16 @@ static int exercise_now(const orc_spec *s, int method, const double *row,
         return F > 0.0;
     }
     double xi[1 + 63 + 63 * 64 / 2];
-    iz_features(s, logS, xi);
     int p = orc_rule_width(ORC_IZ, s->d);
+    int region = 0;
+    if (iz_direction_is_call(s))   /* region of the largest asset (first one on ties) */
+        for (int i = 1; i < s->d; ++i)
+            if (logS[i] > logS[region]) region = i;
+    iz_features(s, logS, region, xi);
+    const double *b = row + (size_t)region * p;
     double bnd = 0.0;
-    for (int f = 0; f < p; ++f) bnd += row[f] * xi[f];
-    if (iz_direction_is_call(s)) return logS[0] > bnd;
+    for (int f = 0; f < p; ++f) bnd += b[f] * xi[f];
+    if (iz_direction_is_call(s)) return logS[region] > bnd;
     return logS[0] < bnd;
 }
 
@@ -259,6 +281,7 @@ typedef struct {
     int m;
     const double *L;     /* d*d */
     uint32_t k0, k1;
+    uint32_t slot;       /* fourth counter word: I&Z region (0 otherwise) */
 } path_ctx;
 
 /* Runs paths p_lo..p_hi-1 of point j from log-point logx; accumulates the
@@ -275,7 +298,7 @@ static void run_paths(const path_ctx *c, const double *logx, uint32_t j,
         for (int i = 0; i < d; ++i) logS[i] = logx[i];
         for (int k = m + 1; k <= NT; ++k) {
             double dt = date_of(s, k) - date_of(s, k - 1);
-            step_normals(d, c->k0, c->k1, k, (uint32_t)p, j, z);
+            step_normals(d, c->k0, c->k1, k, (uint32_t)p, j, c->slot, z);
             for (int i = 0; i < d; ++i) {
                 double corr = 0.0;
                 for (int l = 0; l <= i; ++l) corr += c->L[i * d + l] * z[l];
@@ -361,7 +384,7 @@ int orc_continuation(const orc_spec *s, int method, const double *rules, int m,
     if (!L) return ORC_ENOMEM;
     rc = orc_cholesky(d, s->rho, L);
     if (rc) { free(L); return rc; }
-    path_ctx c = {s, method, rules, orc_rule_width(method, d), m, L, seed, key_hi(stream, m)};
+    path_ctx c = {s, method, rules, orc_rule_width_spec(s, method), m, L, seed, key_hi(stream, m), 0u};
     cont_job job;
     job.c = &c; job.x = x; job.ids = ids; job.N = N; job.n = n;
     job.nchunk = (n + CHUNK - 1) / CHUNK;
@@ -529,11 +552,12 @@ static double norm_inv(double u)
     return 0.5 * (lo + hi);
 }
 
-int orc_points_iz(const orc_spec *s, int m, int64_t J, double *x)
+int orc_points_iz(const orc_spec *s, int m, int region, int64_t J, double *x)
 {
     int rc = check_spec(s);
     if (rc) return rc;
-    if (m < 1 || m > s->n_dates || J < 1) return ORC_EINVAL;
+    if (m < 1 || m > s->n_dates || J < 1 || region < 0 || region >= orc_iz_regions(s))
+        return ORC_EINVAL;
     int d = s->d, q = d - 1;
     double tm = date_of(s, m);
     int64_t a = orc_korobov(J, q);
@@ -543,10 +567,10 @@ int orc_points_iz(const orc_spec *s, int m, int64_t J, double *x)
         for (int i = 1; i < q; ++i) g[i] = (g[i - 1] * a) % J;
     }
     for (int64_t j = 0; j < J; ++j) {
-        x[j] = s->K;
+        x[(size_t)region * J + j] = s->K;
         for (int i = 0; i < q; ++i) {
             double u = ((double)((j * g[i]) % J) + 0.5) / (double)J;
-            int asset = i + 1;
+            int asset = i < region ? i : i + 1;
             double drift = s->r - s->delta[asset] - 0.5 * s->sigma[asset] * s->sigma[asset];
             x[(size_t)asset * J + j] =
                 s->S0[asset] * exp(drift * tm + s->sigma[asset] * sqrt(tm) * norm_inv(u));
@@ -680,13 +704,15 @@ int orc_fit_cmc(const orc_spec *s, const double *x, const double *cont,
 
 /* ------------------------------------------------------------------------- */
 /* I&Z boundary-point search (Section 2.1 eq. (1), Section 2.4): start the
- * searched coordinate at K and iterate s <- Phi_1^{-1}(C(s)) with the same
+ * searched coordinate at K and iterate s <- Phi^{-1}(C(s)) with the same
  * inner paths each time (common random numbers), until |s' - s| < eps.
- * Phi_1^{-1}(c) is the first-asset price whose payoff equals c:
+ * The searched coordinate is asset 1 for the put family and the asset of the
+ * region for the max-call; Phi^{-1}(c) is its price whose payoff equals c:
  *   geometric put      (K - c)^d / prod_{i>=2} x_i,
  *   arithmetic put     d (K - c) - sum_{i>=2} x_i,
- *   one-asset call     K + c.
- * A non-positive inverse drops the point. */
+ *   max-call           K + c.
+ * A non-positive inverse drops the point; so does a max-call fixed point that
+ * is not the largest asset (it lies outside the region). */
 
 static double iz_invert(const orc_spec *s, const double *x_other, double c)
 {
@@ -706,6 +732,7 @@ static double iz_invert(const orc_spec *s, const double *x_other, double c)
 typedef struct {
     const path_ctx *c;
     const double *x;
+    int region;
     int64_t J, n;
     double eps;
     int max_iter;
@@ -727,20 +754,27 @@ static void *iz_worker(void *arg)
         int64_t j = job->next++;
         pthread_mutex_unlock(&job->lock);
         if (j >= job->J) break;
-        for (int i = 0; i < d; ++i) xo[i] = job->x[(size_t)i * job->J + j];
+        int r = job->region;
+        double others_max = 0.0;
+        for (int i = 0; i < d; ++i) {
+            xo[i] = job->x[(size_t)i * job->J + j];
+            if (i != r && xo[i] > others_max) others_max = xo[i];
+        }
         double sv = s->K, result = -1.0;
         int it = 0;
         int64_t st = 0;
         while (it < job->max_iter) {
-            logx[0] = log(sv);
-            for (int i = 1; i < d; ++i) logx[i] = log(xo[i]);
+            for (int i = 0; i < d; ++i) logx[i] = i == r ? log(sv) : log(xo[i]);
             double sum = 0.0, sq = 0.0;
             run_paths(job->c, logx, (uint32_t)j, 0, job->n, &sum, &sq, &st);
             double cval = sum / (double)job->n;
             double snew = iz_invert(s, xo, cval);
             ++it;
             if (!(snew > 0.0) || !isfinite(snew)) break;
-            if (fabs(snew - sv) < job->eps) { result = snew; break; }
+            if (fabs(snew - sv) < job->eps) {
+                if (!(s->payoff == ORC_CALL_MAX && snew <= others_max)) result = snew;
+                break;
+            }
             sv = snew;
         }
         job->s_out[j] = result;
@@ -750,24 +784,25 @@ static void *iz_worker(void *arg)
     return NULL;
 }
 
-int orc_iz_search(const orc_spec *s, const double *rules, int m, const double *x,
-                  int64_t J, int64_t n, uint32_t seed, double eps, int max_iter,
-                  int nthreads, double *s_out, int32_t *iters, int64_t *steps_total)
+int orc_iz_search(const orc_spec *s, const double *rules, int m, int region,
+                  const double *x, int64_t J, int64_t n, uint32_t seed, double eps,
+                  int max_iter, int nthreads, double *s_out, int32_t *iters,
+                  int64_t *steps_total)
 {
     int rc = check_spec(s);
     if (rc) return rc;
-    if (m < 1 || m >= s->n_dates || J < 1 || n < 2 || max_iter < 1 || !(eps > 0.0))
+    if (m < 1 || m >= s->n_dates || J < 1 || n < 2 || max_iter < 1 || !(eps > 0.0) ||
+        region < 0 || region >= orc_iz_regions(s))
         return ORC_EINVAL;
-    if (s->payoff == ORC_CALL_MAX && s->d > 1) return ORC_EUNSUPPORTED;
     int d = s->d;
     double *L = malloc(sizeof(double) * d * d);
     int64_t *st = calloc(J, sizeof(int64_t));
     if (!L || !st) { free(L); free(st); return ORC_ENOMEM; }
     rc = orc_cholesky(d, s->rho, L);
     if (rc) { free(L); free(st); return rc; }
-    path_ctx c = {s, ORC_IZ, rules, orc_rule_width(ORC_IZ, d), m, L, seed,
-                  key_hi(ORC_STREAM_INNER, m)};
-    iz_job job = {&c, x, J, n, eps, max_iter, s_out, iters, st, 0};
+    path_ctx c = {s, ORC_IZ, rules, orc_rule_width_spec(s, ORC_IZ), m, L, seed,
+                  key_hi(ORC_STREAM_INNER, m), (uint32_t)region};
+    iz_job job = {&c, x, region, J, n, eps, max_iter, s_out, iters, st, 0};
     pthread_mutex_init(&job.lock, NULL);
     int nt = resolve_threads(nthreads);
     if (nt > J) nt = (int)J;
@@ -784,14 +819,15 @@ int orc_iz_search(const orc_spec *s, const double *rules, int m, const double *x
 }
 
 /* [reg] (Section 2.3): least squares of ln s*_j on the full quadratic in the
- * log-moneyness of the other assets, over the converged points, through the
- * normal equations with a ridge of 1e-10 tr/p.  No converged point: never
- * exercise. */
-int orc_fit_iz(const orc_spec *s, const double *x, const double *sstar,
+ * log-moneyness of the other assets (those of the region's boundary), over the
+ * converged points, through the normal equations with a ridge of 1e-10 tr/p.
+ * No converged point: never exercise. */
+int orc_fit_iz(const orc_spec *s, int region, const double *x, const double *sstar,
                int64_t J, double *b)
 {
     int rc = check_spec(s);
     if (rc) return rc;
+    if (region < 0 || region >= orc_iz_regions(s) || J < 1) return ORC_EINVAL;
     int d = s->d, p = orc_rule_width(ORC_IZ, d);
     double *A = calloc((size_t)p * p, sizeof(double)), *bv = calloc(p, sizeof(double));
     double xi[1 + 63 + 63 * 64 / 2], logS[64];
@@ -799,7 +835,7 @@ int orc_fit_iz(const orc_spec *s, const double *x, const double *sstar,
     for (int64_t j = 0; j < J; ++j) {
         if (!(sstar[j] > 0.0)) continue;
         for (int i = 0; i < d; ++i) logS[i] = log(x[(size_t)i * J + j]);
-        iz_features(s, logS, xi);
+        iz_features(s, logS, region, xi);
         double y = log(sstar[j]);
         for (int a = 0; a < p; ++a) {
             bv[a] += xi[a] * y;
@@ -833,8 +869,8 @@ int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_fin
     if (rc) return rc;
     if (N < 2 || n < 2 || n_final < 2 || (method != ORC_CMC && method != ORC_IZ))
         return ORC_EINVAL;
-    if (method == ORC_IZ && s->payoff == ORC_CALL_MAX && s->d > 1) return ORC_EUNSUPPORTED;
-    int d = s->d, NT = s->n_dates, width = orc_rule_width(method, d);
+    int d = s->d, NT = s->n_dates, width = orc_rule_width_spec(s, method);
+    int regions = method == ORC_IZ ? orc_iz_regions(s) : 1, pw = width / regions;
     double *rules = calloc((size_t)(NT + 1) * width, sizeof(double));
     double *L = malloc(sizeof(double) * d * d);
     double *x = malloc(sizeof(double) * d * N);
@@ -860,19 +896,23 @@ int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_fin
         }
     } else {
         for (int m = NT - 1; m >= 1; --m) {
-            rc = orc_points_iz(s, m, N, x);
-            if (rc) goto done;
-            int64_t st = 0;
-            rc = orc_iz_search(s, rules, m, x, N, n, seed, eps, max_iter, nthreads,
-                               cont, iters, &st);
-            if (rc) goto done;
-            inner += st;
-            for (int64_t j = 0; j < N; ++j) {
-                iz_it += iters[j];
-                if (!(cont[j] > 0.0)) ++unconv;
+            /* Algorithm 1: one search and one regression per region; every
+             * region's search at date m sees the rules of dates > m only. */
+            for (int r = 0; r < regions; ++r) {
+                rc = orc_points_iz(s, m, r, N, x);
+                if (rc) goto done;
+                int64_t st = 0;
+                rc = orc_iz_search(s, rules, m, r, x, N, n, seed, eps, max_iter, nthreads,
+                                   cont, iters, &st);
+                if (rc) goto done;
+                inner += st;
+                for (int64_t j = 0; j < N; ++j) {
+                    iz_it += iters[j];
+                    if (!(cont[j] > 0.0)) ++unconv;
+                }
+                rc = orc_fit_iz(s, r, x, cont, N, rules + (size_t)m * width + (size_t)r * pw);
+                if (rc) goto done;
             }
-            rc = orc_fit_iz(s, x, cont, N, rules + (size_t)m * width);
-            if (rc) goto done;
         }
     }
     {

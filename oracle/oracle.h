@@ -41,8 +41,14 @@ typedef struct {
     int32_t payoff;       /* ORC_PUT_BASKET / ORC_CALL_MAX / ORC_PUT_GEO */
 } orc_spec;
 
-/* Number of rule coefficients per date for a method and dimension. */
+/* Number of rule coefficients per date for a method and dimension (for I&Z:
+ * one region's boundary). */
 int orc_rule_width(int method, int d);
+/* I&Z exercise regions (Section 2.2): d for the max-call, 1 otherwise. */
+int orc_iz_regions(const orc_spec *s);
+/* Width of a rule row: CMC weights, or the I&Z boundary blocks of every
+ * region, region r at offset r * orc_rule_width(ORC_IZ, d). */
+int orc_rule_width_spec(const orc_spec *s, int method);
 
 /* Philox4x32-10 block function (Salmon et al., SC'11). */
 void orc_philox(uint32_t k0, uint32_t k1, const uint32_t ctr[4], uint32_t out[4]);
@@ -59,8 +65,10 @@ int orc_points_cmc(const orc_spec *s, int m, int64_t N, uint32_t seed, double *x
 
 /* Korobov generator maximising the minimal toroidal distance. */
 int64_t orc_korobov(int64_t J, int q);
-/* I&Z lattice points at date m; asset 0 is set to K. */
-int orc_points_iz(const orc_spec *s, int m, int64_t J, double *x);
+/* I&Z lattice points at date m for a region's boundary: the lattice spans
+ * the other assets; the region's own asset (asset 0 for the put family) is
+ * set to K. */
+int orc_points_iz(const orc_spec *s, int m, int region, int64_t J, double *x);
 
 /*
  * Continuation estimate at date m (0 <= m < N_T) for N points x, n inner paths
@@ -80,19 +88,22 @@ int orc_continuation(const orc_spec *s, int method, const double *rules, int m,
 int orc_fit_cmc(const orc_spec *s, const double *x, const double *cont,
                 int64_t N, int rounds, double *w);
 
-/* I&Z fixed-point search of the boundary coordinate for J points at date m.
+/* I&Z fixed-point search of a region's boundary coordinate for J points at
+ * date m; the inner paths of region r use r as the fourth counter word.
  * Writes s_out[J] (<= 0 if dropped or unconverged) and iters[J]. */
-int orc_iz_search(const orc_spec *s, const double *rules, int m, const double *x,
-                  int64_t J, int64_t n, uint32_t seed, double eps, int max_iter,
-                  int nthreads, double *s_out, int32_t *iters, int64_t *steps_total);
+int orc_iz_search(const orc_spec *s, const double *rules, int m, int region,
+                  const double *x, int64_t J, int64_t n, uint32_t seed, double eps,
+                  int max_iter, int nthreads, double *s_out, int32_t *iters,
+                  int64_t *steps_total);
 
-/* I&Z quadratic boundary regression over the converged points. */
-int orc_fit_iz(const orc_spec *s, const double *x, const double *sstar,
+/* I&Z quadratic boundary regression of one region over its converged points;
+ * b holds orc_rule_width(ORC_IZ, d) coefficients. */
+int orc_fit_iz(const orc_spec *s, int region, const double *x, const double *sstar,
                int64_t J, double *b);
 
 /*
  * Whole pricer (Algorithm 1 for ORC_IZ, Algorithm 2 for ORC_CMC).
- * rules_out: [(N_T+1) * width] or NULL.
+ * rules_out: [(N_T+1) * orc_rule_width_spec(s, method)] or NULL.
  * result[8] = {price, variance, std_err, ci95, inner_steps, final_steps,
  *              iz_unconverged, iz_iterations}.
  */

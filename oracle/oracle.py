@@ -53,6 +53,8 @@ def lib():
                                 C.POINTER(C.c_int32), C.POINTER(C.c_uint32))
         sp = C.POINTER(_Spec)
         L.orc_rule_width.argtypes = [C.c_int, C.c_int]
+        L.orc_iz_regions.argtypes = [sp]
+        L.orc_rule_width_spec.argtypes = [sp, C.c_int]
         L.orc_philox.argtypes = [C.c_uint32, C.c_uint32, u32p, u32p]
         L.orc_philox.restype = None
         L.orc_normal_block.argtypes = [C.c_uint32, C.c_uint32, u32p, dp]
@@ -63,13 +65,13 @@ def lib():
         L.orc_points_cmc.argtypes = [sp, C.c_int, C.c_int64, C.c_uint32, dp]
         L.orc_korobov.argtypes = [C.c_int64, C.c_int]
         L.orc_korobov.restype = C.c_int64
-        L.orc_points_iz.argtypes = [sp, C.c_int, C.c_int64, dp]
+        L.orc_points_iz.argtypes = [sp, C.c_int, C.c_int, C.c_int64, dp]
         L.orc_continuation.argtypes = [sp, C.c_int, dp, C.c_int, dp, C.c_int64, u32p, C.c_int64,
                                        C.c_uint32, C.c_int, C.c_int, dp, dp, i64p, dp, dp]
         L.orc_fit_cmc.argtypes = [sp, dp, dp, C.c_int64, C.c_int, dp]
-        L.orc_iz_search.argtypes = [sp, dp, C.c_int, dp, C.c_int64, C.c_int64, C.c_uint32,
+        L.orc_iz_search.argtypes = [sp, dp, C.c_int, C.c_int, dp, C.c_int64, C.c_int64, C.c_uint32,
                                     C.c_double, C.c_int, C.c_int, dp, i32p, i64p]
-        L.orc_fit_iz.argtypes = [sp, dp, dp, C.c_int64, dp]
+        L.orc_fit_iz.argtypes = [sp, C.c_int, dp, dp, C.c_int64, dp]
         L.orc_price.argtypes = [sp, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_uint32,
                                 C.c_int, C.c_double, C.c_int, C.c_int, dp, dp]
         _lib = L
@@ -107,7 +109,17 @@ def _check(rc: int, what: str):
 
 
 def rule_width(method: int, d: int) -> int:
+    """Coefficients of one CMC rule or of one I&Z region's boundary."""
     return int(lib().orc_rule_width(method, d))
+
+
+def iz_regions(spec) -> int:
+    return int(lib().orc_iz_regions(_SpecHolder(spec).ptr))
+
+
+def row_width(spec, method: int) -> int:
+    """Width of a rule row: every I&Z region's boundary block side by side."""
+    return int(lib().orc_rule_width_spec(_SpecHolder(spec).ptr, method))
 
 
 def philox(k0: int, k1: int, ctr) -> np.ndarray:
@@ -153,15 +165,15 @@ def korobov(J: int, q: int) -> int:
     return int(lib().orc_korobov(J, q))
 
 
-def points_iz(spec, m: int, J: int) -> np.ndarray:
+def points_iz(spec, m: int, J: int, region: int = 0) -> np.ndarray:
     h = _SpecHolder(spec)
     x = np.zeros((h.d, J))
-    _check(lib().orc_points_iz(h.ptr, m, J, _dp(x)), "points_iz")
+    _check(lib().orc_points_iz(h.ptr, m, region, J, _dp(x)), "points_iz")
     return x
 
 
 def empty_rules(spec, method: int) -> np.ndarray:
-    return np.zeros((len(spec.dates) + 1, rule_width(method, int(spec.d))))
+    return np.zeros((len(spec.dates) + 1, row_width(spec, method)))
 
 
 def continuation(spec, method: int, rules, m: int, x: np.ndarray, n: int, seed: int,
@@ -205,7 +217,7 @@ def fit_cmc(spec, x: np.ndarray, cont: np.ndarray, rounds: int = 8) -> np.ndarra
 
 
 def iz_search(spec, rules, m: int, x: np.ndarray, n: int, seed: int, eps: float = 0.01,
-              max_iter: int = 100, nthreads: int = 0) -> dict:
+              max_iter: int = 100, nthreads: int = 0, region: int = 0) -> dict:
     h = _SpecHolder(spec)
     x = np.ascontiguousarray(x, dtype=np.float64)
     J = x.shape[1]
@@ -213,25 +225,25 @@ def iz_search(spec, rules, m: int, x: np.ndarray, n: int, seed: int, eps: float 
     s = np.zeros(J)
     it = np.zeros(J, dtype=np.int32)
     st = C.c_int64(0)
-    _check(lib().orc_iz_search(h.ptr, _dp(rules), m, _dp(x), J, n, seed, eps, max_iter, nthreads,
+    _check(lib().orc_iz_search(h.ptr, _dp(rules), m, region, _dp(x), J, n, seed, eps, max_iter, nthreads,
                                _dp(s), it.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(st)),
            "iz_search")
     return {"s": s, "iters": it, "steps": int(st.value)}
 
 
-def fit_iz(spec, x: np.ndarray, sstar: np.ndarray) -> np.ndarray:
+def fit_iz(spec, x: np.ndarray, sstar: np.ndarray, region: int = 0) -> np.ndarray:
     h = _SpecHolder(spec)
     x = np.ascontiguousarray(x, dtype=np.float64)
     sstar = np.ascontiguousarray(sstar, dtype=np.float64)
     b = np.zeros(rule_width(IZ, h.d))
-    _check(lib().orc_fit_iz(h.ptr, _dp(x), _dp(sstar), x.shape[1], _dp(b)), "fit_iz")
+    _check(lib().orc_fit_iz(h.ptr, region, _dp(x), _dp(sstar), x.shape[1], _dp(b)), "fit_iz")
     return b
 
 
 def price(spec, method: int, N: int, n: int, n_final: int, seed: int, rounds: int = 8,
           eps: float = 0.01, max_iter: int = 100, nthreads: int = 0) -> dict:
     h = _SpecHolder(spec)
-    rules = np.zeros((h.n_dates + 1, rule_width(method, h.d)))
+    rules = np.zeros((h.n_dates + 1, row_width(spec, method)))
     res = np.zeros(8)
     _check(lib().orc_price(h.ptr, method, N, n, n_final, seed, rounds, eps, max_iter, nthreads,
                            _dp(rules), _dp(res)), "price")

@@ -63,6 +63,58 @@ def crr_put(S0, K, r, q, sigma, T, steps, n_dates=None, american=False, want_bou
     return float(V[0])
 
 
+def max_call2_tree(S0, K, r, delta, sigma, T, steps, n_dates, want_boundary=False):
+    """Bermudan call on the maximum of two independent assets: the product of
+    two CRR trees (four branches per step), exercise at t_m = m T / n_dates,
+    m = 1..n_dates.  With want_boundary, for every exercise step i and asset a
+    the critical prices of asset a (the smallest price above the other asset
+    at which exercise is optimal) against the other asset's node prices:
+    boundary[i][a] = (other prices, critical prices), found by linear
+    interpolation in ln S_a of exercise value minus continuation value."""
+    assert steps % n_dates == 0
+    dt = T / steps
+    u = [math.exp(s * math.sqrt(dt)) for s in sigma]
+    p = [(math.exp((r - q) * dt) - 1.0 / uu) / (uu - 1.0 / uu) for q, uu in zip(delta, u)]
+    disc = math.exp(-r * dt)
+
+    def prices(i):
+        k = np.arange(i + 1)
+        return [S0[a] * u[a] ** (2.0 * k - i) for a in range(2)]
+
+    Sa, Sb = prices(steps)
+    V = np.maximum(np.maximum(Sa[:, None], Sb[None, :]) - K, 0.0)
+    ex_steps = {m * steps // n_dates for m in range(1, n_dates)}
+    boundary = {}
+    for i in range(steps - 1, -1, -1):
+        pa, pb = p
+        V = disc * (pa * pb * V[1:, 1:] + pa * (1 - pb) * V[1:, :-1]
+                    + (1 - pa) * pb * V[:-1, 1:] + (1 - pa) * (1 - pb) * V[:-1, :-1])
+        if i in ex_steps:
+            Sa, Sb = prices(i)
+            pay = np.maximum(np.maximum(Sa[:, None], Sb[None, :]) - K, 0.0)
+            if want_boundary:
+                g = pay - V
+                out = {}
+                for a in range(2):
+                    ga = g if a == 0 else g.T          # rows: asset a, columns: the other
+                    own, other = (Sa, Sb) if a == 0 else (Sb, Sa)
+                    xs, ys = [], []
+                    for c in range(len(other)):
+                        col = ga[:, c]
+                        for k in range(1, len(own)):
+                            if own[k - 1] > other[c] and col[k - 1] <= 0.0 < col[k]:
+                                w = col[k - 1] / (col[k - 1] - col[k])
+                                ys.append(math.exp((1 - w) * math.log(own[k - 1]) + w * math.log(own[k])))
+                                xs.append(other[c])
+                                break
+                    out[a] = (np.array(xs), np.array(ys))
+                boundary[i] = out
+            V = np.maximum(V, pay)
+    if want_boundary:
+        return float(V[0, 0]), boundary
+    return float(V[0, 0])
+
+
 def geometric_reduction(spec):
     """The geometric average of d correlated GBMs is one GBM:
     sigma_G^2 = sum_ij rho_ij sigma_i sigma_j / d^2,

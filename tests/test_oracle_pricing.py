@@ -234,3 +234,91 @@ def test_same_seed_same_price_bitwise(orc, inputs):
     assert a["price"] == b["price"] and np.array_equal(a["rules"], b["rules"])
     c = orc.price(spec, orc.CMC, 64, 64, 4096, 10, nthreads=NT)
     assert c["price"] != a["price"]
+
+
+# ---------------------------------------------------------------------------
+# I&Z on the max-call: d exercise regions (Section 2.2, Algorithm 1).
+
+def _asym_max_call2(inputs):
+    """Two independent assets with unequal spot and volatility, delta = 0.1."""
+    return inputs.basket(2, [100.0, 90.0], 100.0, 0.05, 0.1, [0.2, 0.3], 0.0, 3.0, 9, inputs.CALL_MAX)
+
+
+def test_iz_max_call_fixed_points_per_region(orc, inputs):
+    """At the last date before maturity the continuation is the one-period
+    European max-call, so every region's boundary point solves
+    s = K + C_E(s, others) with C_E by quadrature; the searched coordinate is
+    the region's own asset and the fixed point lies above the other asset."""
+    from scipy import optimize
+    spec = _asym_max_call2(inputs)
+    m, J, n = 8, 8, 20000
+    tau = spec.T / spec.n_dates
+    rules = orc.empty_rules(spec, orc.IZ)
+    assert rules.shape[1] == 2 * orc.rule_width(orc.IZ, 2) == 2 * 3
+    for a in (0, 1):
+        x = orc.points_iz(spec, m, J, region=a)
+        assert np.all(x[a] == spec.K)
+        assert not np.allclose(x[1 - a], x[1 - a][0])
+        res = orc.iz_search(spec, rules, m, x, n, seed=1, nthreads=NT, region=a, max_iter=300)
+        assert np.all(res["s"] > x[1 - a])
+        for j in range(J):
+            xo = x[:, j].copy()
+
+            def g(s):
+                xx = xo.copy()
+                xx[a] = s
+                return spec.K + pins.max_call_european(xx, spec.K, spec.r, spec.delta, spec.sigma, tau) - s
+
+            ref = optimize.brentq(g, max(spec.K, xo[1 - a]) + 1e-9, 10 * spec.K)
+            assert res["s"][j] == pytest.approx(ref, rel=0.01), (a, j, xo[1 - a])
+
+
+def test_iz_max_call2_against_two_asset_tree(orc, inputs):
+    """Price against the product binomial tree of the two assets (15.345), and
+    each region's regressed boundary against the tree's critical prices where
+    the other asset is low (flat part of the boundary): the more volatile
+    asset has the higher boundary, so a region mix-up shows."""
+    spec = _asym_max_call2(inputs)
+    tree, bnd = pins.max_call2_tree(spec.S0, spec.K, spec.r, spec.delta, spec.sigma, spec.T, 360, 9,
+                                    want_boundary=True)
+    assert tree == pytest.approx(15.345, abs=0.01)
+    r = orc.price(spec, orc.IZ, 128, 2000, 200000, 1, nthreads=NT, max_iter=200)
+    se = r["std_err"]
+    assert abs(r["price"] - tree) <= 3 * se + 0.01 * tree
+    euro = pins.max_call_european(spec.S0, spec.K, spec.r, spec.delta, spec.sigma, spec.T)
+    assert r["price"] > euro + 10 * se
+    W = orc.rule_width(orc.IZ, 2)
+    for m in (8, 6, 4):
+        flat = {}
+        for a in (0, 1):
+            others, crit = bnd[m * 40][a]
+            x = orc.points_iz(spec, m, 128, region=a)
+            lo, hi = np.quantile(x[1 - a], [0.05, 0.3])
+            sel = (others > lo) & (others < hi)
+            assert sel.sum() >= 3
+            v = np.log(others[sel] / spec.K)
+            c = r["rules"][m, a * W:(a + 1) * W]
+            learned = np.exp(c[0] + c[1] * v + c[2] * v * v)
+            assert np.all(np.abs(learned / crit[sel] - 1.0) < 0.05), (m, a)
+            flat[a] = float(np.median(learned))
+        assert flat[1] > flat[0] + 3.0, (m, flat)
+
+
+@pytest.mark.parametrize("S0", [90, 100, 110])
+def test_iz_max_call_d3_against_paper_table1(orc, inputs, S0):
+    """Table 1 (Section 2.4, I&Z, J = 128): binomial references 11.29 /
+    18.69 / 27.58; by the symmetry of the three assets the three regions learn
+    the same boundary."""
+    gold = json.loads((GOLDEN / "paper_tables.json").read_text())["table1_iz"]["rows"]
+    row = [g for g in gold if g["S0"] == S0][0]
+    spec = inputs.max_call(3, float(S0))
+    r = orc.price(spec, orc.IZ, 128, 1500, 200000, 1, nthreads=NT, max_iter=200)
+    se = r["std_err"]
+    assert abs(r["price"] - row["binomial"]) <= 3 * se + 0.01 * row["binomial"]
+    assert abs(r["price"] - row["price"]) <= 3 * se + 0.01 * row["price"]
+    euro = pins.max_call_european(spec.S0, 100.0, 0.05, 0.1, 0.2, 3.0)
+    assert r["price"] > euro + 10 * se
+    W = orc.rule_width(orc.IZ, 3)
+    blocks = r["rules"][1:9].reshape(8, 3, W)
+    assert np.all(np.abs(blocks[:, :, 0] - blocks[:, :1, 0]) < 0.02)
+    assert r["iz_unconverged"] < 0.2 * 3 * 128 * 8

@@ -216,10 +216,14 @@ bmc_status bmc_server_stats_get(bmc_server *server, bmc_server_stats *out);
 /* Exercise-rule table of one spec and method: one row of width w per date
  * (rows 1..N_T-1 used).  CMC (Section 3.2): F(x) = sum_f w_f phi_f(x) with
  * phi = [1, u_1..u_d, u_1^2..u_d^2, g, g^2], u_i = ln(S_i/K), g = Phi(S)/K;
- * exercise iff Phi > 0 and F > 0.  I&Z (Section 2.2): boundary
- * b(x) = sum_f w_f xi_f with xi = [1, v_2..v_d, v_a v_b (a <= b)],
- * v_i = ln(S_i/K); puts exercise iff Phi > 0 and ln S_1 < b, the one-asset
- * call iff ln S_1 > b.  A new table never exercises. */
+ * exercise iff Phi > 0 and F > 0.  I&Z (Section 2.2): one boundary block of
+ * p = 1 + q + q(q+1)/2 coefficients (q = d - 1) per exercise region, region r
+ * at offset r p of the row; b_r(x) = sum_f w_f xi_f with
+ * xi = [1, v_1..v_q, v_a v_c (a <= c)] over v = ln(S_i/K) of the assets
+ * i != r in increasing order.  The put family has one region (r = 0): it
+ * exercises iff Phi > 0 and ln S_1 < b_0.  The max-call has d regions: with
+ * r the largest asset (the first on ties) it exercises iff Phi > 0 and
+ * ln S_r > b_r.  A new table never exercises. */
 bmc_status bmc_rules_create(bmc_ctx *ctx, const bmc_spec *spec, int32_t method, bmc_rules **out);
 void bmc_rules_destroy(bmc_rules *rules);
 int32_t bmc_rules_width(const bmc_rules *rules);
@@ -231,11 +235,17 @@ bmc_status bmc_rules_get(const bmc_rules *rules, int32_t date, double *w_host);
 bmc_status bmc_rules_export(const bmc_rules *rules, void *buf, size_t *bytes);
 bmc_status bmc_rules_import(bmc_ctx *ctx, const void *buf, size_t bytes, bmc_rules **out);
 
+/* Number of I&Z exercise regions of a spec (Section 2.2): d for the
+ * max-call, 1 for the put family; 0 for a NULL or empty spec. */
+int32_t bmc_iz_regions(const bmc_spec *spec);
+
 /* Sample points at `date` (1..N_T) into device x[d*N].  CMC: training points
- * from the Brownian bridge run back from T (Section 3.2-3.3).  I&Z: rank-1
- * lattice points (Section 2.3, [glp]) with asset 1 set to K. */
+ * from the Brownian bridge run back from T (Section 3.2-3.3); region must be
+ * 0.  I&Z: rank-1 lattice points (Section 2.3, [glp]) over the assets other
+ * than the region's own one (0 <= region < bmc_iz_regions), whose row is set
+ * to K. */
 bmc_status bmc_sample_points(bmc_ctx *ctx, const bmc_spec *spec, int32_t method, int32_t date,
-                             int64_t N, uint64_t seed, double *x);
+                             int32_t region, int64_t N, uint64_t seed, double *x);
 
 /* Continuation values at `date` m (0..N_T-1) of the N device points x: n inner
  * paths per point from t_m to T under the rules of later dates (Section 3.2,
@@ -247,24 +257,29 @@ bmc_status bmc_estimate_continuation(bmc_ctx *ctx, const bmc_spec *spec, const b
                                      uint64_t seed, int32_t precision,
                                      double *cont, double *std_err, int64_t *steps);
 
-/* Fits the rule row of `date` from N device points.  CMC: values = device
- * continuation estimates; boosting on the in-the-money points (Section 3.2
- * [class]).  I&Z: x[0*N + j] holds the converged boundary coordinate s*_j
- * (<= 0 marks a dropped point) and values is ignored; quadratic least squares
- * of ln s* (Section 2.3 [reg]).  rounds: CMC boosting rounds (0 = 8). */
+/* Fits the rule row of `date` from N device points.  CMC: region 0,
+ * values = device continuation estimates; boosting on the in-the-money points
+ * (Section 3.2 [class]).  I&Z: fits the boundary block of `region`;
+ * x[region*N + j] holds the converged boundary coordinate s*_j (<= 0 marks a
+ * dropped point) and values is ignored; quadratic least squares of ln s*
+ * (Section 2.3 [reg]).  rounds: CMC boosting rounds (0 = 8). */
 bmc_status bmc_fit_rule(bmc_ctx *ctx, const bmc_spec *spec, bmc_rules *rules, int32_t date,
-                        const double *x, const double *values, int64_t N, int32_t rounds);
+                        int32_t region, const double *x, const double *values, int64_t N,
+                        int32_t rounds);
 
-/* I&Z boundary-point search at `date` (Section 2.1 eq. (1), Section 2.4):
- * for each of the J device points x (asset 1 ignored) iterate
- * s <- Phi_1^{-1}(C(s)) from s = K with common random numbers until
- * |s' - s| < eps or max_iter.  Writes device s_out[J] (<= 0: dropped or not
- * converged) and iters[J]; *steps (host, may be NULL) receives the executed
- * path-steps.  Synchronous. */
+/* I&Z boundary-point search of one region at `date` (Section 2.1 eq. (1),
+ * Sections 2.2 and 2.4): for each of the J device points x (the region's own
+ * asset ignored) iterate s <- Phi^{-1}(C(s)) on that asset from s = K with
+ * common random numbers (the region is the fourth Philox counter word) until
+ * |s' - s| < eps or max_iter.  Phi^{-1}: (K - c)^d / prod_{i>=2} x_i for the
+ * geometric put, d (K - c) - sum_{i>=2} x_i for the arithmetic put, K + c for
+ * the max-call.  Writes device s_out[J] (<= 0: dropped, not converged, or a
+ * max-call fixed point not above every other asset) and iters[J]; *steps
+ * (host, may be NULL) receives the executed path-steps.  Synchronous. */
 bmc_status bmc_iz_search(bmc_ctx *ctx, const bmc_spec *spec, const bmc_rules *rules, int32_t date,
-                         const double *x, int64_t J, int64_t n, uint64_t seed, int32_t precision,
-                         double eps, int32_t max_iter, double *s_out, int32_t *iters,
-                         int64_t *steps);
+                         int32_t region, const double *x, int64_t J, int64_t n, uint64_t seed,
+                         int32_t precision, double eps, int32_t max_iter, double *s_out,
+                         int32_t *iters, int64_t *steps);
 
 /* Final pricing [mc] (Algorithms 1-2): n_final paths from S0 on the FINAL
  * stream under the rules; FP64 merge to price, sample variance, standard

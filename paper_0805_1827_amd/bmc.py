@@ -29,7 +29,7 @@ SYMBOLS = [
     "bmc_fit_rule", "bmc_iz_search", "bmc_final_price", "bmc_philox", "bmc_normals", "bmc_price_batch",
     "bmc_tuning_set", "bmc_tuning_get", "bmc_server_create", "bmc_server_destroy", "bmc_server_submit",
     "bmc_server_poll", "bmc_server_wait", "bmc_server_stats_get", "bmc_ctx_set_graphs", "bmc_ctx_graph_stats",
-    "bmc_autotune",
+    "bmc_autotune", "bmc_iz_regions",
 ]
 
 
@@ -121,12 +121,14 @@ def load():
     L.bmc_rules_get.argtypes = [vp, C.c_int32, dp]
     L.bmc_rules_export.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
     L.bmc_rules_import.argtypes = [vp, vp, C.c_size_t, C.POINTER(vp)]
-    L.bmc_sample_points.argtypes = [vp, sp, C.c_int32, C.c_int32, C.c_int64, C.c_uint64, vp]
+    L.bmc_iz_regions.argtypes = [sp]
+    L.bmc_iz_regions.restype = C.c_int32
+    L.bmc_sample_points.argtypes = [vp, sp, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_uint64, vp]
     L.bmc_estimate_continuation.argtypes = [vp, sp, vp, C.c_int32, vp, C.c_int64, C.c_int64, C.c_uint64,
                                             C.c_int32, vp, vp, vp]
-    L.bmc_fit_rule.argtypes = [vp, sp, vp, C.c_int32, vp, vp, C.c_int64, C.c_int32]
-    L.bmc_iz_search.argtypes = [vp, sp, vp, C.c_int32, vp, C.c_int64, C.c_int64, C.c_uint64, C.c_int32,
-                                C.c_double, C.c_int32, vp, vp, C.POINTER(C.c_int64)]
+    L.bmc_fit_rule.argtypes = [vp, sp, vp, C.c_int32, C.c_int32, vp, vp, C.c_int64, C.c_int32]
+    L.bmc_iz_search.argtypes = [vp, sp, vp, C.c_int32, C.c_int32, vp, C.c_int64, C.c_int64, C.c_uint64,
+                                C.c_int32, C.c_double, C.c_int32, vp, vp, C.POINTER(C.c_int64)]
     L.bmc_final_price.argtypes = [vp, sp, vp, C.c_int64, C.c_uint64, C.c_int32, C.POINTER(bmc_result)]
     L.bmc_philox.argtypes = [vp, C.c_uint32, C.c_uint32, vp, C.c_int64, vp]
     L.bmc_normals.argtypes = [vp, C.c_uint32, C.c_uint32, vp, C.c_int64, C.c_int32, vp]
@@ -365,6 +367,10 @@ def bmc_rules_set(rules: Rules, date: int, w) -> None:
     _check(load().bmc_rules_set(rules.h, date, _dp(w)))
 
 
+def bmc_rules_width(rules: Rules) -> int:
+    return int(load().bmc_rules_width(rules.h))
+
+
 def bmc_rules_get(rules: Rules, date: int) -> np.ndarray:
     w = np.zeros(rules.width)
     _check(load().bmc_rules_get(rules.h, date, _dp(w)))
@@ -403,11 +409,15 @@ def _dev_zeros(shape, dtype, ctx: Context):
     return torch.zeros(shape, dtype=dtype, device=f"cuda:{ctx.device}")
 
 
-def bmc_sample_points(ctx: Context, spec, method: int, date: int, N: int, seed: int):
+def bmc_iz_regions(spec) -> int:
+    return int(load().bmc_iz_regions(as_spec(spec).ptr))
+
+
+def bmc_sample_points(ctx: Context, spec, method: int, date: int, N: int, seed: int, region: int = 0):
     import torch
     s = as_spec(spec)
     x = _dev_zeros((s.d, N), torch.float64, ctx)
-    _check(load().bmc_sample_points(ctx.h, s.ptr, method, date, N, seed, _ptr(x)))
+    _check(load().bmc_sample_points(ctx.h, s.ptr, method, date, region, N, seed, _ptr(x)))
     return x
 
 
@@ -425,16 +435,17 @@ def bmc_estimate_continuation(ctx: Context, spec, rules: Rules, date: int, x, n:
     return cont, se, steps
 
 
-def bmc_fit_rule(ctx: Context, spec, rules: Rules, date: int, x, values=None, rounds: int = 0) -> None:
+def bmc_fit_rule(ctx: Context, spec, rules: Rules, date: int, x, values=None, rounds: int = 0,
+                 region: int = 0) -> None:
     s = as_spec(spec)
     x = x.contiguous()
-    _check(load().bmc_fit_rule(ctx.h, s.ptr, rules.h, date, _ptr(x),
+    _check(load().bmc_fit_rule(ctx.h, s.ptr, rules.h, date, region, _ptr(x),
                                _ptr(values.contiguous()) if values is not None else None,
                                int(x.shape[1]), rounds))
 
 
 def bmc_iz_search(ctx: Context, spec, rules: Rules, date: int, x, n: int, seed: int,
-                  precision: int = FP64, eps: float = 0.01, max_iter: int = 100):
+                  precision: int = FP64, eps: float = 0.01, max_iter: int = 100, region: int = 0):
     import torch
     s = as_spec(spec)
     x = x.contiguous()
@@ -442,7 +453,7 @@ def bmc_iz_search(ctx: Context, spec, rules: Rules, date: int, x, n: int, seed: 
     s_out = _dev_zeros(J, torch.float64, ctx)
     iters = _dev_zeros(J, torch.int32, ctx)
     steps = C.c_int64(0)
-    _check(load().bmc_iz_search(ctx.h, s.ptr, rules.h, date, _ptr(x), J, n, seed, precision, eps,
+    _check(load().bmc_iz_search(ctx.h, s.ptr, rules.h, date, region, _ptr(x), J, n, seed, precision, eps,
                                 max_iter, _ptr(s_out), _ptr(iters), C.byref(steps)))
     return s_out, iters, int(steps.value)
 

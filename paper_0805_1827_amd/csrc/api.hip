@@ -264,8 +264,9 @@ static bmc_status rules_alloc(bmc_ctx* ctx, int method, int d, int n_dates, int 
     r->d = d;
     r->n_dates = n_dates;
     r->payoff = payoff;
-    r->width = rule_width(method, d);
+    r->width = rule_row_width(method, d, payoff);
     const size_t rows = (size_t)(n_dates + 1) * r->width;
+    const int block = method == BMC_CMC ? r->width : rule_width(method, d);
     hipError_t e;
     if ((e = hipMalloc((void**)&r->w64, sizeof(double) * rows)) ||
         (e = hipMalloc((void**)&r->w32, sizeof(float) * rows))) {
@@ -276,9 +277,9 @@ static bmc_status rules_alloc(bmc_ctx* ctx, int method, int d, int n_dates, int 
     std::vector<double> h(rows, 0.0);
     std::vector<float> hf(rows, 0.0f);
     const double nv = never_value(method, payoff);
-    for (int k = 0; k <= n_dates; ++k) {
-        h[(size_t)k * r->width] = nv;
-        hf[(size_t)k * r->width] = (float)nv;
+    for (size_t f = 0; f < rows; f += block) {   // every region's block starts "never"
+        h[f] = nv;
+        hf[f] = (float)nv;
     }
     if ((e = hipMemcpy(r->w64, h.data(), sizeof(double) * rows, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(r->w32, hf.data(), sizeof(float) * rows, hipMemcpyHostToDevice))) {
@@ -296,14 +297,16 @@ bmc_status bmc::scratch_rules(bmc_ctx* ctx, const bmc_spec* spec, int method, bm
     r->d = spec->d;
     r->n_dates = spec->n_dates;
     r->payoff = spec->payoff;
-    r->width = rule_width(method, spec->d);
+    r->width = rule_row_width(method, spec->d, spec->payoff);
     const size_t rows = (size_t)(spec->n_dates + 1) * r->width;
     const size_t b64 = (sizeof(double) * rows + 255) & ~(size_t)255;
     hipError_t e = ctx->srules.ensure(b64 + sizeof(float) * rows);
     if (e) return hip_fail(e, "rule scratch");
     r->w64 = (double*)ctx->srules.ptr;
     r->w32 = (float*)((char*)ctx->srules.ptr + b64);
-    if ((e = launch_rules_fill(r->w64, r->w32, spec->n_dates + 1, r->width, never_value(method, spec->payoff),
+    // rows of one boundary block each: every I&Z region's block starts "never"
+    const int block = method == BMC_CMC ? r->width : rule_width(method, spec->d);
+    if ((e = launch_rules_fill(r->w64, r->w32, (int)(rows / block), block, never_value(method, spec->payoff),
                                ctx->stream)))
         return hip_fail(e, "rule scratch");
     return BMC_OK;
@@ -318,8 +321,6 @@ extern "C" bmc_status bmc_rules_create(bmc_ctx* ctx, const bmc_spec* spec, int32
     if (method != BMC_CMC && method != BMC_IZ) return fail(BMC_EINVAL, "unknown method %d", method);
     if (method == BMC_IZ && spec->d > IZ_D_MAX)
         return fail(BMC_EUNSUPPORTED, "I&Z supports d <= %d", IZ_D_MAX);
-    if (method == BMC_IZ && spec->payoff == BMC_CALL_MAX && spec->d > 1)
-        return fail(BMC_EUNSUPPORTED, "I&Z for the max-call needs d boundaries (not provided)");
     (void)hipSetDevice(ctx->device);
     return rules_alloc(ctx, method, spec->d, spec->n_dates, spec->payoff, out);
 }
@@ -403,7 +404,7 @@ extern "C" bmc_status bmc_rules_import(bmc_ctx* ctx, const void* buf, size_t byt
     std::memcpy(&h, buf, sizeof(h));
     if (std::memcmp(h.magic, "BMCR", 4) != 0 || h.version != 1) return fail(BMC_EINVAL, "not a rule table");
     if (h.d < 1 || h.d > BMC_D_MAX || h.n_dates < 1 || h.n_dates > BMC_NT_MAX ||
-        (h.method != BMC_CMC && h.method != BMC_IZ) || h.width != rule_width(h.method, h.d))
+        (h.method != BMC_CMC && h.method != BMC_IZ) || h.width != rule_row_width(h.method, h.d, h.payoff))
         return fail(BMC_EINVAL, "corrupt rule table header");
     const size_t rows = (size_t)(h.n_dates + 1) * h.width;
     if (bytes < sizeof(h) + sizeof(double) * rows) return fail(BMC_EINVAL, "truncated rule table");
@@ -431,6 +432,8 @@ static bmc_status check_rules(const bmc_rules* r, const bmc_spec* s)
     if (r->d != s->d || r->n_dates != s->n_dates)
         return fail(BMC_EINVAL, "rule table (d=%d, dates=%d) does not match the spec (d=%d, dates=%d)",
                     r->d, r->n_dates, s->d, s->n_dates);
+    if (r->width != rule_row_width(r->method, s->d, s->payoff))
+        return fail(BMC_EINVAL, "rule table rows (%d coefficients) do not fit this payoff's I&Z regions", r->width);
     return BMC_OK;
 }
 
@@ -622,7 +625,7 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
                          const double* x, int64_t N, const int32_t* ids, const int32_t* n_ids,
                          uint32_t n, uint32_t k0, uint32_t k1, double* cont, double* se,
                          int64_t* steps, double* sums, unsigned long long* steps_total,
-                         const Tuning* tune)
+                         const Tuning* tune, uint32_t slot)
 {
     const int block = (tune && tune->block > 0) ? tune->block : 256;
     const uint32_t ppt = choose_ppt(ctx, d, prec, N, n, tune);
@@ -650,6 +653,7 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
     a.nchunk = nchunk;
     a.k0 = k0;
     a.k1 = k1;
+    a.slot = slot;
     a.part = (double*)ctx->part.ptr;
     if ((e = launch_cont(d, prec, a, (int)grid, block, lds, ctx->stream))) return hip_fail(e, "continuation launch");
     if ((e = launch_finalize(a.part, nchunk, n, N, ids, n_ids, cont, se, steps, sums, steps_total,
@@ -680,7 +684,7 @@ extern "C" bmc_status bmc_estimate_continuation(bmc_ctx* ctx, const bmc_spec* sp
 }
 
 bmc_status bmc::fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rules* rules, int date,
-                              const double* x, const double* values, int64_t N, int rounds)
+                              const double* x, const double* values, int64_t N, int rounds, int region)
 {
     hipError_t e;
     double* row64 = rules->w64 + (size_t)date * rules->width;
@@ -694,33 +698,48 @@ bmc_status bmc::fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rule
         if ((e = launch_fit_cmc((const DevSpec*)devspec, d, x, values, N, rounds, fs, row64, row32, ctx->stream)))
             return hip_fail(e, "fit launch");
     } else {
-        if ((e = ctx->fit.ensure(sizeof(double) * fitiz_scratch_doubles(N, rules->width))))
-            return hip_fail(e, "fit scratch");
-        if ((e = launch_fit_iz((const DevSpec*)devspec, d, x, N, (double*)ctx->fit.ptr, row64, row32,
-                               ctx->stream)))
+        const int p = rule_width(BMC_IZ, d);
+        if ((e = ctx->fit.ensure(sizeof(double) * fitiz_scratch_doubles(N, p)))) return hip_fail(e, "fit scratch");
+        if ((e = launch_fit_iz((const DevSpec*)devspec, d, region, x, N, (double*)ctx->fit.ptr,
+                               row64 + (size_t)region * p, row32 + (size_t)region * p, ctx->stream)))
             return hip_fail(e, "fit launch");
     }
     return BMC_OK;
 }
 
+static bmc_status check_region(int method, const bmc_spec* spec, int32_t region)
+{
+    const int regions = method == BMC_IZ ? iz_regions(spec->payoff, spec->d) : 1;
+    if (region < 0 || region >= regions)
+        return fail(BMC_EINVAL, "region %d outside 0..%d", region, regions - 1);
+    return BMC_OK;
+}
+
+extern "C" int32_t bmc_iz_regions(const bmc_spec* spec)
+{
+    if (!spec || spec->d < 1) return 0;
+    return iz_regions(spec->payoff, spec->d);
+}
+
 extern "C" bmc_status bmc_fit_rule(bmc_ctx* ctx, const bmc_spec* spec, bmc_rules* rules, int32_t date,
-                                   const double* x, const double* values, int64_t N, int32_t rounds)
+                                   int32_t region, const double* x, const double* values, int64_t N,
+                                   int32_t rounds)
 {
     if (!ctx || !x) return fail(BMC_EINVAL, "NULL argument");
     (void)hipSetDevice(ctx->device);
     bmc_status st;
     if ((st = upload_spec(ctx, spec, ctx->spec))) return st;
-    if ((st = check_rules(rules, spec))) return st;
+    if ((st = check_rules(rules, spec)) || (st = check_region(rules->method, spec, region))) return st;
     if (date < 1 || date >= spec->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, spec->n_dates - 1);
     if (N < 1 || N > 0x7FFFFFFF) return fail(BMC_EINVAL, "N out of range");
     if (rules->method == BMC_CMC && !values) return fail(BMC_EINVAL, "CMC fit needs continuation values");
     if (rounds <= 0) rounds = 8;
     if (rounds > 64) return fail(BMC_EINVAL, "rounds must be <= 64");
-    return fit_rule_impl(ctx, ctx->spec.ptr, spec->d, rules, date, x, values, N, rounds);
+    return fit_rule_impl(ctx, ctx->spec.ptr, spec->d, rules, date, x, values, N, rounds, region);
 }
 
 bmc_status bmc::sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, int method,
-                                   int date, int64_t N, uint32_t seed, double* x, double* Bbuf)
+                                   int date, int64_t N, uint32_t seed, double* x, double* Bbuf, int region)
 {
     hipError_t e;
     const DevSpec* ds = (const DevSpec*)devspec;
@@ -741,32 +760,34 @@ bmc_status bmc::sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_
                 return hip_fail(e, "korobov");
             best = (const unsigned long long*)ctx->korobov.ptr;
         }
-        if ((e = launch_lattice(ds, d, date, N, best, x, ctx->stream))) return hip_fail(e, "lattice");
+        if ((e = launch_lattice(ds, d, date, region, N, best, x, ctx->stream))) return hip_fail(e, "lattice");
     }
     return BMC_OK;
 }
 
 extern "C" bmc_status bmc_sample_points(bmc_ctx* ctx, const bmc_spec* spec, int32_t method, int32_t date,
-                                        int64_t N, uint64_t seed, double* x)
+                                        int32_t region, int64_t N, uint64_t seed, double* x)
 {
     if (!ctx || !x) return fail(BMC_EINVAL, "NULL argument");
     (void)hipSetDevice(ctx->device);
     bmc_status st;
     if ((st = upload_spec(ctx, spec, ctx->spec)) || (st = check_seed(seed))) return st;
     if (method != BMC_CMC && method != BMC_IZ) return fail(BMC_EINVAL, "unknown method %d", method);
+    if ((st = check_region(method, spec, region))) return st;
     if (date < 1 || date > spec->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, spec->n_dates);
     if (N < 1 || N > 0x7FFFFFFF) return fail(BMC_EINVAL, "N out of range");
     if (method == BMC_IZ && (spec->d > IZ_D_MAX || N > 65536))
         return fail(BMC_EUNSUPPORTED, "I&Z lattice supports d <= %d and J <= 65536", IZ_D_MAX);
     hipError_t e = ctx->B.ensure(sizeof(double) * spec->d * N);
     if (e) return hip_fail(e, "bridge buffer");
-    return sample_points_impl(ctx, ctx->spec.ptr, spec, method, date, N, (uint32_t)seed, x, (double*)ctx->B.ptr);
+    return sample_points_impl(ctx, ctx->spec.ptr, spec, method, date, N, (uint32_t)seed, x, (double*)ctx->B.ptr,
+                              region);
 }
 
 bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, const bmc_rules* rules,
-                               int date, const double* x, int64_t J, uint32_t n, uint32_t seed, int prec,
-                               double eps, int max_iter, double* s_out, int32_t* iters, int64_t* steps_out,
-                               const Tuning* tune)
+                               int date, int region, const double* x, int64_t J, uint32_t n, uint32_t seed,
+                               int prec, double eps, int max_iter, double* s_out, int32_t* iters,
+                               int64_t* steps_out, const Tuning* tune)
 {
     const int d = spec->d;
     hipError_t e;
@@ -786,7 +807,7 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     // counters buffer: [0,8) step total, [16,40) final sums/steps, [48,56) active counts
     int32_t* cnt = (int32_t*)((char*)ctx->counters.ptr + 48);
     const DevSpec* ds = (const DevSpec*)devspec;
-    if ((e = launch_iz_init(ds, x, d, J, x_work, s_cur, s_out, iters, ids_a, &cnt[0], acc, ctx->stream)))
+    if ((e = launch_iz_init(ds, x, d, region, J, x_work, s_cur, s_out, iters, ids_a, &cnt[0], acc, ctx->stream)))
         return hip_fail(e, "search init");
     const uint32_t k1 = key_hi(BMC_STREAM_INNER, date);
     for (int it = 0; it < max_iter; ++it) {
@@ -797,9 +818,9 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
         if ((e = hipMemsetAsync(n_out, 0, sizeof(int32_t), ctx->stream))) return hip_fail(e, "search");
         bmc_status st = run_cont(ctx, devspec, d, spec->n_dates, rules->method, rules->width, rules->w64,
                                  rules->w32, prec, date, x_work, J, ids_in, n_in, n, seed, k1, cont,
-                                 nullptr, stp, nullptr, nullptr, tune);
+                                 nullptr, stp, nullptr, nullptr, tune, (uint32_t)region);
         if (st) return st;
-        if ((e = launch_iz_update(ds, d, J, cont, stp, ids_in, n_in, ids_out, n_out, s_cur, x_work, s_out,
+        if ((e = launch_iz_update(ds, d, region, J, cont, stp, ids_in, n_in, ids_out, n_out, s_cur, x_work, s_out,
                                   iters, acc, eps, max_iter, it, ctx->stream)))
             return hip_fail(e, "search update");
         if ((it & 3) == 3 || it == max_iter - 1) {
@@ -824,8 +845,9 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
 }
 
 extern "C" bmc_status bmc_iz_search(bmc_ctx* ctx, const bmc_spec* spec, const bmc_rules* rules, int32_t date,
-                                    const double* x, int64_t J, int64_t n, uint64_t seed, int32_t precision,
-                                    double eps, int32_t max_iter, double* s_out, int32_t* iters, int64_t* steps)
+                                    int32_t region, const double* x, int64_t J, int64_t n, uint64_t seed,
+                                    int32_t precision, double eps, int32_t max_iter, double* s_out,
+                                    int32_t* iters, int64_t* steps)
 {
     if (!ctx || !x || !s_out || !iters) return fail(BMC_EINVAL, "NULL argument");
     (void)hipSetDevice(ctx->device);
@@ -833,11 +855,12 @@ extern "C" bmc_status bmc_iz_search(bmc_ctx* ctx, const bmc_spec* spec, const bm
     if ((st = upload_spec(ctx, spec, ctx->spec))) return st;
     if ((st = check_rules(rules, spec)) || (st = check_prec(precision)) || (st = check_seed(seed))) return st;
     if (rules->method != BMC_IZ) return fail(BMC_EINVAL, "I&Z search needs an I&Z rule table");
+    if ((st = check_region(BMC_IZ, spec, region))) return st;
     if (date < 1 || date >= spec->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, spec->n_dates - 1);
     if (J < 1 || J > 0x7FFFFFFF || n < 2 || n > 0x7FFFFFFF) return fail(BMC_EINVAL, "J or n out of range");
     if (!(eps > 0.0) || max_iter < 1) return fail(BMC_EINVAL, "eps must be > 0 and max_iter >= 1");
-    st = iz_search_impl(ctx, ctx->spec.ptr, spec, rules, date, x, J, (uint32_t)n, (uint32_t)seed, precision, eps,
-                        max_iter, s_out, iters, steps, nullptr);
+    st = iz_search_impl(ctx, ctx->spec.ptr, spec, rules, date, region, x, J, (uint32_t)n, (uint32_t)seed,
+                        precision, eps, max_iter, s_out, iters, steps, nullptr);
     if (st) return st;
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e) return hip_fail(e, "stream sync");

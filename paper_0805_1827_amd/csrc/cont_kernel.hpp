@@ -146,8 +146,9 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
     const uint32_t lo = chunk * a.paths_per_wg;
     const uint32_t hi = min(a.n, lo + a.paths_per_wg);
     const uint32_t nb = (uint32_t)(d + 3) >> 2;
-    const uint32_t k0 = a.k0, k1 = a.k1;
+    const uint32_t k0 = a.k0, k1 = a.k1, slot = a.slot;
     const bool call_dir = payk == CALL_MAX;
+    const int W1 = rule_width(IZ, d);   // one I&Z region's boundary block
     const R K = S.K, lnK = S.lnK, invK = S.invK, inv_d = S.inv_d;
 
     // dp: the extent of the per-asset loops (D for padded buckets)
@@ -186,7 +187,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 #pragma unroll
             for (int b = 0; b < D4 / 4; ++b) {
                 R z[4] = {R(0), R(0), R(0), R(0)};
-                const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, 0u);
+                const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, slot);
                 box_muller(w.w[0], w.w[1], z[0], z[1]);
                 if (4 * b + 2 < dp) box_muller(w.w[2], w.w[3], z[2], z[3]);
 #pragma unroll
@@ -198,7 +199,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 #pragma unroll
             for (int b = 0; b < (D + 3) / 4; ++b) {
                 if (4 * b < dp) {
-                    const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, 0u);
+                    const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, slot);
                     R z[4];
                     box_muller(w.w[0], w.w[1], z[0], z[1]);
                     if (4 * b + 2 < dp) box_muller(w.w[2], w.w[3], z[2], z[3]);
@@ -228,8 +229,21 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
                 stop = cmc_score<D4, R>(dp, w, lnK, phi * invK, ls) > R(0);
             } else {
                 if constexpr (D <= 16) {
-                    const R bnd = iz_boundary<D4, R>(d, w, lnK, ls);
-                    stop = call_dir ? (ls[0] > bnd) : (ls[0] < bnd);
+                    if (call_dir) {
+                        // region of the largest asset (the first one on ties);
+                        // exercise above that region's boundary
+                        int reg = 0;
+                        R mx = ls[0];
+#pragma unroll
+                        for (int i = 1; i < D; ++i)
+                            if (i < d && ls[i] > mx) {
+                                mx = ls[i];
+                                reg = i;
+                            }
+                        stop = mx > iz_boundary<D4, R>(d, w + reg * W1, lnK, ls, reg);
+                    } else {
+                        stop = ls[0] < iz_boundary<D4, R>(d, w, lnK, ls, 0);
+                    }
                 }
             }
         }

@@ -186,9 +186,11 @@ __device__ __forceinline__ R cmc_score(int d, const R* __restrict__ w, R lnK, R 
     return F;
 }
 
-// I&Z boundary b = w . [1, v_2..v_d, v_a v_b (a <= b)], v_i = ln S_i - ln K.
+// I&Z boundary of a region, b = w . [1, v_1..v_q, v_a v_c (a <= c)], over the
+// log-moneyness v = ln S_i - ln K of the assets other than the region's own
+// one, in increasing order (region 0 of the put family: assets 2..d).
 template <int D, class R>
-__device__ __forceinline__ R iz_boundary(int d, const R* __restrict__ w, R lnK, const R (&x)[D])
+__device__ __forceinline__ R iz_boundary(int d, const R* __restrict__ w, R lnK, const R (&x)[D], int region)
 {
     const int q = d - 1;
     R v[D > 1 ? D - 1 : 1];
@@ -196,7 +198,7 @@ __device__ __forceinline__ R iz_boundary(int d, const R* __restrict__ w, R lnK, 
 #pragma unroll
     for (int a = 0; a + 1 < D; ++a) {
         if (a < q) {
-            v[a] = x[a + 1] - lnK;
+            v[a] = (a < region ? x[a] : x[a + 1]) - lnK;
             b += w[1 + a] * v[a];
         }
     }
@@ -221,6 +223,20 @@ __host__ __device__ __forceinline__ int rule_width(int method, int d)
     if (method == CMC) return 2 * d + 3;
     const int q = d - 1;
     return 1 + q + q * (q + 1) / 2;
+}
+
+// I&Z exercise regions (Section 2.2): one per asset for the max-call (asset i
+// the largest), one for the put family.
+__host__ __device__ __forceinline__ int iz_regions(int payoff, int d)
+{
+    return payoff == CALL_MAX ? d : 1;
+}
+
+// Rule row width: the CMC weights, or one I&Z boundary block per region
+// (region r at offset r * rule_width(IZ, d)).
+__host__ __device__ __forceinline__ int rule_row_width(int method, int d, int payoff)
+{
+    return method == CMC ? rule_width(CMC, d) : iz_regions(payoff, d) * rule_width(IZ, d);
 }
 
 }  // namespace bmc

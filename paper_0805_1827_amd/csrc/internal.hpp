@@ -33,6 +33,7 @@ struct ContArgs {
     uint32_t paths_per_wg;    // paths of one workgroup (a chunk)
     uint32_t nchunk;          // chunks per point
     uint32_t k0, k1;          // Philox key
+    uint32_t slot;            // fourth Philox counter word (I&Z region, else 0)
     double* part;             // [N * nchunk * 3]: sum, sum of squares, steps
 };
 
@@ -126,12 +127,13 @@ hipError_t launch_bridge_end(const DevSpec* s, int d, int64_t N, uint32_t seed, 
 hipError_t launch_bridge_back(const DevSpec* s, int d, int m, int64_t N, uint32_t seed, double* B,
                               double* x, int bridge, hipStream_t st);
 hipError_t launch_korobov(int64_t J, int q, unsigned long long* best, hipStream_t st);
-hipError_t launch_lattice(const DevSpec* s, int d, int m, int64_t J, const unsigned long long* best,
+// I&Z region `region`: lattice over the other assets, search of its own asset.
+hipError_t launch_lattice(const DevSpec* s, int d, int m, int region, int64_t J, const unsigned long long* best,
                           double* x, hipStream_t st);
-hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int64_t J, double* x_work,
+hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int region, int64_t J, double* x_work,
                           double* s_cur, double* s_out, int32_t* iters, int32_t* ids,
                           int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st);
-hipError_t launch_iz_update(const DevSpec* s, int d, int64_t J, const double* cont,
+hipError_t launch_iz_update(const DevSpec* s, int d, int region, int64_t J, const double* cont,
                             const int64_t* steps, const int32_t* ids_in, const int32_t* n_in,
                             int32_t* ids_out, int32_t* n_out, double* s_cur, double* x_work,
                             double* s_out, int32_t* iters, unsigned long long* steps_acc,
@@ -186,7 +188,8 @@ hipError_t launch_fit_cmc(const DevSpec* s, int d, const double* x, const double
                           hipStream_t st);
 // I&Z quadratic regression of rule row m; x[0*J + j] = s*_j.
 size_t fitiz_scratch_doubles(int64_t J, int p);
-hipError_t launch_fit_iz(const DevSpec* s, int d, const double* x, int64_t J, double* scratch,
+// Boundary block of one region (row64/row32 point at the block).
+hipError_t launch_fit_iz(const DevSpec* s, int d, int region, const double* x, int64_t J, double* scratch,
                          double* row64, float* row32, hipStream_t st);
 
 hipError_t launch_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t M, uint32_t* out,

@@ -432,7 +432,9 @@ hipError_t launch_korobov(int64_t J, int q, unsigned long long* best, hipStream_
     return hipGetLastError();
 }
 
-__global__ void k_lattice(const DevSpec* __restrict__ s, int m, int64_t J,
+// Lattice of one region's boundary: coordinate i maps to the i-th asset other
+// than the region's own one, whose row is set to K.
+__global__ void k_lattice(const DevSpec* __restrict__ s, int m, int region, int64_t J,
                           const unsigned long long* __restrict__ best, double* x)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -441,38 +443,39 @@ __global__ void k_lattice(const DevSpec* __restrict__ s, int m, int64_t J,
     const int d = S.d, q = d - 1;
     const int64_t a = best ? (int64_t)(0xFFFFFF - (*best & 0xFFFFFFull)) : 1;
     const double tm = S.t[m], sq = sqrt(tm);
-    x[j] = S.K;
+    x[region * J + j] = S.K;
     int64_t g = 1;
     for (int i = 0; i < q; ++i) {
         const double u = ((double)((j * g) % J) + 0.5) / (double)J;
-        const int asset = i + 1;
+        const int asset = i < region ? i : i + 1;
         x[asset * J + j] = S.S0[asset] * exp(S.drift[asset] * tm + S.sigma[asset] * sq * normcdfinv(u));
         g = (g * a) % J;
     }
 }
 
-hipError_t launch_lattice(const DevSpec* s, int d, int m, int64_t J, const unsigned long long* best,
+hipError_t launch_lattice(const DevSpec* s, int d, int m, int region, int64_t J, const unsigned long long* best,
                           double* x, hipStream_t st)
 {
     (void)d;
-    hipLaunchKernelGGL(k_lattice, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, st, s, m, J, best, x);
+    hipLaunchKernelGGL(k_lattice, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, st, s, m, region, J, best, x);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// I&Z boundary-point search state.  s <- Phi_1^{-1}(C(s)):
+// I&Z boundary-point search state.  The searched coordinate is the region's
+// own asset (asset 1 for the put family), s <- Phi^{-1}(C(s)):
 //   geometric put (K - c)^d / prod_{i>=2} x_i, arithmetic put d (K - c) -
-//   sum_{i>=2} x_i, one-asset call K + c.  Non-positive: dropped.
+//   sum_{i>=2} x_i, max-call K + c.  Non-positive: dropped; a max-call fixed
+//   point not above every other asset lies outside the region: dropped.
 
-__global__ void k_iz_init(const DevSpec* __restrict__ s, const double* __restrict__ x_in, int d,
+__global__ void k_iz_init(const DevSpec* __restrict__ s, const double* __restrict__ x_in, int d, int region,
                           int64_t J, double* x_work, double* s_cur, double* s_out, int32_t* iters,
                           int32_t* ids, int32_t* n_ids, unsigned long long* steps_acc)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= J) return;
     const double K = s->f64.K;
-    x_work[j] = K;
-    for (int i = 1; i < d; ++i) x_work[i * J + j] = x_in[i * J + j];
+    for (int i = 0; i < d; ++i) x_work[i * J + j] = i == region ? K : x_in[i * J + j];
     s_cur[j] = K;
     s_out[j] = -1.0;
     iters[j] = 0;
@@ -481,16 +484,16 @@ __global__ void k_iz_init(const DevSpec* __restrict__ s, const double* __restric
     if (j == 0) *n_ids = (int32_t)J;
 }
 
-hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int64_t J, double* x_work,
+hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int region, int64_t J, double* x_work,
                           double* s_cur, double* s_out, int32_t* iters, int32_t* ids,
                           int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_iz_init, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, st, s, x_in, d, J,
+    hipLaunchKernelGGL(k_iz_init, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, st, s, x_in, d, region, J,
                        x_work, s_cur, s_out, iters, ids, n_ids, steps_acc);
     return hipGetLastError();
 }
 
-__global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int64_t J,
+__global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region, int64_t J,
                             const double* __restrict__ cont, const int64_t* __restrict__ steps,
                             const int32_t* __restrict__ ids_in, const int32_t* __restrict__ n_in,
                             int32_t* ids_out, int32_t* n_out, double* s_cur, double* x_work,
@@ -520,21 +523,28 @@ __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int64_t J,
     const int it1 = it + 1;
     iters[j] = it1;
     if (!(snew > 0.0) || !isfinite(snew)) { s_out[j] = -1.0; return; }
-    if (fabs(snew - s_cur[j]) < eps) { s_out[j] = snew; return; }
+    if (fabs(snew - s_cur[j]) < eps) {
+        double others = 0.0;
+        if (S.payoff == CALL_MAX)
+            for (int i = 0; i < d; ++i)
+                if (i != region) others = fmax(others, x_work[i * J + j]);
+        s_out[j] = snew > others ? snew : -1.0;
+        return;
+    }
     if (it1 >= max_iter) { s_out[j] = -1.0; return; }
     s_cur[j] = snew;
-    x_work[j] = snew;
+    x_work[region * J + j] = snew;
     const int pos = atomicAdd(n_out, 1);
     ids_out[pos] = (int32_t)j;
 }
 
-hipError_t launch_iz_update(const DevSpec* s, int d, int64_t J, const double* cont,
+hipError_t launch_iz_update(const DevSpec* s, int d, int region, int64_t J, const double* cont,
                             const int64_t* steps, const int32_t* ids_in, const int32_t* n_in,
                             int32_t* ids_out, int32_t* n_out, double* s_cur, double* x_work,
                             double* s_out, int32_t* iters, unsigned long long* steps_acc,
                             double eps, int max_iter, int it, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_iz_update, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, st, s, d, J,
+    hipLaunchKernelGGL(k_iz_update, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, st, s, d, region, J,
                        cont, steps, ids_in, n_in, ids_out, n_out, s_cur, x_work, s_out, iters,
                        steps_acc, eps, max_iter, it);
     return hipGetLastError();

@@ -127,20 +127,25 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
         int32_t* iters = (int32_t*)((char*)ctx->steps.ptr + sizeof(int64_t) * N);
         std::vector<double> hs(N);
         std::vector<int32_t> hi(N);
-        for (int m = NT - 1; m >= 1 && !st; --m) {
-            if ((st = sample_points_impl(ctx, ds, spec, BMC_IZ, m, N, seed, x, B))) break;
+        const int regions = iz_regions(spec->payoff, d);
+        // Algorithm 1: per date, one search and one regression per region; a
+        // region's search at date m uses the rules of later dates only.
+        for (int it = (NT - 1) * regions - 1; it >= 0 && !st; --it) {
+            const int m = it / regions + 1, region = regions - 1 - it % regions;
+            if ((st = sample_points_impl(ctx, ds, spec, BMC_IZ, m, N, seed, x, B, region))) break;
             timer.mark(PH_CALC);
             int64_t stp = 0;
-            st = iz_search_impl(ctx, ds, spec, rules, m, x, N, n, seed, prec, eps, max_iter, s_out, iters, &stp,
-                                tune);
+            st = iz_search_impl(ctx, ds, spec, rules, m, region, x, N, n, seed, prec, eps, max_iter, s_out, iters,
+                                &stp, tune);
             if (st) break;
             iz_steps += stp;
             timer.mark(PH_FIT);
-            if ((e = hipMemcpyAsync(x, s_out, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream))) {
+            if ((e = hipMemcpyAsync(x + (size_t)region * N, s_out, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                                    ctx->stream))) {
                 st = hip_fail(e, "boundary copy");
                 break;
             }
-            if ((st = fit_rule_impl(ctx, ds, d, rules, m, x, nullptr, N, rounds))) break;
+            if ((st = fit_rule_impl(ctx, ds, d, rules, m, x, nullptr, N, rounds, region))) break;
             timer.mark(-1);
             if ((e = hipMemcpyAsync(hs.data(), s_out, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream)) ||
                 (e = hipMemcpyAsync(hi.data(), iters, sizeof(int32_t) * N, hipMemcpyDeviceToHost, ctx->stream)) ||

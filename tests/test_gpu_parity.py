@@ -135,12 +135,22 @@ def test_cmc_points_parity(bmc, ctx, orc, torch_mod, inputs):
             assert_close(x, orc.points_cmc(spec, m, N, 7), spec.K, rel=1e-12, what=f"points m={m}")
 
 
+def asym_max_call2(inputs):
+    return inputs.basket(2, [100.0, 90.0], 100.0, 0.05, 0.1, [0.2, 0.3], 0.0, 3.0, 9, inputs.CALL_MAX)
+
+
 def test_iz_lattice_parity(bmc, ctx, orc, torch_mod, inputs):
     for spec, J in ((inputs.geometric_put5(), 256), (inputs.one_asset_put(), 8),
-                    (inputs.basket(3, 100.0, 100.0, 0.05, 0.0, 0.25, 0.2, 1.0, 6, inputs.PUT_BASKET), 97)):
-        for m in (1, spec.n_dates - 1):
-            x = host(bmc.bmc_sample_points(ctx, spec, bmc.IZ, m, J, 1))
-            assert_close(x, orc.points_iz(spec, m, J), spec.K, rel=1e-12, what=f"lattice m={m}")
+                    (inputs.basket(3, 100.0, 100.0, 0.05, 0.0, 0.25, 0.2, 1.0, 6, inputs.PUT_BASKET), 97),
+                    (inputs.basket(3, [90.0, 100.0, 115.0], 100.0, 0.05, 0.1, [0.2, 0.25, 0.3], 0.3, 3.0, 9,
+                                   inputs.CALL_MAX), 61),
+                    (asym_max_call2(inputs), 20)):
+        assert bmc.bmc_iz_regions(spec) == orc.iz_regions(spec)
+        for region in range(bmc.bmc_iz_regions(spec)):
+            for m in (1, spec.n_dates - 1):
+                x = host(bmc.bmc_sample_points(ctx, spec, bmc.IZ, m, J, 1, region=region))
+                assert_close(x, orc.points_iz(spec, m, J, region=region), spec.K, rel=1e-12,
+                             what=f"lattice m={m} region={region}")
 
 
 # --- continuation estimates -------------------------------------------------
@@ -272,6 +282,29 @@ def test_iz_fit_parity(bmc, ctx, orc, torch_mod, inputs):
     assert np.allclose(bmc.bmc_rules_get(rules, m), b_ref, rtol=1e-9, atol=1e-11)
 
 
+def test_iz_fit_parity_max_call_regions(bmc, ctx, orc, torch_mod, inputs):
+    """Each region's block is fitted from its own row of s* and its own
+    features, and lands at its offset in the row; other blocks untouched."""
+    spec = inputs.basket(3, [90.0, 100.0, 115.0], 100.0, 0.05, 0.1, [0.2, 0.25, 0.3], 0.3, 3.0, 9,
+                         inputs.CALL_MAX)
+    m, J = 6, 150
+    rules = bmc.bmc_rules_create(ctx, spec, bmc.IZ)
+    W = orc.rule_width(orc.IZ, 3)
+    assert bmc.bmc_rules_width(rules) == orc.row_width(spec, orc.IZ) == 3 * W
+    want = bmc.bmc_rules_get(rules, m)
+    rng = np.random.default_rng(4)
+    for region in (2, 0, 1):
+        x = orc.points_iz(spec, m, J, region=region)
+        sstar = (130.0 + 10 * region) * np.exp(rng.normal(0, 0.05, J))
+        sstar[region::13] = -1.0
+        b_ref = orc.fit_iz(spec, x, sstar, region=region)
+        xs = x.copy()
+        xs[region] = sstar
+        bmc.bmc_fit_rule(ctx, spec, rules, m, dev(torch_mod, xs), region=region)
+        want[region * W:(region + 1) * W] = b_ref
+        assert np.allclose(bmc.bmc_rules_get(rules, m), want, rtol=1e-9, atol=1e-11), region
+
+
 def test_iz_fit_without_points_never_exercises(bmc, ctx, orc, torch_mod, inputs):
     spec = inputs.geometric_put5()
     x = orc.points_iz(spec, 3, 16)
@@ -285,21 +318,29 @@ def test_iz_fit_without_points_never_exercises(bmc, ctx, orc, torch_mod, inputs)
 
 # --- I&Z search -------------------------------------------------------------------
 
-@pytest.mark.parametrize("case", ["put1", "geo5"])
+@pytest.mark.parametrize("case", ["put1", "geo5", "maxcall3", "maxcall2"])
 def test_iz_search_parity(bmc, ctx, orc, torch_mod, inputs, case):
-    spec = inputs.one_asset_put() if case == "put1" else inputs.geometric_put5()
-    J, n = (8, 3000) if case == "put1" else (40, 1500)
+    """Per region: the searched asset, the region's counter word, the rules
+    of later dates (every region's block exercised on the inner paths) and
+    the drop of fixed points outside the region."""
+    spec = {"put1": inputs.one_asset_put(), "geo5": inputs.geometric_put5(),
+            "maxcall3": inputs.max_call(3, 100.0), "maxcall2": asym_max_call2(inputs)}[case]
+    J, n = {"put1": (8, 3000), "geo5": (40, 1500), "maxcall3": (24, 800), "maxcall2": (40, 1000)}[case]
     table = orc.empty_rules(spec, orc.IZ)
-    if case == "geo5":
+    if case != "put1":
         table = orc.price(spec, orc.IZ, 16, 300, 256, 2, nthreads=NT_CPU)["rules"]
+    dropped = 0
     for m in (spec.n_dates - 1, 3):
-        x = orc.points_iz(spec, m, J)
-        rules = gpu_rules(bmc, ctx, spec, bmc.IZ, table)
-        s, it, steps = bmc.bmc_iz_search(ctx, spec, rules, m, dev(torch_mod, x), n, 2)
-        ref = orc.iz_search(spec, table, m, x, n, 2, nthreads=NT_CPU)
-        assert np.array_equal(host(it), ref["iters"])
-        assert_close(host(s), ref["s"], spec.K, what=f"s* m={m}")
-        assert steps == ref["steps"]
+        for region in range(orc.iz_regions(spec)):
+            x = orc.points_iz(spec, m, J, region=region)
+            rules = gpu_rules(bmc, ctx, spec, bmc.IZ, table)
+            s, it, steps = bmc.bmc_iz_search(ctx, spec, rules, m, dev(torch_mod, x), n, 2, region=region)
+            ref = orc.iz_search(spec, table, m, x, n, 2, nthreads=NT_CPU, region=region)
+            assert np.array_equal(host(it), ref["iters"]), (m, region)
+            assert_close(host(s), ref["s"], spec.K, what=f"s* m={m} region={region}")
+            assert steps == ref["steps"]
+            dropped += int(np.sum(ref["s"] <= 0))
+    assert case != "maxcall2" or dropped < 2 * 2 * J
 
 
 # --- final pricing and the whole pricer ----------------------------------------------
@@ -314,13 +355,15 @@ def test_final_price_parity(bmc, ctx, orc, torch_mod, c1_rules):
     assert r["final_path_steps"] == ref["final_steps"]
 
 
-@pytest.mark.parametrize("case", ["c1_cmc", "c1_iz", "geo5_cmc", "geo5_iz", "maxcall3_cmc"])
+@pytest.mark.parametrize("case", ["c1_cmc", "c1_iz", "geo5_cmc", "geo5_iz", "maxcall3_cmc", "maxcall3_iz",
+                                  "maxcall2_iz"])
 def test_price_end_to_end_fp64(bmc, ctx, orc, torch_mod, inputs, case):
     spec = {"c1": inputs.one_asset_put(), "geo5": inputs.geometric_put5(),
-            "maxcall3": inputs.max_call(3, 100.0)}[case.split("_")[0]]
+            "maxcall3": inputs.max_call(3, 100.0), "maxcall2": asym_max_call2(inputs)}[case.split("_")[0]]
     method = bmc.CMC if case.endswith("cmc") else bmc.IZ
     N, n, nf = {"c1_cmc": (500, 500, 100000), "c1_iz": (16, 500, 100000), "geo5_cmc": (512, 512, 100000),
-                "geo5_iz": (48, 400, 50000), "maxcall3_cmc": (400, 300, 50000)}[case]
+                "geo5_iz": (48, 400, 50000), "maxcall3_cmc": (400, 300, 50000), "maxcall3_iz": (32, 300, 50000),
+                "maxcall2_iz": (48, 400, 50000)}[case]
     res, rules = bmc.bmc_price(ctx, spec, method, bmc.FP64, N=N, n=n, n_final=nf, seed=1, want_rules=True)
     ref = orc.price(spec, method, N, n, nf, 1, nthreads=NT_CPU)
     assert_close(res["price"], ref["price"], spec.K, what="price")
@@ -338,9 +381,10 @@ def test_price_end_to_end_fp64(bmc, ctx, orc, torch_mod, inputs, case):
 
 
 @pytest.mark.parametrize("prec", ["FP32", "FP32_KAHAN"])
-@pytest.mark.parametrize("case", ["c1_cmc", "geo5_cmc", "geo5_iz"])
+@pytest.mark.parametrize("case", ["c1_cmc", "geo5_cmc", "geo5_iz", "maxcall3_iz"])
 def test_price_fp32_within_tenth_of_std_err(bmc, ctx, orc, torch_mod, inputs, case, prec):
-    spec = inputs.one_asset_put() if case.startswith("c1") else inputs.geometric_put5()
+    spec = {"c1": inputs.one_asset_put(), "geo5": inputs.geometric_put5(),
+            "maxcall3": inputs.max_call(3, 100.0)}[case.split("_")[0]]
     method = bmc.CMC if case.endswith("cmc") else bmc.IZ
     N, n = (500, 500) if method == bmc.CMC else (256, 1000)
     res = bmc.bmc_price(ctx, spec, method, getattr(bmc, prec), N=N, n=n, n_final=200000, seed=1)
@@ -415,9 +459,25 @@ def test_error_statuses(bmc, ctx, torch_mod, inputs):
     with pytest.raises(bmc.BmcError) as e:
         bmc.bmc_price(ctx, spec, N=8, n=8, n_final=8, seed=2 ** 32)
     assert e.value.status == bmc.EINVAL
+    mc3 = inputs.max_call(3, 100.0)
+    mc_rules = bmc.bmc_rules_create(ctx, mc3, bmc.IZ)
+    assert bmc.bmc_rules_width(mc_rules) == 3 * 6
+    assert np.all(bmc.bmc_rules_get(mc_rules, 4)[::6] == 1e300)    # every region starts "never"
+    x3 = bmc.bmc_sample_points(ctx, mc3, bmc.IZ, 4, 8, 1, region=2)
+    for region in (-1, 3):
+        with pytest.raises(bmc.BmcError) as e:
+            bmc.bmc_sample_points(ctx, mc3, bmc.IZ, 4, 8, 1, region=region)
+        assert e.value.status == bmc.EINVAL
+        with pytest.raises(bmc.BmcError) as e:
+            bmc.bmc_iz_search(ctx, mc3, mc_rules, 4, x3, 100, 1, region=region)
+        assert e.value.status == bmc.EINVAL
     with pytest.raises(bmc.BmcError) as e:
-        bmc.bmc_rules_create(ctx, inputs.max_call(3, 100.0), bmc.IZ)
-    assert e.value.status == bmc.EUNSUPPORTED
+        bmc.bmc_sample_points(ctx, mc3, bmc.CMC, 4, 8, 1, region=1)
+    assert e.value.status == bmc.EINVAL
+    put3 = inputs.basket(3, 100.0, 100.0, 0.05, 0.0, 0.2, 0.0, 3.0, 9, inputs.PUT_BASKET)
+    with pytest.raises(bmc.BmcError) as e:       # one region's rows for a three-region payoff
+        bmc.bmc_iz_search(ctx, mc3, bmc.bmc_rules_create(ctx, put3, bmc.IZ), 4, x3, 100, 1)
+    assert e.value.status == bmc.EINVAL
     other = bmc.bmc_rules_create(ctx, inputs.one_asset_put(), bmc.CMC)
     with pytest.raises(bmc.BmcError) as e:
         bmc.bmc_final_price(ctx, spec, other, 100, 1)

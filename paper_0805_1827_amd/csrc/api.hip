@@ -625,7 +625,7 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
                          const double* x, int64_t N, const int32_t* ids, const int32_t* n_ids,
                          uint32_t n, uint32_t k0, uint32_t k1, double* cont, double* se,
                          int64_t* steps, double* sums, unsigned long long* steps_total,
-                         const Tuning* tune, uint32_t slot)
+                         const Tuning* tune, uint32_t slot, uint32_t region_pts)
 {
     const int block = (tune && tune->block > 0) ? tune->block : 256;
     const uint32_t ppt = choose_ppt(ctx, d, prec, N, n, tune);
@@ -654,6 +654,7 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
     a.k0 = k0;
     a.k1 = k1;
     a.slot = slot;
+    a.region_pts = region_pts;
     a.part = (double*)ctx->part.ptr;
     if ((e = launch_cont(d, prec, a, (int)grid, block, lds, ctx->stream))) return hip_fail(e, "continuation launch");
     if ((e = launch_finalize(a.part, nchunk, n, N, ids, n_ids, cont, se, steps, sums, steps_total,
@@ -684,7 +685,8 @@ extern "C" bmc_status bmc_estimate_continuation(bmc_ctx* ctx, const bmc_spec* sp
 }
 
 bmc_status bmc::fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rules* rules, int date,
-                              const double* x, const double* values, int64_t N, int rounds, int region)
+                              const double* x, const double* values, int64_t N, int rounds, int region,
+                              int64_t ld)
 {
     hipError_t e;
     double* row64 = rules->w64 + (size_t)date * rules->width;
@@ -700,7 +702,7 @@ bmc_status bmc::fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rule
     } else {
         const int p = rule_width(BMC_IZ, d);
         if ((e = ctx->fit.ensure(sizeof(double) * fitiz_scratch_doubles(N, p)))) return hip_fail(e, "fit scratch");
-        if ((e = launch_fit_iz((const DevSpec*)devspec, d, region, x, N, (double*)ctx->fit.ptr,
+        if ((e = launch_fit_iz((const DevSpec*)devspec, d, region, x, N, ld > 0 ? ld : N, (double*)ctx->fit.ptr,
                                row64 + (size_t)region * p, row32 + (size_t)region * p, ctx->stream)))
             return hip_fail(e, "fit launch");
     }
@@ -739,7 +741,8 @@ extern "C" bmc_status bmc_fit_rule(bmc_ctx* ctx, const bmc_spec* spec, bmc_rules
 }
 
 bmc_status bmc::sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, int method,
-                                   int date, int64_t N, uint32_t seed, double* x, double* Bbuf, int region)
+                                   int date, int64_t N, uint32_t seed, double* x, double* Bbuf, int region,
+                                   int nreg)
 {
     hipError_t e;
     const DevSpec* ds = (const DevSpec*)devspec;
@@ -760,7 +763,7 @@ bmc_status bmc::sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_
                 return hip_fail(e, "korobov");
             best = (const unsigned long long*)ctx->korobov.ptr;
         }
-        if ((e = launch_lattice(ds, d, date, region, N, best, x, ctx->stream))) return hip_fail(e, "lattice");
+        if ((e = launch_lattice(ds, d, date, region, nreg, N, best, x, ctx->stream))) return hip_fail(e, "lattice");
     }
     return BMC_OK;
 }
@@ -785,11 +788,13 @@ extern "C" bmc_status bmc_sample_points(bmc_ctx* ctx, const bmc_spec* spec, int3
 }
 
 bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, const bmc_rules* rules,
-                               int date, int region, const double* x, int64_t J, uint32_t n, uint32_t seed,
-                               int prec, double eps, int max_iter, double* s_out, int32_t* iters,
+                               int date, int region, int nreg, const double* x, int64_t J, uint32_t n,
+                               uint32_t seed, int prec, double eps, int max_iter, double* s_out, int32_t* iters,
                                int64_t* steps_out, const Tuning* tune)
 {
     const int d = spec->d;
+    const int64_t Jr = J;   // points per region
+    J *= nreg;              // columns of all regions
     hipError_t e;
     // x_work [d][J], s_cur, cont [J], steps [J], steps_acc [J], ids x2, counters
     const size_t need = sizeof(double) * ((size_t)d * J + 3 * J) + sizeof(unsigned long long) * J +
@@ -807,7 +812,8 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     // counters buffer: [0,8) step total, [16,40) final sums/steps, [48,56) active counts
     int32_t* cnt = (int32_t*)((char*)ctx->counters.ptr + 48);
     const DevSpec* ds = (const DevSpec*)devspec;
-    if ((e = launch_iz_init(ds, x, d, region, J, x_work, s_cur, s_out, iters, ids_a, &cnt[0], acc, ctx->stream)))
+    if ((e = launch_iz_init(ds, x, d, region, nreg, Jr, x_work, s_cur, s_out, iters, ids_a, &cnt[0], acc,
+                            ctx->stream)))
         return hip_fail(e, "search init");
     const uint32_t k1 = key_hi(BMC_STREAM_INNER, date);
     for (int it = 0; it < max_iter; ++it) {
@@ -818,9 +824,10 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
         if ((e = hipMemsetAsync(n_out, 0, sizeof(int32_t), ctx->stream))) return hip_fail(e, "search");
         bmc_status st = run_cont(ctx, devspec, d, spec->n_dates, rules->method, rules->width, rules->w64,
                                  rules->w32, prec, date, x_work, J, ids_in, n_in, n, seed, k1, cont,
-                                 nullptr, stp, nullptr, nullptr, tune, (uint32_t)region);
+                                 nullptr, stp, nullptr, nullptr, tune, (uint32_t)region,
+                                 nreg > 1 ? (uint32_t)Jr : 0u);
         if (st) return st;
-        if ((e = launch_iz_update(ds, d, region, J, cont, stp, ids_in, n_in, ids_out, n_out, s_cur, x_work, s_out,
+        if ((e = launch_iz_update(ds, d, region, nreg, Jr, cont, stp, ids_in, n_in, ids_out, n_out, s_cur, x_work, s_out,
                                   iters, acc, eps, max_iter, it, ctx->stream)))
             return hip_fail(e, "search update");
         if ((it & 3) == 3 || it == max_iter - 1) {
@@ -859,7 +866,7 @@ extern "C" bmc_status bmc_iz_search(bmc_ctx* ctx, const bmc_spec* spec, const bm
     if (date < 1 || date >= spec->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, spec->n_dates - 1);
     if (J < 1 || J > 0x7FFFFFFF || n < 2 || n > 0x7FFFFFFF) return fail(BMC_EINVAL, "J or n out of range");
     if (!(eps > 0.0) || max_iter < 1) return fail(BMC_EINVAL, "eps must be > 0 and max_iter >= 1");
-    st = iz_search_impl(ctx, ctx->spec.ptr, spec, rules, date, region, x, J, (uint32_t)n, (uint32_t)seed,
+    st = iz_search_impl(ctx, ctx->spec.ptr, spec, rules, date, region, 1, x, J, (uint32_t)n, (uint32_t)seed,
                         precision, eps, max_iter, s_out, iters, steps, nullptr);
     if (st) return st;
     hipError_t e = hipStreamSynchronize(ctx->stream);

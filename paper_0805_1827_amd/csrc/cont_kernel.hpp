@@ -146,7 +146,14 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
     const uint32_t lo = chunk * a.paths_per_wg;
     const uint32_t hi = min(a.n, lo + a.paths_per_wg);
     const uint32_t nb = (uint32_t)(d + 3) >> 2;
-    const uint32_t k0 = a.k0, k1 = a.k1, slot = a.slot;
+    const uint32_t k0 = a.k0, k1 = a.k1;
+    // counter point and fourth counter word of this job's point
+    uint32_t slot = a.slot, pj = j;
+    if (a.region_pts) {
+        const uint32_t r = j / a.region_pts;
+        slot += r;
+        pj = j - r * a.region_pts;
+    }
     const bool call_dir = payk == CALL_MAX;
     const int W1 = rule_width(IZ, d);   // one I&Z region's boundary block
     const R K = S.K, lnK = S.lnK, invK = S.invK, inv_d = S.inv_d;
@@ -187,7 +194,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 #pragma unroll
             for (int b = 0; b < D4 / 4; ++b) {
                 R z[4] = {R(0), R(0), R(0), R(0)};
-                const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, slot);
+                const Words w = philox(k0, k1, c0 + (uint32_t)b, p, pj, slot);
                 box_muller(w.w[0], w.w[1], z[0], z[1]);
                 if (4 * b + 2 < dp) box_muller(w.w[2], w.w[3], z[2], z[3]);
 #pragma unroll
@@ -199,7 +206,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 #pragma unroll
             for (int b = 0; b < (D + 3) / 4; ++b) {
                 if (4 * b < dp) {
-                    const Words w = philox(k0, k1, c0 + (uint32_t)b, p, j, slot);
+                    const Words w = philox(k0, k1, c0 + (uint32_t)b, p, pj, slot);
                     R z[4];
                     box_muller(w.w[0], w.w[1], z[0], z[1]);
                     if (4 * b + 2 < dp) box_muller(w.w[2], w.w[3], z[2], z[3]);

@@ -153,7 +153,7 @@ hipError_t launch_fit_cmc(const DevSpec* s, int d, const double* x, const double
 // s*_j > 0; v over the other assets in increasing order), then one solve.
 
 __global__ void k_fitiz_part(const DevSpec* __restrict__ s, const double* __restrict__ x, int region, int64_t J,
-                             int p, double* part)
+                             int64_t ld, int p, double* part)
 {
     extern __shared__ double sh[];
     const SpecT<double>& S = s->f64;
@@ -164,10 +164,10 @@ __global__ void k_fitiz_part(const DevSpec* __restrict__ s, const double* __rest
     const int64_t j0 = (int64_t)blockIdx.x * T;
     const int64_t j = j0 + threadIdx.x;
     const int tl = threadIdx.x;
-    const double sst = j < J ? x[region * J + j] : -1.0;
+    const double sst = j < J ? x[region * ld + j] : -1.0;
     if (sst > 0.0) {
         xi[tl * p] = 1.0;
-        for (int a = 0; a < q; ++a) xi[tl * p + 1 + a] = log(x[(a < region ? a : a + 1) * J + j]) - S.lnK;
+        for (int a = 0; a < q; ++a) xi[tl * p + 1 + a] = log(x[(a < region ? a : a + 1) * ld + j]) - S.lnK;
         int f = 1 + q;
         for (int a = 0; a < q; ++a)
             for (int c = a; c < q; ++c) {
@@ -250,8 +250,8 @@ size_t fitiz_scratch_doubles(int64_t J, int p)
     return (size_t)(tiles * (npairs + p + 1) + npairs + 2 * p + 64);
 }
 
-hipError_t launch_fit_iz(const DevSpec* s, int d, int region, const double* x, int64_t J, double* scratch,
-                         double* row64, float* row32, hipStream_t st)
+hipError_t launch_fit_iz(const DevSpec* s, int d, int region, const double* x, int64_t J, int64_t ld,
+                         double* scratch, double* row64, float* row32, hipStream_t st)
 {
     const int p = rule_width(IZ, d);
     const int T = fitiz_tile(p);
@@ -260,7 +260,7 @@ hipError_t launch_fit_iz(const DevSpec* s, int d, int region, const double* x, i
     double* part = scratch;
     double* Awork = scratch + (size_t)tiles * (npairs + p + 1);
     const size_t lds = sizeof(double) * ((size_t)T * p + 2 * T);
-    hipLaunchKernelGGL(k_fitiz_part, dim3(tiles), dim3(T), lds, st, s, x, region, J, p, part);
+    hipLaunchKernelGGL(k_fitiz_part, dim3(tiles), dim3(T), lds, st, s, x, region, J, ld, p, part);
     hipLaunchKernelGGL(k_fitiz_solve, dim3(1), dim3(256), 0, st, s, p, tiles, part, Awork, row64, row32);
     return hipGetLastError();
 }

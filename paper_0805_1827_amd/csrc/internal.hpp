@@ -34,6 +34,9 @@ struct ContArgs {
     uint32_t nchunk;          // chunks per point
     uint32_t k0, k1;          // Philox key
     uint32_t slot;            // fourth Philox counter word (I&Z region, else 0)
+    uint32_t region_pts;      // > 0: points of several I&Z regions side by side, region_pts
+                              // each; point j counts as point j % region_pts of
+                              // region slot + j / region_pts in the counters
     double* part;             // [N * nchunk * 3]: sum, sum of squares, steps
 };
 
@@ -127,13 +130,16 @@ hipError_t launch_bridge_end(const DevSpec* s, int d, int64_t N, uint32_t seed, 
 hipError_t launch_bridge_back(const DevSpec* s, int d, int m, int64_t N, uint32_t seed, double* B,
                               double* x, int bridge, hipStream_t st);
 hipError_t launch_korobov(int64_t J, int q, unsigned long long* best, hipStream_t st);
-// I&Z region `region`: lattice over the other assets, search of its own asset.
-hipError_t launch_lattice(const DevSpec* s, int d, int m, int region, int64_t J, const unsigned long long* best,
-                          double* x, hipStream_t st);
-hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int region, int64_t J, double* x_work,
-                          double* s_cur, double* s_out, int32_t* iters, int32_t* ids,
+// I&Z regions region0 .. region0 + nreg - 1 side by side: J points each,
+// region region0 + r in columns r J .. r J + J - 1 of rows of nreg J entries.
+// Lattice: over the other assets, the region's own asset set to K.  Search
+// state: the region's own asset is the searched coordinate.
+hipError_t launch_lattice(const DevSpec* s, int d, int m, int region0, int nreg, int64_t J,
+                          const unsigned long long* best, double* x, hipStream_t st);
+hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int region0, int nreg, int64_t J,
+                          double* x_work, double* s_cur, double* s_out, int32_t* iters, int32_t* ids,
                           int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st);
-hipError_t launch_iz_update(const DevSpec* s, int d, int region, int64_t J, const double* cont,
+hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* cont,
                             const int64_t* steps, const int32_t* ids_in, const int32_t* n_in,
                             int32_t* ids_out, int32_t* n_out, double* s_cur, double* x_work,
                             double* s_out, int32_t* iters, unsigned long long* steps_acc,
@@ -188,9 +194,10 @@ hipError_t launch_fit_cmc(const DevSpec* s, int d, const double* x, const double
                           hipStream_t st);
 // I&Z quadratic regression of rule row m; x[0*J + j] = s*_j.
 size_t fitiz_scratch_doubles(int64_t J, int p);
-// Boundary block of one region (row64/row32 point at the block).
-hipError_t launch_fit_iz(const DevSpec* s, int d, int region, const double* x, int64_t J, double* scratch,
-                         double* row64, float* row32, hipStream_t st);
+// Boundary block of one region (row64/row32 point at the block) from J
+// points in rows of ld entries.
+hipError_t launch_fit_iz(const DevSpec* s, int d, int region, const double* x, int64_t J, int64_t ld,
+                         double* scratch, double* row64, float* row32, hipStream_t st);
 
 hipError_t launch_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t M, uint32_t* out,
                          hipStream_t st);

@@ -432,32 +432,37 @@ hipError_t launch_korobov(int64_t J, int q, unsigned long long* best, hipStream_
     return hipGetLastError();
 }
 
-// Lattice of one region's boundary: coordinate i maps to the i-th asset other
-// than the region's own one, whose row is set to K.
-__global__ void k_lattice(const DevSpec* __restrict__ s, int m, int region, int64_t J,
-                          const unsigned long long* __restrict__ best, double* x)
+// Lattice of a region's boundary (region region0 + blockIdx.y in the
+// column block blockIdx.y; rows of gridDim.y J entries): coordinate i maps to
+// the i-th asset other than the region's own one, whose row is set to K.
+__global__ void k_lattice(const DevSpec* __restrict__ s, int m, int region0, int64_t J,
+                          const unsigned long long* __restrict__ best, double* x_all)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= J) return;
+    const int region = region0 + (int)blockIdx.y;
+    const int64_t ld = (int64_t)gridDim.y * J;
+    double* x = x_all + (int64_t)blockIdx.y * J;
     const SpecT<double>& S = s->f64;
     const int d = S.d, q = d - 1;
     const int64_t a = best ? (int64_t)(0xFFFFFF - (*best & 0xFFFFFFull)) : 1;
     const double tm = S.t[m], sq = sqrt(tm);
-    x[region * J + j] = S.K;
+    x[region * ld + j] = S.K;
     int64_t g = 1;
     for (int i = 0; i < q; ++i) {
         const double u = ((double)((j * g) % J) + 0.5) / (double)J;
         const int asset = i < region ? i : i + 1;
-        x[asset * J + j] = S.S0[asset] * exp(S.drift[asset] * tm + S.sigma[asset] * sq * normcdfinv(u));
+        x[asset * ld + j] = S.S0[asset] * exp(S.drift[asset] * tm + S.sigma[asset] * sq * normcdfinv(u));
         g = (g * a) % J;
     }
 }
 
-hipError_t launch_lattice(const DevSpec* s, int d, int m, int region, int64_t J, const unsigned long long* best,
-                          double* x, hipStream_t st)
+hipError_t launch_lattice(const DevSpec* s, int d, int m, int region0, int nreg, int64_t J,
+                          const unsigned long long* best, double* x, hipStream_t st)
 {
     (void)d;
-    hipLaunchKernelGGL(k_lattice, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, st, s, m, region, J, best, x);
+    hipLaunchKernelGGL(k_lattice, dim3((unsigned)((J + 255) / 256), (unsigned)nreg), dim3(256), 0, st, s, m,
+                       region0, J, best, x);
     return hipGetLastError();
 }
 
@@ -468,32 +473,35 @@ hipError_t launch_lattice(const DevSpec* s, int d, int m, int region, int64_t J,
 //   sum_{i>=2} x_i, max-call K + c.  Non-positive: dropped; a max-call fixed
 //   point not above every other asset lies outside the region: dropped.
 
-__global__ void k_iz_init(const DevSpec* __restrict__ s, const double* __restrict__ x_in, int d, int region,
-                          int64_t J, double* x_work, double* s_cur, double* s_out, int32_t* iters,
+// Columns j of nreg regions side by side (J each, rows of Jt = nreg J).
+__global__ void k_iz_init(const DevSpec* __restrict__ s, const double* __restrict__ x_in, int d, int region0,
+                          int64_t J, int64_t Jt, double* x_work, double* s_cur, double* s_out, int32_t* iters,
                           int32_t* ids, int32_t* n_ids, unsigned long long* steps_acc)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= J) return;
+    if (j >= Jt) return;
+    const int region = region0 + (int)(j / J);
     const double K = s->f64.K;
-    for (int i = 0; i < d; ++i) x_work[i * J + j] = i == region ? K : x_in[i * J + j];
+    for (int i = 0; i < d; ++i) x_work[i * Jt + j] = i == region ? K : x_in[i * Jt + j];
     s_cur[j] = K;
     s_out[j] = -1.0;
     iters[j] = 0;
     ids[j] = (int32_t)j;
     steps_acc[j] = 0;
-    if (j == 0) *n_ids = (int32_t)J;
+    if (j == 0) *n_ids = (int32_t)Jt;
 }
 
-hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int region, int64_t J, double* x_work,
-                          double* s_cur, double* s_out, int32_t* iters, int32_t* ids,
+hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int region0, int nreg, int64_t J,
+                          double* x_work, double* s_cur, double* s_out, int32_t* iters, int32_t* ids,
                           int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_iz_init, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, st, s, x_in, d, region, J,
+    const int64_t Jt = (int64_t)nreg * J;
+    hipLaunchKernelGGL(k_iz_init, dim3((unsigned)((Jt + 255) / 256)), dim3(256), 0, st, s, x_in, d, region0, J, Jt,
                        x_work, s_cur, s_out, iters, ids, n_ids, steps_acc);
     return hipGetLastError();
 }
 
-__global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region, int64_t J,
+__global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region0, int64_t J, int64_t Jt,
                             const double* __restrict__ cont, const int64_t* __restrict__ steps,
                             const int32_t* __restrict__ ids_in, const int32_t* __restrict__ n_in,
                             int32_t* ids_out, int32_t* n_out, double* s_cur, double* x_work,
@@ -503,6 +511,7 @@ __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region, in
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= *n_in) return;
     const int64_t j = ids_in[slot];
+    const int region = region0 + (int)(j / J);
     const SpecT<double>& S = s->f64;
     const double c = cont[j];
     steps_acc[j] += (unsigned long long)steps[j];
@@ -513,11 +522,11 @@ __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region, in
         snew = -1.0;
     } else if (S.payoff == PUT_GEO || d == 1) {
         double prod = 1.0;
-        for (int i = 1; i < d; ++i) prod *= x_work[i * J + j];
+        for (int i = 1; i < d; ++i) prod *= x_work[i * Jt + j];
         snew = pow(S.K - c, (double)d) / prod;
     } else {
         double rest = 0.0;
-        for (int i = 1; i < d; ++i) rest += x_work[i * J + j];
+        for (int i = 1; i < d; ++i) rest += x_work[i * Jt + j];
         snew = (double)d * (S.K - c) - rest;
     }
     const int it1 = it + 1;
@@ -527,24 +536,25 @@ __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region, in
         double others = 0.0;
         if (S.payoff == CALL_MAX)
             for (int i = 0; i < d; ++i)
-                if (i != region) others = fmax(others, x_work[i * J + j]);
+                if (i != region) others = fmax(others, x_work[i * Jt + j]);
         s_out[j] = snew > others ? snew : -1.0;
         return;
     }
     if (it1 >= max_iter) { s_out[j] = -1.0; return; }
     s_cur[j] = snew;
-    x_work[region * J + j] = snew;
+    x_work[region * Jt + j] = snew;
     const int pos = atomicAdd(n_out, 1);
     ids_out[pos] = (int32_t)j;
 }
 
-hipError_t launch_iz_update(const DevSpec* s, int d, int region, int64_t J, const double* cont,
+hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* cont,
                             const int64_t* steps, const int32_t* ids_in, const int32_t* n_in,
                             int32_t* ids_out, int32_t* n_out, double* s_cur, double* x_work,
                             double* s_out, int32_t* iters, unsigned long long* steps_acc,
                             double eps, int max_iter, int it, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_iz_update, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, st, s, d, region, J,
+    const int64_t Jt = (int64_t)nreg * J;
+    hipLaunchKernelGGL(k_iz_update, dim3((unsigned)((Jt + 255) / 256)), dim3(256), 0, st, s, d, region0, J, Jt,
                        cont, steps, ids_in, n_in, ids_out, n_out, s_cur, x_work, s_out, iters,
                        steps_acc, eps, max_iter, it);
     return hipGetLastError();

@@ -91,9 +91,11 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     hipError_t e;
     PhaseTimer timer(ctx);
     int64_t unconv = 0, iz_iters = 0, iz_steps = 0;
-    if ((e = ctx->counters.ensure(64)) || (e = ctx->x.ensure(sizeof(double) * d * N)) ||
-        (e = ctx->cont.ensure(sizeof(double) * N)) || (e = ctx->B.ensure(sizeof(double) * d * N)) ||
-        (e = ctx->steps.ensure(sizeof(int64_t) * N + sizeof(int32_t) * N))) {
+    // I&Z: the points of every region side by side
+    const int64_t NR = method == BMC_IZ ? N * iz_regions(spec->payoff, d) : N;
+    if ((e = ctx->counters.ensure(64)) || (e = ctx->x.ensure(sizeof(double) * d * NR)) ||
+        (e = ctx->cont.ensure(sizeof(double) * NR)) || (e = ctx->B.ensure(sizeof(double) * d * N)) ||
+        (e = ctx->steps.ensure(sizeof(int64_t) * N + sizeof(int32_t) * NR))) {
         release();
         return fail(BMC_ENOMEM, "device buffers: %s", hipGetErrorString(e));
     }
@@ -125,35 +127,40 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     } else {
         double* s_out = cont;
         int32_t* iters = (int32_t*)((char*)ctx->steps.ptr + sizeof(int64_t) * N);
-        std::vector<double> hs(N);
-        std::vector<int32_t> hi(N);
+        std::vector<double> hs(NR);
+        std::vector<int32_t> hi(NR);
         const int regions = iz_regions(spec->payoff, d);
-        // Algorithm 1: per date, one search and one regression per region; a
-        // region's search at date m uses the rules of later dates only.
-        for (int it = (NT - 1) * regions - 1; it >= 0 && !st; --it) {
-            const int m = it / regions + 1, region = regions - 1 - it % regions;
-            if ((st = sample_points_impl(ctx, ds, spec, BMC_IZ, m, N, seed, x, B, region))) break;
+        // Algorithm 1: per date, the boundary points of every region, then one
+        // regression per region.  The regions' searches are independent (each
+        // uses the rules of later dates only), so they run side by side in the
+        // same launches: region r in columns r N .. r N + N - 1.
+        for (int m = NT - 1; m >= 1 && !st; --m) {
+            if ((st = sample_points_impl(ctx, ds, spec, BMC_IZ, m, N, seed, x, B, 0, regions))) break;
             timer.mark(PH_CALC);
             int64_t stp = 0;
-            st = iz_search_impl(ctx, ds, spec, rules, m, region, x, N, n, seed, prec, eps, max_iter, s_out, iters,
-                                &stp, tune);
+            st = iz_search_impl(ctx, ds, spec, rules, m, 0, regions, x, N, n, seed, prec, eps, max_iter, s_out,
+                                iters, &stp, tune);
             if (st) break;
             iz_steps += stp;
             timer.mark(PH_FIT);
-            if ((e = hipMemcpyAsync(x + (size_t)region * N, s_out, sizeof(double) * N, hipMemcpyDeviceToDevice,
-                                    ctx->stream))) {
-                st = hip_fail(e, "boundary copy");
-                break;
+            for (int r = 0; r < regions && !st; ++r) {
+                // s* of region r into the region's own asset row of its columns
+                double* xr = x + (size_t)r * N;
+                if ((e = hipMemcpyAsync(xr + (size_t)r * NR, s_out + (size_t)r * N, sizeof(double) * N,
+                                        hipMemcpyDeviceToDevice, ctx->stream)))
+                    st = hip_fail(e, "boundary copy");
+                else
+                    st = fit_rule_impl(ctx, ds, d, rules, m, xr, nullptr, N, rounds, r, NR);
             }
-            if ((st = fit_rule_impl(ctx, ds, d, rules, m, x, nullptr, N, rounds, region))) break;
+            if (st) break;
             timer.mark(-1);
-            if ((e = hipMemcpyAsync(hs.data(), s_out, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream)) ||
-                (e = hipMemcpyAsync(hi.data(), iters, sizeof(int32_t) * N, hipMemcpyDeviceToHost, ctx->stream)) ||
+            if ((e = hipMemcpyAsync(hs.data(), s_out, sizeof(double) * NR, hipMemcpyDeviceToHost, ctx->stream)) ||
+                (e = hipMemcpyAsync(hi.data(), iters, sizeof(int32_t) * NR, hipMemcpyDeviceToHost, ctx->stream)) ||
                 (e = hipStreamSynchronize(ctx->stream))) {
                 st = hip_fail(e, "search results");
                 break;
             }
-            for (int64_t j = 0; j < N; ++j) {
+            for (int64_t j = 0; j < NR; ++j) {
                 if (!(hs[j] > 0.0)) ++unconv;
                 iz_iters += hi[j];
             }

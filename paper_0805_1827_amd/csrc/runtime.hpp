@@ -87,14 +87,22 @@ bmc_status run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int m
                     const void* rules64, const void* rules32, int prec, int m, const double* x,
                     int64_t N, const int32_t* ids, const int32_t* n_ids, uint32_t n, uint32_t k0,
                     uint32_t k1, double* cont, double* se, int64_t* steps, double* sums,
-                    unsigned long long* steps_total, const Tuning* tune, uint32_t slot = 0);
-// region: the I&Z region whose boundary row block is fitted (0 for CMC).
+                    unsigned long long* steps_total, const Tuning* tune, uint32_t slot = 0,
+                    uint32_t region_pts = 0);
+// region: the I&Z region whose boundary row block is fitted (0 for CMC), from
+// N points in rows of ld entries (0: N).
 bmc_status fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rules* rules, int date,
-                         const double* x, const double* values, int64_t N, int rounds, int region = 0);
+                         const double* x, const double* values, int64_t N, int rounds, int region = 0,
+                         int64_t ld = 0);
+// I&Z: regions region .. region + nreg - 1 side by side (N points each, rows
+// of nreg N entries).
 bmc_status sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, int method,
-                              int date, int64_t N, uint32_t seed, double* x, double* Bbuf, int region = 0);
+                              int date, int64_t N, uint32_t seed, double* x, double* Bbuf, int region = 0,
+                              int nreg = 1);
+// Searches regions region .. region + nreg - 1 together: x, s_out and iters
+// hold nreg J points side by side, as sample_points_impl lays them out.
 bmc_status iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec,
-                          const bmc_rules* rules, int date, int region, const double* x, int64_t J,
+                          const bmc_rules* rules, int date, int region, int nreg, const double* x, int64_t J,
                           uint32_t n, uint32_t seed, int prec, double eps, int max_iter, double* s_out,
                           int32_t* iters, int64_t* steps_out, const Tuning* tune);
 bmc_status final_price_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec,

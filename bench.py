@@ -249,6 +249,48 @@ def saturation_form(ctx, bmc, inputs, precision: int, N: int = 256) -> dict:
             "path_steps_per_s": steps / wall, "inner_path_steps": st["inner_path_steps"]}
 
 
+# Binomial references of the max-call of Table 1 (d = 3, K = 100, r = 0.05,
+# delta = 0.1, sigma = 0.2, rho = 0, T = 3, 9 dates) and the running times the
+# paper reports for its I&Z pricer on 16 processors (Tables 2 and 3, S0 = 90).
+IZ_BINOMIAL = {90: 11.29, 100: 18.69, 110: 27.58}
+IZ_PAPER_MINUTES = {("J", 128): 4.6, ("J", 256): 8.1, ("J", 1024): 29.5,
+                    ("N1", 5000): 4.6, ("N1", 10000): 6.9, ("N1", 100000): 35.7}
+
+
+def iz_form(ctx, bmc, inputs, reps: int = 3) -> dict:
+    """I&Z on the three-asset max-call: the Table 1 prices (S0 = 90, 100, 110;
+    J = 128 lattice points, N_1 = 5000 inner paths, N = 1e6 final paths) in
+    both precisions, and the J and N_1 sweeps of Tables 2-3 at S0 = 90.  Each
+    configuration is priced reps times (same seed); the median wall time is
+    reported."""
+    def one(S0, J, N1, prec):
+        spec = inputs.max_call(3, float(S0))
+        bmc.bmc_price(ctx, spec, bmc.IZ, prec, N=J, n=N1, n_final=1_000_000, seed=1)   # warm
+        runs = [bmc.bmc_price(ctx, spec, bmc.IZ, prec, N=J, n=N1, n_final=1_000_000, seed=1) for _ in range(reps)]
+        r = runs[-1]
+        wall = float(np.median([x["seconds"] for x in runs]))
+        calc = float(np.median([x["calc_seconds"] for x in runs]))
+        return {"S0": S0, "J": J, "N1": N1, "price": r["price"], "std_err": r["std_err"],
+                "error_vs_binomial": IZ_BINOMIAL[S0] - r["price"], "ms": 1e3 * wall, "calc_ms": 1e3 * calc,
+                "inner_path_steps": r["inner_path_steps"],
+                "inner_path_steps_per_s": r["inner_path_steps"] / calc,
+                "iterations_per_point": r["iz_iterations"] / (3 * (spec.n_dates - 1) * J),
+                "unconverged": r["iz_unconverged"]}
+
+    out = {"workload": "call on the max of 3 assets (Table 1 parameters), I&Z with 3 exercise regions, "
+                       "eps = 0.01, seed 1",
+           "table1_fp32": [one(S0, 128, 5000, bmc.FP32) for S0 in (90, 100, 110)],
+           "table1_fp64": [one(S0, 128, 5000, bmc.FP64) for S0 in (90, 100, 110)]}
+    sweep = []
+    for key, J, N1 in (("J", 128, 5000), ("J", 256, 5000), ("J", 1024, 5000), ("N1", 128, 10000),
+                       ("N1", 128, 100000)):
+        row = one(90, J, N1, bmc.FP32)
+        row["paper_minutes_16_procs"] = IZ_PAPER_MINUTES[(key, J if key == "J" else N1)]
+        sweep.append(row)
+    out["sweeps_fp32"] = sweep
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +309,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the Poisson arrival window of the serving form (0 disables it)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="arrival rate of the serving form (1/s)")
+    ap.add_argument("--no-iz", action="store_true", help="skip the I&Z max-call form (Tables 1-3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the pricer runs on a single device and this build has no "
@@ -355,6 +398,8 @@ def main():
         bctx = bmc.Context(0)
         out["batch"] = batch_form(bctx, bmc, inputs, args.batch, args.batch_N, 100_000)
         bctx.close()
+    if not args.no_iz:
+        out["iz"] = iz_form(ctx, bmc, inputs)
     if args.serve_seconds > 0:
         out["serving"] = {
             "workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s from a catalogue "

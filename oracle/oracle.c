@@ -181,6 +181,7 @@ double orc_payoff(const orc_spec *s, const double *logS)
 int orc_rule_width(int method, int d)
 {
     if (method == ORC_CMC) return 2 * d + 3;
+    if (method == ORC_CMC_ADA) return 1 + (d + 1) + 2 * ORC_ADA_TMAX;
     int q = d - 1;
     return 1 + q + q * (q + 1) / 2;
 }
@@ -197,7 +198,7 @@ int orc_iz_regions(const orc_spec *s)
 
 int orc_rule_width_spec(const orc_spec *s, int method)
 {
-    if (method == ORC_CMC) return orc_rule_width(ORC_CMC, s->d);
+    if (method != ORC_IZ) return orc_rule_width(method, s->d);
     return orc_iz_regions(s) * orc_rule_width(ORC_IZ, s->d);
 }
 
@@ -233,6 +234,15 @@ static void iz_features(const orc_spec *s, const double *logS, int region, doubl
         for (int b = a; b < q; ++b) xi[f++] = xi[1 + a] * xi[1 + b];
 }
 
+/* AdaBoost stump features: psi = [u_1..u_d, g], u_i = ln(S_i/K), g = Phi/K. */
+static void ada_features(const orc_spec *s, const double *logS, double payoff, double *psi)
+{
+    int d = s->d;
+    double lnK = log(s->K);
+    for (int i = 0; i < d; ++i) psi[i] = logS[i] - lnK;
+    psi[d] = payoff / s->K;
+}
+
 /* I&Z: puts search the first asset and exercise below its boundary; the
  * max-call searches the asset of the region and exercises above it. */
 static int iz_direction_is_call(const orc_spec *s)
@@ -254,6 +264,20 @@ static int exercise_now(const orc_spec *s, int method, const double *row,
         int p = orc_rule_width(ORC_CMC, s->d);
         double F = 0.0;
         for (int f = 0; f < p; ++f) F += row[f] * phi[f];
+        return F > 0.0;
+    }
+    if (method == ORC_CMC_ADA) {
+        /* folded stumps: F = base + sum of delta over the thresholds that
+         * the feature reaches, feature by feature in row order */
+        double psi[65];
+        ada_features(s, logS, payoff, psi);
+        int nf = s->d + 1, at = 1 + nf;
+        double F = row[0];
+        for (int f = 0; f < nf; ++f) {
+            int cnt = (int)row[1 + f];
+            for (int e = 0; e < cnt; ++e, at += 2)
+                if (psi[f] >= row[at]) F += row[at + 1];
+        }
         return F > 0.0;
     }
     double xi[1 + 63 + 63 * 64 / 2];
@@ -703,6 +727,154 @@ int orc_fit_cmc(const orc_spec *s, const double *x, const double *cont,
 }
 
 /* ------------------------------------------------------------------------- */
+/* [class] with AdaBoost and decision stumps (Section 3.2 names AdaBoost or
+ * LogitBoost; the stump form and its constants are this library's reading).
+ *
+ * Training set: the in-the-money points; label y_j = +1 (exercise) iff
+ * Phi_j - C_j > 0, else -1; initial weight c_j = |Phi_j - C_j|, the value lost
+ * by taking the wrong decision at x_j.  A stump on feature f is
+ * h(x) = s for psi_f(x) in bins k..B-1 and -s below, with B = 64 uniform bins
+ * between the smallest and largest psi_f over the training points; k = 0 is
+ * the constant stump (taken on feature 0 only).  Each round takes the stump
+ * of least weighted error, ties to the smaller (f, k) and to s = +1, with
+ * weights rounded to a fixed-point grid 2^-shift (shift from the largest
+ * possible total weight), so that every error is an exact integer;
+ * eps = error / total, alpha = ln((1 - eps) / eps) / 2 (eps >= 1e-10), and
+ * the AdaBoost update in its normalised form, w / (2 eps) for misclassified
+ * points and w / (2 (1 - eps)) for the others.  Boosting stops when no stump
+ * beats chance (2 error >= total) or after a perfect stump. */
+
+static int ada_bin(double v, double lo, double hi, double inv)
+{
+    if (!(hi > lo)) return 0;
+    double t = floor((v - lo) * inv);
+    if (t < 0.0) return 0;
+    if (t > ORC_ADA_BINS - 1) return ORC_ADA_BINS - 1;
+    return (int)t;
+}
+
+int orc_fit_ada(const orc_spec *s, const double *x, const double *cont, int64_t N,
+                int rounds, double *row, int *n_stumps, int *feat, int *bin, int *sign,
+                double *eps_out, double *alpha_out, double *lo_out, double *hi_out)
+{
+    int rc = check_spec(s);
+    if (rc) return rc;
+    if (rounds < 1 || rounds > ORC_ADA_TMAX || N < 1) return ORC_EINVAL;
+    const int d = s->d, nf = d + 1, B = ORC_ADA_BINS, width = orc_rule_width(ORC_CMC_ADA, d);
+    for (int f = 0; f < width; ++f) row[f] = 0.0;
+    if (n_stumps) *n_stumps = 0;
+    double *psi = malloc(sizeof(double) * nf * N), *w = malloc(sizeof(double) * N);
+    int *y = malloc(sizeof(int) * N), *bins = malloc(sizeof(int) * nf * N);
+    int64_t *W = malloc(sizeof(int64_t) * N), *H = malloc(sizeof(int64_t) * nf * B * 2);
+    if (!psi || !w || !y || !bins || !W || !H) {
+        free(psi); free(w); free(y); free(bins); free(W); free(H);
+        return ORC_ENOMEM;
+    }
+    double logS[64];
+    int64_t nI = 0;
+    double cmax = 0.0;
+    for (int64_t j = 0; j < N; ++j) {
+        for (int i = 0; i < d; ++i) logS[i] = log(x[(size_t)i * N + j]);
+        double payoff = orc_payoff(s, logS);
+        if (!(payoff > 0.0)) continue;
+        double pz[65];
+        ada_features(s, logS, payoff, pz);
+        for (int f = 0; f < nf; ++f) psi[(size_t)f * N + nI] = pz[f];
+        double beta = payoff - cont[j];
+        y[nI] = beta > 0.0 ? 1 : -1;
+        w[nI] = fabs(beta);
+        if (w[nI] > cmax) cmax = w[nI];
+        ++nI;
+    }
+    double lo[65], hi[65], inv[65];
+    for (int f = 0; f < nf; ++f) {
+        lo[f] = hi[f] = 0.0;
+        for (int64_t j = 0; j < nI; ++j) {
+            double v = psi[(size_t)f * N + j];
+            if (j == 0 || v < lo[f]) lo[f] = v;
+            if (j == 0 || v > hi[f]) hi[f] = v;
+        }
+        inv[f] = hi[f] > lo[f] ? (double)B / (hi[f] - lo[f]) : 0.0;
+        if (lo_out) lo_out[f] = lo[f];
+        if (hi_out) hi_out[f] = hi[f];
+        for (int64_t j = 0; j < nI; ++j)
+            bins[(size_t)f * N + j] = ada_bin(psi[(size_t)f * N + j], lo[f], hi[f], inv[f]);
+    }
+    int T = 0;
+    int tf[ORC_ADA_TMAX], tk[ORC_ADA_TMAX], ts[ORC_ADA_TMAX];
+    double ta[ORC_ADA_TMAX];
+    if (nI > 0 && cmax > 0.0) {
+        int e2;
+        frexp((double)nI * cmax, &e2);       /* total weight < 2^e2 */
+        const int shift = 50 - e2;
+        for (int t = 0; t < rounds; ++t) {
+            int64_t Wp = 0, Wm = 0;
+            memset(H, 0, sizeof(int64_t) * nf * B * 2);
+            for (int64_t j = 0; j < nI; ++j) {
+                W[j] = (int64_t)llrint(ldexp(w[j], shift));
+                int c = y[j] > 0;
+                if (c) Wp += W[j]; else Wm += W[j];
+                for (int f = 0; f < nf; ++f) H[((size_t)f * B + bins[(size_t)f * N + j]) * 2 + c] += W[j];
+            }
+            const int64_t Wt = Wp + Wm;
+            if (Wt == 0) break;
+            int64_t best = -1;
+            int bf = 0, bk = 0, bs = 1;
+            for (int f = 0; f < nf; ++f) {
+                int64_t Pp = 0, Pm = 0;
+                for (int k = 0; k < B; ++k) {
+                    if (k > 0) {
+                        Pp += H[((size_t)f * B + k - 1) * 2 + 1];
+                        Pm += H[((size_t)f * B + k - 1) * 2 + 0];
+                    }
+                    if (k == 0 && f > 0) continue;
+                    const int64_t Eplus = Pp + (Wm - Pm), Eminus = Wt - Eplus;
+                    if (best < 0 || Eplus < best) { best = Eplus; bf = f; bk = k; bs = 1; }
+                    if (Eminus < best) { best = Eminus; bf = f; bk = k; bs = -1; }
+                }
+            }
+            if (2 * best >= Wt) break;                    /* no stump beats chance */
+            const double eps = (double)best / (double)Wt;
+            const double ea = eps > 1e-10 ? eps : 1e-10;
+            tf[T] = bf; tk[T] = bk; ts[T] = bs;
+            ta[T] = 0.5 * log((1.0 - ea) / ea);
+            if (feat) feat[T] = bf;
+            if (bin) bin[T] = bk;
+            if (sign) sign[T] = bs;
+            if (eps_out) eps_out[T] = eps;
+            if (alpha_out) alpha_out[T] = ta[T];
+            ++T;
+            if (best == 0) break;                         /* perfect stump */
+            const double up = 2.0 * eps, dn = 2.0 * (1.0 - eps);
+            for (int64_t j = 0; j < nI; ++j) {
+                int h = bins[(size_t)bf * N + j] >= bk ? bs : -bs;
+                w[j] = h != y[j] ? w[j] / up : w[j] / dn;
+            }
+        }
+    }
+    /* fold: base, per-feature counts, (theta, delta) in feature then round order */
+    double base = 0.0;
+    for (int t = 0; t < T; ++t) base -= ta[t] * ts[t];
+    row[0] = base;
+    int at = 1 + nf;
+    for (int f = 0; f < nf; ++f) {
+        int cnt = 0;
+        for (int t = 0; t < T; ++t) {
+            if (tf[t] != f) continue;
+            double step = (hi[f] - lo[f]) / (double)B;
+            row[at] = tk[t] == 0 ? -1e300 : lo[f] + (double)tk[t] * step;
+            row[at + 1] = 2.0 * ta[t] * ts[t];
+            at += 2;
+            ++cnt;
+        }
+        row[1 + f] = (double)cnt;
+    }
+    if (n_stumps) *n_stumps = T;
+    free(psi); free(w); free(y); free(bins); free(W); free(H);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* I&Z boundary-point search (Section 2.1 eq. (1), Section 2.4): start the
  * searched coordinate at K and iterate s <- Phi^{-1}(C(s)) with the same
  * inner paths each time (common random numbers), until |s' - s| < eps.
@@ -867,8 +1039,10 @@ int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_fin
 {
     int rc = check_spec(s);
     if (rc) return rc;
-    if (N < 2 || n < 2 || n_final < 2 || (method != ORC_CMC && method != ORC_IZ))
+    if (N < 2 || n < 2 || n_final < 2 ||
+        (method != ORC_CMC && method != ORC_IZ && method != ORC_CMC_ADA))
         return ORC_EINVAL;
+    if (method == ORC_CMC_ADA && (rounds < 1 || rounds > ORC_ADA_TMAX)) return ORC_EINVAL;
     int d = s->d, NT = s->n_dates, width = orc_rule_width_spec(s, method);
     int regions = method == ORC_IZ ? orc_iz_regions(s) : 1, pw = width / regions;
     double *rules = calloc((size_t)(NT + 1) * width, sizeof(double));
@@ -882,7 +1056,7 @@ int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_fin
     rc = orc_cholesky(d, s->rho, L);
     if (rc) goto done;
     int64_t inner = 0, unconv = 0, iz_it = 0;
-    if (method == ORC_CMC) {
+    if (method != ORC_IZ) {
         bridge_endpoint(s, N, seed, B);
         for (int m = NT - 1; m >= 1; --m) {
             bridge_back(s, m, N, seed, B);
@@ -891,7 +1065,11 @@ int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_fin
                                   nthreads, cont, NULL, steps, NULL, NULL);
             if (rc) goto done;
             for (int64_t j = 0; j < N; ++j) inner += steps[j];
-            rc = orc_fit_cmc(s, x, cont, N, rounds, rules + (size_t)m * width);
+            if (method == ORC_CMC)
+                rc = orc_fit_cmc(s, x, cont, N, rounds, rules + (size_t)m * width);
+            else
+                rc = orc_fit_ada(s, x, cont, N, rounds, rules + (size_t)m * width, NULL, NULL, NULL,
+                                 NULL, NULL, NULL, NULL, NULL);
             if (rc) goto done;
         }
     } else {

@@ -23,7 +23,10 @@ extern "C" {
 #endif
 
 enum { ORC_PUT_BASKET = 0, ORC_CALL_MAX = 1, ORC_PUT_GEO = 2 };
-enum { ORC_CMC = 0, ORC_IZ = 1 };
+enum { ORC_CMC = 0, ORC_IZ = 1, ORC_CMC_ADA = 2 };
+/* AdaBoost stumps (ORC_CMC_ADA): bins per feature and the largest number of
+ * boosting rounds a rule row holds. */
+enum { ORC_ADA_BINS = 64, ORC_ADA_TMAX = 64 };
 enum { ORC_STREAM_OUTER = 1, ORC_STREAM_INNER = 2, ORC_STREAM_FINAL = 3 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOTSPD = -2, ORC_ENOMEM = -3,
        ORC_EUNSUPPORTED = -5 };
@@ -87,6 +90,16 @@ int orc_continuation(const orc_spec *s, int method, const double *rules, int m,
 /* CMC LogitBoost fit of the exercise rule at one date (folded weights). */
 int orc_fit_cmc(const orc_spec *s, const double *x, const double *cont,
                 int64_t N, int rounds, double *w);
+
+/* CMC AdaBoost fit with decision stumps at one date (1 <= rounds <= ORC_ADA_TMAX),
+ * written as a folded rule row of orc_rule_width(ORC_CMC_ADA, d) entries:
+ * [base, count_0..count_d, (theta, delta) pairs feature by feature].
+ * Optional trace (any pointer may be NULL): *n_stumps, and per stump its
+ * feature, first bin of the upper side, sign, weighted error eps and alpha;
+ * lo[d+1], hi[d+1]: the feature ranges over the in-the-money points. */
+int orc_fit_ada(const orc_spec *s, const double *x, const double *cont, int64_t N,
+                int rounds, double *row, int *n_stumps, int *feat, int *bin, int *sign,
+                double *eps, double *alpha, double *lo, double *hi);
 
 /* I&Z fixed-point search of a region's boundary coordinate for J points at
  * date m; the inner paths of region r use r as the fourth counter word.

@@ -18,7 +18,9 @@ HERE = Path(__file__).resolve().parent
 LIB_PATH = HERE / "liboracle.so"
 
 PUT_BASKET, CALL_MAX, PUT_GEO = 0, 1, 2
-CMC, IZ = 0, 1
+CMC, IZ, CMC_ADA = 0, 1, 2
+ADA_BINS, ADA_TMAX = 64, 64
+ADA_ROUNDS = 64          # default AdaBoost rounds
 STREAM_OUTER, STREAM_INNER, STREAM_FINAL = 1, 2, 3
 
 
@@ -69,6 +71,7 @@ def lib():
         L.orc_continuation.argtypes = [sp, C.c_int, dp, C.c_int, dp, C.c_int64, u32p, C.c_int64,
                                        C.c_uint32, C.c_int, C.c_int, dp, dp, i64p, dp, dp]
         L.orc_fit_cmc.argtypes = [sp, dp, dp, C.c_int64, C.c_int, dp]
+        L.orc_fit_ada.argtypes = [sp, dp, dp, C.c_int64, C.c_int, dp, i32p, i32p, i32p, i32p, dp, dp, dp, dp]
         L.orc_iz_search.argtypes = [sp, dp, C.c_int, C.c_int, dp, C.c_int64, C.c_int64, C.c_uint32,
                                     C.c_double, C.c_int, C.c_int, dp, i32p, i64p]
         L.orc_fit_iz.argtypes = [sp, C.c_int, dp, dp, C.c_int64, dp]
@@ -240,8 +243,32 @@ def fit_iz(spec, x: np.ndarray, sstar: np.ndarray, region: int = 0) -> np.ndarra
     return b
 
 
-def price(spec, method: int, N: int, n: int, n_final: int, seed: int, rounds: int = 8,
+def fit_ada(spec, x: np.ndarray, cont: np.ndarray, rounds: int = ADA_ROUNDS, trace: bool = False):
+    """AdaBoost-stump rule row; with trace, also the stumps and feature ranges."""
+    h = _SpecHolder(spec)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    cont = np.ascontiguousarray(cont, dtype=np.float64)
+    row = np.zeros(rule_width(CMC_ADA, h.d))
+    nf = h.d + 1
+    T = np.zeros(1, dtype=np.int32)
+    feat, k, sg = (np.zeros(ADA_TMAX, dtype=np.int32) for _ in range(3))
+    eps, alpha = np.zeros(ADA_TMAX), np.zeros(ADA_TMAX)
+    lo, hi = np.zeros(nf), np.zeros(nf)
+    ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+    _check(lib().orc_fit_ada(h.ptr, _dp(x), _dp(cont), x.shape[1], rounds, _dp(row), ip(T), ip(feat), ip(k),
+                             ip(sg), _dp(eps), _dp(alpha), _dp(lo), _dp(hi)), "fit_ada")
+    if not trace:
+        return row
+    t = int(T[0])
+    return row, {"feature": feat[:t].copy(), "bin": k[:t].copy(), "sign": sg[:t].copy(), "eps": eps[:t].copy(),
+                 "alpha": alpha[:t].copy(), "lo": lo, "hi": hi}
+
+
+def price(spec, method: int, N: int, n: int, n_final: int, seed: int, rounds: int = 0,
           eps: float = 0.01, max_iter: int = 100, nthreads: int = 0) -> dict:
+    """rounds: boosting rounds (0: 8 for CMC, 64 for CMC_ADA)."""
+    if rounds <= 0:
+        rounds = ADA_ROUNDS if method == CMC_ADA else 8
     h = _SpecHolder(spec)
     rules = np.zeros((h.n_dates + 1, row_width(spec, method)))
     res = np.zeros(8)

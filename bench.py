@@ -398,6 +398,16 @@ def main():
         bctx = bmc.Context(0)
         out["batch"] = batch_form(bctx, bmc, inputs, args.batch, args.batch_N, 100_000)
         bctx.close()
+    # the same workload with the AdaBoost-stump classifier (64 rounds)
+    ada = [bmc.bmc_price(ctx, spec, bmc.CMC_ADA, bmc.FP32, **kw) for _ in range(3)]
+    out["cmc_adaboost"] = {
+        "workload": "as the headline, CMC with AdaBoost stumps (64 rounds, 64 bins) instead of LogitBoost",
+        "ms_per_price": 1e3 * float(np.median([r["seconds"] for r in ada])),
+        "fit_ms_per_price": 1e3 * float(np.median([r["fit_seconds"] for r in ada])),
+        "calc_ms_per_price": 1e3 * float(np.median([r["calc_seconds"] for r in ada])),
+        "inner_path_steps_per_s": ada[-1]["inner_path_steps"] / float(np.median([r["calc_seconds"] for r in ada])),
+        "price": ada[-1]["price"], "std_err": ada[-1]["std_err"],
+        "logitboost_price": p32["price"]}
     if not args.no_iz:
         out["iz"] = iz_form(ctx, bmc, inputs)
     if args.serve_seconds > 0:

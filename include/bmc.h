@@ -50,9 +50,11 @@ typedef enum {
  * (K - (prod S)^(1/d))^+.  For d = 1 the two puts coincide. */
 typedef enum { BMC_PUT_BASKET = 0, BMC_CALL_MAX = 1, BMC_PUT_GEO = 2 } bmc_payoff;
 
-/* Pricers: Classification-Monte Carlo (Section 3) and Ibanez-Zapatero
- * boundary computation (Section 2). */
-typedef enum { BMC_CMC = 0, BMC_IZ = 1 } bmc_method;
+/* Pricers: Classification-Monte Carlo (Section 3) with the LogitBoost linear
+ * classifier (BMC_CMC) or AdaBoost with decision stumps (BMC_CMC_ADA; Section
+ * 3.2 names both boosters), and Ibanez-Zapatero boundary computation
+ * (Section 2). */
+typedef enum { BMC_CMC = 0, BMC_IZ = 1, BMC_CMC_ADA = 2 } bmc_method;
 
 /* Arithmetic of the inner paths.  FP64: everything in double.  FP32: path
  * stepping, exp and the uniform-to-normal map in float, per-lane payoff sums
@@ -85,7 +87,7 @@ typedef struct {
     int64_t n;              /* inner paths per point */
     int64_t n_final;        /* final-pricing paths */
     uint64_t seed;          /* < 2^32 */
-    int32_t cls_rounds;     /* CMC boosting rounds (default 8 when 0) */
+    int32_t cls_rounds;     /* boosting rounds, <= 64 (0: 8 for BMC_CMC, 64 for BMC_CMC_ADA) */
     int32_t iz_max_iter;    /* I&Z iteration cap (default 100 when 0) */
     double iz_eps;          /* I&Z tolerance in price units (default 0.01 when 0) */
 } bmc_opts;
@@ -216,6 +218,11 @@ bmc_status bmc_server_stats_get(bmc_server *server, bmc_server_stats *out);
 /* Exercise-rule table of one spec and method: one row of width w per date
  * (rows 1..N_T-1 used).  CMC (Section 3.2): F(x) = sum_f w_f phi_f(x) with
  * phi = [1, u_1..u_d, u_1^2..u_d^2, g, g^2], u_i = ln(S_i/K), g = Phi(S)/K;
+ * exercise iff Phi > 0 and F > 0.  CMC_ADA: AdaBoost stumps on
+ * psi = [u_1..u_d, g] folded into per-feature threshold tables, row
+ * [base, c_0..c_d, (theta, delta) x (c_0 + .. + c_d), zeros] of
+ * 1 + (d + 1) + 2 * 64 entries; F(x) = base + sum of delta over the pairs of
+ * each feature f (its c_f pairs, features in order) with psi_f(x) >= theta;
  * exercise iff Phi > 0 and F > 0.  I&Z (Section 2.2): one boundary block of
  * p = 1 + q + q(q+1)/2 coefficients (q = d - 1) per exercise region, region r
  * at offset r p of the row; b_r(x) = sum_f w_f xi_f with
@@ -259,10 +266,15 @@ bmc_status bmc_estimate_continuation(bmc_ctx *ctx, const bmc_spec *spec, const b
 
 /* Fits the rule row of `date` from N device points.  CMC: region 0,
  * values = device continuation estimates; boosting on the in-the-money points
- * (Section 3.2 [class]).  I&Z: fits the boundary block of `region`;
+ * (Section 3.2 [class]): LogitBoost with a linear base learner (BMC_CMC) or
+ * AdaBoost with stumps (BMC_CMC_ADA: labels sign(Phi - C), initial weights
+ * |Phi - C|, 64 uniform bins per feature between its extremes over the
+ * training points, weights rounded to a fixed-point grid so that the stump
+ * errors are exact integers; bit-reproducible).  I&Z: fits the boundary block of `region`;
  * x[region*N + j] holds the converged boundary coordinate s*_j (<= 0 marks a
  * dropped point) and values is ignored; quadratic least squares of ln s*
- * (Section 2.3 [reg]).  rounds: CMC boosting rounds (0 = 8). */
+ * (Section 2.3 [reg]).  rounds: boosting rounds, <= 64 (0: 8 for BMC_CMC, 64
+ * for BMC_CMC_ADA). */
 bmc_status bmc_fit_rule(bmc_ctx *ctx, const bmc_spec *spec, bmc_rules *rules, int32_t date,
                         int32_t region, const double *x, const double *values, int64_t N,
                         int32_t rounds);

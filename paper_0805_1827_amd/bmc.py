@@ -16,7 +16,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libbmc.so"
 
 OK, EINVAL, ENOTSPD, ENOMEM, EDEVICE, EUNSUPPORTED, ENOCONV, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 PUT_BASKET, CALL_MAX, PUT_GEO = 0, 1, 2
-CMC, IZ = 0, 1
+CMC, IZ, CMC_ADA = 0, 1, 2
 FP64, FP32, FP32_KAHAN = 0, 1, 2
 STREAM_OUTER, STREAM_INNER, STREAM_FINAL = 1, 2, 3
 D_MAX, NT_MAX = 64, 512

@@ -251,7 +251,7 @@ extern "C" bmc_status bmc_sync(bmc_ctx* ctx)
 
 static double never_value(int method, int payoff)
 {
-    if (method == BMC_CMC) return 0.0;
+    if (method != BMC_IZ) return 0.0;   // classifier rows of zeros: F = 0, never exercise
     return payoff == BMC_CALL_MAX ? 1e300 : -1e300;
 }
 
@@ -266,7 +266,7 @@ static bmc_status rules_alloc(bmc_ctx* ctx, int method, int d, int n_dates, int 
     r->payoff = payoff;
     r->width = rule_row_width(method, d, payoff);
     const size_t rows = (size_t)(n_dates + 1) * r->width;
-    const int block = method == BMC_CMC ? r->width : rule_width(method, d);
+    const int block = method == BMC_IZ ? rule_width(method, d) : r->width;
     hipError_t e;
     if ((e = hipMalloc((void**)&r->w64, sizeof(double) * rows)) ||
         (e = hipMalloc((void**)&r->w32, sizeof(float) * rows))) {
@@ -305,7 +305,7 @@ bmc_status bmc::scratch_rules(bmc_ctx* ctx, const bmc_spec* spec, int method, bm
     r->w64 = (double*)ctx->srules.ptr;
     r->w32 = (float*)((char*)ctx->srules.ptr + b64);
     // rows of one boundary block each: every I&Z region's block starts "never"
-    const int block = method == BMC_CMC ? r->width : rule_width(method, spec->d);
+    const int block = method == BMC_IZ ? rule_width(method, spec->d) : r->width;
     if ((e = launch_rules_fill(r->w64, r->w32, (int)(rows / block), block, never_value(method, spec->payoff),
                                ctx->stream)))
         return hip_fail(e, "rule scratch");
@@ -318,7 +318,8 @@ extern "C" bmc_status bmc_rules_create(bmc_ctx* ctx, const bmc_spec* spec, int32
     if (!ctx || !out) return fail(BMC_EINVAL, "NULL argument");
     bmc_status st = validate_spec(spec);
     if (st) return st;
-    if (method != BMC_CMC && method != BMC_IZ) return fail(BMC_EINVAL, "unknown method %d", method);
+    if (method != BMC_CMC && method != BMC_IZ && method != BMC_CMC_ADA)
+        return fail(BMC_EINVAL, "unknown method %d", method);
     if (method == BMC_IZ && spec->d > IZ_D_MAX)
         return fail(BMC_EUNSUPPORTED, "I&Z supports d <= %d", IZ_D_MAX);
     (void)hipSetDevice(ctx->device);
@@ -404,7 +405,8 @@ extern "C" bmc_status bmc_rules_import(bmc_ctx* ctx, const void* buf, size_t byt
     std::memcpy(&h, buf, sizeof(h));
     if (std::memcmp(h.magic, "BMCR", 4) != 0 || h.version != 1) return fail(BMC_EINVAL, "not a rule table");
     if (h.d < 1 || h.d > BMC_D_MAX || h.n_dates < 1 || h.n_dates > BMC_NT_MAX ||
-        (h.method != BMC_CMC && h.method != BMC_IZ) || h.width != rule_row_width(h.method, h.d, h.payoff))
+        (h.method != BMC_CMC && h.method != BMC_IZ && h.method != BMC_CMC_ADA) ||
+        h.width != rule_row_width(h.method, h.d, h.payoff))
         return fail(BMC_EINVAL, "corrupt rule table header");
     const size_t rows = (size_t)(h.n_dates + 1) * h.width;
     if (bytes < sizeof(h) + sizeof(double) * rows) return fail(BMC_EINVAL, "truncated rule table");
@@ -699,6 +701,11 @@ bmc_status bmc::fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rule
         fit_scratch_carve((double*)ctx->fit.ptr, N, p, rounds, &fs);
         if ((e = launch_fit_cmc((const DevSpec*)devspec, d, x, values, N, rounds, fs, row64, row32, ctx->stream)))
             return hip_fail(e, "fit launch");
+    } else if (rules->method == BMC_CMC_ADA) {
+        if ((e = ctx->fit.ensure(fit_ada_scratch_bytes(N, d)))) return hip_fail(e, "fit scratch");
+        if ((e = launch_fit_ada((const DevSpec*)devspec, d, x, values, N, rounds, ctx->fit.ptr, row64, row32,
+                                rules->width, ctx->stream)))
+            return hip_fail(e, "fit launch");
     } else {
         const int p = rule_width(BMC_IZ, d);
         if ((e = ctx->fit.ensure(sizeof(double) * fitiz_scratch_doubles(N, p)))) return hip_fail(e, "fit scratch");
@@ -734,8 +741,8 @@ extern "C" bmc_status bmc_fit_rule(bmc_ctx* ctx, const bmc_spec* spec, bmc_rules
     if ((st = check_rules(rules, spec)) || (st = check_region(rules->method, spec, region))) return st;
     if (date < 1 || date >= spec->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, spec->n_dates - 1);
     if (N < 1 || N > 0x7FFFFFFF) return fail(BMC_EINVAL, "N out of range");
-    if (rules->method == BMC_CMC && !values) return fail(BMC_EINVAL, "CMC fit needs continuation values");
-    if (rounds <= 0) rounds = 8;
+    if (rules->method != BMC_IZ && !values) return fail(BMC_EINVAL, "CMC fit needs continuation values");
+    if (rounds <= 0) rounds = rules->method == BMC_CMC_ADA ? ADA_TMAX : 8;
     if (rounds > 64) return fail(BMC_EINVAL, "rounds must be <= 64");
     return fit_rule_impl(ctx, ctx->spec.ptr, spec->d, rules, date, x, values, N, rounds, region);
 }
@@ -747,7 +754,7 @@ bmc_status bmc::sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_
     hipError_t e;
     const DevSpec* ds = (const DevSpec*)devspec;
     const int d = spec->d, NT = spec->n_dates;
-    if (method == BMC_CMC) {
+    if (method != BMC_IZ) {
         if ((e = launch_bridge_end(ds, d, N, seed, Bbuf, ctx->stream))) return hip_fail(e, "bridge");
         for (int mm = NT - 1; mm >= date; --mm)
             if ((e = launch_bridge_back(ds, d, mm, N, seed, Bbuf, nullptr, 1, ctx->stream)))
@@ -775,7 +782,8 @@ extern "C" bmc_status bmc_sample_points(bmc_ctx* ctx, const bmc_spec* spec, int3
     (void)hipSetDevice(ctx->device);
     bmc_status st;
     if ((st = upload_spec(ctx, spec, ctx->spec)) || (st = check_seed(seed))) return st;
-    if (method != BMC_CMC && method != BMC_IZ) return fail(BMC_EINVAL, "unknown method %d", method);
+    if (method != BMC_CMC && method != BMC_IZ && method != BMC_CMC_ADA)
+        return fail(BMC_EINVAL, "unknown method %d", method);
     if ((st = check_region(method, spec, region))) return st;
     if (date < 1 || date > spec->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, spec->n_dates);
     if (N < 1 || N > 0x7FFFFFFF) return fail(BMC_EINVAL, "N out of range");

@@ -71,9 +71,15 @@ __device__ __forceinline__ void corr_mfma(const float* __restrict__ arow, const 
 template <int D, class R> constexpr bool uses_mfma() { return D >= 9 && sizeof(R) == 4; }
 template <int D> constexpr bool uses_lds_coef() { return D >= 9; }
 
+// I&Z rules need their own kernels (IZK): the boundary test of d <= 16 assets
+// (a full quadratic, and the region search of the max-call) would otherwise
+// hold registers in every classifier kernel of those dimensions.
+template <int D, bool EXACT> constexpr bool has_iz_kernel() { return EXACT && D <= 16; }
+
 // One (point j, chunk) job of a continuation launch, run by a whole block;
-// lds: the dynamic table area, red: [3][16] wave partials.
-template <int D, bool EXACT, class R, class ACC>
+// lds: the dynamic table area, red: [3][16] wave partials.  IZK: the job's
+// rules are I&Z boundaries; otherwise classifier rules (CMC or AdaBoost).
+template <int D, bool EXACT, class R, class ACC, bool IZK = false>
 __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, const uint32_t chunk, double* lds,
                                          double (*red)[16])
 {
@@ -232,10 +238,11 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
         bool stop = (k == NT);
         if (!stop && phi > R(0)) {
             const R* w = wt + k * WL;
-            if (a.method == CMC) {
-                stop = cmc_score<D4, R>(dp, w, lnK, phi * invK, ls) > R(0);
+            if constexpr (!IZK) {
+                if (a.method == CMC) stop = cmc_score<D4, R>(dp, w, lnK, phi * invK, ls) > R(0);
+                else stop = ada_score<D4, R>(d, w, lnK, phi * invK, ls) > R(0);
             } else {
-                if constexpr (D <= 16) {
+                if constexpr (has_iz_kernel<D, EXACT>()) {
                     if (call_dir) {
                         // region of the largest asset (the first one on ties);
                         // exercise above that region's boundary
@@ -299,7 +306,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 }
 
 // One launch per (spec, date): block = one (point, chunk) job.
-template <int D, bool EXACT, class R, class ACC>
+template <int D, bool EXACT, class R, class ACC, bool IZK = false>
 __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
 {
     extern __shared__ __align__(16) double lds[];
@@ -308,7 +315,7 @@ __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
     const uint32_t chunk = blockIdx.x - slot * a.nchunk;
     if (a.n_ids && slot >= (uint32_t)*a.n_ids) return;   // retired job (whole block)
     const uint32_t j = a.ids ? (uint32_t)a.ids[slot] : slot;
-    cont_job<D, EXACT, R, ACC>(a, j, chunk, lds, red);
+    cont_job<D, EXACT, R, ACC, IZK>(a, j, chunk, lds, red);
 }
 
 // One launch over the jobs of many tasks (options at their own dates): block
@@ -348,6 +355,12 @@ bool cont_allow_lds()
                         reinterpret_cast<const void*>(k_cont_multi<D, EXACT, float, Acc<double>>),
                         reinterpret_cast<const void*>(k_cont_multi<D, EXACT, float, KahanAcc>)};
     for (const void* f : ks) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    if constexpr (has_iz_kernel<D, EXACT>()) {
+        const void* kz[] = {reinterpret_cast<const void*>(k_cont<D, EXACT, double, Acc<double>, true>),
+                            reinterpret_cast<const void*>(k_cont<D, EXACT, float, Acc<double>, true>),
+                            reinterpret_cast<const void*>(k_cont<D, EXACT, float, KahanAcc, true>)};
+        for (const void* f : kz) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    }
     (void)hipGetLastError();   // a refused attribute must not surface at the next launch check
     return true;
 }
@@ -358,6 +371,20 @@ hipError_t launch_cont_d(int prec, const ContArgs& a, int grid, int block, size_
 {
     static const bool lds_ok = cont_allow_lds<D, EXACT>();
     (void)lds_ok;
+    if (a.method == IZ) {
+        if constexpr (has_iz_kernel<D, EXACT>()) {
+            if (prec == PREC_FP64)
+                hipLaunchKernelGGL((k_cont<D, EXACT, double, Acc<double>, true>), dim3(grid), dim3(block), lds, st,
+                                   a);
+            else if (prec == PREC_FP32)
+                hipLaunchKernelGGL((k_cont<D, EXACT, float, Acc<double>, true>), dim3(grid), dim3(block), lds, st,
+                                   a);
+            else
+                hipLaunchKernelGGL((k_cont<D, EXACT, float, KahanAcc, true>), dim3(grid), dim3(block), lds, st, a);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;   // I&Z rules exist for d <= 16 only
+    }
     if (prec == PREC_FP64)
         hipLaunchKernelGGL((k_cont<D, EXACT, double, Acc<double>>), dim3(grid), dim3(block), lds, st, a);
     else if (prec == PREC_FP32)

@@ -12,7 +12,10 @@ constexpr int D_MAX = 64;
 constexpr int NT_MAX = 512;
 
 enum { PUT_BASKET = 0, CALL_MAX = 1, PUT_GEO = 2 };
-enum { CMC = 0, IZ = 1 };
+// CMC with the LogitBoost linear classifier, I&Z, CMC with AdaBoost stumps
+enum { CMC = 0, IZ = 1, ADA = 2 };
+// AdaBoost stumps: bins per feature, largest number of rounds a rule row holds
+enum { ADA_BINS = 64, ADA_TMAX = 64 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP32_KAHAN = 2 };
 enum { STREAM_OUTER = 1, STREAM_INNER = 2, STREAM_FINAL = 3 };
 
@@ -186,6 +189,27 @@ __device__ __forceinline__ R cmc_score(int d, const R* __restrict__ w, R lnK, R 
     return F;
 }
 
+// AdaBoost stump rule F = base + sum of delta over the thresholds theta that
+// each feature reaches, psi = [u_1..u_d, g]; row [base, count_0..count_d,
+// (theta, delta) pairs feature by feature].  Features are visited in order
+// and each one's pairs in row order.
+template <int D, class R>
+__device__ __forceinline__ R ada_score(int d, const R* __restrict__ w, R lnK, R g, const R (&x)[D])
+{
+    R F = w[0];
+    const R* pr = w + 2 + d;
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+        if (i <= d) {
+            const R v = i < d ? x[i < D ? i : 0] - lnK : g;
+            const int cnt = (int)w[1 + i];
+            for (int e = 0; e < cnt; ++e, pr += 2)
+                if (v >= pr[0]) F += pr[1];
+        }
+    }
+    return F;
+}
+
 // I&Z boundary of a region, b = w . [1, v_1..v_q, v_a v_c (a <= c)], over the
 // log-moneyness v = ln S_i - ln K of the assets other than the region's own
 // one, in increasing order (region 0 of the put family: assets 2..d).
@@ -221,6 +245,7 @@ __device__ __forceinline__ R iz_boundary(int d, const R* __restrict__ w, R lnK, 
 __host__ __device__ __forceinline__ int rule_width(int method, int d)
 {
     if (method == CMC) return 2 * d + 3;
+    if (method == ADA) return 1 + (d + 1) + 2 * ADA_TMAX;
     const int q = d - 1;
     return 1 + q + q * (q + 1) / 2;
 }
@@ -236,7 +261,7 @@ __host__ __device__ __forceinline__ int iz_regions(int payoff, int d)
 // (region r at offset r * rule_width(IZ, d)).
 __host__ __device__ __forceinline__ int rule_row_width(int method, int d, int payoff)
 {
-    return method == CMC ? rule_width(CMC, d) : iz_regions(payoff, d) * rule_width(IZ, d);
+    return method != IZ ? rule_width(method, d) : iz_regions(payoff, d) * rule_width(IZ, d);
 }
 
 }  // namespace bmc

@@ -1,0 +1,371 @@
+// CMC classification [class] by AdaBoost with decision stumps (Section 3.2
+// names AdaBoost or LogitBoost).  Training set: the in-the-money points of a
+// date; label y = +1 (exercise) iff Phi - C > 0, else -1; initial weight
+// |Phi - C|, the value lost by the wrong decision.  Features
+// psi = [u_1..u_d, g], u_i = ln(S_i/K), g = Phi/K.  A stump on feature f
+// predicts s in bins k..B-1 and -s below, with B uniform bins between the
+// feature's extremes over the training points (k = 0, the constant stump, on
+// feature 0 only).
+//
+// Every round runs on the device without host round trips:
+//   k_ada_hist    weights rounded to a fixed-point grid 2^-shift and summed
+//                 per (feature, bin, label) with 64-bit integer atomics, so
+//                 the sums are exact and independent of the order;
+//   k_ada_pick    one thread per feature scans its bins for the stump of
+//                 least error (ties: smaller bin, then s = +1), thread 0 takes
+//                 the best feature (ties: smaller feature), eps = error/total,
+//                 alpha = ln((1 - eps)/eps)/2 (eps >= 1e-10); stops when no
+//                 stump beats chance, or after a perfect stump;
+//   k_ada_update  the normalised AdaBoost step w/(2 eps) for misclassified
+//                 points, w/(2 (1 - eps)) for the others (correctly rounded
+//                 divisions, no exponentials).
+// k_ada_fold then writes the rule row [base, count_0..count_d, (theta, delta)
+// feature by feature]: F(x) = base + sum of delta over the thresholds theta
+// that psi reaches; exercise iff Phi > 0 and F > 0.
+#include "fit_common.hpp"
+#include "internal.hpp"
+
+namespace bmc {
+
+namespace {
+
+constexpr int NFMAX = D_MAX + 1;
+
+struct AdaState {
+    int32_t n_itm, shift, T, stop;
+    int32_t f[ADA_TMAX], k[ADA_TMAX], s[ADA_TMAX];
+    double alpha[ADA_TMAX], eps[ADA_TMAX];
+    double lo[NFMAX], hi[NFMAX], inv[NFMAX];
+};
+
+__device__ inline int ada_bin(double v, double lo, double hi, double inv)
+{
+    if (!(hi > lo)) return 0;
+    const double t = floor((v - lo) * inv);
+    if (t < 0.0) return 0;
+    if (t > (double)(ADA_BINS - 1)) return ADA_BINS - 1;
+    return (int)t;
+}
+
+// Payoff of point j in the arithmetic of the classifier's definition: price
+// by price from the log-prices, the basket mean divided by d, the largest of
+// the prices for the max-call (the weights are exact only up to the rounding
+// of the fixed-point grid, so the costs |Phi - C| follow the definition).
+__device__ inline double ada_payoff(const SpecT<double>& S, const double* __restrict__ x, int64_t N, int64_t j)
+{
+#pragma clang fp contract(off)
+    const int d = S.d;
+    double v;
+    if (S.payoff == CALL_MAX) {
+        double mx = exp(log(x[j]));
+        for (int i = 1; i < d; ++i) mx = fmax(mx, exp(log(x[i * N + j])));
+        v = mx - S.K;
+    } else if (S.payoff == PUT_GEO) {
+        double sl = 0.0;
+        for (int i = 0; i < d; ++i) sl += log(x[i * N + j]);
+        v = S.K - exp(sl / (double)d);
+    } else {
+        double sm = 0.0;
+        for (int i = 0; i < d; ++i) sm += exp(log(x[i * N + j]));
+        v = S.K - sm / (double)d;
+    }
+    return v > 0.0 ? v : 0.0;
+}
+
+// Per point: features, label, initial weight; per block: feature extremes,
+// largest weight and count over the in-the-money points.
+__global__ void __launch_bounds__(256) k_ada_prep(const DevSpec* __restrict__ s, const double* __restrict__ x,
+                                                  const double* __restrict__ cont, int64_t N, double* psi, double* w,
+                                                  int8_t* y, double* part)
+{
+    const SpecT<double>& S = s->f64;
+    const int d = S.d, nf = d + 1;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool itm = false;
+    if (j < N) {
+        const double pay = ada_payoff(S, x, N, j);
+        itm = pay > 0.0;
+        if (itm) {
+            for (int i = 0; i < d; ++i) psi[i * N + j] = log(x[i * N + j]) - S.lnK;
+            psi[d * N + j] = pay / S.K;
+            const double beta = pay - cont[j];
+            y[j] = beta > 0.0 ? 1 : -1;
+            w[j] = fabs(beta);
+        } else {
+            y[j] = 0;
+            w[j] = 0.0;
+        }
+    }
+    __shared__ double red[2][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double* out = part + (size_t)blockIdx.x * (2 * nf + 2);
+    for (int f = 0; f < nf + 1; ++f) {
+        // f < nf: extremes of feature f; f == nf: largest weight and count
+        double a, b;
+        if (f < nf) {
+            a = itm ? psi[(int64_t)f * N + j] : INFINITY;
+            b = itm ? psi[(int64_t)f * N + j] : -INFINITY;
+        } else {
+            a = itm ? w[j] : 0.0;
+            b = itm ? 1.0 : 0.0;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ao = __shfl_xor(a, off), bo = __shfl_xor(b, off);
+            if (f < nf) {
+                a = fmin(a, ao);
+                b = fmax(b, bo);
+            } else {
+                a = fmax(a, ao);
+                b += bo;
+            }
+        }
+        if (lane == 0) {
+            red[0][wv] = a;
+            red[1][wv] = b;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double ra = red[0][0], rb = red[1][0];
+            for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+                if (f < nf) {
+                    ra = fmin(ra, red[0][q]);
+                    rb = fmax(rb, red[1][q]);
+                } else {
+                    ra = fmax(ra, red[0][q]);
+                    rb += red[1][q];
+                }
+            }
+            out[2 * f] = ra;
+            out[2 * f + 1] = rb;
+        }
+        __syncthreads();
+    }
+}
+
+// Ranges, fixed-point shift, cleared histograms and stump list.
+__global__ void k_ada_setup(int nf, int nblocks, const double* __restrict__ part, AdaState* st, int64_t* H)
+{
+    const int t = threadIdx.x;
+    for (int f = t; f < nf; f += blockDim.x) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int b = 0; b < nblocks; ++b) {
+            lo = fmin(lo, part[(size_t)b * (2 * nf + 2) + 2 * f]);
+            hi = fmax(hi, part[(size_t)b * (2 * nf + 2) + 2 * f + 1]);
+        }
+        st->lo[f] = lo;
+        st->hi[f] = hi;
+        st->inv[f] = hi > lo ? (double)ADA_BINS / (hi - lo) : 0.0;
+    }
+    for (int e = t; e < 2 * nf * ADA_BINS * 2; e += blockDim.x) H[e] = 0;
+    if (t == 0) {
+        double cmax = 0.0, cnt = 0.0;
+        for (int b = 0; b < nblocks; ++b) {
+            cmax = fmax(cmax, part[(size_t)b * (2 * nf + 2) + 2 * nf]);
+            cnt += part[(size_t)b * (2 * nf + 2) + 2 * nf + 1];
+        }
+        const int nI = (int)cnt;
+        int e2 = 0;
+        frexp((double)nI * cmax, &e2);          // total weight < 2^e2
+        st->n_itm = nI;
+        st->shift = 50 - e2;
+        st->T = 0;
+        st->stop = (nI == 0 || !(cmax > 0.0)) ? 1 : 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_ada_bins(const double* __restrict__ psi, const int8_t* __restrict__ y,
+                                                  int64_t N, int nf, const AdaState* __restrict__ st,
+                                                  uint8_t* bins)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N || y[j] == 0) return;
+    for (int f = 0; f < nf; ++f)
+        bins[(int64_t)f * N + j] = (uint8_t)ada_bin(psi[(int64_t)f * N + j], st->lo[f], st->hi[f], st->inv[f]);
+}
+
+__device__ inline int64_t ada_fixed(double w, int shift)
+{
+    return (int64_t)llrint(ldexp(w, shift));
+}
+
+// Round histogram: H[(f*B + bin)*2 + (y > 0)] += fixed-point weight.
+__global__ void __launch_bounds__(256) k_ada_hist(const double* __restrict__ w, const int8_t* __restrict__ y,
+                                                  const uint8_t* __restrict__ bins, int64_t N, int nf,
+                                                  const AdaState* __restrict__ st, int64_t* H)
+{
+    if (st->stop) return;
+    extern __shared__ unsigned long long hs[];
+    const int nh = nf * ADA_BINS * 2;
+    for (int e = threadIdx.x; e < nh; e += blockDim.x) hs[e] = 0ull;
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < N && y[j] != 0) {
+        const unsigned long long W = (unsigned long long)ada_fixed(w[j], st->shift);
+        const int c = y[j] > 0;
+        if (W)
+            for (int f = 0; f < nf; ++f) atomicAdd(&hs[((int)bins[(int64_t)f * N + j] + f * ADA_BINS) * 2 + c], W);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nh; e += blockDim.x)
+        if (hs[e]) atomicAdd(reinterpret_cast<unsigned long long*>(H) + e, hs[e]);
+}
+
+// Best stump of round t from the histogram Hc; clears the other histogram.
+__global__ void k_ada_pick(int t, int nf, const int64_t* __restrict__ Hc, int64_t* Hn, AdaState* st)
+{
+    __shared__ long long best_e[NFMAX];
+    __shared__ int best_k[NFMAX], best_s[NFMAX];
+    __shared__ long long totals[2];
+    if (st->stop) return;
+    const int f = threadIdx.x;
+    if (f < nf) {
+        const int64_t* h = Hc + (size_t)f * ADA_BINS * 2;
+        long long Wp = 0, Wm = 0;
+        for (int b = 0; b < ADA_BINS; ++b) {
+            Wm += h[2 * b];
+            Wp += h[2 * b + 1];
+        }
+        const long long Wt = Wp + Wm;
+        long long Pp = 0, Pm = 0, be = -1;
+        int bk = 0, bs = 1;
+        for (int k = 0; k < ADA_BINS; ++k) {
+            if (k > 0) {
+                Pm += h[2 * (k - 1)];
+                Pp += h[2 * (k - 1) + 1];
+            }
+            if (k == 0 && f > 0) continue;
+            const long long Eplus = Pp + (Wm - Pm), Eminus = Wt - Eplus;
+            if (be < 0 || Eplus < be) {
+                be = Eplus;
+                bk = k;
+                bs = 1;
+            }
+            if (Eminus < be) {
+                be = Eminus;
+                bk = k;
+                bs = -1;
+            }
+        }
+        best_e[f] = be;
+        best_k[f] = bk;
+        best_s[f] = bs;
+        if (f == 0) {
+            totals[0] = Wt;
+            totals[1] = 0;
+        }
+    }
+    for (int e = threadIdx.x; e < nf * ADA_BINS * 2; e += blockDim.x) Hn[e] = 0;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const long long Wt = totals[0];
+    long long be = best_e[0];
+    int bf = 0;
+    for (int g = 1; g < nf; ++g)
+        if (best_e[g] < be) {
+            be = best_e[g];
+            bf = g;
+        }
+    if (Wt == 0 || 2 * be >= Wt) {   // no stump beats chance
+        st->stop = 1;
+        return;
+    }
+    const double eps = (double)be / (double)Wt;
+    const double ea = eps > 1e-10 ? eps : 1e-10;
+    st->f[t] = bf;
+    st->k[t] = best_k[bf];
+    st->s[t] = best_s[bf];
+    st->eps[t] = eps;
+    st->alpha[t] = 0.5 * log((1.0 - ea) / ea);
+    st->T = t + 1;
+    if (be == 0) st->stop = 1;   // perfect stump: nothing left to reweight
+}
+
+__global__ void __launch_bounds__(256) k_ada_update(int t, double* w, const int8_t* __restrict__ y,
+                                                    const uint8_t* __restrict__ bins, int64_t N,
+                                                    const AdaState* __restrict__ st)
+{
+    if (st->stop || st->T != t + 1) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N || y[j] == 0) return;
+    const int f = st->f[t], k = st->k[t], s = st->s[t];
+    const double eps = st->eps[t];
+    const int h = (int)bins[(int64_t)f * N + j] >= k ? s : -s;
+    w[j] = h != y[j] ? w[j] / (2.0 * eps) : w[j] / (2.0 * (1.0 - eps));
+}
+
+// Folded rule row (FP64 and its FP32 copy), zero-padded to width.
+__global__ void k_ada_fold(int nf, int width, const AdaState* __restrict__ st, double* row64, float* row32)
+{
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0) return;
+    const int T = st->T;
+    double base = 0.0;
+    for (int t = 0; t < T; ++t) base -= st->alpha[t] * (double)st->s[t];
+    row64[0] = base;
+    int at = 1 + nf;
+    for (int f = 0; f < nf; ++f) {
+        int cnt = 0;
+        const double step = (st->hi[f] - st->lo[f]) / (double)ADA_BINS;
+        for (int t = 0; t < T; ++t) {
+            if (st->f[t] != f) continue;
+            row64[at] = st->k[t] == 0 ? -1e300 : st->lo[f] + (double)st->k[t] * step;
+            row64[at + 1] = 2.0 * st->alpha[t] * (double)st->s[t];
+            at += 2;
+            ++cnt;
+        }
+        row64[1 + f] = (double)cnt;
+    }
+    for (int e = at; e < width; ++e) row64[e] = 0.0;
+    for (int e = 0; e < width; ++e) row32[e] = (float)row64[e];
+}
+
+}  // namespace
+
+// Scratch (bytes): psi [nf][N], w [N], block partials, histograms [2][nf][B][2],
+// state, labels [N], bins [nf][N].
+size_t fit_ada_scratch_bytes(int64_t N, int d)
+{
+    const int nf = d + 1;
+    const int64_t blocks = (N + 255) / 256;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    return al(sizeof(double) * nf * N) + al(sizeof(double) * N) + al(sizeof(double) * blocks * (2 * nf + 2)) +
+           al(sizeof(int64_t) * 2 * nf * ADA_BINS * 2) + al(sizeof(AdaState)) + al(N) + al((size_t)nf * N);
+}
+
+hipError_t launch_fit_ada(const DevSpec* s, int d, const double* x, const double* cont, int64_t N, int rounds,
+                          void* scratch, double* row64, float* row32, int width, hipStream_t st)
+{
+    const int nf = d + 1;
+    const int blocks = (int)((N + 255) / 256);
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    char* c = (char*)scratch;
+    double* psi = (double*)c;
+    c += al(sizeof(double) * nf * N);
+    double* w = (double*)c;
+    c += al(sizeof(double) * N);
+    double* part = (double*)c;
+    c += al(sizeof(double) * blocks * (2 * nf + 2));
+    int64_t* H = (int64_t*)c;
+    c += al(sizeof(int64_t) * 2 * nf * ADA_BINS * 2);
+    AdaState* state = (AdaState*)c;
+    c += al(sizeof(AdaState));
+    int8_t* y = (int8_t*)c;
+    c += al(N);
+    uint8_t* bins = (uint8_t*)c;
+    const int nh = nf * ADA_BINS * 2;
+    hipLaunchKernelGGL(k_ada_prep, dim3(blocks), dim3(256), 0, st, s, x, cont, N, psi, w, y, part);
+    hipLaunchKernelGGL(k_ada_setup, dim3(1), dim3(256), 0, st, nf, blocks, part, state, H);
+    hipLaunchKernelGGL(k_ada_bins, dim3(blocks), dim3(256), 0, st, psi, y, N, nf, state, bins);
+    for (int t = 0; t < rounds; ++t) {
+        int64_t* Hc = H + (size_t)(t & 1) * nh;
+        int64_t* Hn = H + (size_t)((t + 1) & 1) * nh;
+        hipLaunchKernelGGL(k_ada_hist, dim3(blocks), dim3(256), sizeof(unsigned long long) * nh, st, w, y, bins, N,
+                           nf, state, Hc);
+        hipLaunchKernelGGL(k_ada_pick, dim3(1), dim3(128), 0, st, t, nf, Hc, Hn, state);
+        hipLaunchKernelGGL(k_ada_update, dim3(blocks), dim3(256), 0, st, t, w, y, bins, N, state);
+    }
+    hipLaunchKernelGGL(k_ada_fold, dim3(1), dim3(64), 0, st, nf, width, state, row64, row32);
+    return hipGetLastError();
+}
+
+}  // namespace bmc

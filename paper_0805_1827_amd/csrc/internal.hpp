@@ -194,6 +194,11 @@ hipError_t launch_fit_cmc(const DevSpec* s, int d, const double* x, const double
                           hipStream_t st);
 // I&Z quadratic regression of rule row m; x[0*J + j] = s*_j.
 size_t fitiz_scratch_doubles(int64_t J, int p);
+// AdaBoost-stump fit of one date (rounds <= ADA_TMAX) into a rule row of width
+// entries; scratch of fit_ada_scratch_bytes(N, d) bytes.
+size_t fit_ada_scratch_bytes(int64_t N, int d);
+hipError_t launch_fit_ada(const DevSpec* s, int d, const double* x, const double* cont, int64_t N, int rounds,
+                          void* scratch, double* row64, float* row32, int width, hipStream_t st);
 // Boundary block of one region (row64/row32 point at the block) from J
 // points in rows of ld entries.
 hipError_t launch_fit_iz(const DevSpec* s, int d, int region, const double* x, int64_t J, int64_t ld,

@@ -57,13 +57,14 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     if (!ctx || !opts || !out) return fail(BMC_EINVAL, "NULL argument");
     (void)hipSetDevice(ctx->device);
     const int method = opts->method, prec = opts->precision;
-    if (method != BMC_CMC && method != BMC_IZ) return fail(BMC_EINVAL, "unknown method %d", method);
+    if (method != BMC_CMC && method != BMC_IZ && method != BMC_CMC_ADA)
+        return fail(BMC_EINVAL, "unknown method %d", method);
     if (prec < BMC_FP64 || prec > BMC_FP32_KAHAN) return fail(BMC_EINVAL, "unknown precision %d", prec);
     if (opts->N < 2 || opts->N > 0x7FFFFFFF || opts->n < 2 || opts->n > 0x7FFFFFFF || opts->n_final < 2 ||
         opts->n_final > 0x7FFFFFFF)
         return fail(BMC_EINVAL, "N, n and n_final must be in 2..2^31-1");
     if (opts->seed > 0xFFFFFFFFull) return fail(BMC_EINVAL, "seed must fit in 32 bits");
-    const int rounds = opts->cls_rounds > 0 ? opts->cls_rounds : 8;
+    const int rounds = opts->cls_rounds > 0 ? opts->cls_rounds : (method == BMC_CMC_ADA ? ADA_TMAX : 8);
     const int max_iter = opts->iz_max_iter > 0 ? opts->iz_max_iter : 100;
     const double eps = opts->iz_eps > 0.0 ? opts->iz_eps : 0.01;
     if (rounds > 64) return fail(BMC_EINVAL, "cls_rounds must be <= 64");
@@ -108,7 +109,7 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
         return hip_fail(e, "counter reset");
     }
 
-    if (method == BMC_CMC) {
+    if (method != BMC_IZ) {
         if ((e = launch_bridge_end((const DevSpec*)ds, d, N, seed, B, ctx->stream))) st = hip_fail(e, "bridge");
         for (int m = NT - 1; m >= 1 && !st; --m) {
             if ((e = launch_bridge_back((const DevSpec*)ds, d, m, N, seed, B, x, 1, ctx->stream))) {
@@ -187,7 +188,7 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     bmc_result r;
     std::memset(&r, 0, sizeof(r));
     fill_price(sums, opts->n_final, &r);
-    r.inner_path_steps = method == BMC_CMC ? (int64_t)inner : iz_steps;
+    r.inner_path_steps = method != BMC_IZ ? (int64_t)inner : iz_steps;
     r.iz_unconverged = unconv;
     r.iz_iterations = iz_iters;
     double sec[3] = {0, 0, 0};

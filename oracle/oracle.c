@@ -147,7 +147,7 @@ static int check_spec(const orc_spec *s)
         for (int j = 0; j < i; ++j)
             if (fabs(s->rho[i * s->d + j] - s->rho[j * s->d + i]) > 1e-12) return ORC_EINVAL;
     }
-    if (s->payoff < ORC_PUT_BASKET || s->payoff > ORC_PUT_GEO) return ORC_EINVAL;
+    if (s->payoff < ORC_PUT_BASKET || s->payoff > ORC_CALL_MIN) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -170,6 +170,13 @@ double orc_payoff(const orc_spec *s, const double *logS)
             if (Si > mx) mx = Si;
         }
         v = mx - s->K;
+    } else if (s->payoff == ORC_CALL_MIN) {
+        double mn = exp(logS[0]);
+        for (int i = 1; i < d; ++i) {
+            double Si = exp(logS[i]);
+            if (Si < mn) mn = Si;
+        }
+        v = mn - s->K;
     } else {
         double meanlog = 0.0;
         for (int i = 0; i < d; ++i) meanlog += logS[i];
@@ -188,12 +195,13 @@ int orc_rule_width(int method, int d)
 
 /* I&Z regions (Section 2.2): the call on the maximum of d assets has d
  * exercise regions, region i where asset i is the largest, each with its own
- * boundary in the other d - 1 assets; the put family has one boundary in
+ * boundary in the other d - 1 assets; the call on the minimum likewise with
+ * region i where asset i is the smallest; the put family has one boundary in
  * assets 2..d.  A rule row holds one block of orc_rule_width(IZ, d)
  * coefficients per region. */
 int orc_iz_regions(const orc_spec *s)
 {
-    return s->payoff == ORC_CALL_MAX ? s->d : 1;
+    return (s->payoff == ORC_CALL_MAX || s->payoff == ORC_CALL_MIN) ? s->d : 1;
 }
 
 int orc_rule_width_spec(const orc_spec *s, int method)
@@ -244,10 +252,11 @@ static void ada_features(const orc_spec *s, const double *logS, double payoff, d
 }
 
 /* I&Z: puts search the first asset and exercise below its boundary; the
- * max-call searches the asset of the region and exercises above it. */
+ * calls on the maximum and the minimum search the asset of the region and
+ * exercise above it. */
 static int iz_direction_is_call(const orc_spec *s)
 {
-    return s->payoff == ORC_CALL_MAX;
+    return s->payoff == ORC_CALL_MAX || s->payoff == ORC_CALL_MIN;
 }
 
 static const double IZ_NEVER = 1e300;
@@ -283,9 +292,14 @@ static int exercise_now(const orc_spec *s, int method, const double *row,
     double xi[1 + 63 + 63 * 64 / 2];
     int p = orc_rule_width(ORC_IZ, s->d);
     int region = 0;
-    if (iz_direction_is_call(s))   /* region of the largest asset (first one on ties) */
+    /* region of the largest (max-call) or smallest (min-call) asset, the
+     * first one on ties */
+    if (s->payoff == ORC_CALL_MAX)
         for (int i = 1; i < s->d; ++i)
             if (logS[i] > logS[region]) region = i;
+    if (s->payoff == ORC_CALL_MIN)
+        for (int i = 1; i < s->d; ++i)
+            if (logS[i] < logS[region]) region = i;
     iz_features(s, logS, region, xi);
     const double *b = row + (size_t)region * p;
     double bnd = 0.0;
@@ -879,17 +893,24 @@ int orc_fit_ada(const orc_spec *s, const double *x, const double *cont, int64_t 
  * searched coordinate at K and iterate s <- Phi^{-1}(C(s)) with the same
  * inner paths each time (common random numbers), until |s' - s| < eps.
  * The searched coordinate is asset 1 for the put family and the asset of the
- * region for the max-call; Phi^{-1}(c) is its price whose payoff equals c:
+ * region for the calls; Phi^{-1}(c) is its price whose payoff equals c:
  *   geometric put      (K - c)^d / prod_{i>=2} x_i,
  *   arithmetic put     d (K - c) - sum_{i>=2} x_i,
- *   max-call           K + c.
- * A non-positive inverse drops the point; so does a max-call fixed point that
- * is not the largest asset (it lies outside the region). */
+ *   max- and min-call  K + c.
+ * A non-positive inverse drops the point; so does a fixed point outside the
+ * region (a max-call point not above every other asset, a min-call point not
+ * below every other asset).
+ *
+ * Secant mode (the paper speaks of Newton iterations): with r(s) = G(s) - s,
+ * G the plain map, the first step is the plain one and each later step goes
+ * to s - r(s) (s - s_prev) / (r(s) - r(s_prev)), limited to 20 |r(s)|; a zero
+ * denominator, a non-finite or a non-positive result takes the plain step.
+ * Both modes stop at the first evaluated s with |r(s)| < eps and return G(s). */
 
 static double iz_invert(const orc_spec *s, const double *x_other, double c)
 {
     int d = s->d;
-    if (s->payoff == ORC_CALL_MAX) return s->K + c;
+    if (s->payoff == ORC_CALL_MAX || s->payoff == ORC_CALL_MIN) return s->K + c;
     if (!(s->K - c > 0.0)) return -1.0;
     if (s->payoff == ORC_PUT_GEO || d == 1) {
         double prod = 1.0;
@@ -907,7 +928,7 @@ typedef struct {
     int region;
     int64_t J, n;
     double eps;
-    int max_iter;
+    int max_iter, mode;
     double *s_out;
     int32_t *iters;
     int64_t *steps;
@@ -927,13 +948,14 @@ static void *iz_worker(void *arg)
         pthread_mutex_unlock(&job->lock);
         if (j >= job->J) break;
         int r = job->region;
-        double others_max = 0.0;
+        double others_max = 0.0, others_min = INFINITY;
         for (int i = 0; i < d; ++i) {
             xo[i] = job->x[(size_t)i * job->J + j];
             if (i != r && xo[i] > others_max) others_max = xo[i];
+            if (i != r && xo[i] < others_min) others_min = xo[i];
         }
-        double sv = s->K, result = -1.0;
-        int it = 0;
+        double sv = s->K, result = -1.0, s_prev = 0.0, r_prev = 0.0;
+        int it = 0, have_prev = 0;
         int64_t st = 0;
         while (it < job->max_iter) {
             for (int i = 0; i < d; ++i) logx[i] = i == r ? log(sv) : log(xo[i]);
@@ -943,11 +965,28 @@ static void *iz_worker(void *arg)
             double snew = iz_invert(s, xo, cval);
             ++it;
             if (!(snew > 0.0) || !isfinite(snew)) break;
-            if (fabs(snew - sv) < job->eps) {
-                if (!(s->payoff == ORC_CALL_MAX && snew <= others_max)) result = snew;
+            double res = snew - sv;
+            if (fabs(res) < job->eps) {
+                int outside = (s->payoff == ORC_CALL_MAX && snew <= others_max) ||
+                              (s->payoff == ORC_CALL_MIN && snew >= others_min);
+                if (!outside) result = snew;
                 break;
             }
-            sv = snew;
+            double next = snew;
+            if (job->mode == ORC_SEARCH_SECANT && have_prev) {
+                double den = res - r_prev;
+                if (den != 0.0) {
+                    double step = -res * (sv - s_prev) / den;
+                    double lim = 20.0 * fabs(res);
+                    if (step > lim) step = lim;
+                    if (step < -lim) step = -lim;
+                    if (isfinite(step) && sv + step > 0.0) next = sv + step;
+                }
+            }
+            s_prev = sv;
+            r_prev = res;
+            have_prev = 1;
+            sv = next;
         }
         job->s_out[j] = result;
         job->iters[j] = it;
@@ -958,13 +997,14 @@ static void *iz_worker(void *arg)
 
 int orc_iz_search(const orc_spec *s, const double *rules, int m, int region,
                   const double *x, int64_t J, int64_t n, uint32_t seed, double eps,
-                  int max_iter, int nthreads, double *s_out, int32_t *iters,
+                  int max_iter, int mode, int nthreads, double *s_out, int32_t *iters,
                   int64_t *steps_total)
 {
     int rc = check_spec(s);
     if (rc) return rc;
     if (m < 1 || m >= s->n_dates || J < 1 || n < 2 || max_iter < 1 || !(eps > 0.0) ||
-        region < 0 || region >= orc_iz_regions(s))
+        region < 0 || region >= orc_iz_regions(s) ||
+        (mode != ORC_SEARCH_PLAIN && mode != ORC_SEARCH_SECANT))
         return ORC_EINVAL;
     int d = s->d;
     double *L = malloc(sizeof(double) * d * d);
@@ -974,7 +1014,7 @@ int orc_iz_search(const orc_spec *s, const double *rules, int m, int region,
     if (rc) { free(L); free(st); return rc; }
     path_ctx c = {s, ORC_IZ, rules, orc_rule_width_spec(s, ORC_IZ), m, L, seed,
                   key_hi(ORC_STREAM_INNER, m), (uint32_t)region};
-    iz_job job = {&c, x, region, J, n, eps, max_iter, s_out, iters, st, 0};
+    iz_job job = {&c, x, region, J, n, eps, max_iter, mode, s_out, iters, st, 0};
     pthread_mutex_init(&job.lock, NULL);
     int nt = resolve_threads(nthreads);
     if (nt > J) nt = (int)J;
@@ -1034,8 +1074,8 @@ int orc_fit_iz(const orc_spec *s, int region, const double *x, const double *sst
  * consistent). */
 
 int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_final,
-              uint32_t seed, int rounds, double eps, int max_iter, int nthreads,
-              double *rules_out, double *result)
+              uint32_t seed, int rounds, double eps, int max_iter, int search_mode,
+              int nthreads, double *rules_out, double *result)
 {
     int rc = check_spec(s);
     if (rc) return rc;
@@ -1080,8 +1120,8 @@ int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_fin
                 rc = orc_points_iz(s, m, r, N, x);
                 if (rc) goto done;
                 int64_t st = 0;
-                rc = orc_iz_search(s, rules, m, r, x, N, n, seed, eps, max_iter, nthreads,
-                                   cont, iters, &st);
+                rc = orc_iz_search(s, rules, m, r, x, N, n, seed, eps, max_iter, search_mode,
+                                   nthreads, cont, iters, &st);
                 if (rc) goto done;
                 inner += st;
                 for (int64_t j = 0; j < N; ++j) {

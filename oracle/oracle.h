@@ -22,7 +22,9 @@
 extern "C" {
 #endif
 
-enum { ORC_PUT_BASKET = 0, ORC_CALL_MAX = 1, ORC_PUT_GEO = 2 };
+enum { ORC_PUT_BASKET = 0, ORC_CALL_MAX = 1, ORC_PUT_GEO = 2, ORC_CALL_MIN = 3 };
+/* I&Z boundary-point search: plain fixed point, or secant steps on its residual */
+enum { ORC_SEARCH_PLAIN = 0, ORC_SEARCH_SECANT = 1 };
 enum { ORC_CMC = 0, ORC_IZ = 1, ORC_CMC_ADA = 2 };
 /* AdaBoost stumps (ORC_CMC_ADA): bins per feature and the largest number of
  * boosting rounds a rule row holds. */
@@ -41,13 +43,14 @@ typedef struct {
     double K, r, T;
     int32_t n_dates;      /* N_T exercise dates t_1 < ... < t_NT = T */
     const double *dates;  /* [n_dates] */
-    int32_t payoff;       /* ORC_PUT_BASKET / ORC_CALL_MAX / ORC_PUT_GEO */
+    int32_t payoff;       /* ORC_PUT_BASKET / ORC_CALL_MAX / ORC_PUT_GEO / ORC_CALL_MIN */
 } orc_spec;
 
 /* Number of rule coefficients per date for a method and dimension (for I&Z:
  * one region's boundary). */
 int orc_rule_width(int method, int d);
-/* I&Z exercise regions (Section 2.2): d for the max-call, 1 otherwise. */
+/* I&Z exercise regions (Section 2.2): d for the calls on the maximum and the
+ * minimum, 1 otherwise. */
 int orc_iz_regions(const orc_spec *s);
 /* Width of a rule row: CMC weights, or the I&Z boundary blocks of every
  * region, region r at offset r * orc_rule_width(ORC_IZ, d). */
@@ -103,10 +106,11 @@ int orc_fit_ada(const orc_spec *s, const double *x, const double *cont, int64_t 
 
 /* I&Z fixed-point search of a region's boundary coordinate for J points at
  * date m; the inner paths of region r use r as the fourth counter word.
+ * mode: ORC_SEARCH_PLAIN or ORC_SEARCH_SECANT.
  * Writes s_out[J] (<= 0 if dropped or unconverged) and iters[J]. */
 int orc_iz_search(const orc_spec *s, const double *rules, int m, int region,
                   const double *x, int64_t J, int64_t n, uint32_t seed, double eps,
-                  int max_iter, int nthreads, double *s_out, int32_t *iters,
+                  int max_iter, int mode, int nthreads, double *s_out, int32_t *iters,
                   int64_t *steps_total);
 
 /* I&Z quadratic boundary regression of one region over its converged points;
@@ -121,8 +125,8 @@ int orc_fit_iz(const orc_spec *s, int region, const double *x, const double *sst
  *              iz_unconverged, iz_iterations}.
  */
 int orc_price(const orc_spec *s, int method, int64_t N, int64_t n, int64_t n_final,
-              uint32_t seed, int rounds, double eps, int max_iter, int nthreads,
-              double *rules_out, double *result);
+              uint32_t seed, int rounds, double eps, int max_iter, int search_mode,
+              int nthreads, double *rules_out, double *result);
 
 #ifdef __cplusplus
 }

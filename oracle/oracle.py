@@ -17,7 +17,8 @@ import numpy as np
 HERE = Path(__file__).resolve().parent
 LIB_PATH = HERE / "liboracle.so"
 
-PUT_BASKET, CALL_MAX, PUT_GEO = 0, 1, 2
+PUT_BASKET, CALL_MAX, PUT_GEO, CALL_MIN = 0, 1, 2, 3
+SEARCH_PLAIN, SEARCH_SECANT = 0, 1
 CMC, IZ, CMC_ADA = 0, 1, 2
 ADA_BINS, ADA_TMAX = 64, 64
 ADA_ROUNDS = 64          # default AdaBoost rounds
@@ -73,10 +74,10 @@ def lib():
         L.orc_fit_cmc.argtypes = [sp, dp, dp, C.c_int64, C.c_int, dp]
         L.orc_fit_ada.argtypes = [sp, dp, dp, C.c_int64, C.c_int, dp, i32p, i32p, i32p, i32p, dp, dp, dp, dp]
         L.orc_iz_search.argtypes = [sp, dp, C.c_int, C.c_int, dp, C.c_int64, C.c_int64, C.c_uint32,
-                                    C.c_double, C.c_int, C.c_int, dp, i32p, i64p]
+                                    C.c_double, C.c_int, C.c_int, C.c_int, dp, i32p, i64p]
         L.orc_fit_iz.argtypes = [sp, C.c_int, dp, dp, C.c_int64, dp]
         L.orc_price.argtypes = [sp, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_uint32,
-                                C.c_int, C.c_double, C.c_int, C.c_int, dp, dp]
+                                C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, dp, dp]
         _lib = L
     return _lib
 
@@ -220,7 +221,7 @@ def fit_cmc(spec, x: np.ndarray, cont: np.ndarray, rounds: int = 8) -> np.ndarra
 
 
 def iz_search(spec, rules, m: int, x: np.ndarray, n: int, seed: int, eps: float = 0.01,
-              max_iter: int = 100, nthreads: int = 0, region: int = 0) -> dict:
+              max_iter: int = 100, nthreads: int = 0, region: int = 0, mode: int = SEARCH_PLAIN) -> dict:
     h = _SpecHolder(spec)
     x = np.ascontiguousarray(x, dtype=np.float64)
     J = x.shape[1]
@@ -228,7 +229,7 @@ def iz_search(spec, rules, m: int, x: np.ndarray, n: int, seed: int, eps: float 
     s = np.zeros(J)
     it = np.zeros(J, dtype=np.int32)
     st = C.c_int64(0)
-    _check(lib().orc_iz_search(h.ptr, _dp(rules), m, region, _dp(x), J, n, seed, eps, max_iter, nthreads,
+    _check(lib().orc_iz_search(h.ptr, _dp(rules), m, region, _dp(x), J, n, seed, eps, max_iter, mode, nthreads,
                                _dp(s), it.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(st)),
            "iz_search")
     return {"s": s, "iters": it, "steps": int(st.value)}
@@ -265,14 +266,14 @@ def fit_ada(spec, x: np.ndarray, cont: np.ndarray, rounds: int = ADA_ROUNDS, tra
 
 
 def price(spec, method: int, N: int, n: int, n_final: int, seed: int, rounds: int = 0,
-          eps: float = 0.01, max_iter: int = 100, nthreads: int = 0) -> dict:
+          eps: float = 0.01, max_iter: int = 100, nthreads: int = 0, search_mode: int = SEARCH_PLAIN) -> dict:
     """rounds: boosting rounds (0: 8 for CMC, 64 for CMC_ADA)."""
     if rounds <= 0:
         rounds = ADA_ROUNDS if method == CMC_ADA else 8
     h = _SpecHolder(spec)
     rules = np.zeros((h.n_dates + 1, row_width(spec, method)))
     res = np.zeros(8)
-    _check(lib().orc_price(h.ptr, method, N, n, n_final, seed, rounds, eps, max_iter, nthreads,
+    _check(lib().orc_price(h.ptr, method, N, n, n_final, seed, rounds, eps, max_iter, search_mode, nthreads,
                            _dp(rules), _dp(res)), "price")
     return {"price": res[0], "variance": res[1], "std_err": res[2], "ci95": res[3],
             "inner_path_steps": int(res[4]), "final_path_steps": int(res[5]),

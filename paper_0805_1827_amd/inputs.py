@@ -12,8 +12,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-PUT_BASKET, CALL_MAX, PUT_GEO = 0, 1, 2
-PAYOFF_NAMES = {PUT_BASKET: "basket_put", CALL_MAX: "max_call", PUT_GEO: "geometric_put"}
+PUT_BASKET, CALL_MAX, PUT_GEO, CALL_MIN = 0, 1, 2, 3
+PAYOFF_NAMES = {PUT_BASKET: "basket_put", CALL_MAX: "max_call", PUT_GEO: "geometric_put", CALL_MIN: "min_call"}
 
 
 @dataclass
@@ -70,6 +70,12 @@ def max_call(d: int, S0: float, n_dates: int = 9, T: float = 3.0) -> OptionSpec:
     """Max-call of Section 2.2 / Section 3.2: K = 100, r = 0.05, delta = 0.1,
     sigma = 0.2, independent assets, T = 3, 9 dates."""
     return basket(d, S0, 100.0, 0.05, 0.1, 0.2, 0.0, T, n_dates, CALL_MAX)
+
+
+def min_call(d: int, S0, sigma=0.2, n_dates: int = 9, T: float = 3.0, delta: float = 0.1) -> OptionSpec:
+    """Call on the minimum of d independent assets with the max-call's market
+    block: K = 100, r = 0.05, T = 3, 9 dates."""
+    return basket(d, S0, 100.0, 0.05, delta, sigma, 0.0, T, n_dates, CALL_MIN)
 
 
 def wishart_corr(d: int, rng: np.random.Generator) -> np.ndarray:

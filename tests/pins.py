@@ -63,14 +63,17 @@ def crr_put(S0, K, r, q, sigma, T, steps, n_dates=None, american=False, want_bou
     return float(V[0])
 
 
-def max_call2_tree(S0, K, r, delta, sigma, T, steps, n_dates, want_boundary=False):
-    """Bermudan call on the maximum of two independent assets: the product of
-    two CRR trees (four branches per step), exercise at t_m = m T / n_dates,
-    m = 1..n_dates.  With want_boundary, for every exercise step i and asset a
-    the critical prices of asset a (the smallest price above the other asset
-    at which exercise is optimal) against the other asset's node prices:
-    boundary[i][a] = (other prices, critical prices), found by linear
-    interpolation in ln S_a of exercise value minus continuation value."""
+def max_call2_tree(S0, K, r, delta, sigma, T, steps, n_dates, want_boundary=False, kind="max"):
+    """Bermudan call on the maximum (kind="max") or the minimum (kind="min")
+    of two independent assets: the product of two CRR trees (four branches per
+    step), exercise at t_m = m T / n_dates, m = 1..n_dates.  With
+    want_boundary, for every exercise step i and asset a the critical prices
+    of asset a against the other asset's node prices: boundary[i][a] = (other
+    prices, critical prices), the smallest price of asset a at which exercise
+    becomes optimal, above the other asset for the max-call and below it for
+    the min-call, by linear interpolation in ln S_a of exercise value minus
+    continuation value."""
+    best = np.maximum if kind == "max" else np.minimum
     assert steps % n_dates == 0
     dt = T / steps
     u = [math.exp(s * math.sqrt(dt)) for s in sigma]
@@ -82,7 +85,7 @@ def max_call2_tree(S0, K, r, delta, sigma, T, steps, n_dates, want_boundary=Fals
         return [S0[a] * u[a] ** (2.0 * k - i) for a in range(2)]
 
     Sa, Sb = prices(steps)
-    V = np.maximum(np.maximum(Sa[:, None], Sb[None, :]) - K, 0.0)
+    V = np.maximum(best(Sa[:, None], Sb[None, :]) - K, 0.0)
     ex_steps = {m * steps // n_dates for m in range(1, n_dates)}
     boundary = {}
     for i in range(steps - 1, -1, -1):
@@ -91,7 +94,7 @@ def max_call2_tree(S0, K, r, delta, sigma, T, steps, n_dates, want_boundary=Fals
                     + (1 - pa) * pb * V[:-1, 1:] + (1 - pa) * (1 - pb) * V[:-1, :-1])
         if i in ex_steps:
             Sa, Sb = prices(i)
-            pay = np.maximum(np.maximum(Sa[:, None], Sb[None, :]) - K, 0.0)
+            pay = np.maximum(best(Sa[:, None], Sb[None, :]) - K, 0.0)
             if want_boundary:
                 g = pay - V
                 out = {}
@@ -102,7 +105,8 @@ def max_call2_tree(S0, K, r, delta, sigma, T, steps, n_dates, want_boundary=Fals
                     for c in range(len(other)):
                         col = ga[:, c]
                         for k in range(1, len(own)):
-                            if own[k - 1] > other[c] and col[k - 1] <= 0.0 < col[k]:
+                            inside = own[k - 1] > other[c] if kind == "max" else own[k] < other[c]
+                            if inside and col[k - 1] <= 0.0 < col[k]:
                                 w = col[k - 1] / (col[k - 1] - col[k])
                                 ys.append(math.exp((1 - w) * math.log(own[k - 1]) + w * math.log(own[k])))
                                 xs.append(other[c])
@@ -148,6 +152,23 @@ def max_call_european(x, K, r, delta, sigma, tau):
         return 1.0 - float(np.prod(stats.norm.cdf((math.log(y) - mu) / sd)))
 
     hi = float(np.max(np.exp(mu + 12 * sd)))
+    val, _ = integrate.quad(tail, K, hi, limit=400, epsabs=1e-10, epsrel=1e-10)
+    return math.exp(-r * tau) * val
+
+
+def min_call_european(x, K, r, delta, sigma, tau):
+    """European call on the minimum of independent GBMs, by quadrature of
+    E[(m - K)^+] = int_K^inf prod_i (1 - F_i(y)) dy, F_i the lognormal CDFs."""
+    x = np.asarray(x, dtype=float)
+    delta = np.broadcast_to(delta, x.shape)
+    sigma = np.broadcast_to(sigma, x.shape)
+    mu = np.log(x) + (r - delta - 0.5 * sigma ** 2) * tau
+    sd = sigma * math.sqrt(tau)
+
+    def tail(y):
+        return float(np.prod(stats.norm.sf((math.log(y) - mu) / sd)))
+
+    hi = float(np.min(np.exp(mu + 12 * sd)))
     val, _ = integrate.quad(tail, K, hi, limit=400, epsabs=1e-10, epsrel=1e-10)
     return math.exp(-r * tau) * val
 

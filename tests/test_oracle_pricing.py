@@ -322,3 +322,120 @@ def test_iz_max_call_d3_against_paper_table1(orc, inputs, S0):
     blocks = r["rules"][1:9].reshape(8, 3, W)
     assert np.all(np.abs(blocks[:, :, 0] - blocks[:, :1, 0]) < 0.02)
     assert r["iz_unconverged"] < 0.2 * 3 * 128 * 8
+
+
+# ---------------------------------------------------------------------------
+# Call on the minimum (regions by the smallest asset) and the secant search.
+
+def _asym_min_call2(inputs):
+    return inputs.min_call(2, [100.0, 110.0], sigma=[0.2, 0.3])
+
+
+def test_min_call_single_date_is_european(orc, inputs):
+    spec = inputs.min_call(3, [100.0, 105.0, 110.0], sigma=[0.2, 0.25, 0.3], n_dates=1, T=1.0)
+    ref = pins.min_call_european(spec.S0, 100.0, 0.05, 0.1, spec.sigma, 1.0)
+    r = orc.price(spec, orc.CMC, 50, 50, 400000, 2, nthreads=NT)
+    assert abs(r["price"] - ref) < 3 * r["std_err"]
+    assert r["inner_path_steps"] == 0
+
+
+def test_iz_min_call_fixed_points_per_region(orc, inputs):
+    """Last date before maturity: each region's point solves
+    s = K + C_E(s, other) with the one-period European min-call, and lies
+    below the other asset (the region of the smallest asset)."""
+    from scipy import optimize
+    spec = _asym_min_call2(inputs)
+    m, J, n = 8, 8, 20000
+    tau = spec.T / spec.n_dates
+    rules = orc.empty_rules(spec, orc.IZ)
+    assert orc.iz_regions(spec) == 2
+    kept = 0
+    for a in (0, 1):
+        x = orc.points_iz(spec, m, J, region=a)
+        res = orc.iz_search(spec, rules, m, x, n, seed=1, nthreads=NT, region=a, max_iter=300)
+        for j in range(J):
+            xo = x[:, j].copy()
+
+            def g(s):
+                xx = xo.copy()
+                xx[a] = s
+                return spec.K + pins.min_call_european(xx, spec.K, spec.r, spec.delta, spec.sigma, tau) - s
+
+            if res["s"][j] > 0:
+                kept += 1
+                assert res["s"][j] < xo[1 - a]
+                ref = optimize.brentq(g, spec.K, xo[1 - a])
+                assert res["s"][j] == pytest.approx(ref, rel=0.01), (a, j, xo[1 - a])
+            else:   # dropped: no fixed point below the other asset (within the search tolerance)
+                assert g(xo[1 - a] - 0.05) > -0.05 or xo[1 - a] <= spec.K
+    assert kept >= 4
+
+
+@pytest.mark.parametrize("method", ["CMC", "CMC_ADA", "IZ"])
+def test_min_call2_against_two_asset_tree(orc, inputs, method):
+    """Price of the asymmetric two-asset min-call against the product tree
+    (3.770 within its discretisation wobble); for I&Z, each region's boundary
+    where the other asset is high against the tree's critical prices (there
+    the boundary is the one-asset call boundary of the region's asset: the
+    more volatile asset's is higher)."""
+    spec = _asym_min_call2(inputs)
+    tree, bnd = pins.max_call2_tree(spec.S0, spec.K, spec.r, spec.delta, spec.sigma, spec.T, 720, 9,
+                                    want_boundary=True, kind="min")
+    assert tree == pytest.approx(3.770, abs=0.01)
+    m_ = getattr(orc, method)
+    N, n = (128, 2000) if m_ == orc.IZ else (1000, 500)
+    r = orc.price(spec, m_, N, n, 200000, 1, nthreads=NT, max_iter=200)
+    se = r["std_err"]
+    assert abs(r["price"] - tree) <= 3 * se + 0.01 * tree
+    euro = pins.min_call_european(spec.S0, spec.K, spec.r, spec.delta, spec.sigma, spec.T)
+    assert r["price"] > euro + 10 * se
+    if m_ != orc.IZ:
+        return
+    W = orc.rule_width(orc.IZ, 2)
+    for m in (8, 6, 4):
+        for a in (0, 1):
+            others, crit = bnd[m * 80][a]
+            x = orc.points_iz(spec, m, 128, region=a)
+            lo, hi = np.quantile(x[1 - a], [0.75, 0.97])
+            sel = (others > lo) & (others < hi)
+            assert sel.sum() >= 3
+            v = np.log(others[sel] / spec.K)
+
+            def boundary(block):
+                c = r["rules"][m, block * W:(block + 1) * W]
+                return np.exp(c[0] + c[1] * v + c[2] * v * v)
+
+            own = np.abs(boundary(a) / crit[sel] - 1.0)
+            swapped = np.abs(boundary(1 - a) / crit[sel] - 1.0)
+            assert np.all(own < 0.03), (m, a, own)
+            assert swapped.mean() > 2 * own.mean() + 0.005, (m, a, own.mean(), swapped.mean())
+
+
+@pytest.mark.parametrize("case", ["put1", "maxcall3"])
+def test_secant_search_agrees_with_plain_and_saves_iterations(orc, inputs, case):
+    """Both searches stop at |G(s) - s| < eps on the same common-random-number
+    map, so their points agree to a few eps; the secant needs fewer map
+    evaluations in total."""
+    spec = inputs.one_asset_put() if case == "put1" else inputs.max_call(3, 90.0)
+    m = spec.n_dates - 3
+    table = orc.price(spec, orc.IZ, 16, 300, 256, 2, nthreads=NT)["rules"]
+    tot_plain = tot_sec = 0
+    for region in range(orc.iz_regions(spec)):
+        x = orc.points_iz(spec, m, 32, region=region)
+        a = orc.iz_search(spec, table, m, x, 3000, 5, nthreads=NT, region=region, max_iter=300)
+        b = orc.iz_search(spec, table, m, x, 3000, 5, nthreads=NT, region=region, max_iter=300,
+                          mode=orc.SEARCH_SECANT)
+        both = (a["s"] > 0) & (b["s"] > 0)
+        assert both.sum() >= 0.8 * max((a["s"] > 0).sum(), 1)
+        assert np.all(np.abs(a["s"][both] - b["s"][both]) < 0.25), np.max(np.abs(a["s"][both] - b["s"][both]))
+        tot_plain += int(a["iters"].sum())
+        tot_sec += int(b["iters"].sum())
+    assert tot_sec < 0.75 * tot_plain, (tot_sec, tot_plain)
+
+
+def test_secant_price_matches_tree(orc, inputs, c1_tree):
+    spec = inputs.one_asset_put()
+    r = orc.price(spec, orc.IZ, 16, 4000, 200000, 5, nthreads=NT, search_mode=orc.SEARCH_SECANT)
+    p = orc.price(spec, orc.IZ, 16, 4000, 200000, 5, nthreads=NT)
+    assert abs(r["price"] - c1_tree["berm"]) <= 3 * r["std_err"] + 0.01 * c1_tree["berm"]
+    assert r["iz_iterations"] < 0.6 * p["iz_iterations"]

@@ -263,10 +263,11 @@ def iz_form(ctx, bmc, inputs, reps: int = 3) -> dict:
     both precisions, and the J and N_1 sweeps of Tables 2-3 at S0 = 90.  Each
     configuration is priced reps times (same seed); the median wall time is
     reported."""
-    def one(S0, J, N1, prec):
+    def one(S0, J, N1, prec, search=bmc.SEARCH_PLAIN):
         spec = inputs.max_call(3, float(S0))
-        bmc.bmc_price(ctx, spec, bmc.IZ, prec, N=J, n=N1, n_final=1_000_000, seed=1)   # warm
-        runs = [bmc.bmc_price(ctx, spec, bmc.IZ, prec, N=J, n=N1, n_final=1_000_000, seed=1) for _ in range(reps)]
+        kw = dict(N=J, n=N1, n_final=1_000_000, seed=1, iz_search=search)
+        bmc.bmc_price(ctx, spec, bmc.IZ, prec, **kw)   # warm
+        runs = [bmc.bmc_price(ctx, spec, bmc.IZ, prec, **kw) for _ in range(reps)]
         r = runs[-1]
         wall = float(np.median([x["seconds"] for x in runs]))
         calc = float(np.median([x["calc_seconds"] for x in runs]))
@@ -280,7 +281,8 @@ def iz_form(ctx, bmc, inputs, reps: int = 3) -> dict:
     out = {"workload": "call on the max of 3 assets (Table 1 parameters), I&Z with 3 exercise regions, "
                        "eps = 0.01, seed 1",
            "table1_fp32": [one(S0, 128, 5000, bmc.FP32) for S0 in (90, 100, 110)],
-           "table1_fp64": [one(S0, 128, 5000, bmc.FP64) for S0 in (90, 100, 110)]}
+           "table1_fp64": [one(S0, 128, 5000, bmc.FP64) for S0 in (90, 100, 110)],
+           "table1_fp32_secant": [one(S0, 128, 5000, bmc.FP32, bmc.SEARCH_SECANT) for S0 in (90, 100, 110)]}
     sweep = []
     for key, J, N1 in (("J", 128, 5000), ("J", 256, 5000), ("J", 1024, 5000), ("N1", 128, 10000),
                        ("N1", 128, 100000)):

@@ -48,7 +48,15 @@ typedef enum {
 /* Payoffs (Section 2.1-2.2, Section 3.2): arithmetic-basket put
  * (K - mean S)^+, call on the maximum (max S - K)^+, geometric-average put
  * (K - (prod S)^(1/d))^+.  For d = 1 the two puts coincide. */
-typedef enum { BMC_PUT_BASKET = 0, BMC_CALL_MAX = 1, BMC_PUT_GEO = 2 } bmc_payoff;
+typedef enum { BMC_PUT_BASKET = 0, BMC_CALL_MAX = 1, BMC_PUT_GEO = 2, BMC_CALL_MIN = 3 } bmc_payoff;
+
+/* I&Z boundary-point search: the plain fixed point s <- G(s) (Section 2.4), or
+ * secant steps on its residual r(s) = G(s) - s (the paper's "Newton
+ * iterations", Section 2.3): first step plain, then
+ * s - r(s) (s - s_prev) / (r(s) - r(s_prev)) limited to 20 |r(s)|, the plain
+ * step where that is undefined or not positive.  Both stop at the first
+ * evaluated s with |r(s)| < eps and return G(s). */
+typedef enum { BMC_SEARCH_PLAIN = 0, BMC_SEARCH_SECANT = 1 } bmc_search;
 
 /* Pricers: Classification-Monte Carlo (Section 3) with the LogitBoost linear
  * classifier (BMC_CMC) or AdaBoost with decision stumps (BMC_CMC_ADA; Section
@@ -90,6 +98,7 @@ typedef struct {
     int32_t cls_rounds;     /* boosting rounds, <= 64 (0: 8 for BMC_CMC, 64 for BMC_CMC_ADA) */
     int32_t iz_max_iter;    /* I&Z iteration cap (default 100 when 0) */
     double iz_eps;          /* I&Z tolerance in price units (default 0.01 when 0) */
+    int32_t iz_search;      /* bmc_search (BMC_SEARCH_PLAIN when 0) */
 } bmc_opts;
 
 typedef struct {
@@ -290,8 +299,8 @@ bmc_status bmc_fit_rule(bmc_ctx *ctx, const bmc_spec *spec, bmc_rules *rules, in
  * (host, may be NULL) receives the executed path-steps.  Synchronous. */
 bmc_status bmc_iz_search(bmc_ctx *ctx, const bmc_spec *spec, const bmc_rules *rules, int32_t date,
                          int32_t region, const double *x, int64_t J, int64_t n, uint64_t seed,
-                         int32_t precision, double eps, int32_t max_iter, double *s_out,
-                         int32_t *iters, int64_t *steps);
+                         int32_t precision, double eps, int32_t max_iter, int32_t mode,
+                         double *s_out, int32_t *iters, int64_t *steps);
 
 /* Final pricing [mc] (Algorithms 1-2): n_final paths from S0 on the FINAL
  * stream under the rules; FP64 merge to price, sample variance, standard

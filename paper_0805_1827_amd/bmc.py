@@ -15,7 +15,8 @@ import numpy as np
 LIB_PATH = Path(__file__).resolve().parent / "libbmc.so"
 
 OK, EINVAL, ENOTSPD, ENOMEM, EDEVICE, EUNSUPPORTED, ENOCONV, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
-PUT_BASKET, CALL_MAX, PUT_GEO = 0, 1, 2
+PUT_BASKET, CALL_MAX, PUT_GEO, CALL_MIN = 0, 1, 2, 3
+SEARCH_PLAIN, SEARCH_SECANT = 0, 1
 CMC, IZ, CMC_ADA = 0, 1, 2
 FP64, FP32, FP32_KAHAN = 0, 1, 2
 STREAM_OUTER, STREAM_INNER, STREAM_FINAL = 1, 2, 3
@@ -49,7 +50,7 @@ class bmc_spec(C.Structure):
 class bmc_opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("N", C.c_int64), ("n", C.c_int64),
                 ("n_final", C.c_int64), ("seed", C.c_uint64), ("cls_rounds", C.c_int32),
-                ("iz_max_iter", C.c_int32), ("iz_eps", C.c_double)]
+                ("iz_max_iter", C.c_int32), ("iz_eps", C.c_double), ("iz_search", C.c_int32)]
 
 
 class bmc_result(C.Structure):
@@ -128,7 +129,7 @@ def load():
                                             C.c_int32, vp, vp, vp]
     L.bmc_fit_rule.argtypes = [vp, sp, vp, C.c_int32, C.c_int32, vp, vp, C.c_int64, C.c_int32]
     L.bmc_iz_search.argtypes = [vp, sp, vp, C.c_int32, C.c_int32, vp, C.c_int64, C.c_int64, C.c_uint64,
-                                C.c_int32, C.c_double, C.c_int32, vp, vp, C.POINTER(C.c_int64)]
+                                C.c_int32, C.c_double, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int64)]
     L.bmc_final_price.argtypes = [vp, sp, vp, C.c_int64, C.c_uint64, C.c_int32, C.POINTER(bmc_result)]
     L.bmc_philox.argtypes = [vp, C.c_uint32, C.c_uint32, vp, C.c_int64, vp]
     L.bmc_normals.argtypes = [vp, C.c_uint32, C.c_uint32, vp, C.c_int64, C.c_int32, vp]
@@ -248,9 +249,9 @@ def bmc_sync(ctx: Context):
 
 def bmc_price(ctx: Context, spec, method: int = CMC, precision: int = FP64, N: int = 500, n: int = 500,
               n_final: int = 100000, seed: int = 1, cls_rounds: int = 0, iz_max_iter: int = 0,
-              iz_eps: float = 0.0, want_rules: bool = False):
+              iz_eps: float = 0.0, want_rules: bool = False, iz_search: int = SEARCH_PLAIN):
     s = as_spec(spec)
-    o = bmc_opts(method, precision, N, n, n_final, seed, cls_rounds, iz_max_iter, iz_eps)
+    o = bmc_opts(method, precision, N, n, n_final, seed, cls_rounds, iz_max_iter, iz_eps, iz_search)
     res = bmc_result()
     rh = C.c_void_p()
     _check(load().bmc_price(ctx.h, s.ptr, C.byref(o), C.byref(rh) if want_rules else None, C.byref(res)))
@@ -274,7 +275,7 @@ def bmc_price_batch(ctx: Context, specs, opts, want_rules: bool = False):
     for i, o in enumerate(opts):
         oarr[i] = bmc_opts(o.get("method", CMC), o.get("precision", FP64), o.get("N", 500), o.get("n", 500),
                            o.get("n_final", 100000), o.get("seed", 1), o.get("cls_rounds", 0),
-                           o.get("iz_max_iter", 0), o.get("iz_eps", 0.0))
+                           o.get("iz_max_iter", 0), o.get("iz_eps", 0.0), o.get("iz_search", SEARCH_PLAIN))
     res = (bmc_result * count)()
     rh = (C.c_void_p * count)()
     _check(load().bmc_price_batch(ctx.h, count, sarr, oarr, rh if want_rules else None, res))
@@ -445,7 +446,8 @@ def bmc_fit_rule(ctx: Context, spec, rules: Rules, date: int, x, values=None, ro
 
 
 def bmc_iz_search(ctx: Context, spec, rules: Rules, date: int, x, n: int, seed: int,
-                  precision: int = FP64, eps: float = 0.01, max_iter: int = 100, region: int = 0):
+                  precision: int = FP64, eps: float = 0.01, max_iter: int = 100, region: int = 0,
+                  mode: int = 0):
     import torch
     s = as_spec(spec)
     x = x.contiguous()
@@ -454,7 +456,7 @@ def bmc_iz_search(ctx: Context, spec, rules: Rules, date: int, x, n: int, seed: 
     iters = _dev_zeros(J, torch.int32, ctx)
     steps = C.c_int64(0)
     _check(load().bmc_iz_search(ctx.h, s.ptr, rules.h, date, region, _ptr(x), J, n, seed, precision, eps,
-                                max_iter, _ptr(s_out), _ptr(iters), C.byref(steps)))
+                                max_iter, mode, _ptr(s_out), _ptr(iters), C.byref(steps)))
     return s_out, iters, int(steps.value)
 
 

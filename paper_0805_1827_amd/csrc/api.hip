@@ -83,7 +83,7 @@ bmc_status bmc::validate_spec(const bmc_spec* s)
     if (!(s->K > 0.0) || !std::isfinite(s->K)) return fail(BMC_EINVAL, "K must be > 0");
     if (!(s->T > 0.0) || !std::isfinite(s->T)) return fail(BMC_EINVAL, "T must be > 0");
     if (!std::isfinite(s->r)) return fail(BMC_EINVAL, "r must be finite");
-    if (s->payoff < BMC_PUT_BASKET || s->payoff > BMC_PUT_GEO)
+    if (s->payoff < BMC_PUT_BASKET || s->payoff > BMC_CALL_MIN)
         return fail(BMC_EINVAL, "unknown payoff %d", s->payoff);
     double prev = 0.0;
     for (int k = 0; k < s->n_dates; ++k) {
@@ -252,7 +252,7 @@ extern "C" bmc_status bmc_sync(bmc_ctx* ctx)
 static double never_value(int method, int payoff)
 {
     if (method != BMC_IZ) return 0.0;   // classifier rows of zeros: F = 0, never exercise
-    return payoff == BMC_CALL_MAX ? 1e300 : -1e300;
+    return (payoff == BMC_CALL_MAX || payoff == BMC_CALL_MIN) ? 1e300 : -1e300;
 }
 
 static bmc_status rules_alloc(bmc_ctx* ctx, int method, int d, int n_dates, int payoff,
@@ -797,21 +797,23 @@ extern "C" bmc_status bmc_sample_points(bmc_ctx* ctx, const bmc_spec* spec, int3
 
 bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, const bmc_rules* rules,
                                int date, int region, int nreg, const double* x, int64_t J, uint32_t n,
-                               uint32_t seed, int prec, double eps, int max_iter, double* s_out, int32_t* iters,
-                               int64_t* steps_out, const Tuning* tune)
+                               uint32_t seed, int prec, double eps, int max_iter, int mode, double* s_out,
+                               int32_t* iters, int64_t* steps_out, const Tuning* tune)
 {
     const int d = spec->d;
     const int64_t Jr = J;   // points per region
     J *= nreg;              // columns of all regions
     hipError_t e;
-    // x_work [d][J], s_cur, cont [J], steps [J], steps_acc [J], ids x2, counters
-    const size_t need = sizeof(double) * ((size_t)d * J + 3 * J) + sizeof(unsigned long long) * J +
+    // x_work [d][J], s_cur, s_prev, r_prev, cont [J], steps [J], steps_acc [J], ids x2, counters
+    const size_t need = sizeof(double) * ((size_t)d * J + 5 * J) + sizeof(unsigned long long) * J +
                         sizeof(int32_t) * 2 * J + 64;
     if ((e = ctx->iz.ensure(need))) return hip_fail(e, "search buffers");
     if ((e = ctx->counters.ensure(64))) return hip_fail(e, "counters");
     char* c = (char*)ctx->iz.ptr;
     double* x_work = (double*)c; c += sizeof(double) * d * J;
     double* s_cur = (double*)c; c += sizeof(double) * J;
+    double* s_prev = (double*)c; c += sizeof(double) * J;
+    double* r_prev = (double*)c; c += sizeof(double) * J;
     double* cont = (double*)c; c += sizeof(double) * J;
     int64_t* stp = (int64_t*)c; c += sizeof(int64_t) * J;
     unsigned long long* acc = (unsigned long long*)c; c += sizeof(unsigned long long) * J;
@@ -835,8 +837,8 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
                                  nullptr, stp, nullptr, nullptr, tune, (uint32_t)region,
                                  nreg > 1 ? (uint32_t)Jr : 0u);
         if (st) return st;
-        if ((e = launch_iz_update(ds, d, region, nreg, Jr, cont, stp, ids_in, n_in, ids_out, n_out, s_cur, x_work, s_out,
-                                  iters, acc, eps, max_iter, it, ctx->stream)))
+        if ((e = launch_iz_update(ds, d, region, nreg, Jr, cont, stp, ids_in, n_in, ids_out, n_out, s_cur, s_prev,
+                                  r_prev, x_work, s_out, iters, acc, eps, max_iter, mode, it, ctx->stream)))
             return hip_fail(e, "search update");
         if ((it & 3) == 3 || it == max_iter - 1) {
             int32_t left = 0;
@@ -861,8 +863,8 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
 
 extern "C" bmc_status bmc_iz_search(bmc_ctx* ctx, const bmc_spec* spec, const bmc_rules* rules, int32_t date,
                                     int32_t region, const double* x, int64_t J, int64_t n, uint64_t seed,
-                                    int32_t precision, double eps, int32_t max_iter, double* s_out,
-                                    int32_t* iters, int64_t* steps)
+                                    int32_t precision, double eps, int32_t max_iter, int32_t mode,
+                                    double* s_out, int32_t* iters, int64_t* steps)
 {
     if (!ctx || !x || !s_out || !iters) return fail(BMC_EINVAL, "NULL argument");
     (void)hipSetDevice(ctx->device);
@@ -874,8 +876,9 @@ extern "C" bmc_status bmc_iz_search(bmc_ctx* ctx, const bmc_spec* spec, const bm
     if (date < 1 || date >= spec->n_dates) return fail(BMC_EINVAL, "date %d outside 1..%d", date, spec->n_dates - 1);
     if (J < 1 || J > 0x7FFFFFFF || n < 2 || n > 0x7FFFFFFF) return fail(BMC_EINVAL, "J or n out of range");
     if (!(eps > 0.0) || max_iter < 1) return fail(BMC_EINVAL, "eps must be > 0 and max_iter >= 1");
+    if (mode != BMC_SEARCH_PLAIN && mode != BMC_SEARCH_SECANT) return fail(BMC_EINVAL, "unknown search mode %d", mode);
     st = iz_search_impl(ctx, ctx->spec.ptr, spec, rules, date, region, 1, x, J, (uint32_t)n, (uint32_t)seed,
-                        precision, eps, max_iter, s_out, iters, steps, nullptr);
+                        precision, eps, max_iter, mode, s_out, iters, steps, nullptr);
     if (st) return st;
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e) return hip_fail(e, "stream sync");

@@ -137,7 +137,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
     }
     if ((int)threadIdx.x < D)
         lx[threadIdx.x] = (int)threadIdx.x < d ? (R)log(a.x[(int64_t)threadIdx.x * a.N + j])
-                                                : (payk == PUT_GEO ? R(0) : R(-1e30));
+                                                : (payk == PUT_GEO ? R(0) : payk == CALL_MIN ? R(1e30) : R(-1e30));
     if constexpr (LC) {
         // FP32: row-major A[i][l] (matrix-core operand rows); FP64: column-major
         // A[l][i] (consecutive rows of one column in one read).  Zero beyond d.
@@ -160,7 +160,8 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
         slot += r;
         pj = j - r * a.region_pts;
     }
-    const bool call_dir = payk == CALL_MAX;
+    const bool call_dir = payk == CALL_MAX || payk == CALL_MIN;
+    const bool min_dir = payk == CALL_MIN;
     const int W1 = rule_width(IZ, d);   // one I&Z region's boundary block
     const R K = S.K, lnK = S.lnK, invK = S.invK, inv_d = S.inv_d;
 
@@ -244,13 +245,14 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
             } else {
                 if constexpr (has_iz_kernel<D, EXACT>()) {
                     if (call_dir) {
-                        // region of the largest asset (the first one on ties);
-                        // exercise above that region's boundary
+                        // region of the largest (max-call) or smallest (min-call)
+                        // asset, the first one on ties; exercise above that
+                        // region's boundary
                         int reg = 0;
                         R mx = ls[0];
 #pragma unroll
                         for (int i = 1; i < D; ++i)
-                            if (i < d && ls[i] > mx) {
+                            if (i < d && (min_dir ? ls[i] < mx : ls[i] > mx)) {
                                 mx = ls[i];
                                 reg = i;
                             }

@@ -11,9 +11,11 @@ namespace bmc {
 constexpr int D_MAX = 64;
 constexpr int NT_MAX = 512;
 
-enum { PUT_BASKET = 0, CALL_MAX = 1, PUT_GEO = 2 };
+enum { PUT_BASKET = 0, CALL_MAX = 1, PUT_GEO = 2, CALL_MIN = 3 };
 // CMC with the LogitBoost linear classifier, I&Z, CMC with AdaBoost stumps
 enum { CMC = 0, IZ = 1, ADA = 2 };
+// I&Z boundary-point search: plain fixed point or secant steps on its residual
+enum { SEARCH_PLAIN = 0, SEARCH_SECANT = 1 };
 // AdaBoost stumps: bins per feature, largest number of rounds a rule row holds
 enum { ADA_BINS = 64, ADA_TMAX = 64 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP32_KAHAN = 2 };
@@ -157,6 +159,12 @@ __device__ __forceinline__ R payoff(int kind, int d, R K, R inv_d, const R (&x)[
         for (int i = 1; i < D; ++i)
             if (i < d) mx = fmax(mx, x[i]);
         v = fexp(mx) - K;
+    } else if (kind == CALL_MIN) {
+        R mn = x[0];
+#pragma unroll
+        for (int i = 1; i < D; ++i)
+            if (i < d) mn = fmin(mn, x[i]);
+        v = fexp(mn) - K;
     } else if (kind == PUT_GEO) {
         R s = x[0];
 #pragma unroll
@@ -251,10 +259,10 @@ __host__ __device__ __forceinline__ int rule_width(int method, int d)
 }
 
 // I&Z exercise regions (Section 2.2): one per asset for the max-call (asset i
-// the largest), one for the put family.
+// the largest) and the min-call (asset i the smallest), one for the put family.
 __host__ __device__ __forceinline__ int iz_regions(int payoff, int d)
 {
-    return payoff == CALL_MAX ? d : 1;
+    return (payoff == CALL_MAX || payoff == CALL_MIN) ? d : 1;
 }
 
 // Rule row width: the CMC weights, or one I&Z boundary block per region

@@ -206,7 +206,7 @@ __global__ void k_fitiz_solve(const DevSpec* __restrict__ s, int p, int ntiles, 
     __shared__ int flag;
     __shared__ double lam, cnt;
     // no converged point: a boundary no price crosses (puts below, the call above)
-    const double never = s->f64.payoff == CALL_MAX ? 1e300 : -1e300;
+    const double never = (s->f64.payoff == CALL_MAX || s->f64.payoff == CALL_MIN) ? 1e300 : -1e300;
     const int npairs = p * (p + 1) / 2;
     double* A = Awork;
     double* b = Awork + npairs;

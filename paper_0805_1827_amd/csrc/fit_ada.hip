@@ -60,6 +60,10 @@ __device__ inline double ada_payoff(const SpecT<double>& S, const double* __rest
         double mx = exp(log(x[j]));
         for (int i = 1; i < d; ++i) mx = fmax(mx, exp(log(x[i * N + j])));
         v = mx - S.K;
+    } else if (S.payoff == CALL_MIN) {
+        double mn = exp(log(x[j]));
+        for (int i = 1; i < d; ++i) mn = fmin(mn, exp(log(x[i * N + j])));
+        v = mn - S.K;
     } else if (S.payoff == PUT_GEO) {
         double sl = 0.0;
         for (int i = 0; i < d; ++i) sl += log(x[i * N + j]);

@@ -189,6 +189,10 @@ __device__ inline double point_payoff(const SpecT<double>& S, const double* __re
         double mx = log(x[j]);
         for (int i = 1; i < d; ++i) mx = fmax(mx, log(x[i * N + j]));
         v = exp(mx) - S.K;
+    } else if (S.payoff == CALL_MIN) {
+        double mn = log(x[j]);
+        for (int i = 1; i < d; ++i) mn = fmin(mn, log(x[i * N + j]));
+        v = exp(mn) - S.K;
     } else if (S.payoff == PUT_GEO) {
         double sl = 0.0;
         for (int i = 0; i < d; ++i) sl += log(x[i * N + j]);

@@ -504,10 +504,11 @@ hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int regio
 __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region0, int64_t J, int64_t Jt,
                             const double* __restrict__ cont, const int64_t* __restrict__ steps,
                             const int32_t* __restrict__ ids_in, const int32_t* __restrict__ n_in,
-                            int32_t* ids_out, int32_t* n_out, double* s_cur, double* x_work,
-                            double* s_out, int32_t* iters, unsigned long long* steps_acc,
-                            double eps, int max_iter, int it)
+                            int32_t* ids_out, int32_t* n_out, double* s_cur, double* s_prev, double* r_prev,
+                            double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
+                            double eps, int max_iter, int mode, int it)
 {
+#pragma clang fp contract(off)
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= *n_in) return;
     const int64_t j = ids_in[slot];
@@ -516,7 +517,7 @@ __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region0, i
     const double c = cont[j];
     steps_acc[j] += (unsigned long long)steps[j];
     double snew;
-    if (S.payoff == CALL_MAX) {
+    if (S.payoff == CALL_MAX || S.payoff == CALL_MIN) {
         snew = S.K + c;
     } else if (!(S.K - c > 0.0)) {
         snew = -1.0;
@@ -532,31 +533,51 @@ __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region0, i
     const int it1 = it + 1;
     iters[j] = it1;
     if (!(snew > 0.0) || !isfinite(snew)) { s_out[j] = -1.0; return; }
-    if (fabs(snew - s_cur[j]) < eps) {
-        double others = 0.0;
-        if (S.payoff == CALL_MAX)
+    const double sv = s_cur[j], res = snew - sv;
+    if (fabs(res) < eps) {
+        // inside the region: above every other asset (max-call), below
+        // every other asset (min-call)
+        double omax = 0.0, omin = INFINITY;
+        if (S.payoff == CALL_MAX || S.payoff == CALL_MIN)
             for (int i = 0; i < d; ++i)
-                if (i != region) others = fmax(others, x_work[i * Jt + j]);
-        s_out[j] = snew > others ? snew : -1.0;
+                if (i != region) {
+                    omax = fmax(omax, x_work[i * Jt + j]);
+                    omin = fmin(omin, x_work[i * Jt + j]);
+                }
+        const bool outside = (S.payoff == CALL_MAX && snew <= omax) || (S.payoff == CALL_MIN && snew >= omin);
+        s_out[j] = outside ? -1.0 : snew;
         return;
     }
     if (it1 >= max_iter) { s_out[j] = -1.0; return; }
-    s_cur[j] = snew;
-    x_work[region * Jt + j] = snew;
+    double next = snew;
+    if (mode == SEARCH_SECANT && it > 0) {
+        const double den = res - r_prev[j];
+        if (den != 0.0) {
+            double step = -res * (sv - s_prev[j]) / den;
+            const double lim = 20.0 * fabs(res);
+            if (step > lim) step = lim;
+            if (step < -lim) step = -lim;
+            if (isfinite(step) && sv + step > 0.0) next = sv + step;
+        }
+    }
+    s_prev[j] = sv;
+    r_prev[j] = res;
+    s_cur[j] = next;
+    x_work[region * Jt + j] = next;
     const int pos = atomicAdd(n_out, 1);
     ids_out[pos] = (int32_t)j;
 }
 
 hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* cont,
                             const int64_t* steps, const int32_t* ids_in, const int32_t* n_in,
-                            int32_t* ids_out, int32_t* n_out, double* s_cur, double* x_work,
-                            double* s_out, int32_t* iters, unsigned long long* steps_acc,
-                            double eps, int max_iter, int it, hipStream_t st)
+                            int32_t* ids_out, int32_t* n_out, double* s_cur, double* s_prev, double* r_prev,
+                            double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
+                            double eps, int max_iter, int mode, int it, hipStream_t st)
 {
     const int64_t Jt = (int64_t)nreg * J;
     hipLaunchKernelGGL(k_iz_update, dim3((unsigned)((Jt + 255) / 256)), dim3(256), 0, st, s, d, region0, J, Jt,
-                       cont, steps, ids_in, n_in, ids_out, n_out, s_cur, x_work, s_out, iters,
-                       steps_acc, eps, max_iter, it);
+                       cont, steps, ids_in, n_in, ids_out, n_out, s_cur, s_prev, r_prev, x_work, s_out, iters,
+                       steps_acc, eps, max_iter, mode, it);
     return hipGetLastError();
 }
 

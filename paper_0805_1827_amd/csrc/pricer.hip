@@ -67,6 +67,9 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     const int rounds = opts->cls_rounds > 0 ? opts->cls_rounds : (method == BMC_CMC_ADA ? ADA_TMAX : 8);
     const int max_iter = opts->iz_max_iter > 0 ? opts->iz_max_iter : 100;
     const double eps = opts->iz_eps > 0.0 ? opts->iz_eps : 0.01;
+    const int search = opts->iz_search;
+    if (search != BMC_SEARCH_PLAIN && search != BMC_SEARCH_SECANT)
+        return fail(BMC_EINVAL, "unknown I&Z search mode %d", search);
     if (rounds > 64) return fail(BMC_EINVAL, "cls_rounds must be <= 64");
     if (method == BMC_IZ && opts->N > 65536) return fail(BMC_EUNSUPPORTED, "I&Z supports N <= 65536 lattice points");
     // spec setup status and the step total come back with the final sums (one sync)
@@ -139,8 +142,8 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
             if ((st = sample_points_impl(ctx, ds, spec, BMC_IZ, m, N, seed, x, B, 0, regions))) break;
             timer.mark(PH_CALC);
             int64_t stp = 0;
-            st = iz_search_impl(ctx, ds, spec, rules, m, 0, regions, x, N, n, seed, prec, eps, max_iter, s_out,
-                                iters, &stp, tune);
+            st = iz_search_impl(ctx, ds, spec, rules, m, 0, regions, x, N, n, seed, prec, eps, max_iter, search,
+                                s_out, iters, &stp, tune);
             if (st) break;
             iz_steps += stp;
             timer.mark(PH_FIT);

@@ -103,8 +103,8 @@ bmc_status sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec*
 // hold nreg J points side by side, as sample_points_impl lays them out.
 bmc_status iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec,
                           const bmc_rules* rules, int date, int region, int nreg, const double* x, int64_t J,
-                          uint32_t n, uint32_t seed, int prec, double eps, int max_iter, double* s_out,
-                          int32_t* iters, int64_t* steps_out, const Tuning* tune);
+                          uint32_t n, uint32_t seed, int prec, double eps, int max_iter, int mode,
+                          double* s_out, int32_t* iters, int64_t* steps_out, const Tuning* tune);
 bmc_status final_price_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec,
                             const bmc_rules* rules, int64_t n_final, uint32_t seed, int prec,
                             double* host_sums, const Tuning* tune, bool sync = true);

@@ -70,6 +70,7 @@ def specs(inputs):
         "put1": inputs.one_asset_put(),
         "geo5": inputs.geometric_put5(),
         "maxcall3": inputs.max_call(3, 100.0),
+        "mincall2": inputs.min_call(2, [100.0, 110.0], sigma=[0.2, 0.3]),
         "basket2": inputs.basket(2, 100.0, 100.0, 0.05, 0.0, [0.2, 0.3], 0.3, 1.0, 6, inputs.PUT_BASKET),
         "wide12": inputs.basket(12, 100.0, 100.0, 0.05, 0.0, rng.uniform(0.15, 0.35, 12),
                                 inputs.wishart_corr(12, rng), 1.0, 5, inputs.PUT_GEO),
@@ -132,7 +133,8 @@ def test_continuation_under_stump_rules(bmc, ctx, orc, torch_mod, inputs, case):
         assert np.array_equal(st.cpu().numpy(), ref["steps"]), m
 
 
-@pytest.mark.parametrize("case,N,n", [("put1", 500, 500), ("geo5", 512, 256), ("maxcall3", 400, 300)])
+@pytest.mark.parametrize("case,N,n", [("put1", 500, 500), ("geo5", 512, 256), ("maxcall3", 400, 300),
+                                      ("mincall2", 400, 300)])
 def test_price_end_to_end_fp64(bmc, ctx, orc, torch_mod, inputs, case, N, n):
     spec = specs(inputs)[case]
     res, rules = bmc.bmc_price(ctx, spec, bmc.CMC_ADA, bmc.FP64, N=N, n=n, n_final=50000, seed=1, want_rules=True)

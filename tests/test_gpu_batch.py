@@ -143,3 +143,24 @@ def test_batch_graph_replays_match_direct(bmc, ctx, inputs):
         assert (captures, replays) == (1, 3)
     finally:
         gctx.close()
+
+
+def test_batch_min_call_and_padded_buckets(bmc, ctx, inputs):
+    """Calls on the minimum in shared launches, including padded buckets
+    (d = 34 and 45: padded assets carry the neutral +1e30 log-price)."""
+    rng = np.random.default_rng(17)
+    specs = [inputs.min_call(2, [100.0, 110.0], sigma=[0.2, 0.3]),
+             inputs.min_call(5, 120.0, sigma=rng.uniform(0.15, 0.3, 5), n_dates=6),
+             inputs.basket(34, 200.0, 100.0, 0.05, 0.1, rng.uniform(0.1, 0.3, 34), inputs.wishart_corr(34, rng),
+                           3.0, 4, inputs.CALL_MIN),
+             inputs.basket(45, 200.0, 100.0, 0.05, 0.1, rng.uniform(0.1, 0.3, 45), inputs.wishart_corr(45, rng),
+                           3.0, 3, inputs.CALL_MIN),
+             inputs.geometric_put5()]
+    opts = [dict(method=bmc.CMC, precision=p, N=N, n=n, n_final=20000, seed=70 + k)
+            for k, (p, N, n) in enumerate([(bmc.FP64, 128, 512), (bmc.FP32, 100, 1000), (bmc.FP32, 64, 512),
+                                            (bmc.FP64, 70, 300), (bmc.FP32, 96, 700)])]
+    res = bmc.bmc_price_batch(ctx, specs, opts)
+    for k, (s, o) in enumerate(zip(specs, opts)):
+        alone = bmc.bmc_price(ctx, s, **o)
+        assert res[k]["price"] == alone["price"] and res[k]["inner_path_steps"] == alone["inner_path_steps"], k
+        assert res[k]["price"] > 0.0, k            # every option pays on some paths

@@ -139,12 +139,17 @@ def asym_max_call2(inputs):
     return inputs.basket(2, [100.0, 90.0], 100.0, 0.05, 0.1, [0.2, 0.3], 0.0, 3.0, 9, inputs.CALL_MAX)
 
 
+def asym_min_call2(inputs):
+    return inputs.min_call(2, [100.0, 110.0], sigma=[0.2, 0.3])
+
+
 def test_iz_lattice_parity(bmc, ctx, orc, torch_mod, inputs):
     for spec, J in ((inputs.geometric_put5(), 256), (inputs.one_asset_put(), 8),
                     (inputs.basket(3, 100.0, 100.0, 0.05, 0.0, 0.25, 0.2, 1.0, 6, inputs.PUT_BASKET), 97),
                     (inputs.basket(3, [90.0, 100.0, 115.0], 100.0, 0.05, 0.1, [0.2, 0.25, 0.3], 0.3, 3.0, 9,
                                    inputs.CALL_MAX), 61),
-                    (asym_max_call2(inputs), 20)):
+                    (asym_max_call2(inputs), 20), (asym_min_call2(inputs), 33),
+                    (inputs.min_call(3, [95.0, 100.0, 108.0], sigma=[0.2, 0.3, 0.25]), 40)):
         assert bmc.bmc_iz_regions(spec) == orc.iz_regions(spec)
         for region in range(bmc.bmc_iz_regions(spec)):
             for m in (1, spec.n_dates - 1):
@@ -177,11 +182,12 @@ def _small_rules(orc, spec, method=0, N=128, n=128):
     return orc.price(spec, method, N, n, 256, 11, nthreads=NT_CPU)["rules"]
 
 
-@pytest.mark.parametrize("case", ["geo5", "maxcall3", "basket4"])
+@pytest.mark.parametrize("case", ["geo5", "maxcall3", "basket4", "mincall3"])
 def test_continuation_multi_asset(bmc, ctx, orc, torch_mod, inputs, case):
     spec = {"geo5": inputs.geometric_put5(), "maxcall3": inputs.max_call(3, 100.0),
             "basket4": inputs.basket(4, [95, 100, 105, 110], 100.0, 0.05, [0.0, 0.01, 0.02, 0.0],
-                                     [0.2, 0.25, 0.3, 0.15], 0.4, 1.0, 8, inputs.PUT_BASKET)}[case]
+                                     [0.2, 0.25, 0.3, 0.15], 0.4, 1.0, 8, inputs.PUT_BASKET),
+            "mincall3": inputs.min_call(3, [100.0, 110.0, 120.0], sigma=[0.2, 0.3, 0.25])}[case]
     table = _small_rules(orc, spec)
     for m, n in ((1, 1000), (spec.n_dates // 2, 4096), (spec.n_dates - 1, 777)):
         x = orc.points_cmc(spec, m, 48, 3)
@@ -191,14 +197,16 @@ def test_continuation_multi_asset(bmc, ctx, orc, torch_mod, inputs, case):
         assert_same_labels(orc, spec, x, c, ref["cont"], what=f"{case} labels m={m}")
 
 
-@pytest.mark.parametrize("d,payoff", [(12, 0), (20, 1), (40, 2)])
+@pytest.mark.parametrize("d,payoff", [(12, 0), (20, 1), (40, 2), (34, 3), (13, 3)])
 def test_continuation_large_d(bmc, ctx, orc, torch_mod, inputs, d, payoff):
-    """Dimension buckets (runtime d below the compiled bound), Wishart correlation."""
+    """Dimension buckets (runtime d below the compiled bound, so padded assets
+    carry the payoff's neutral log-price), Wishart correlation."""
     rng = np.random.default_rng(d)
     sigma = rng.uniform(0.1, 0.4, size=d)
     rho = inputs.wishart_corr(d, rng)
-    T, delta = (3.0, 0.1) if payoff == 1 else (1.0, 0.0)
-    spec = inputs.basket(d, 100.0, 100.0, 0.05, delta, sigma, rho, T, 6, payoff)
+    T, delta = (3.0, 0.1) if payoff in (1, 3) else (1.0, 0.0)
+    S0 = 130.0 if payoff == 3 else 100.0          # the min of 34 assets: start in the money
+    spec = inputs.basket(d, S0, 100.0, 0.05, delta, sigma, rho, T, 6, payoff)
     table = _small_rules(orc, spec, N=96, n=64)
     for m in (1, 5):
         x = orc.points_cmc(spec, m, 24, 2)
@@ -318,14 +326,19 @@ def test_iz_fit_without_points_never_exercises(bmc, ctx, orc, torch_mod, inputs)
 
 # --- I&Z search -------------------------------------------------------------------
 
-@pytest.mark.parametrize("case", ["put1", "geo5", "maxcall3", "maxcall2"])
-def test_iz_search_parity(bmc, ctx, orc, torch_mod, inputs, case):
+@pytest.mark.parametrize("mode", ["plain", "secant"])
+@pytest.mark.parametrize("case", ["put1", "geo5", "maxcall3", "maxcall2", "mincall2"])
+def test_iz_search_parity(bmc, ctx, orc, torch_mod, inputs, case, mode):
     """Per region: the searched asset, the region's counter word, the rules
     of later dates (every region's block exercised on the inner paths) and
-    the drop of fixed points outside the region."""
+    the drop of fixed points outside the region; plain and secant steps."""
     spec = {"put1": inputs.one_asset_put(), "geo5": inputs.geometric_put5(),
-            "maxcall3": inputs.max_call(3, 100.0), "maxcall2": asym_max_call2(inputs)}[case]
-    J, n = {"put1": (8, 3000), "geo5": (40, 1500), "maxcall3": (24, 800), "maxcall2": (40, 1000)}[case]
+            "maxcall3": inputs.max_call(3, 100.0), "maxcall2": asym_max_call2(inputs),
+            "mincall2": asym_min_call2(inputs)}[case]
+    J, n = {"put1": (8, 3000), "geo5": (40, 1500), "maxcall3": (24, 800), "maxcall2": (40, 1000),
+            "mincall2": (40, 1000)}[case]
+    md = bmc.SEARCH_SECANT if mode == "secant" else bmc.SEARCH_PLAIN
+    assert md == (orc.SEARCH_SECANT if mode == "secant" else orc.SEARCH_PLAIN)
     table = orc.empty_rules(spec, orc.IZ)
     if case != "put1":
         table = orc.price(spec, orc.IZ, 16, 300, 256, 2, nthreads=NT_CPU)["rules"]
@@ -334,13 +347,13 @@ def test_iz_search_parity(bmc, ctx, orc, torch_mod, inputs, case):
         for region in range(orc.iz_regions(spec)):
             x = orc.points_iz(spec, m, J, region=region)
             rules = gpu_rules(bmc, ctx, spec, bmc.IZ, table)
-            s, it, steps = bmc.bmc_iz_search(ctx, spec, rules, m, dev(torch_mod, x), n, 2, region=region)
-            ref = orc.iz_search(spec, table, m, x, n, 2, nthreads=NT_CPU, region=region)
+            s, it, steps = bmc.bmc_iz_search(ctx, spec, rules, m, dev(torch_mod, x), n, 2, region=region, mode=md)
+            ref = orc.iz_search(spec, table, m, x, n, 2, nthreads=NT_CPU, region=region, mode=md)
             assert np.array_equal(host(it), ref["iters"]), (m, region)
             assert_close(host(s), ref["s"], spec.K, what=f"s* m={m} region={region}")
             assert steps == ref["steps"]
             dropped += int(np.sum(ref["s"] <= 0))
-    assert case != "maxcall2" or dropped < 2 * 2 * J
+    assert case not in ("maxcall2", "mincall2") or dropped < 2 * 2 * J
 
 
 # --- final pricing and the whole pricer ----------------------------------------------
@@ -356,16 +369,22 @@ def test_final_price_parity(bmc, ctx, orc, torch_mod, c1_rules):
 
 
 @pytest.mark.parametrize("case", ["c1_cmc", "c1_iz", "geo5_cmc", "geo5_iz", "maxcall3_cmc", "maxcall3_iz",
-                                  "maxcall2_iz"])
+                                  "maxcall2_iz", "mincall2_cmc", "mincall2_iz", "c1_izsec", "maxcall3_izsec",
+                                  "mincall2_izsec"])
 def test_price_end_to_end_fp64(bmc, ctx, orc, torch_mod, inputs, case):
     spec = {"c1": inputs.one_asset_put(), "geo5": inputs.geometric_put5(),
-            "maxcall3": inputs.max_call(3, 100.0), "maxcall2": asym_max_call2(inputs)}[case.split("_")[0]]
+            "maxcall3": inputs.max_call(3, 100.0), "maxcall2": asym_max_call2(inputs),
+            "mincall2": asym_min_call2(inputs)}[case.split("_")[0]]
     method = bmc.CMC if case.endswith("cmc") else bmc.IZ
+    search = bmc.SEARCH_SECANT if case.endswith("izsec") else bmc.SEARCH_PLAIN
     N, n, nf = {"c1_cmc": (500, 500, 100000), "c1_iz": (16, 500, 100000), "geo5_cmc": (512, 512, 100000),
                 "geo5_iz": (48, 400, 50000), "maxcall3_cmc": (400, 300, 50000), "maxcall3_iz": (32, 300, 50000),
-                "maxcall2_iz": (48, 400, 50000)}[case]
-    res, rules = bmc.bmc_price(ctx, spec, method, bmc.FP64, N=N, n=n, n_final=nf, seed=1, want_rules=True)
-    ref = orc.price(spec, method, N, n, nf, 1, nthreads=NT_CPU)
+                "maxcall2_iz": (48, 400, 50000), "mincall2_cmc": (400, 300, 50000),
+                "mincall2_iz": (48, 400, 50000), "c1_izsec": (16, 500, 100000),
+                "maxcall3_izsec": (32, 300, 50000), "mincall2_izsec": (48, 400, 50000)}[case]
+    res, rules = bmc.bmc_price(ctx, spec, method, bmc.FP64, N=N, n=n, n_final=nf, seed=1, want_rules=True,
+                               iz_search=search)
+    ref = orc.price(spec, method, N, n, nf, 1, nthreads=NT_CPU, search_mode=search)
     assert_close(res["price"], ref["price"], spec.K, what="price")
     table = bmc.rules_table(rules)
     for m in range(1, spec.n_dates):
@@ -446,6 +465,14 @@ def test_repeat_is_bit_identical(bmc, ctx, torch_mod, inputs):
 
 def test_error_statuses(bmc, ctx, torch_mod, inputs):
     spec = inputs.geometric_put5()
+    odd = inputs.geometric_put5()
+    odd.payoff = 4
+    with pytest.raises(bmc.BmcError) as e:
+        bmc.bmc_price(ctx, odd, N=8, n=8, n_final=8)
+    assert e.value.status == bmc.EINVAL
+    with pytest.raises(bmc.BmcError) as e:
+        bmc.bmc_price(ctx, spec, bmc.IZ, N=8, n=8, n_final=8, iz_search=2)
+    assert e.value.status == bmc.EINVAL
     bad = inputs.basket(3, 100.0, 100.0, 0.05, 0.0, 0.2, 0.0, 1.0, 4, inputs.PUT_GEO)
     bad.rho = np.array([[1.0, 0.9, 0.9], [0.9, 1.0, -0.9], [0.9, -0.9, 1.0]])
     with pytest.raises(bmc.BmcError) as e:

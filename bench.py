@@ -93,7 +93,7 @@ def percentile(xs, q):
 
 
 TRAFFIC_FILE = ROOT / "profiles" / "k_cont_geo5_fp32_traffic.json"
-KERNEL_SOURCES = ("cont_kernel.hpp", "device.hpp", "internal.hpp")
+KERNEL_SOURCES = ("cont_kernel.hpp", "device.hpp", "cont_args.hpp")
 
 
 def measured_traffic():
@@ -312,6 +312,7 @@ def main():
                     help="length of the Poisson arrival window of the serving form (0 disables it)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="arrival rate of the serving form (1/s)")
     ap.add_argument("--no-iz", action="store_true", help="skip the I&Z max-call form (Tables 1-3)")
+    ap.add_argument("--no-ada", action="store_true", help="skip the AdaBoost-stump line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the pricer runs on a single device and this build has no "
@@ -401,8 +402,8 @@ def main():
         out["batch"] = batch_form(bctx, bmc, inputs, args.batch, args.batch_N, 100_000)
         bctx.close()
     # the same workload with the AdaBoost-stump classifier (64 rounds)
-    ada = [bmc.bmc_price(ctx, spec, bmc.CMC_ADA, bmc.FP32, **kw) for _ in range(3)]
-    out["cmc_adaboost"] = {
+    ada = [] if args.no_ada else [bmc.bmc_price(ctx, spec, bmc.CMC_ADA, bmc.FP32, **kw) for _ in range(3)]
+    out["cmc_adaboost"] = None if args.no_ada else {
         "workload": "as the headline, CMC with AdaBoost stumps (64 rounds, 64 bins) instead of LogitBoost",
         "ms_per_price": 1e3 * float(np.median([r["seconds"] for r in ada])),
         "fit_ms_per_price": 1e3 * float(np.median([r["fit_seconds"] for r in ada])),

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cont_args.hpp"
 #include "device.hpp"
 
 namespace bmc {
@@ -16,28 +17,6 @@ struct HostSpecPack {
     double S0[D_MAX], delta[D_MAX], sigma[D_MAX];
     double rho[D_MAX * D_MAX];
     double dates[NT_MAX];
-};
-
-// One continuation launch: points (ids or 0..N-1) x chunks of paths.
-struct ContArgs {
-    const DevSpec* spec;
-    const void* rules;        // R[(NT+1) * width], row k = date k
-    const double* x;          // SoA points [d][N]
-    int64_t N;                // row stride of x
-    const int32_t* ids;       // active point ids, or null for 0..N-1
-    const int32_t* n_ids;     // device count of ids, or null
-    uint32_t n;               // paths per point
-    int32_t m;                // start date
-    int32_t method;           // CMC / IZ
-    int32_t width;            // rule row width
-    uint32_t paths_per_wg;    // paths of one workgroup (a chunk)
-    uint32_t nchunk;          // chunks per point
-    uint32_t k0, k1;          // Philox key
-    uint32_t slot;            // fourth Philox counter word (I&Z region, else 0)
-    uint32_t region_pts;      // > 0: points of several I&Z regions side by side, region_pts
-                              // each; point j counts as point j % region_pts of
-                              // region slot + j / region_pts in the counters
-    double* part;             // [N * nchunk * 3]: sum, sum of squares, steps
 };
 
 // Finalize of one task inside a multi-task launch (see launch_finalize).
@@ -75,40 +54,6 @@ hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStre
                         const uint32_t* slots = nullptr);
 hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, size_t lds,
                        hipStream_t st);
-// Dimension buckets: every d <= 32 has its own instantiation (bucket_exact);
-// larger d share a bound D with dim_floor(D) < d <= D (36, 40, then
-// multiples of 8) and pad the path state to D.  For d >= 9 the correlation
-// coefficients live in LDS and, in FP32, the correlation runs on the matrix
-// cores in chunks of four assets.
-__host__ __device__ constexpr bool bucket_exact(int D) { return D <= 32; }
-__host__ __device__ constexpr int dim_floor(int D) { return bucket_exact(D) ? D - 1 : (D <= 40 ? D - 4 : D - 8); }
-int cont_bucket(int d);
-
-// Row stride of the rule rows in LDS: padded buckets widen classifier rows
-// to 2D+3 (zero weights for the padded assets).
-__host__ __device__ inline int cont_rule_stride(int D, int width)
-{
-    return !bucket_exact(D) && width < 2 * D + 3 ? 2 * D + 3 : width;
-}
-
-// LDS bytes of a continuation job: discount table (double), then in the
-// stepping precision: log-point [D_MAX], dt and sqrt(dt) [NT+1], rule rows
-// [(NT+1) stride], and for D >= 9 the correlation coefficients [D4][D4]
-// (D4 = D rounded up to a multiple of 4; 16-byte aligned, at *coef_off)
-// and the drifts [D4].
-__host__ __device__ inline size_t cont_lds_layout(size_t rsize, int D, int n_dates, int width, size_t* coef_off)
-{
-    size_t off = sizeof(double) * (n_dates + 1) +
-                 rsize * (D_MAX + 2 * (size_t)(n_dates + 1) + (size_t)(n_dates + 1) * cont_rule_stride(D, width));
-    off = (off + 15) & ~(size_t)15;
-    if (coef_off) *coef_off = off;
-    const size_t D4 = (size_t)((D + 3) & ~3);
-    if (D >= 9) off += rsize * (D4 * D4 + D4);
-    return off + 16;
-}
-size_t cont_lds_bytes(int prec, int d, int n_dates, int width);
-// Dynamic LDS a continuation workgroup may use on the current device.
-size_t cont_lds_limit();
 // One launch over jobs job0 .. job0+jobs-1 of many tasks of one bucket;
 // prefix[t] is the first job of task t, prefix[ntasks] the total.
 hipError_t launch_cont_multi(int bucket, int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks,

@@ -22,6 +22,8 @@
 // k_ada_fold then writes the rule row [base, count_0..count_d, (theta, delta)
 // feature by feature]: F(x) = base + sum of delta over the thresholds theta
 // that psi reaches; exercise iff Phi > 0 and F > 0.
+#include <climits>
+
 #include "fit_common.hpp"
 #include "internal.hpp"
 
@@ -30,6 +32,8 @@ namespace bmc {
 namespace {
 
 constexpr int NFMAX = D_MAX + 1;
+// Training sets up to this size are fitted by one workgroup.
+constexpr int64_t ADA_BLOCK_N = 1 << 16;
 
 struct AdaState {
     int32_t n_itm, shift, T, stop;
@@ -323,6 +327,194 @@ __global__ void k_ada_fold(int nf, int width, const AdaState* __restrict__ st, d
     for (int e = 0; e < width; ++e) row32[e] = (float)row64[e];
 }
 
+// ---------------------------------------------------------------------------
+// The whole fit of a date in one workgroup (N up to ADA_BLOCK_N points): the
+// same steps and arithmetic as the multi-kernel sequence, with the histogram
+// in LDS and block barriers instead of launches.
+
+constexpr int ADA_BT = 1024;
+
+// Block-wide min and max (f < nf) or max and sum (the weight statistics).
+__device__ inline void ada_block_reduce(double& a, double& b, bool minmax, double (*red)[ADA_BT / 64])
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ao = __shfl_xor(a, off), bo = __shfl_xor(b, off);
+        a = minmax ? fmin(a, ao) : fmax(a, ao);
+        b = minmax ? fmax(b, bo) : b + bo;
+    }
+    if (lane == 0) {
+        red[0][wv] = a;
+        red[1][wv] = b;
+    }
+    __syncthreads();
+    a = red[0][0];
+    b = red[1][0];
+    for (int q = 1; q < ADA_BT / 64; ++q) {
+        a = minmax ? fmin(a, red[0][q]) : fmax(a, red[0][q]);
+        b = minmax ? fmax(b, red[1][q]) : b + red[1][q];
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(ADA_BT) k_ada_fit_block(const DevSpec* __restrict__ s, const double* __restrict__ x,
+                                                         const double* __restrict__ cont, int64_t N, int rounds,
+                                                         double* psi, double* w, int8_t* y, uint8_t* bins,
+                                                         AdaState* st, double* row64, float* row32, int width)
+{
+    extern __shared__ unsigned long long hs[];   // [nf][B][2]
+    __shared__ double red[2][ADA_BT / 64];
+    __shared__ long long best_e[NFMAX];
+    __shared__ int best_k[NFMAX], best_s[NFMAX], flag;
+    __shared__ long long total;
+    const SpecT<double>& S = s->f64;
+    const int d = S.d, nf = d + 1, nh = nf * ADA_BINS * 2, tid = threadIdx.x;
+    // training set
+    for (int64_t j = tid; j < N; j += ADA_BT) {
+        const double pay = ada_payoff(S, x, N, j);
+        if (pay > 0.0) {
+            for (int i = 0; i < d; ++i) psi[i * N + j] = log(x[i * N + j]) - S.lnK;
+            psi[d * N + j] = pay / S.K;
+            const double beta = pay - cont[j];
+            y[j] = beta > 0.0 ? 1 : -1;
+            w[j] = fabs(beta);
+        } else {
+            y[j] = 0;
+            w[j] = 0.0;
+        }
+    }
+    __syncthreads();
+    // feature ranges, largest weight, count
+    for (int f = 0; f < nf; ++f) {
+        double a = INFINITY, b = -INFINITY;
+        for (int64_t j = tid; j < N; j += ADA_BT)
+            if (y[j] != 0) {
+                a = fmin(a, psi[(int64_t)f * N + j]);
+                b = fmax(b, psi[(int64_t)f * N + j]);
+            }
+        ada_block_reduce(a, b, true, red);
+        if (tid == 0) {
+            st->lo[f] = a;
+            st->hi[f] = b;
+            st->inv[f] = b > a ? (double)ADA_BINS / (b - a) : 0.0;
+        }
+    }
+    {
+        double a = 0.0, b = 0.0;
+        for (int64_t j = tid; j < N; j += ADA_BT)
+            if (y[j] != 0) {
+                a = fmax(a, w[j]);
+                b += 1.0;
+            }
+        ada_block_reduce(a, b, false, red);
+        if (tid == 0) {
+            const int nI = (int)b;
+            int e2 = 0;
+            frexp((double)nI * a, &e2);   // total weight < 2^e2
+            st->n_itm = nI;
+            st->shift = 50 - e2;
+            st->T = 0;
+            st->stop = (nI == 0 || !(a > 0.0)) ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    for (int64_t j = tid; j < N; j += ADA_BT)
+        if (y[j] != 0)
+            for (int f = 0; f < nf; ++f)
+                bins[(int64_t)f * N + j] =
+                    (uint8_t)ada_bin(psi[(int64_t)f * N + j], st->lo[f], st->hi[f], st->inv[f]);
+    const int shift = st->shift;
+    for (int t = 0; t < rounds && !st->stop; ++t) {
+        for (int e = tid; e < nh; e += ADA_BT) hs[e] = 0ull;
+        __syncthreads();
+        for (int64_t j = tid; j < N; j += ADA_BT) {
+            if (y[j] == 0) continue;
+            const unsigned long long W = (unsigned long long)ada_fixed(w[j], shift);
+            const int c = y[j] > 0;
+            if (W)
+                for (int f = 0; f < nf; ++f)
+                    atomicAdd(&hs[((int)bins[(int64_t)f * N + j] + f * ADA_BINS) * 2 + c], W);
+        }
+        __syncthreads();
+        // one wavefront per feature, lane k = split before bin k: prefix sums
+        // by shuffles, then the least error in the scan order (k ascending,
+        // s = +1 before -1) by a lexicographic (error, k) minimum
+        static_assert(ADA_BINS == 64, "one lane per bin");
+        for (int f = tid >> 6; f < nf; f += ADA_BT / 64) {
+            const int k = tid & 63;
+            const long long m0 = (long long)hs[(f * ADA_BINS + k) * 2], p0 = (long long)hs[(f * ADA_BINS + k) * 2 + 1];
+            long long Pm = m0, Pp = p0;   // inclusive prefix over bins <= k
+            for (int off = 1; off < 64; off <<= 1) {
+                const long long um = __shfl_up(Pm, off), up = __shfl_up(Pp, off);
+                if (k >= off) {
+                    Pm += um;
+                    Pp += up;
+                }
+            }
+            const long long Wm = __shfl(Pm, 63), Wp = __shfl(Pp, 63), Wt = Wm + Wp;
+            Pm -= m0;   // bins below k
+            Pp -= p0;
+            const long long Eplus = Pp + (Wm - Pm), Eminus = Wt - Eplus;
+            long long e = Eplus <= Eminus ? Eplus : Eminus;
+            int sg = Eplus <= Eminus ? 1 : -1;
+            int kk = k;
+            if (k == 0 && f > 0) e = LLONG_MAX;   // the constant stump lives on feature 0
+            for (int off = 32; off > 0; off >>= 1) {
+                const long long eo = __shfl_xor(e, off);
+                const int ko = __shfl_xor(kk, off), so = __shfl_xor(sg, off);
+                if (eo < e || (eo == e && ko < kk)) {
+                    e = eo;
+                    kk = ko;
+                    sg = so;
+                }
+            }
+            if (k == 0) {
+                best_e[f] = e;
+                best_k[f] = kk;
+                best_s[f] = sg;
+                if (f == 0) total = Wt;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const long long Wt = total;
+            long long be = best_e[0];
+            int bf = 0;
+            for (int g = 1; g < nf; ++g)
+                if (best_e[g] < be) {
+                    be = best_e[g];
+                    bf = g;
+                }
+            flag = 0;
+            if (Wt == 0 || 2 * be >= Wt) {
+                st->stop = 1;
+            } else {
+                const double eps = (double)be / (double)Wt;
+                const double ea = eps > 1e-10 ? eps : 1e-10;
+                st->f[t] = bf;
+                st->k[t] = best_k[bf];
+                st->s[t] = best_s[bf];
+                st->eps[t] = eps;
+                st->alpha[t] = 0.5 * log((1.0 - ea) / ea);
+                st->T = t + 1;
+                if (be == 0) st->stop = 1;
+                else flag = 1;
+            }
+        }
+        __syncthreads();
+        if (flag) {
+            const int f = st->f[t], k = st->k[t], sg = st->s[t];
+            const double eps = st->eps[t];
+            for (int64_t j = tid; j < N; j += ADA_BT) {
+                if (y[j] == 0) continue;
+                const int h = (int)bins[(int64_t)f * N + j] >= k ? sg : -sg;
+                w[j] = h != y[j] ? w[j] / (2.0 * eps) : w[j] / (2.0 * (1.0 - eps));
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 // Scratch (bytes): psi [nf][N], w [N], block partials, histograms [2][nf][B][2],
@@ -357,6 +549,24 @@ hipError_t launch_fit_ada(const DevSpec* s, int d, const double* x, const double
     c += al(N);
     uint8_t* bins = (uint8_t*)c;
     const int nh = nf * ADA_BINS * 2;
+    // histograms of wide rows exceed the default 64 KB of dynamic LDS
+    static const bool lds_ok = [] {
+        const int v = (int)(sizeof(unsigned long long) * NFMAX * ADA_BINS * 2);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ada_fit_block),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, v);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ada_hist),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, v);
+        (void)hipGetLastError();
+        return true;
+    }();
+    (void)lds_ok;
+    if (N <= ADA_BLOCK_N) {
+        // one workgroup runs every round (no launch per step of a round)
+        hipLaunchKernelGGL(k_ada_fit_block, dim3(1), dim3(ADA_BT), sizeof(unsigned long long) * nh, st, s, x, cont, N,
+                           rounds, psi, w, y, bins, state, row64, row32, width);
+        hipLaunchKernelGGL(k_ada_fold, dim3(1), dim3(64), 0, st, nf, width, state, row64, row32);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_ada_prep, dim3(blocks), dim3(256), 0, st, s, x, cont, N, psi, w, y, part);
     hipLaunchKernelGGL(k_ada_setup, dim3(1), dim3(256), 0, st, nf, blocks, part, state, H);
     hipLaunchKernelGGL(k_ada_bins, dim3(blocks), dim3(256), 0, st, psi, y, N, nf, state, bins);

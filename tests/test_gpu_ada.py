@@ -75,11 +75,14 @@ def specs(inputs):
         "wide12": inputs.basket(12, 100.0, 100.0, 0.05, 0.0, rng.uniform(0.15, 0.35, 12),
                                 inputs.wishart_corr(12, rng), 1.0, 5, inputs.PUT_GEO),
         "wide40": inputs.random_option(3, d_range=(40, 40), dates_range=(4, 4), n_choices=(1024,)),
+        "wide64": inputs.basket(64, 100.0, 100.0, 0.05, 0.0, rng.uniform(0.15, 0.35, 64),
+                                inputs.wishart_corr(64, rng), 1.0, 4, inputs.PUT_BASKET),
     }
 
 
 @pytest.mark.parametrize("case,N,rounds", [("put1", 1000, 64), ("geo5", 4097, 64), ("maxcall3", 333, 40),
-                                           ("basket2", 2048, 64), ("wide12", 1500, 64), ("wide40", 700, 24)])
+                                           ("basket2", 2048, 64), ("wide12", 1500, 64), ("wide40", 700, 24),
+                                           ("put1", 70001, 48), ("wide64", 900, 32), ("mincall2", 66000, 20)])
 def test_ada_fit_parity(bmc, ctx, orc, torch_mod, inputs, case, N, rounds):
     spec = specs(inputs)[case]
     m = max(1, spec.n_dates // 2)

@@ -627,7 +627,7 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
                          const double* x, int64_t N, const int32_t* ids, const int32_t* n_ids,
                          uint32_t n, uint32_t k0, uint32_t k1, double* cont, double* se,
                          int64_t* steps, double* sums, unsigned long long* steps_total,
-                         const Tuning* tune, uint32_t slot, uint32_t region_pts)
+                         const Tuning* tune, uint32_t slot, uint32_t region_pts, uint32_t* nchunk_out)
 {
     const int block = (tune && tune->block > 0) ? tune->block : 256;
     const uint32_t ppt = choose_ppt(ctx, d, prec, N, n, tune);
@@ -659,6 +659,10 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
     a.region_pts = region_pts;
     a.part = (double*)ctx->part.ptr;
     if ((e = launch_cont(d, prec, a, (int)grid, block, lds, ctx->stream))) return hip_fail(e, "continuation launch");
+    if (nchunk_out) {   // the caller merges the partials (ctx->part) itself
+        *nchunk_out = nchunk;
+        return BMC_OK;
+    }
     if ((e = launch_finalize(a.part, nchunk, n, N, ids, n_ids, cont, se, steps, sums, steps_total,
                              ctx->stream)))
         return hip_fail(e, "finalize launch");
@@ -804,8 +808,8 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     const int64_t Jr = J;   // points per region
     J *= nreg;              // columns of all regions
     hipError_t e;
-    // x_work [d][J], s_cur, s_prev, r_prev, cont [J], steps [J], steps_acc [J], ids x2, counters
-    const size_t need = sizeof(double) * ((size_t)d * J + 5 * J) + sizeof(unsigned long long) * J +
+    // x_work [d][J], s_cur, s_prev, r_prev [J], steps_acc [J], ids x2
+    const size_t need = sizeof(double) * ((size_t)d * J + 3 * J) + sizeof(unsigned long long) * J +
                         sizeof(int32_t) * 2 * J + 64;
     if ((e = ctx->iz.ensure(need))) return hip_fail(e, "search buffers");
     if ((e = ctx->counters.ensure(64))) return hip_fail(e, "counters");
@@ -814,12 +818,12 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     double* s_cur = (double*)c; c += sizeof(double) * J;
     double* s_prev = (double*)c; c += sizeof(double) * J;
     double* r_prev = (double*)c; c += sizeof(double) * J;
-    double* cont = (double*)c; c += sizeof(double) * J;
-    int64_t* stp = (int64_t*)c; c += sizeof(int64_t) * J;
     unsigned long long* acc = (unsigned long long*)c; c += sizeof(unsigned long long) * J;
     int32_t* ids_a = (int32_t*)c; c += sizeof(int32_t) * J;
     int32_t* ids_b = (int32_t*)c;
-    // counters buffer: [0,8) step total, [16,40) final sums/steps, [48,56) active counts
+    // counters buffer: [0,8) step total, [16,40) final sums/steps, [48,60) three
+    // rotating active counts: iteration it reads cnt[it % 3], appends to
+    // cnt[(it + 1) % 3] and clears cnt[(it + 2) % 3] for the next iteration
     int32_t* cnt = (int32_t*)((char*)ctx->counters.ptr + 48);
     const DevSpec* ds = (const DevSpec*)devspec;
     if ((e = launch_iz_init(ds, x, d, region, nreg, Jr, x_work, s_cur, s_out, iters, ids_a, &cnt[0], acc,
@@ -829,16 +833,18 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     for (int it = 0; it < max_iter; ++it) {
         int32_t* ids_in = (it & 1) ? ids_b : ids_a;
         int32_t* ids_out = (it & 1) ? ids_a : ids_b;
-        int32_t* n_in = &cnt[it & 1];
-        int32_t* n_out = &cnt[1 - (it & 1)];
-        if ((e = hipMemsetAsync(n_out, 0, sizeof(int32_t), ctx->stream))) return hip_fail(e, "search");
+        int32_t* n_in = &cnt[it % 3];
+        int32_t* n_out = &cnt[(it + 1) % 3];
+        int32_t* n_next = &cnt[(it + 2) % 3];
+        uint32_t nchunk = 0;
         bmc_status st = run_cont(ctx, devspec, d, spec->n_dates, rules->method, rules->width, rules->w64,
-                                 rules->w32, prec, date, x_work, J, ids_in, n_in, n, seed, k1, cont,
-                                 nullptr, stp, nullptr, nullptr, tune, (uint32_t)region,
-                                 nreg > 1 ? (uint32_t)Jr : 0u);
+                                 rules->w32, prec, date, x_work, J, ids_in, n_in, n, seed, k1, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr, tune, (uint32_t)region,
+                                 nreg > 1 ? (uint32_t)Jr : 0u, &nchunk);
         if (st) return st;
-        if ((e = launch_iz_update(ds, d, region, nreg, Jr, cont, stp, ids_in, n_in, ids_out, n_out, s_cur, s_prev,
-                                  r_prev, x_work, s_out, iters, acc, eps, max_iter, mode, it, ctx->stream)))
+        if ((e = launch_iz_update(ds, d, region, nreg, Jr, (const double*)ctx->part.ptr, nchunk, n, ids_in, n_in,
+                                  ids_out, n_out, n_next, s_cur, s_prev, r_prev, x_work, s_out, iters, acc, eps,
+                                  max_iter, mode, it, ctx->stream)))
             return hip_fail(e, "search update");
         if ((it & 3) == 3 || it == max_iter - 1) {
             int32_t left = 0;

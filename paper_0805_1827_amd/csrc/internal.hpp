@@ -84,13 +84,16 @@ hipError_t launch_lattice(const DevSpec* s, int d, int m, int region0, int nreg,
 hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int region0, int nreg, int64_t J,
                           double* x_work, double* s_cur, double* s_out, int32_t* iters, int32_t* ids,
                           int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st);
-// mode: SEARCH_PLAIN or SEARCH_SECANT (s_prev, r_prev: the secant's previous
-// point and residual per column).
-hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* cont,
-                            const int64_t* steps, const int32_t* ids_in, const int32_t* n_in,
-                            int32_t* ids_out, int32_t* n_out, double* s_cur, double* s_prev, double* r_prev,
-                            double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
-                            double eps, int max_iter, int mode, int it, hipStream_t st);
+// One search step: merges the continuation partials (part, nchunk chunks of
+// n paths in all) of the active points and updates them; mode SEARCH_PLAIN or
+// SEARCH_SECANT (s_prev, r_prev: the secant's previous point and residual per
+// column); clears *n_next.
+hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* part,
+                            uint32_t nchunk, uint32_t n, const int32_t* ids_in, const int32_t* n_in,
+                            int32_t* ids_out, int32_t* n_out, int32_t* n_next, double* s_cur, double* s_prev,
+                            double* r_prev, double* x_work, double* s_out, int32_t* iters,
+                            unsigned long long* steps_acc, double eps, int max_iter, int mode, int it,
+                            hipStream_t st);
 hipError_t launch_rules_fill(double* w64, float* w32, int rows, int width, double nv, hipStream_t st);
 hipError_t launch_rules_narrow(const double* w64, float* w32, int64_t count, hipStream_t st);
 

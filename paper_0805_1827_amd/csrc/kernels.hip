@@ -474,6 +474,8 @@ hipError_t launch_lattice(const DevSpec* s, int d, int m, int region0, int nreg,
 //   point not above every other asset lies outside the region: dropped.
 
 // Columns j of nreg regions side by side (J each, rows of Jt = nreg J).
+// n_ids: the three rotating active counts; the first starts at every column,
+// the other two at zero.
 __global__ void k_iz_init(const DevSpec* __restrict__ s, const double* __restrict__ x_in, int d, int region0,
                           int64_t J, int64_t Jt, double* x_work, double* s_cur, double* s_out, int32_t* iters,
                           int32_t* ids, int32_t* n_ids, unsigned long long* steps_acc)
@@ -488,7 +490,11 @@ __global__ void k_iz_init(const DevSpec* __restrict__ s, const double* __restric
     iters[j] = 0;
     ids[j] = (int32_t)j;
     steps_acc[j] = 0;
-    if (j == 0) *n_ids = (int32_t)Jt;
+    if (j == 0) {
+        n_ids[0] = (int32_t)Jt;
+        n_ids[1] = 0;
+        n_ids[2] = 0;
+    }
 }
 
 hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int region0, int nreg, int64_t J,
@@ -501,21 +507,27 @@ hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int regio
     return hipGetLastError();
 }
 
+// One search step per active point: merge the point's chunk partials of this
+// iteration's continuation launch (chunk order, as k_finalize), then the
+// update.  Also clears n_next, the active count of the iteration after next.
 __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region0, int64_t J, int64_t Jt,
-                            const double* __restrict__ cont, const int64_t* __restrict__ steps,
+                            const double* __restrict__ part, uint32_t nchunk, uint32_t n,
                             const int32_t* __restrict__ ids_in, const int32_t* __restrict__ n_in,
-                            int32_t* ids_out, int32_t* n_out, double* s_cur, double* s_prev, double* r_prev,
-                            double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
-                            double eps, int max_iter, int mode, int it)
+                            int32_t* ids_out, int32_t* n_out, int32_t* n_next, double* s_cur, double* s_prev,
+                            double* r_prev, double* x_work, double* s_out, int32_t* iters,
+                            unsigned long long* steps_acc, double eps, int max_iter, int mode, int it)
 {
 #pragma clang fp contract(off)
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot == 0) *n_next = 0;
     if (slot >= *n_in) return;
     const int64_t j = ids_in[slot];
     const int region = region0 + (int)(j / J);
     const SpecT<double>& S = s->f64;
-    const double c = cont[j];
-    steps_acc[j] += (unsigned long long)steps[j];
+    double psum, psq, pst;
+    merge_serial(part, nchunk, j, psum, psq, pst);
+    const double c = psum / (double)n;
+    steps_acc[j] += (unsigned long long)(int64_t)pst;
     double snew;
     if (S.payoff == CALL_MAX || S.payoff == CALL_MIN) {
         snew = S.K + c;
@@ -568,16 +580,17 @@ __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region0, i
     ids_out[pos] = (int32_t)j;
 }
 
-hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* cont,
-                            const int64_t* steps, const int32_t* ids_in, const int32_t* n_in,
-                            int32_t* ids_out, int32_t* n_out, double* s_cur, double* s_prev, double* r_prev,
-                            double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
-                            double eps, int max_iter, int mode, int it, hipStream_t st)
+hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* part,
+                            uint32_t nchunk, uint32_t n, const int32_t* ids_in, const int32_t* n_in,
+                            int32_t* ids_out, int32_t* n_out, int32_t* n_next, double* s_cur, double* s_prev,
+                            double* r_prev, double* x_work, double* s_out, int32_t* iters,
+                            unsigned long long* steps_acc, double eps, int max_iter, int mode, int it,
+                            hipStream_t st)
 {
     const int64_t Jt = (int64_t)nreg * J;
     hipLaunchKernelGGL(k_iz_update, dim3((unsigned)((Jt + 255) / 256)), dim3(256), 0, st, s, d, region0, J, Jt,
-                       cont, steps, ids_in, n_in, ids_out, n_out, s_cur, s_prev, r_prev, x_work, s_out, iters,
-                       steps_acc, eps, max_iter, mode, it);
+                       part, nchunk, n, ids_in, n_in, ids_out, n_out, n_next, s_cur, s_prev, r_prev, x_work, s_out,
+                       iters, steps_acc, eps, max_iter, mode, it);
     return hipGetLastError();
 }
 

@@ -156,8 +156,57 @@ __device__ bool wave_spd_solve(int p, double* A, double lam, const double* b, do
     return ok;
 }
 
+// Sum of the diagonal of the packed A by one wavefront, in row order (lane
+// i reads A_ii; the sum runs over lane broadcasts).
+template <int P>
+__device__ __forceinline__ double wave_trace(int p, const double* A)
+{
+    const int lane = threadIdx.x & 63;
+    const double v = lane < p ? A[tri(lane, lane)] : 0.0;
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) tr += bcast_lane(v, i);
+    return tr;
+}
+
 // Dispatch for a whole block: one wavefront solves small systems in
 // registers, larger ones use the block form.  A and b are scratch.
+__device__ inline bool spd_solve(int p, double* A, double lam, double* b, double* x, int* flag);
+
+// The same with the ridge lam = scale tr(A) / p: for p <= 32 the trace is
+// summed by the solving wavefront itself (no block barrier before the solve);
+// *lam_out (LDS) receives lam.
+__device__ inline bool spd_solve_ridge(int p, double* A, double scale, double* b, double* x, int* flag,
+                                       double* lam_out)
+{
+    if (p <= 32) {
+        if (threadIdx.x < 64) {
+            const double lam = scale * (p <= 16 ? wave_trace<16>(p, A) : wave_trace<32>(p, A)) / p;
+            if (threadIdx.x == 0) *lam_out = lam;
+            bool ok;
+            switch (p) {
+            case 5: ok = wave_spd_solve<5>(p, A, lam, b, x); break;
+            case 7: ok = wave_spd_solve<7>(p, A, lam, b, x); break;
+            case 9: ok = wave_spd_solve<9>(p, A, lam, b, x); break;
+            case 11: ok = wave_spd_solve<11>(p, A, lam, b, x); break;
+            case 13: ok = wave_spd_solve<13>(p, A, lam, b, x); break;
+            case 15: ok = wave_spd_solve<15>(p, A, lam, b, x); break;
+            default: ok = p <= 16 ? wave_spd_solve<16>(p, A, lam, b, x) : wave_spd_solve<32>(p, A, lam, b, x);
+            }
+            if (threadIdx.x == 0) *flag = ok ? 0 : 1;
+        }
+        __syncthreads();
+        return *flag == 0;
+    }
+    if (threadIdx.x == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < p; ++i) tr += A[tri(i, i)];
+        *lam_out = scale * tr / p;
+    }
+    __syncthreads();
+    return block_spd_solve(p, A, *lam_out, b, x, flag);
+}
+
 __device__ inline bool spd_solve(int p, double* A, double lam, double* b, double* x, int* flag)
 {
     if (p <= 32) {

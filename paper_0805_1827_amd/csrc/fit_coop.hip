@@ -36,36 +36,27 @@ __host__ __device__ inline int coop_aux(int p, int T)
     return a > b ? a : b;
 }
 
-// Sum over tiles, in tile order, of the Q columns of a [ntiles][Q] array,
-// staged through LDS in chunks of whole tiles with coalesced loads by the
-// whole block (straight from memory when one tile exceeds the staging area);
-// out[Q] in LDS.  Same order as a sequential merge from zero.
-__device__ void merge_tiles(const double* __restrict__ part, int ntiles, int Q, double* stage, int cap,
-                            double* out)
+// Sum over tiles, in tile order, of the Q columns of a [ntiles][Q] array
+// into out[Q] (LDS): thread q reads its column straight from memory (the
+// threads of a tile row read consecutive words), eight tiles' loads in
+// flight before their adds, which keep the order of a sequential merge from
+// zero.
+__device__ void merge_tiles(const double* __restrict__ part, int ntiles, int Q, double* out)
 {
     const int T = blockDim.x, tid = threadIdx.x;
-    const int chunk = cap / Q;
-    if (chunk < 1) {
-        __syncthreads();
-        for (int q = tid; q < Q; q += T) {
-            double acc = 0.0;
-            for (int t = 0; t < ntiles; ++t) acc += part[(size_t)t * Q + q];
-            out[q] = acc;
+    __syncthreads();
+    for (int q = tid; q < Q; q += T) {
+        double acc = 0.0;
+        int t = 0;
+        for (; t + 8 <= ntiles; t += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(t + u) * Q + q];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
         }
-        __syncthreads();
-        return;
-    }
-    for (int q = tid; q < Q; q += T) out[q] = 0.0;
-    for (int t0 = 0; t0 < ntiles; t0 += chunk) {
-        const int nt = min(chunk, ntiles - t0);
-        __syncthreads();
-        for (int e = tid; e < nt * Q; e += T) stage[e] = part[(size_t)t0 * Q + e];
-        __syncthreads();
-        for (int q = tid; q < Q; q += T) {
-            double acc = out[q];
-            for (int t = 0; t < nt; ++t) acc += stage[t * Q + q];
-            out[q] = acc;
-        }
+        for (; t < ntiles; ++t) acc += part[(size_t)t * Q + q];
+        out[q] = acc;
     }
     __syncthreads();
 }
@@ -115,7 +106,6 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
     double* beta = bv + p;                              // [p]
     double* mu = beta + p;                              // [p]
     double* sd = mu + p;                                // [p]
-    const int cap = T * coop_psi_width(p);
     const SpecT<double>& S = a.s->f64;
     const FitScratch& fs = a.fs;
     const int64_t N = a.N;
@@ -135,7 +125,7 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
     grp.sync();
     FIT_MARK(2);
     // means (every block), tile sums of squared deviations
-    merge_tiles(fs.part1, a.ntiles, p + 1, psi, cap, A);
+    merge_tiles(fs.part1, a.ntiles, p + 1, A);
     if (tid == 0) cnt_s = A[p];
     __syncthreads();
     const double cnt = cnt_s;
@@ -155,8 +145,8 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
     FIT_MARK(3);
     grp.sync();
     FIT_MARK(4);
-    merge_tiles(fs.part1, a.ntiles, p + 1, psi, cap, A);          // feature sums
-    merge_tiles(fs.part2, a.ntiles, p, psi, cap, A + (p + 1));    // squared deviations
+    merge_tiles(fs.part1, a.ntiles, p + 1, A);          // feature sums
+    merge_tiles(fs.part2, a.ntiles, p, A + (p + 1));    // squared deviations
     for (int f = tid; f < p; f += T) {
         fit_mu_sd(f, cnt, A[f], A[p + 1 + f], &mu[f], &sd[f]);
         if (grp.rank() == 0) {
@@ -176,8 +166,7 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
     // after reading round r's, so one barrier per round suffices.
     const size_t part_stride = (size_t)a.ntiles * Q;
     // A block with (at most) one tile keeps it for the whole fit: its rows
-    // stay in psi, F, the label and the mask in registers, and the merges
-    // stage through aux instead.
+    // stay in psi, F, the label and the mask in registers.
     const bool resident = mode != 0 && a.ntiles <= grp.size();
     double F_reg = 0.0, lab_reg = 0.0, msk_reg = 0.0;
     const int64_t j_own = (int64_t)grp.rank() * T + tid;
@@ -186,8 +175,6 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
         lab_reg = fs.lab[j_own];
         msk_reg = fs.msk[j_own];
     }
-    double* mstage = resident ? aux : psi;
-    const int mcap = resident ? coop_aux(p, T) : cap;
     for (int r = 0; r < a.rounds; ++r) {
         double* partA = fs.partA + (size_t)(r & 1) * part_stride;
         FIT_MARK(8 + 8 * r);
@@ -225,15 +212,10 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
         FIT_MARK(10 + 8 * r);
         grp.sync();
         FIT_MARK(11 + 8 * r);
-        merge_tiles(partA, a.ntiles, Q, mstage, mcap, A);   // A then bv
+        merge_tiles(partA, a.ntiles, Q, A);   // A then bv
         FIT_MARK(12 + 8 * r);
-        if (tid == 0) {
-            double tr = 0.0;
-            for (int i = 0; i < p; ++i) tr += A[tri(i, i)];
-            lam = 1e-8 * tr / p;
-        }
-        __syncthreads();
-        if (!spd_solve(p, A, lam, bv, beta, &flag))
+        // ridge 1e-8 tr / p, the trace summed inside the solver's wavefront
+        if (!spd_solve_ridge(p, A, 1e-8, bv, beta, &flag, &lam))
             for (int f = tid; f < p; f += T) beta[f] = 0.0;
         __syncthreads();
         FIT_MARK(13 + 8 * r);

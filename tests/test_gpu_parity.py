@@ -215,6 +215,42 @@ def test_continuation_large_d(bmc, ctx, orc, torch_mod, inputs, d, payoff):
         assert np.array_equal(st, ref["steps"])
 
 
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+def test_maximum_dimension_and_dates(bmc, ctx, orc, torch_mod, inputs, prec):
+    """d = 64 (the largest bound, every asset live) and N_T = 512 exercise
+    dates (the largest table): continuation estimates against the oracle;
+    FP32 within a tenth of the standard error."""
+    rng = np.random.default_rng(64)
+    wide = inputs.basket(64, 100.0, 100.0, 0.05, 0.0, rng.uniform(0.1, 0.3, 64), inputs.wishart_corr(64, rng),
+                         1.0, 5, inputs.PUT_GEO)
+    long = inputs.one_asset_put(n_dates=512)
+    p = getattr(bmc, prec)
+    for spec, ms, npts, n in ((wide, (1, 3), 20, 500), (long, (1, 256, 511), 16, 300)):
+        table = _small_rules(orc, spec, N=64, n=32)
+        for m in ms:
+            x = orc.points_cmc(spec, m, npts, 4)
+            c, se, st, ref = cont_parity(bmc, ctx, orc, torch_mod, spec, bmc.CMC, table, m, x, n, 6, prec=p)
+            if p == bmc.FP64:
+                assert_close(c, ref["cont"], spec.K, what=f"d={spec.d} dates={spec.n_dates} m={m}")
+                assert np.array_equal(st, ref["steps"])
+            else:
+                assert np.all(np.abs(c - ref["cont"]) <= 0.1 * ref["se"] + 1e-9 * spec.K), (spec.d, m)
+
+
+def test_oversized_rule_table_is_refused(bmc, ctx, torch_mod, inputs):
+    """An FP64 I&Z min-call on 16 assets with 100 dates has rule rows of
+    16 x 136 coefficients: more than a workgroup's LDS holds."""
+    spec = inputs.min_call(16, 100.0, n_dates=100)
+    with pytest.raises(bmc.BmcError) as e:
+        bmc.bmc_price(ctx, spec, bmc.IZ, bmc.FP64, N=8, n=8, n_final=8)
+    assert e.value.status == bmc.EUNSUPPORTED
+    assert "LDS" in bmc.load().bmc_last_error().decode()
+    rules = bmc.bmc_rules_create(ctx, inputs.one_asset_put(), bmc.CMC)
+    with pytest.raises(bmc.BmcError) as e:        # an empty point set
+        bmc.bmc_estimate_continuation(ctx, inputs.one_asset_put(), rules, 3, dev(torch_mod, np.zeros((1, 0))), 8, 1)
+    assert e.value.status == bmc.EINVAL
+
+
 def test_continuation_under_iz_rules(bmc, ctx, orc, torch_mod, inputs):
     spec = inputs.geometric_put5()
     table = orc.price(spec, orc.IZ, 32, 400, 256, 4, nthreads=NT_CPU)["rules"]

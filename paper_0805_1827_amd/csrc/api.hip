@@ -622,25 +622,25 @@ extern "C" bmc_status bmc_tuning_get(bmc_ctx* ctx, int32_t d, int32_t precision,
     return BMC_OK;
 }
 
-bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int method,
-                         int width, const void* rules64, const void* rules32, int prec, int m,
-                         const double* x, int64_t N, const int32_t* ids, const int32_t* n_ids,
-                         uint32_t n, uint32_t k0, uint32_t k1, double* cont, double* se,
-                         int64_t* steps, double* sums, unsigned long long* steps_total,
-                         const Tuning* tune, uint32_t slot, uint32_t region_pts, uint32_t* nchunk_out)
+// Launch shape, partial-sum buffer and arguments of one continuation pass
+// over N points (ids/n_ids: the active ones, or null for all).
+static bmc_status prepare_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int method, int width,
+                               const void* rules64, const void* rules32, int prec, int m, const double* x, int64_t N,
+                               const int32_t* ids, const int32_t* n_ids, uint32_t n, uint32_t k0, uint32_t k1,
+                               const Tuning* tune, uint32_t slot, uint32_t region_pts, ContArgs& a, int& block,
+                               size_t& lds, int64_t& grid)
 {
-    const int block = (tune && tune->block > 0) ? tune->block : 256;
+    block = (tune && tune->block > 0) ? tune->block : 256;
     const uint32_t ppt = choose_ppt(ctx, d, prec, N, n, tune);
     const uint32_t per_wg = (uint32_t)block * ppt;
     const uint32_t nchunk = (n + per_wg - 1) / per_wg;
     const size_t part_bytes = sizeof(double) * 3 * (size_t)N * nchunk;
     hipError_t e = ctx->part.ensure(part_bytes);
     if (e) return hip_fail(e, "partials allocation");
-    const size_t lds = cont_lds_bytes(prec, d, n_dates, width);
+    lds = cont_lds_bytes(prec, d, n_dates, width);
     if (lds > cont_lds_limit()) return fail(BMC_EUNSUPPORTED, "rule table too large for LDS (%zu bytes)", lds);
-    const int64_t grid = (int64_t)N * nchunk;
+    grid = (int64_t)N * nchunk;
     if (grid > 0x7FFFFFFF) return fail(BMC_EINVAL, "too many jobs in one launch");
-    ContArgs a;
     a.spec = (const DevSpec*)devspec;
     a.rules = prec == BMC_FP64 ? rules64 : rules32;
     a.x = x;
@@ -658,6 +658,25 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
     a.slot = slot;
     a.region_pts = region_pts;
     a.part = (double*)ctx->part.ptr;
+    return BMC_OK;
+}
+
+bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int method,
+                         int width, const void* rules64, const void* rules32, int prec, int m,
+                         const double* x, int64_t N, const int32_t* ids, const int32_t* n_ids,
+                         uint32_t n, uint32_t k0, uint32_t k1, double* cont, double* se,
+                         int64_t* steps, double* sums, unsigned long long* steps_total,
+                         const Tuning* tune, uint32_t slot, uint32_t region_pts, uint32_t* nchunk_out)
+{
+    ContArgs a;
+    int block = 256;
+    size_t lds = 0;
+    int64_t grid = 0;
+    bmc_status st = prepare_cont(ctx, devspec, d, n_dates, method, width, rules64, rules32, prec, m, x, N, ids,
+                                 n_ids, n, k0, k1, tune, slot, region_pts, a, block, lds, grid);
+    if (st) return st;
+    const uint32_t nchunk = a.nchunk;
+    hipError_t e;
     if ((e = launch_cont(d, prec, a, (int)grid, block, lds, ctx->stream))) return hip_fail(e, "continuation launch");
     if (nchunk_out) {   // the caller merges the partials (ctx->part) itself
         *nchunk_out = nchunk;

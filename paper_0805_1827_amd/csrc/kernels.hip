@@ -3,6 +3,7 @@
 #include <math.h>
 
 #include "internal.hpp"
+#include "iz_step.hpp"
 
 namespace bmc {
 
@@ -175,21 +176,6 @@ __device__ __forceinline__ void finalize_point(int64_t j, double s, double q, do
         sums[2 * j + 1] = q;
     }
     if (steps_total) atomicAdd(steps_total, (unsigned long long)c);
-}
-
-// Per point: merge the chunk partials in chunk order.
-__device__ __forceinline__ void merge_serial(const double* __restrict__ part, uint32_t nchunk, int64_t j, double& s,
-                                             double& q, double& c)
-{
-    s = 0.0;
-    q = 0.0;
-    c = 0.0;
-    for (uint32_t ch = 0; ch < nchunk; ++ch) {
-        const double* o = part + ((size_t)j * nchunk + ch) * 3;
-        s += o[0];
-        q += o[1];
-        c += o[2];
-    }
 }
 
 // Same merge for points with many chunks (final pricing), by a 256-thread
@@ -467,11 +453,7 @@ hipError_t launch_lattice(const DevSpec* s, int d, int m, int region0, int nreg,
 }
 
 // ---------------------------------------------------------------------------
-// I&Z boundary-point search state.  The searched coordinate is the region's
-// own asset (asset 1 for the put family), s <- Phi^{-1}(C(s)):
-//   geometric put (K - c)^d / prod_{i>=2} x_i, arithmetic put d (K - c) -
-//   sum_{i>=2} x_i, max-call K + c.  Non-positive: dropped; a max-call fixed
-//   point not above every other asset lies outside the region: dropped.
+// I&Z boundary-point search state (the step itself: iz_step.hpp).
 
 // Columns j of nreg regions side by side (J each, rows of Jt = nreg J).
 // n_ids: the three rotating active counts; the first starts at every column,
@@ -507,9 +489,8 @@ hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int regio
     return hipGetLastError();
 }
 
-// One search step per active point: merge the point's chunk partials of this
-// iteration's continuation launch (chunk order, as k_finalize), then the
-// update.  Also clears n_next, the active count of the iteration after next.
+// One search step per active point (iz_step_slot), one thread per slot.
+// Also clears n_next, the active count of the iteration after next.
 __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region0, int64_t J, int64_t Jt,
                             const double* __restrict__ part, uint32_t nchunk, uint32_t n,
                             const int32_t* __restrict__ ids_in, const int32_t* __restrict__ n_in,
@@ -517,67 +498,11 @@ __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region0, i
                             double* r_prev, double* x_work, double* s_out, int32_t* iters,
                             unsigned long long* steps_acc, double eps, int max_iter, int mode, int it)
 {
-#pragma clang fp contract(off)
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot == 0) *n_next = 0;
     if (slot >= *n_in) return;
-    const int64_t j = ids_in[slot];
-    const int region = region0 + (int)(j / J);
-    const SpecT<double>& S = s->f64;
-    double psum, psq, pst;
-    merge_serial(part, nchunk, j, psum, psq, pst);
-    const double c = psum / (double)n;
-    steps_acc[j] += (unsigned long long)(int64_t)pst;
-    double snew;
-    if (S.payoff == CALL_MAX || S.payoff == CALL_MIN) {
-        snew = S.K + c;
-    } else if (!(S.K - c > 0.0)) {
-        snew = -1.0;
-    } else if (S.payoff == PUT_GEO || d == 1) {
-        double prod = 1.0;
-        for (int i = 1; i < d; ++i) prod *= x_work[i * Jt + j];
-        snew = pow(S.K - c, (double)d) / prod;
-    } else {
-        double rest = 0.0;
-        for (int i = 1; i < d; ++i) rest += x_work[i * Jt + j];
-        snew = (double)d * (S.K - c) - rest;
-    }
-    const int it1 = it + 1;
-    iters[j] = it1;
-    if (!(snew > 0.0) || !isfinite(snew)) { s_out[j] = -1.0; return; }
-    const double sv = s_cur[j], res = snew - sv;
-    if (fabs(res) < eps) {
-        // inside the region: above every other asset (max-call), below
-        // every other asset (min-call)
-        double omax = 0.0, omin = INFINITY;
-        if (S.payoff == CALL_MAX || S.payoff == CALL_MIN)
-            for (int i = 0; i < d; ++i)
-                if (i != region) {
-                    omax = fmax(omax, x_work[i * Jt + j]);
-                    omin = fmin(omin, x_work[i * Jt + j]);
-                }
-        const bool outside = (S.payoff == CALL_MAX && snew <= omax) || (S.payoff == CALL_MIN && snew >= omin);
-        s_out[j] = outside ? -1.0 : snew;
-        return;
-    }
-    if (it1 >= max_iter) { s_out[j] = -1.0; return; }
-    double next = snew;
-    if (mode == SEARCH_SECANT && it > 0) {
-        const double den = res - r_prev[j];
-        if (den != 0.0) {
-            double step = -res * (sv - s_prev[j]) / den;
-            const double lim = 20.0 * fabs(res);
-            if (step > lim) step = lim;
-            if (step < -lim) step = -lim;
-            if (isfinite(step) && sv + step > 0.0) next = sv + step;
-        }
-    }
-    s_prev[j] = sv;
-    r_prev[j] = res;
-    s_cur[j] = next;
-    x_work[region * Jt + j] = next;
-    const int pos = atomicAdd(n_out, 1);
-    ids_out[pos] = (int32_t)j;
+    iz_step_slot(s->f64, d, region0, J, Jt, part, nchunk, n, ids_in[slot], ids_out, n_out, s_cur, s_prev, r_prev,
+                 x_work, s_out, iters, steps_acc, eps, max_iter, mode, it);
 }
 
 hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* part,

@@ -229,10 +229,12 @@ bmc_status bmc_server_stats_get(bmc_server *server, bmc_server_stats *out);
  * phi = [1, u_1..u_d, u_1^2..u_d^2, g, g^2], u_i = ln(S_i/K), g = Phi(S)/K;
  * exercise iff Phi > 0 and F > 0.  CMC_ADA: AdaBoost stumps on
  * psi = [u_1..u_d, g] folded into per-feature threshold tables, row
- * [base, c_0..c_d, (theta, delta) x (c_0 + .. + c_d), zeros] of
- * 1 + (d + 1) + 2 * 64 entries; F(x) = base + sum of delta over the pairs of
- * each feature f (its c_f pairs, features in order) with psi_f(x) >= theta;
- * exercise iff Phi > 0 and F > 0.  I&Z (Section 2.2): one boundary block of
+ * [base, c_0..c_d, then per feature f (in order) its c_f thresholds theta in
+ * ascending order followed by the c_f running sums R of their increments
+ * delta = 2 alpha s in that order, zeros] of 1 + (d + 1) + 2 * 64 entries;
+ * F(x) = base + sum over f of R_f[k_f - 1], k_f the number of thresholds
+ * with psi_f(x) >= theta (no term when k_f = 0); exercise iff Phi > 0 and
+ * F > 0.  I&Z (Section 2.2): one boundary block of
  * p = 1 + q + q(q+1)/2 coefficients (q = d - 1) per exercise region, region r
  * at offset r p of the row; b_r(x) = sum_f w_f xi_f with
  * xi = [1, v_1..v_q, v_a v_c (a <= c)] over v = ln(S_i/K) of the assets

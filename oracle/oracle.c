@@ -276,16 +276,18 @@ static int exercise_now(const orc_spec *s, int method, const double *row,
         return F > 0.0;
     }
     if (method == ORC_CMC_ADA) {
-        /* folded stumps: F = base + sum of delta over the thresholds that
-         * the feature reaches, feature by feature in row order */
+        /* folded stumps: F = base + sum over features of the running sum at
+         * the number of thresholds the feature reaches */
         double psi[65];
         ada_features(s, logS, payoff, psi);
         int nf = s->d + 1, at = 1 + nf;
         double F = row[0];
         for (int f = 0; f < nf; ++f) {
-            int cnt = (int)row[1 + f];
-            for (int e = 0; e < cnt; ++e, at += 2)
-                if (psi[f] >= row[at]) F += row[at + 1];
+            int cnt = (int)row[1 + f], k = 0;
+            for (int e = 0; e < cnt; ++e)
+                if (psi[f] >= row[at + e]) ++k;
+            if (k > 0) F += row[at + cnt + k - 1];
+            at += 2 * cnt;
         }
         return F > 0.0;
     }
@@ -866,21 +868,39 @@ int orc_fit_ada(const orc_spec *s, const double *x, const double *cont, int64_t 
             }
         }
     }
-    /* fold: base, per-feature counts, (theta, delta) in feature then round order */
+    /* fold: F(x) = base + sum over features of the step function
+     * G_f(psi_f) = sum of delta = 2 alpha s over the stumps of f whose
+     * threshold psi_f reaches.  Row: base, per-feature counts, then per
+     * feature its thresholds in ascending order (ties in round order) and the
+     * running sums of their deltas in that order. */
     double base = 0.0;
     for (int t = 0; t < T; ++t) base -= ta[t] * ts[t];
     row[0] = base;
     int at = 1 + nf;
     for (int f = 0; f < nf; ++f) {
+        double th[ORC_ADA_TMAX], de[ORC_ADA_TMAX];
         int cnt = 0;
+        const double step = (hi[f] - lo[f]) / (double)B;
         for (int t = 0; t < T; ++t) {
             if (tf[t] != f) continue;
-            double step = (hi[f] - lo[f]) / (double)B;
-            row[at] = tk[t] == 0 ? -1e300 : lo[f] + (double)tk[t] * step;
-            row[at + 1] = 2.0 * ta[t] * ts[t];
-            at += 2;
-            ++cnt;
+            double v = tk[t] == 0 ? -1e300 : lo[f] + (double)tk[t] * step;
+            double dl = 2.0 * ta[t] * ts[t];
+            int q = cnt++;
+            while (q > 0 && th[q - 1] > v) {   /* stable insertion by threshold */
+                th[q] = th[q - 1];
+                de[q] = de[q - 1];
+                --q;
+            }
+            th[q] = v;
+            de[q] = dl;
         }
+        double run = 0.0;
+        for (int e = 0; e < cnt; ++e) {
+            run += de[e];
+            row[at + e] = th[e];
+            row[at + cnt + e] = run;
+        }
+        at += 2 * cnt;
         row[1 + f] = (double)cnt;
     }
     if (n_stumps) *n_stumps = T;

@@ -96,7 +96,10 @@ int orc_fit_cmc(const orc_spec *s, const double *x, const double *cont,
 
 /* CMC AdaBoost fit with decision stumps at one date (1 <= rounds <= ORC_ADA_TMAX),
  * written as a folded rule row of orc_rule_width(ORC_CMC_ADA, d) entries:
- * [base, count_0..count_d, (theta, delta) pairs feature by feature].
+ * [base, count_0..count_d, then per feature f its count_f thresholds in
+ * ascending order and the running sums of their increments 2 alpha s]; a
+ * point's score is base plus, per feature, the running sum at the number of
+ * thresholds its feature value reaches.
  * Optional trace (any pointer may be NULL): *n_stumps, and per stump its
  * feature, first bin of the upper side, sign, weighted error eps and alpha;
  * lo[d+1], hi[d+1]: the feature ranges over the in-the-money points. */

@@ -199,8 +199,9 @@ __device__ __forceinline__ R cmc_score(int d, const R* __restrict__ w, R lnK, R 
 
 // AdaBoost stump rule F = base + sum of delta over the thresholds theta that
 // each feature reaches, psi = [u_1..u_d, g]; row [base, count_0..count_d,
-// (theta, delta) pairs feature by feature].  Features are visited in order
-// and each one's pairs in row order.
+// then per feature its count thresholds in ascending order and the running
+// sums of their deltas], so each feature adds the running sum at the number
+// of thresholds it reaches.  Features are visited in order.
 template <int D, class R>
 __device__ __forceinline__ R ada_score(int d, const R* __restrict__ w, R lnK, R g, const R (&x)[D])
 {
@@ -211,8 +212,16 @@ __device__ __forceinline__ R ada_score(int d, const R* __restrict__ w, R lnK, R 
         if (i <= d) {
             const R v = i < d ? x[i < D ? i : 0] - lnK : g;
             const int cnt = (int)w[1 + i];
-            for (int e = 0; e < cnt; ++e, pr += 2)
-                if (v >= pr[0]) F += pr[1];
+            // k = number of the (ascending) thresholds pr[0..cnt-1] at or
+            // below v, by binary search in powers of two; the step count
+            // depends on cnt only, the same for every lane
+            int k = 0;
+            for (int h = cnt > 0 ? 1 << (31 - __clz(cnt)) : 0; h > 0; h >>= 1) {
+                const int t = k + h;
+                if (t <= cnt && pr[t - 1] <= v) k = t;
+            }
+            if (k > 0) F += pr[cnt + k - 1];
+            pr += 2 * cnt;
         }
     }
     return F;

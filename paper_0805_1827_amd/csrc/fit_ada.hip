@@ -19,9 +19,11 @@
 //   k_ada_update  the normalised AdaBoost step w/(2 eps) for misclassified
 //                 points, w/(2 (1 - eps)) for the others (correctly rounded
 //                 divisions, no exponentials).
-// k_ada_fold then writes the rule row [base, count_0..count_d, (theta, delta)
-// feature by feature]: F(x) = base + sum of delta over the thresholds theta
-// that psi reaches; exercise iff Phi > 0 and F > 0.
+// k_ada_fold then writes the rule row [base, count_0..count_d, then per
+// feature its thresholds theta in ascending order (ties in round order) and
+// the running sums of the increments delta = 2 alpha s in that order]:
+// F(x) = base + per feature the running sum at the number of thresholds psi
+// reaches; exercise iff Phi > 0 and F > 0.
 #include <climits>
 
 #include "fit_common.hpp"
@@ -312,15 +314,33 @@ __global__ void k_ada_fold(int nf, int width, const AdaState* __restrict__ st, d
     row64[0] = base;
     int at = 1 + nf;
     for (int f = 0; f < nf; ++f) {
+        // the feature's stumps inserted by threshold, stable (round order on
+        // ties), straight into the row: thresholds at at.., increments after
+        // the last stump of the feature, summed once the count is known
         int cnt = 0;
+        for (int t = 0; t < T; ++t) cnt += st->f[t] == f;
+        double* th = row64 + at;
+        double* de = row64 + at + cnt;
+        int c = 0;
         const double step = (st->hi[f] - st->lo[f]) / (double)ADA_BINS;
         for (int t = 0; t < T; ++t) {
             if (st->f[t] != f) continue;
-            row64[at] = st->k[t] == 0 ? -1e300 : st->lo[f] + (double)st->k[t] * step;
-            row64[at + 1] = 2.0 * st->alpha[t] * (double)st->s[t];
-            at += 2;
-            ++cnt;
+            const double v = st->k[t] == 0 ? -1e300 : st->lo[f] + (double)st->k[t] * step;
+            const double dl = 2.0 * st->alpha[t] * (double)st->s[t];
+            int q = c++;
+            for (; q > 0 && th[q - 1] > v; --q) {
+                th[q] = th[q - 1];
+                de[q] = de[q - 1];
+            }
+            th[q] = v;
+            de[q] = dl;
         }
+        double run = 0.0;
+        for (int e = 0; e < cnt; ++e) {
+            run += de[e];
+            de[e] = run;
+        }
+        at += 2 * cnt;
         row64[1 + f] = (double)cnt;
     }
     for (int e = at; e < width; ++e) row64[e] = 0.0;
@@ -355,6 +375,50 @@ __device__ inline void ada_block_reduce(double& a, double& b, bool minmax, doubl
         b = minmax ? fmax(b, red[1][q]) : b + red[1][q];
     }
     __syncthreads();
+}
+
+// Best stump of feature f from its histogram h[(f*B + bin)*2 + (y > 0)], by
+// one wavefront, lane k = split before bin k: prefix sums by shuffles, then
+// the least error in the scan order (k ascending, s = +1 before -1) by a
+// lexicographic (error, k) minimum; lane 0 writes the feature's result (and
+// the total weight, for feature 0).
+__device__ inline void ada_pick_wave(const unsigned long long* h, int f, long long* best_e, int* best_k,
+                                     int* best_s, long long* total)
+{
+    static_assert(ADA_BINS == 64, "one lane per bin");
+    const int k = threadIdx.x & 63;
+    const long long m0 = (long long)h[(f * ADA_BINS + k) * 2], p0 = (long long)h[(f * ADA_BINS + k) * 2 + 1];
+    long long Pm = m0, Pp = p0;   // inclusive prefix over bins <= k
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long um = __shfl_up(Pm, off), up = __shfl_up(Pp, off);
+        if (k >= off) {
+            Pm += um;
+            Pp += up;
+        }
+    }
+    const long long Wm = __shfl(Pm, 63), Wp = __shfl(Pp, 63), Wt = Wm + Wp;
+    Pm -= m0;   // bins below k
+    Pp -= p0;
+    const long long Eplus = Pp + (Wm - Pm), Eminus = Wt - Eplus;
+    long long e = Eplus <= Eminus ? Eplus : Eminus;
+    int sg = Eplus <= Eminus ? 1 : -1;
+    int kk = k;
+    if (k == 0 && f > 0) e = LLONG_MAX;   // the constant stump lives on feature 0
+    for (int off = 32; off > 0; off >>= 1) {
+        const long long eo = __shfl_xor(e, off);
+        const int ko = __shfl_xor(kk, off), so = __shfl_xor(sg, off);
+        if (eo < e || (eo == e && ko < kk)) {
+            e = eo;
+            kk = ko;
+            sg = so;
+        }
+    }
+    if (k == 0) {
+        best_e[f] = e;
+        best_k[f] = kk;
+        best_s[f] = sg;
+        if (f == 0) *total = Wt;
+    }
 }
 
 __global__ void __launch_bounds__(ADA_BT) k_ada_fit_block(const DevSpec* __restrict__ s, const double* __restrict__ x,
@@ -436,45 +500,7 @@ __global__ void __launch_bounds__(ADA_BT) k_ada_fit_block(const DevSpec* __restr
                     atomicAdd(&hs[((int)bins[(int64_t)f * N + j] + f * ADA_BINS) * 2 + c], W);
         }
         __syncthreads();
-        // one wavefront per feature, lane k = split before bin k: prefix sums
-        // by shuffles, then the least error in the scan order (k ascending,
-        // s = +1 before -1) by a lexicographic (error, k) minimum
-        static_assert(ADA_BINS == 64, "one lane per bin");
-        for (int f = tid >> 6; f < nf; f += ADA_BT / 64) {
-            const int k = tid & 63;
-            const long long m0 = (long long)hs[(f * ADA_BINS + k) * 2], p0 = (long long)hs[(f * ADA_BINS + k) * 2 + 1];
-            long long Pm = m0, Pp = p0;   // inclusive prefix over bins <= k
-            for (int off = 1; off < 64; off <<= 1) {
-                const long long um = __shfl_up(Pm, off), up = __shfl_up(Pp, off);
-                if (k >= off) {
-                    Pm += um;
-                    Pp += up;
-                }
-            }
-            const long long Wm = __shfl(Pm, 63), Wp = __shfl(Pp, 63), Wt = Wm + Wp;
-            Pm -= m0;   // bins below k
-            Pp -= p0;
-            const long long Eplus = Pp + (Wm - Pm), Eminus = Wt - Eplus;
-            long long e = Eplus <= Eminus ? Eplus : Eminus;
-            int sg = Eplus <= Eminus ? 1 : -1;
-            int kk = k;
-            if (k == 0 && f > 0) e = LLONG_MAX;   // the constant stump lives on feature 0
-            for (int off = 32; off > 0; off >>= 1) {
-                const long long eo = __shfl_xor(e, off);
-                const int ko = __shfl_xor(kk, off), so = __shfl_xor(sg, off);
-                if (eo < e || (eo == e && ko < kk)) {
-                    e = eo;
-                    kk = ko;
-                    sg = so;
-                }
-            }
-            if (k == 0) {
-                best_e[f] = e;
-                best_k[f] = kk;
-                best_s[f] = sg;
-                if (f == 0) total = Wt;
-            }
-        }
+        for (int f = tid >> 6; f < nf; f += ADA_BT / 64) ada_pick_wave(hs, f, best_e, best_k, best_s, &total);
         __syncthreads();
         if (tid == 0) {
             const long long Wt = total;
@@ -515,6 +541,134 @@ __global__ void __launch_bounds__(ADA_BT) k_ada_fit_block(const DevSpec* __restr
     }
 }
 
+// Dynamic LDS of k_ada_fit_lds: two round histograms, then the weights,
+// labels and bins of the in-the-money points.
+inline size_t ada_lds_bytes(int64_t N, int nf)
+{
+    return 2 * sizeof(unsigned long long) * nf * ADA_BINS * 2 + (size_t)N * (sizeof(double) + 1 + nf);
+}
+
+// The whole fit of a date in one workgroup with the training set resident in
+// LDS: the in-the-money points are packed (in arrival order: every step after
+// is independent of the order, the histogram sums being exact integers), and
+// each round's weight update adds the updated weights straight into the next
+// round's histogram, so a round costs two barriers.  Same stumps, weights and
+// state as k_ada_fit_block.
+__global__ void __launch_bounds__(ADA_BT) k_ada_fit_lds(const DevSpec* __restrict__ s, const double* __restrict__ x,
+                                                       const double* __restrict__ cont, int64_t N, int rounds,
+                                                       double* psi, AdaState* st)
+{
+    extern __shared__ unsigned long long hs[];   // [2][nf][B][2], w [N], y [N], bins [nf][N]
+    __shared__ double red[2][ADA_BT / 64];
+    __shared__ long long best_e[NFMAX];
+    __shared__ int best_k[NFMAX], best_s[NFMAX], n_pack;
+    __shared__ long long total;
+    __shared__ double lo_s[NFMAX], hi_s[NFMAX], inv_s[NFMAX];
+    const SpecT<double>& S = s->f64;
+    const int d = S.d, nf = d + 1, nh = nf * ADA_BINS * 2, tid = threadIdx.x;
+    double* wl = reinterpret_cast<double*>(hs + 2 * nh);
+    int8_t* yl = reinterpret_cast<int8_t*>(wl + N);
+    uint8_t* bl = reinterpret_cast<uint8_t*>(yl + N);
+    if (tid == 0) n_pack = 0;
+    __syncthreads();
+    for (int64_t j = tid; j < N; j += ADA_BT) {
+        const double pay = ada_payoff(S, x, N, j);
+        if (pay > 0.0) {
+            const int q = atomicAdd(&n_pack, 1);
+            for (int i = 0; i < d; ++i) psi[i * N + q] = log(x[i * N + j]) - S.lnK;
+            psi[d * N + q] = pay / S.K;
+            const double beta = pay - cont[j];
+            yl[q] = beta > 0.0 ? 1 : -1;
+            wl[q] = fabs(beta);
+        }
+    }
+    __syncthreads();
+    const int nI = n_pack;
+    for (int f = 0; f < nf; ++f) {
+        double a = INFINITY, b = -INFINITY;
+        for (int q = tid; q < nI; q += ADA_BT) {
+            a = fmin(a, psi[(int64_t)f * N + q]);
+            b = fmax(b, psi[(int64_t)f * N + q]);
+        }
+        ada_block_reduce(a, b, true, red);
+        if (tid == 0) {
+            const double inv = b > a ? (double)ADA_BINS / (b - a) : 0.0;
+            st->lo[f] = lo_s[f] = a;
+            st->hi[f] = hi_s[f] = b;
+            st->inv[f] = inv_s[f] = inv;
+        }
+    }
+    double wmax = 0.0, unused = 0.0;
+    for (int q = tid; q < nI; q += ADA_BT) wmax = fmax(wmax, wl[q]);
+    ada_block_reduce(wmax, unused, false, red);   // ends with a barrier: lo_s .. inv_s are visible
+    int e2 = 0;
+    frexp((double)nI * wmax, &e2);   // total weight < 2^e2
+    const int shift = 50 - e2;
+    bool stop = nI == 0 || !(wmax > 0.0);
+    if (tid == 0) {
+        st->n_itm = nI;
+        st->shift = shift;
+        st->T = 0;
+        st->stop = stop ? 1 : 0;
+    }
+    for (int e = tid; e < nh; e += ADA_BT) hs[e] = 0ull;
+    for (int q = tid; q < nI; q += ADA_BT)
+        for (int f = 0; f < nf; ++f)
+            bl[f * N + q] = (uint8_t)ada_bin(psi[(int64_t)f * N + q], lo_s[f], hi_s[f], inv_s[f]);
+    __syncthreads();
+    for (int q = tid; q < nI; q += ADA_BT) {
+        const unsigned long long W = (unsigned long long)ada_fixed(wl[q], shift);
+        const int c = yl[q] > 0;
+        if (W)
+            for (int f = 0; f < nf; ++f) atomicAdd(&hs[((int)bl[f * N + q] + f * ADA_BINS) * 2 + c], W);
+    }
+    __syncthreads();
+    for (int t = 0; t < rounds && !stop; ++t) {
+        const unsigned long long* hc = hs + (t & 1) * nh;
+        unsigned long long* hn = hs + ((t + 1) & 1) * nh;
+        for (int e = tid; e < nh; e += ADA_BT) hn[e] = 0ull;   // last read by the previous round's pick
+        for (int f = tid >> 6; f < nf; f += ADA_BT / 64) ada_pick_wave(hc, f, best_e, best_k, best_s, &total);
+        __syncthreads();
+        // every thread takes the same decision from the per-feature bests
+        const long long Wt = total;
+        long long be = best_e[0];
+        int bf = 0;
+        for (int g = 1; g < nf; ++g)
+            if (best_e[g] < be) {
+                be = best_e[g];
+                bf = g;
+            }
+        if (Wt == 0 || 2 * be >= Wt) {
+            if (tid == 0) st->stop = 1;
+            break;
+        }
+        const double eps = (double)be / (double)Wt;
+        const double ea = eps > 1e-10 ? eps : 1e-10;
+        const int k = best_k[bf], sg = best_s[bf];
+        if (tid == 0) {
+            st->f[t] = bf;
+            st->k[t] = k;
+            st->s[t] = sg;
+            st->eps[t] = eps;
+            st->alpha[t] = 0.5 * log((1.0 - ea) / ea);
+            st->T = t + 1;
+            if (be == 0) st->stop = 1;
+        }
+        if (be == 0) break;   // perfect stump: nothing left to reweight
+        const bool next = t + 1 < rounds;
+        for (int q = tid; q < nI; q += ADA_BT) {
+            const int h = (int)bl[bf * N + q] >= k ? sg : -sg;
+            const double w = h != yl[q] ? wl[q] / (2.0 * eps) : wl[q] / (2.0 * (1.0 - eps));
+            wl[q] = w;
+            const unsigned long long W = (unsigned long long)ada_fixed(w, shift);
+            const int c = yl[q] > 0;
+            if (next && W)
+                for (int f = 0; f < nf; ++f) atomicAdd(&hn[((int)bl[f * N + q] + f * ADA_BINS) * 2 + c], W);
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 // Scratch (bytes): psi [nf][N], w [N], block partials, histograms [2][nf][B][2],
@@ -550,16 +704,26 @@ hipError_t launch_fit_ada(const DevSpec* s, int d, const double* x, const double
     uint8_t* bins = (uint8_t*)c;
     const int nh = nf * ADA_BINS * 2;
     // histograms of wide rows exceed the default 64 KB of dynamic LDS
+    // the resident fit's static LDS (reductions, bests, ranges) stays below 4 KB
+    static const size_t lds_res = cont_lds_limit() + 1024 - 4096;
     static const bool lds_ok = [] {
         const int v = (int)(sizeof(unsigned long long) * NFMAX * ADA_BINS * 2);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ada_fit_block),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, v);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ada_hist),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, v);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ada_fit_lds),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_res);
         (void)hipGetLastError();
         return true;
     }();
     (void)lds_ok;
+    if (ada_lds_bytes(N, nf) <= lds_res) {
+        hipLaunchKernelGGL(k_ada_fit_lds, dim3(1), dim3(ADA_BT), ada_lds_bytes(N, nf), st, s, x, cont, N, rounds,
+                           psi, state);
+        hipLaunchKernelGGL(k_ada_fold, dim3(1), dim3(64), 0, st, nf, width, state, row64, row32);
+        return hipGetLastError();
+    }
     if (N <= ADA_BLOCK_N) {
         // one workgroup runs every round (no launch per step of a round)
         hipLaunchKernelGGL(k_ada_fit_block, dim3(1), dim3(ADA_BT), sizeof(unsigned long long) * nh, st, s, x, cont, N,

@@ -116,15 +116,39 @@ def test_boosting_rounds_match_brute_force(orc, inputs, case):
 
 
 def _evaluate_row(spec, row, x):
+    """Score of the folded row: base plus, per feature, the running sum at the
+    number of its (ascending) thresholds the feature value reaches."""
     psi, pay = _psi_payoff(spec, x)
     nf = spec.d + 1
     F = np.full(x.shape[1], row[0])
     at = 1 + nf
     for f in range(nf):
-        for _ in range(int(row[1 + f])):
-            F += np.where(psi[f] >= row[at], row[at + 1], 0.0)
-            at += 2
+        c = int(row[1 + f])
+        th, run = row[at:at + c], row[at + c:at + 2 * c]
+        assert np.all(np.diff(th) >= 0)
+        k = (psi[f][:, None] >= th[None, :]).sum(axis=1)
+        F += np.where(k > 0, run[np.maximum(k - 1, 0)], 0.0)
+        at += 2 * c
     return F, pay
+
+
+def test_folded_row_equals_the_stump_sum(orc, inputs):
+    """The folded row scores every point as base + sum_t alpha_t h_t(x)
+    written out stump by stump from the trace."""
+    spec = inputs.basket(2, 100.0, 100.0, 0.05, 0.0, [0.2, 0.3], 0.3, 1.0, 5, inputs.PUT_BASKET)
+    rng = np.random.default_rng(8)
+    x = 100.0 * np.exp(rng.normal(0.0, 0.2, (2, 400)))
+    _, pay = _psi_payoff(spec, x)
+    cont = np.maximum(pay + rng.normal(0.0, 2.0, 400), 0.0)
+    row, tr = orc.fit_ada(spec, x, cont, rounds=30, trace=True)
+    probe = 100.0 * np.exp(rng.normal(0.0, 0.25, (2, 3000)))
+    F, _ = _evaluate_row(spec, row, probe)
+    psi, _ = _psi_payoff(spec, probe)
+    direct = np.zeros(probe.shape[1])
+    for f, k, s, a in zip(tr["feature"], tr["bin"], tr["sign"], tr["alpha"]):
+        theta = -np.inf if k == 0 else tr["lo"][f] + k * ((tr["hi"][f] - tr["lo"][f]) / 64)
+        direct += a * np.where(psi[f] >= theta, s, -s)
+    assert np.allclose(F, direct, atol=1e-9)
 
 
 def test_training_error_within_adaboost_bound(orc, inputs):

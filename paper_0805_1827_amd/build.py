@@ -23,7 +23,7 @@ ARCH = "gfx950"
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
-         # packed FP32 ops stay off (emitted only by hand elsewhere, never here)
+         # no packed FP32 ops: ordinary float code is compiled to scalar VALU ops
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          # matrix-core accumulators in ordinary VGPRs (no AGPR copies around
          # the correlation MFMAs of the continuation kernel)

@@ -293,6 +293,29 @@ def iz_form(ctx, bmc, inputs, reps: int = 3) -> dict:
     return out
 
 
+def maxcall5_form(ctx, bmc, inputs) -> dict:
+    """The five-asset max-call (K = 100, r = 0.05, delta = 0.1, sigma = 0.2,
+    independent assets, T = 3, 9 dates; S0 = 90, 100, 110), CMC at
+    N = n = 16384 with 1e6 final paths: FP32 stepping with compensated FP64
+    sums beside the FP64 form on the same GPU, whose continuation estimates
+    the tests hold to the oracle at 1e-10 relative."""
+    rows = []
+    for S0 in (90, 100, 110):
+        spec = inputs.max_call(5, float(S0))
+        kw = dict(N=16384, n=16384, n_final=1_000_000, seed=1)
+        bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP32_KAHAN, **kw)   # warm
+        a = bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP32_KAHAN, **kw)
+        b = bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP64, **kw)
+        rows.append({"S0": S0, "price_fp32_kahan": a["price"], "price_fp64": b["price"],
+                     "std_err": b["std_err"], "fp32_error_in_std_err": abs(a["price"] - b["price"]) / b["std_err"],
+                     "ms_fp32_kahan": 1e3 * a["seconds"], "ms_fp64": 1e3 * b["seconds"],
+                     "inner_path_steps": a["inner_path_steps"],
+                     "inner_path_steps_per_s_fp32_kahan": a["inner_path_steps"] / a["calc_seconds"],
+                     "inner_path_steps_per_s_fp64": b["inner_path_steps"] / b["calc_seconds"]})
+    return {"workload": "call on the max of 5 independent assets, CMC, N=n=16384, 9 dates, 1e6 final paths, "
+                        "seed 1", "runs": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,6 +336,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="arrival rate of the serving form (1/s)")
     ap.add_argument("--no-iz", action="store_true", help="skip the I&Z max-call form (Tables 1-3)")
     ap.add_argument("--no-ada", action="store_true", help="skip the AdaBoost-stump line")
+    ap.add_argument("--no-maxcall5", action="store_true", help="skip the five-asset max-call line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the pricer runs on a single device and this build has no "
@@ -411,6 +435,8 @@ def main():
         "inner_path_steps_per_s": ada[-1]["inner_path_steps"] / float(np.median([r["calc_seconds"] for r in ada])),
         "price": ada[-1]["price"], "std_err": ada[-1]["std_err"],
         "logitboost_price": p32["price"]}
+    if not args.no_maxcall5:
+        out["maxcall5"] = maxcall5_form(ctx, bmc, inputs)
     if not args.no_iz:
         out["iz"] = iz_form(ctx, bmc, inputs)
     if args.serve_seconds > 0:

@@ -490,6 +490,37 @@ def test_full_size_final_pricing(bmc, ctx, orc, torch_mod, inputs):
     assert r["final_path_steps"] == ref["final_steps"]
 
 
+@pytest.mark.parametrize("S0", [90.0, 100.0, 110.0])
+def test_full_size_max_call5_sampled(bmc, ctx, orc, torch_mod, inputs, S0):
+    """Five-asset max-call at N = n = 16384 with 1e6 final paths (one run per
+    S0): every point on the GPU in FP64 and in FP32 with compensated sums, a
+    sample of points (across several workgroup chunks and the last point)
+    re-evaluated by the oracle, then final pricing in both precisions."""
+    spec = inputs.max_call(5, S0)
+    table = _small_rules(orc, spec, N=256, n=256)
+    m, N, n = 4, 16384, 16384
+    x = orc.points_cmc(spec, m, N, 1)
+    rules = gpu_rules(bmc, ctx, spec, bmc.CMC, table)
+    ids = np.array([0, 1, 4095, 4096, 8191, 12000, 16383])
+    ref = orc.continuation(spec, orc.CMC, table, m, x[:, ids], n, 1, nthreads=NT_CPU, ids=ids)
+    for prec in (bmc.FP64, bmc.FP32_KAHAN):
+        c, se, st = bmc.bmc_estimate_continuation(ctx, spec, rules, m, dev(torch_mod, x), n, 1, prec)
+        c, se, st = host(c), host(se), host(st)
+        if prec == bmc.FP64:
+            assert_close(c[ids], ref["cont"], spec.K, what="max-call full-size cont")
+            assert np.array_equal(st[ids], ref["steps"])
+            assert_same_labels(orc, spec, x[:, ids], c[ids], ref["cont"], what="max-call full-size labels")
+        else:
+            assert np.all(np.abs(c[ids] - ref["cont"]) <= 0.1 * ref["se"] + 1e-12)
+        assert np.all(c >= 0) and np.all(np.isfinite(se))
+    fin = orc.final_price(spec, orc.CMC, table, 1000000, 1, nthreads=NT_CPU)
+    r64 = bmc.bmc_final_price(ctx, spec, rules, 1000000, 1, bmc.FP64)
+    assert_close(r64["price"], fin["price"], spec.K)
+    assert r64["final_path_steps"] == fin["final_steps"]
+    r32 = bmc.bmc_final_price(ctx, spec, rules, 1000000, 1, bmc.FP32_KAHAN)
+    assert abs(r32["price"] - fin["price"]) <= 0.1 * fin["std_err"], (r32["price"], fin["price"], fin["std_err"])
+
+
 # --- determinism, errors, serialisation --------------------------------------------
 
 def test_repeat_is_bit_identical(bmc, ctx, torch_mod, inputs):

@@ -194,6 +194,7 @@ extern "C" bmc_status bmc_ctx_create(int32_t device, void* hip_stream, bmc_ctx**
     }
     if ((e = hipHostMalloc((void**)&c->host_io, 4096, hipHostMallocDefault))) {
         (void)hipHostFree(c->pack_host);
+        c->pack_host = nullptr;
         delete c;
         return hip_fail(e, "pinned staging");
     }
@@ -209,6 +210,8 @@ bmc_ctx::~bmc_ctx()
     if (pack_host) (void)hipHostFree(pack_host);
     if (bhost) (void)hipHostFree(bhost);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : poll_ev)
+        if (e) (void)hipEventDestroy(e);
     srules.release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph_stream) (void)hipStreamDestroy(graph_stream);
@@ -821,7 +824,8 @@ extern "C" bmc_status bmc_sample_points(bmc_ctx* ctx, const bmc_spec* spec, int3
 bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, const bmc_rules* rules,
                                int date, int region, int nreg, const double* x, int64_t J, uint32_t n,
                                uint32_t seed, int prec, double eps, int max_iter, int mode, double* s_out,
-                               int32_t* iters, int64_t* steps_out, const Tuning* tune)
+                               int32_t* iters, int64_t* steps_out, const Tuning* tune,
+                               unsigned long long* tally)
 {
     const int d = spec->d;
     const int64_t Jr = J;   // points per region
@@ -849,7 +853,26 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
                             ctx->stream)))
         return hip_fail(e, "search init");
     const uint32_t k1 = key_hi(BMC_STREAM_INNER, date);
-    for (int it = 0; it < max_iter; ++it) {
+    // Progress polls without stalling the stream: after every fourth
+    // iteration the active count is copied to pinned memory behind an event,
+    // and the host reads it once the event has passed, with at most two polls
+    // outstanding.  Iterations enqueued after the count reached zero find no
+    // active point and change nothing.
+    for (hipEvent_t& ev : ctx->poll_ev)
+        if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming))) return hip_fail(e, "search events");
+    volatile int32_t* poll_host = (volatile int32_t*)((char*)ctx->host_io + 128);
+    int polls_issued = 0, polls_read = 0;
+    bool done = false;
+    auto read_poll = [&](bool wait) -> hipError_t {
+        hipEvent_t ev = ctx->poll_ev[polls_read & 1];
+        const hipError_t q = wait ? hipEventSynchronize(ev) : hipEventQuery(ev);
+        if (q == hipErrorNotReady) return hipSuccess;
+        if (q != hipSuccess) return q;
+        if (poll_host[polls_read & 1] == 0) done = true;
+        ++polls_read;
+        return hipSuccess;
+    };
+    for (int it = 0; it < max_iter && !done; ++it) {
         int32_t* ids_in = (it & 1) ? ids_b : ids_a;
         int32_t* ids_out = (it & 1) ? ids_a : ids_b;
         int32_t* n_in = &cnt[it % 3];
@@ -865,14 +888,22 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
                                   ids_out, n_out, n_next, s_cur, s_prev, r_prev, x_work, s_out, iters, acc, eps,
                                   max_iter, mode, it, ctx->stream)))
             return hip_fail(e, "search update");
-        if ((it & 3) == 3 || it == max_iter - 1) {
-            int32_t left = 0;
-            if ((e = hipMemcpyAsync(&left, n_out, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream)) ||
-                (e = hipStreamSynchronize(ctx->stream)))
+        if ((it & 3) == 3 && it != max_iter - 1) {
+            if (polls_issued - polls_read == 2 && (e = read_poll(true))) return hip_fail(e, "search progress");
+            if (done) break;
+            if ((e = hipMemcpyAsync((void*)&poll_host[polls_issued & 1], n_out, sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, ctx->stream)) ||
+                (e = hipEventRecord(ctx->poll_ev[polls_issued & 1], ctx->stream)))
                 return hip_fail(e, "search progress");
-            if (left == 0) break;
+            ++polls_issued;
+        }
+        while (!done && polls_read < polls_issued) {
+            const int before = polls_read;
+            if ((e = read_poll(false))) return hip_fail(e, "search progress");
+            if (polls_read == before) break;   // the oldest poll has not passed yet
         }
     }
+    if (tally && (e = launch_iz_tally(acc, s_out, iters, J, tally, ctx->stream))) return hip_fail(e, "search tally");
     if (steps_out) {
         std::vector<unsigned long long> h(J);
         if ((e = hipMemcpyAsync(h.data(), acc, sizeof(unsigned long long) * J, hipMemcpyDeviceToHost,

@@ -94,6 +94,10 @@ hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int6
                             double* r_prev, double* x_work, double* s_out, int32_t* iters,
                             unsigned long long* steps_acc, double eps, int max_iter, int mode, int it,
                             hipStream_t st);
+// tally[0] += sum of steps_acc, tally[1] += number of s_out <= 0 (or NaN),
+// tally[2] += sum of iters, over count points.
+hipError_t launch_iz_tally(const unsigned long long* steps_acc, const double* s_out, const int32_t* iters,
+                           int64_t count, unsigned long long* tally, hipStream_t st);
 hipError_t launch_rules_fill(double* w64, float* w32, int rows, int width, double nv, hipStream_t st);
 hipError_t launch_rules_narrow(const double* w64, float* w32, int64_t count, hipStream_t st);
 

@@ -519,6 +519,48 @@ hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int6
     return hipGetLastError();
 }
 
+// Search totals of a date: per block sums, then one 64-bit atomic add per
+// total (integer sums: the result does not depend on the order).
+__global__ void __launch_bounds__(256) k_iz_tally(const unsigned long long* __restrict__ steps_acc,
+                                                  const double* __restrict__ s_out, const int32_t* __restrict__ iters,
+                                                  int64_t count, unsigned long long* tally)
+{
+    __shared__ unsigned long long red[3][4];
+    unsigned long long a = 0, b = 0, c = 0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        a += steps_acc[j];
+        b += s_out[j] > 0.0 ? 0ull : 1ull;
+        c += (unsigned long long)iters[j];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        c += __shfl_xor(c, off);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = a;
+        red[1][wv] = b;
+        red[2][wv] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long v = 0;
+        for (int w = 0; w < 4; ++w) v += red[threadIdx.x][w];
+        atomicAdd(&tally[threadIdx.x], v);
+    }
+}
+
+hipError_t launch_iz_tally(const unsigned long long* steps_acc, const double* s_out, const int32_t* iters,
+                           int64_t count, unsigned long long* tally, hipStream_t st)
+{
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 256);
+    hipLaunchKernelGGL(k_iz_tally, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, steps_acc,
+                       s_out, iters, count, tally);
+    return hipGetLastError();
+}
+
 __global__ void k_narrow(const double* __restrict__ a, float* b, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -131,9 +131,12 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     } else {
         double* s_out = cont;
         int32_t* iters = (int32_t*)((char*)ctx->steps.ptr + sizeof(int64_t) * N);
-        std::vector<double> hs(NR);
-        std::vector<int32_t> hi(NR);
         const int regions = iz_regions(spec->payoff, d);
+        // search totals (path-steps, points without a boundary point,
+        // iterations) summed on the device date by date, read with the price
+        unsigned long long* tally = (unsigned long long*)((char*)ctx->counters.ptr + 64);
+        if ((e = hipMemsetAsync(tally, 0, 3 * sizeof(unsigned long long), ctx->stream)))
+            st = hip_fail(e, "counter reset");
         // Algorithm 1: per date, the boundary points of every region, then one
         // regression per region.  The regions' searches are independent (each
         // uses the rules of later dates only), so they run side by side in the
@@ -141,11 +144,9 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
         for (int m = NT - 1; m >= 1 && !st; --m) {
             if ((st = sample_points_impl(ctx, ds, spec, BMC_IZ, m, N, seed, x, B, 0, regions))) break;
             timer.mark(PH_CALC);
-            int64_t stp = 0;
             st = iz_search_impl(ctx, ds, spec, rules, m, 0, regions, x, N, n, seed, prec, eps, max_iter, search,
-                                s_out, iters, &stp, tune);
+                                s_out, iters, nullptr, tune, tally);
             if (st) break;
-            iz_steps += stp;
             timer.mark(PH_FIT);
             for (int r = 0; r < regions && !st; ++r) {
                 // s* of region r into the region's own asset row of its columns
@@ -158,17 +159,10 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
             }
             if (st) break;
             timer.mark(-1);
-            if ((e = hipMemcpyAsync(hs.data(), s_out, sizeof(double) * NR, hipMemcpyDeviceToHost, ctx->stream)) ||
-                (e = hipMemcpyAsync(hi.data(), iters, sizeof(int32_t) * NR, hipMemcpyDeviceToHost, ctx->stream)) ||
-                (e = hipStreamSynchronize(ctx->stream))) {
-                st = hip_fail(e, "search results");
-                break;
-            }
-            for (int64_t j = 0; j < NR; ++j) {
-                if (!(hs[j] > 0.0)) ++unconv;
-                iz_iters += hi[j];
-            }
         }
+        if (!st && (e = hipMemcpyAsync((char*)ctx->host_io + 80, tally, 3 * sizeof(unsigned long long),
+                                       hipMemcpyDeviceToHost, ctx->stream)))
+            st = hip_fail(e, "search results");
     }
     double sums[3] = {0, 0, 0};
     unsigned long long* inner_host = (unsigned long long*)((char*)ctx->host_io + 64);
@@ -181,6 +175,13 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
         timer.mark(-1);   // before the sync, so that every timing event has completed after it
         if (!st && (e = hipStreamSynchronize(ctx->stream))) st = hip_fail(e, "result read");
         if (!st) read_final_sums(ctx, sums);
+        if (!st && method == BMC_IZ) {
+            unsigned long long t[3];
+            std::memcpy(t, (const char*)ctx->host_io + 80, sizeof(t));
+            iz_steps = (int64_t)t[0];
+            unconv = (int64_t)t[1];
+            iz_iters = (int64_t)t[2];
+        }
     }
     if (!st && *status_host != 0) st = fail(BMC_ENOTSPD, "correlation matrix is not positive definite");
     const unsigned long long inner = st ? 0 : *inner_host;

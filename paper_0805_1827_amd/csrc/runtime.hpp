@@ -53,6 +53,7 @@ struct bmc_ctx {
     // batched date sweeps as a HIP graph: the last captured launch sequence,
     // replayed while the signature (launch shapes and buffers) is unchanged
     std::vector<hipEvent_t> ev_pool;   // reusable timing events
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};   // I&Z search progress polls (host_io + 128)
     bmc::DBuf srules;                  // rule table of bmc_price when the caller keeps none
     bool graphs = false;
     std::string graph_sig;
@@ -101,10 +102,14 @@ bmc_status sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec*
                               int nreg = 1);
 // Searches regions region .. region + nreg - 1 together: x, s_out and iters
 // hold nreg J points side by side, as sample_points_impl lays them out.
+// tally (device, optional): adds the executed path-steps, the points left
+// without a boundary point and the iterations to tally[0..2] on the stream,
+// so that a caller sweeping dates reads them once at the end.
 bmc_status iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec,
                           const bmc_rules* rules, int date, int region, int nreg, const double* x, int64_t J,
                           uint32_t n, uint32_t seed, int prec, double eps, int max_iter, int mode,
-                          double* s_out, int32_t* iters, int64_t* steps_out, const Tuning* tune);
+                          double* s_out, int32_t* iters, int64_t* steps_out, const Tuning* tune,
+                          unsigned long long* tally = nullptr);
 bmc_status final_price_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec,
                             const bmc_rules* rules, int64_t n_final, uint32_t seed, int prec,
                             double* host_sums, const Tuning* tune, bool sync = true);

@@ -151,12 +151,23 @@ def batch_form(ctx, bmc, inputs, count: int, N: int, n_final: int) -> dict:
 
     bmc.bmc_price_batch(ctx, specs[:4], opts(bmc.FP32)[:4])   # warm-up (module load, buffers)
     out = {}
+    rules64 = None
     for name, prec in (("fp32", bmc.FP32), ("fp64", bmc.FP64)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = bmc.bmc_price_batch(ctx, specs, opts(prec))
+        if prec == bmc.FP64:
+            res, rules64 = bmc.bmc_price_batch(ctx, specs, opts(prec), want_rules=True)
+        else:
+            res = bmc.bmc_price_batch(ctx, specs, opts(prec))
         dt = time.perf_counter() - t0
         out[name] = (res, dt)
+    # FP32 final pricing under the FP64 rules (same rules, precision alone)
+    same = []
+    for s, rl, r in zip(specs, rules64, out["fp64"][0]):
+        f = bmc.bmc_final_price(ctx, s, rl, n_final, s.meta["seed"], bmc.FP32)
+        same.append(abs(f["price"] - r["price"]) / r["std_err"])
+        rl.close()
+    same = np.array(same)
     # the same sweep captured as a HIP graph, then replayed
     gctx = bmc.Context(0)
     try:
@@ -190,7 +201,9 @@ def batch_form(ctx, bmc, inputs, count: int, N: int, n_final: int) -> dict:
             "fp32_mfma_tflops": mflops / calc / 1e12,
             "fp32_mfma_frac_of_peak": mflops / calc / PEAK_MFMA_F32,
             "fp32_vs_fp64_price_in_std_err": {"median": float(np.median(dist)), "max": float(dist.max()),
-                                              "frac_within_0.1": float(np.mean(dist <= 0.1))}}
+                                              "frac_within_0.1": float(np.mean(dist <= 0.1))},
+            "fp32_final_under_fp64_rules_in_std_err": {"median": float(np.median(same)), "max": float(same.max()),
+                                                       "frac_within_0.1": float(np.mean(same <= 0.1))}}
 
 
 def serving_form(ctx, bmc, inputs, duration: float, rate: float, precision: int, N: int = 256,

@@ -329,6 +329,31 @@ def maxcall5_form(ctx, bmc, inputs) -> dict:
                         "seed 1", "runs": rows}
 
 
+def mincall_form(ctx, bmc, inputs) -> dict:
+    """Calls on the minimum of 2 and 3 independent assets (S0 = 100, K = 100,
+    r = 0.05, delta = 0.1, sigma = 0.2, T = 3, 9 dates): I&Z with d exercise
+    regions (J = 128, N_1 = 5000; plain and secant searches) and CMC
+    (N = n = 4096), 1e6 final paths, FP32 beside FP64 on the same GPU."""
+    rows = []
+    for d in (2, 3):
+        spec = inputs.min_call(d, 100.0)
+        for name, method, kw in (
+                ("iz_plain", bmc.IZ, dict(N=128, n=5000, iz_search=bmc.SEARCH_PLAIN)),
+                ("iz_secant", bmc.IZ, dict(N=128, n=5000, iz_search=bmc.SEARCH_SECANT)),
+                ("cmc", bmc.CMC, dict(N=4096, n=4096))):
+            kw = dict(kw, n_final=1_000_000, seed=1)
+            bmc.bmc_price(ctx, spec, method, bmc.FP32, **kw)   # warm
+            a = bmc.bmc_price(ctx, spec, method, bmc.FP32, **kw)
+            b = bmc.bmc_price(ctx, spec, method, bmc.FP64, **kw)
+            rows.append({"d": d, "method": name, "price_fp32": a["price"], "price_fp64": b["price"],
+                         "std_err": b["std_err"], "fp32_error_in_std_err": abs(a["price"] - b["price"]) / b["std_err"],
+                         "ms_fp32": 1e3 * a["seconds"], "ms_fp64": 1e3 * b["seconds"],
+                         "inner_path_steps_per_s_fp32": a["inner_path_steps"] / a["calc_seconds"],
+                         "iz_iterations": a["iz_iterations"]})
+    return {"workload": "call on the min of 2 and 3 independent assets, I&Z (J=128, N_1=5000) and CMC "
+                        "(N=n=4096), 1e6 final paths, seed 1", "runs": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +375,7 @@ def main():
     ap.add_argument("--no-iz", action="store_true", help="skip the I&Z max-call form (Tables 1-3)")
     ap.add_argument("--no-ada", action="store_true", help="skip the AdaBoost-stump line")
     ap.add_argument("--no-maxcall5", action="store_true", help="skip the five-asset max-call line")
+    ap.add_argument("--no-mincall", action="store_true", help="skip the min-call line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the pricer runs on a single device and this build has no "
@@ -452,6 +478,8 @@ def main():
         out["maxcall5"] = maxcall5_form(ctx, bmc, inputs)
     if not args.no_iz:
         out["iz"] = iz_form(ctx, bmc, inputs)
+    if not args.no_mincall:
+        out["mincall"] = mincall_form(ctx, bmc, inputs)
     if args.serve_seconds > 0:
         out["serving"] = {
             "workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s from a catalogue "

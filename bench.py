@@ -354,6 +354,14 @@ def mincall_form(ctx, bmc, inputs) -> dict:
                         "(N=n=4096), 1e6 final paths, seed 1", "runs": rows}
 
 
+_T0 = time.perf_counter()
+
+
+def note(msg: str) -> None:
+    """Progress line on stderr (stdout carries only the result line)."""
+    print(f"bench: {msg} ({time.perf_counter() - _T0:.1f} s)", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -405,10 +413,13 @@ def main():
         torch.cuda.synchronize()
         return res, time.perf_counter() - t0
 
+    note("launch shapes tuned")
     res32, t32 = timed(bmc.FP32, args.steps, args.warmup)
+    note("FP32 prices timed")
     fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(2, args.steps // 2)
     if fp64_steps > 0:
         res64, t64 = timed(bmc.FP64, fp64_steps, 1)
+        note("FP64 prices timed")
     else:   # profiling runs of the FP32 form only
         res64, t64, fp64_steps = res32, t32, args.steps
 
@@ -463,6 +474,7 @@ def main():
     if args.batch > 0:
         bctx = bmc.Context(0)
         out["batch"] = batch_form(bctx, bmc, inputs, args.batch, args.batch_N, 100_000)
+        note("batch done")
         bctx.close()
     # the same workload with the AdaBoost-stump classifier (64 rounds)
     ada = [] if args.no_ada else [bmc.bmc_price(ctx, spec, bmc.CMC_ADA, bmc.FP32, **kw) for _ in range(3)]
@@ -474,12 +486,17 @@ def main():
         "inner_path_steps_per_s": ada[-1]["inner_path_steps"] / float(np.median([r["calc_seconds"] for r in ada])),
         "price": ada[-1]["price"], "std_err": ada[-1]["std_err"],
         "logitboost_price": p32["price"]}
+    if not args.no_ada:
+        note("AdaBoost done")
     if not args.no_maxcall5:
         out["maxcall5"] = maxcall5_form(ctx, bmc, inputs)
+        note("five-asset max-call done")
     if not args.no_iz:
         out["iz"] = iz_form(ctx, bmc, inputs)
+        note("I&Z done")
     if not args.no_mincall:
         out["mincall"] = mincall_form(ctx, bmc, inputs)
+        note("min-call done")
     if args.serve_seconds > 0:
         out["serving"] = {
             "workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s from a catalogue "
@@ -489,8 +506,10 @@ def main():
             "fp64": serving_form(ctx, bmc, inputs, args.serve_seconds, args.serve_rate, bmc.FP64),
             "saturation_fp32": saturation_form(ctx, bmc, inputs, bmc.FP32),
             "saturation_fp64": saturation_form(ctx, bmc, inputs, bmc.FP64)}
+        note("serving done")
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(spec, args.N, args.n, args.seed, args.cpu_seconds)
+        note("CPU baseline done")
     print(json.dumps(out), flush=True)
 
 

@@ -392,6 +392,28 @@ def test_iz_search_parity(bmc, ctx, orc, torch_mod, inputs, case, mode):
     assert case not in ("maxcall2", "mincall2") or dropped < 2 * 2 * J
 
 
+@pytest.mark.parametrize("max_iter,eps", [(1, 0.01), (2, 0.01), (3, 0.01), (4, 0.01), (5, 0.01), (8, 1e-4),
+                                          (9, 1e-4), (100, 1e-5)])
+def test_iz_search_iteration_limits(bmc, ctx, orc, torch_mod, inputs, max_iter, eps):
+    """Searches cut off by the iteration limit (points left without a boundary
+    point) and long searches with a tight tolerance: identical iteration
+    counts, boundary points and step totals, whatever the number of
+    iterations enqueued before the host learns that every point has stopped;
+    the same context searches again right after."""
+    spec = inputs.max_call(3, 100.0)
+    table = orc.price(spec, orc.IZ, 16, 300, 256, 2, nthreads=NT_CPU)["rules"]
+    rules = gpu_rules(bmc, ctx, spec, bmc.IZ, table)
+    for m, region in ((spec.n_dates - 1, 0), (4, 2)):
+        x = orc.points_iz(spec, m, 33, region=region)
+        s, it, steps = bmc.bmc_iz_search(ctx, spec, rules, m, dev(torch_mod, x), 700, 5, eps=eps,
+                                         max_iter=max_iter, region=region)
+        ref = orc.iz_search(spec, table, m, x, 700, 5, eps=eps, max_iter=max_iter, nthreads=NT_CPU, region=region)
+        assert np.array_equal(host(it), ref["iters"]), (m, region)
+        assert_close(host(s), ref["s"], spec.K, what=f"s* m={m} max_iter={max_iter}")
+        assert steps == ref["steps"]
+        assert int(host(it).max()) <= max_iter
+
+
 # --- final pricing and the whole pricer ----------------------------------------------
 
 def test_final_price_parity(bmc, ctx, orc, torch_mod, c1_rules):

@@ -173,14 +173,25 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 
     ACC acc;
     uint32_t steps = 0;
-    uint32_t p = lo + threadIdx.x;
+    // Paths are handed out per wavefront: wave w owns the contiguous range
+    // [wlo, whi) of the job's paths.  Each lane starts on one; whenever paths
+    // stop, the lanes whose path stopped take the range's next paths in lane
+    // order (ballot and lane rank), so no lane idles while its wave has paths
+    // left.  The assignment depends only on the paths' lengths, so results
+    // repeat bit for bit.
+    const uint32_t nwave = (blockDim.x + 63) >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t cnt = hi > lo ? hi - lo : 0u;
+    const uint32_t share = (cnt + nwave - 1) / nwave;
+    const uint32_t wlo = lo + min(cnt, wv * share), whi = lo + min(cnt, (wv + 1) * share);
+    uint32_t p = wlo + lane;
+    uint32_t nxt = wlo + min(64u, blockDim.x - 64u * wv);
     int k = m + 1;
     // Matrix-core steps need every lane of the wavefront (operands come from
     // neighbouring lanes): the loop runs while any lane has a path, and lanes
     // without one step through dummy paths whose payoffs are not counted.
-    auto more = [&]() { return MF ? __any(p < hi) != 0 : p < hi; };
+    auto more = [&]() { return MF ? __any(p < whi) != 0 : p < whi; };
     while (more()) {
-        const bool live = MF ? p < hi : true;
+        const bool live = MF ? p < whi : true;
         const R dtk = dtv[k], sk = sdtv[k];
         // Opaque per-iteration offset: keeps the coefficient loads inside the
         // loop instead of hoisted into registers.
@@ -263,12 +274,14 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
                 }
             }
         }
+        const uint64_t ended = __ballot(stop && live);
         if (stop) {
             if (live) {
                 acc.add((double)phi * disc[k]);
                 steps += (uint32_t)(k - m);
+                p = nxt + __builtin_amdgcn_mbcnt_hi((uint32_t)(ended >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)ended, 0u));
             }
-            p += blockDim.x;
             k = m + 1;
 #pragma unroll
             for (int i = 0; i < D; ++i)
@@ -276,6 +289,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
         } else {
             ++k;
         }
+        nxt += (uint32_t)__popcll(ended);
     }
 
     double s1 = acc.sum(), s2 = acc.sumsq(), s3 = (double)steps;

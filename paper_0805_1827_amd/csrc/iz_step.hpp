@@ -5,15 +5,29 @@
 
 namespace bmc {
 
-// Per point: merge the chunk partials in chunk order.
+// Per point: merge the chunk partials in chunk order.  The point's partials
+// are contiguous; eight chunks' loads are issued before their adds, which
+// keep the order of the sequential merge.
 __device__ __forceinline__ void merge_serial(const double* __restrict__ part, uint32_t nchunk, int64_t j, double& s,
                                              double& q, double& c)
 {
     s = 0.0;
     q = 0.0;
     c = 0.0;
-    for (uint32_t ch = 0; ch < nchunk; ++ch) {
-        const double* o = part + ((size_t)j * nchunk + ch) * 3;
+    const double* o = part + (size_t)j * nchunk * 3;
+    uint32_t ch = 0;
+    for (; ch + 8 <= nchunk; ch += 8, o += 24) {
+        double v[24];
+#pragma unroll
+        for (int u = 0; u < 24; ++u) v[u] = o[u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            s += v[3 * u];
+            q += v[3 * u + 1];
+            c += v[3 * u + 2];
+        }
+    }
+    for (; ch < nchunk; ++ch, o += 3) {
         s += o[0];
         q += o[1];
         c += o[2];

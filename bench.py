@@ -386,7 +386,7 @@ def main():
     ap.add_argument("--no-mincall", action="store_true", help="skip the min-call line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the pricer runs on a single device and this build has no "
+        print("bench.py measures one GPU: the pricer runs on a single device and has no "
               "multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 

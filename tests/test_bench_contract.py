@@ -1,0 +1,60 @@
+"""Host-side pieces of bench.py: the one-GPU refusal and the algorithmic
+issue-slot model behind the roofline fraction (no GPU needed)."""
+import subprocess
+import sys
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parent.parent
+sys.path.insert(0, str(ROOT))
+
+import bench  # noqa: E402
+from paper_0805_1827_amd import inputs  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "--gpus must be 1" in r.stderr
+    assert r.stdout == ""
+
+
+def test_slot_model_of_the_headline_step():
+    # d = 5 geometric put under a CMC rule: 2 Philox blocks (10 rounds of two
+    # 32x32->64 multiplies and four xors), 3 Box-Muller pairs, 2d + d(d+1)/2
+    # step FMAs, one exp and d + 3 payoff ops, 3d + 4 rule ops
+    c = bench.COST
+    philox = 2 * 10 * (2 * c["mul64"] + 4 * c["int"])
+    bm = 3 * (4 + 1 + 2 + 4 * c["trans"])
+    step = 5 + 15 + 5
+    pay = c["trans"] + 8
+    rule = 19
+    assert bench.slots_per_step_fp32(5, inputs.PUT_GEO, 0) == pytest.approx(philox + bm + step + pay + rule)
+    assert bench.slots_per_step_fp32(5, inputs.PUT_GEO, 0) == pytest.approx(191.7)
+
+
+def test_slot_model_leaves_matrix_core_correlation_out():
+    # from d = 9 the correlation runs on the matrix cores: the VALU count drops
+    # by d(d+1)/2 and the flops are reported separately
+    v8 = bench.slots_per_step_fp32(8, inputs.PUT_GEO, 0)
+    v9 = bench.slots_per_step_fp32(9, inputs.PUT_GEO, 0)
+    assert not bench.uses_mfma(8) and bench.uses_mfma(9)
+    assert v9 < v8 + 40
+    assert bench.mfma_flops_per_step(9) == 90.0
+    for d in range(1, 65):
+        for pay in (inputs.PUT_BASKET, inputs.PUT_GEO, inputs.CALL_MAX, inputs.CALL_MIN):
+            assert bench.slots_per_step_fp32(d, pay, 0) > 0
+
+
+def test_traffic_record_is_tied_to_the_kernel_sources(tmp_path, monkeypatch):
+    """The committed HBM traffic is reported only while the kernel sources hash
+    to the profiled version."""
+    rec = (ROOT / "profiles" / "k_cont_geo5_fp32_traffic.json").read_text()
+    fake = tmp_path / "traffic.json"
+    fake.write_text(rec.replace('"src_sha256": "', '"src_sha256": "0'))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", fake)
+    assert bench.measured_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", tmp_path / "missing.json")
+    assert bench.measured_traffic() is None

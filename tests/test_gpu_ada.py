@@ -91,10 +91,12 @@ def specs(inputs):
 @pytest.mark.parametrize("case,N,rounds", [("put1", 1000, 64), ("geo5", 4097, 64), ("maxcall3", 333, 40),
                                            ("basket2", 2048, 64), ("wide12", 1500, 64), ("wide40", 700, 24),
                                            ("put1", 70001, 48), ("wide64", 900, 32), ("mincall2", 66000, 20),
-                                           ("geo5", 20000, 64)])
+                                           ("geo5", 20000, 64), ("geo5", 9830, 64), ("geo5", 9831, 64)])
 def test_ada_fit_parity(bmc, ctx, orc, torch_mod, inputs, case, N, rounds):
-    # three fit forms: training set resident in LDS (small N d), one workgroup
-    # over HBM (geo5 at 20000, wide64), one launch per step (N above 65536)
+    # three fit forms: training set resident in LDS (small N d; geo5 at 9830
+    # is the largest that fits 156 KiB, 9831 the smallest that does not), one
+    # workgroup over HBM (geo5 at 9831 and 20000, wide64), one launch per step
+    # (N above 65536)
     spec = specs(inputs)[case]
     m = max(1, spec.n_dates // 2)
     x = orc.points_cmc(spec, m, N, 9)
@@ -121,6 +123,12 @@ def test_ada_fit_degenerate_and_limits(bmc, ctx, orc, torch_mod, inputs):
     bmc.bmc_fit_rule(ctx, spec, rules, 4, dev(torch_mod, x), dev(torch_mod, np.full(50, 10.0)))
     assert np.all(bmc.bmc_rules_get(rules, 4) == 0.0)
     x = orc.points_cmc(spec, 4, 300, 2)
+    # every in-the-money point labelled exercise (C = 0): the constant stump
+    # is perfect, one round, then stop
+    perfect = orc.fit_ada(spec, x, np.zeros(300), rounds=64)
+    bmc.bmc_fit_rule(ctx, spec, rules, 4, dev(torch_mod, x), dev(torch_mod, np.zeros(300)), rounds=64)
+    same_row(spec, bmc.bmc_rules_get(rules, 4), perfect)
+    assert int(perfect[1:3].sum()) == 1
     cont = np.maximum(spec.K - x[0] - 1.0, 0.0) + 0.5
     bmc.bmc_fit_rule(ctx, spec, rules, 4, dev(torch_mod, x), dev(torch_mod, cont), rounds=1)
     same_row(spec, bmc.bmc_rules_get(rules, 4), orc.fit_ada(spec, x, cont, rounds=1))

@@ -19,7 +19,9 @@
  *  - bmc_ctx and bmc_rules are opaque, library-owned, freed by their destroy
  *    calls.  A context is not thread-safe; use one per host thread.
  *  - Random numbers: Philox4x32-10 keyed by (seed, stream << 16 | date), with
- *    counters (step-block, path, point, 0); seeds must fit in 32 bits.
+ *    counters (step-block, path, point, region): region is the I&Z exercise
+ *    region of a boundary-search point, 0 everywhere else; seeds must fit in
+ *    32 bits.
  */
 #ifndef BMC_H
 #define BMC_H
@@ -47,7 +49,8 @@ typedef enum {
 
 /* Payoffs (Section 2.1-2.2, Section 3.2): arithmetic-basket put
  * (K - mean S)^+, call on the maximum (max S - K)^+, geometric-average put
- * (K - (prod S)^(1/d))^+.  For d = 1 the two puts coincide. */
+ * (K - (prod S)^(1/d))^+, call on the minimum (min S - K)^+.  For d = 1 the
+ * two puts coincide, and so do the two calls. */
 typedef enum { BMC_PUT_BASKET = 0, BMC_CALL_MAX = 1, BMC_PUT_GEO = 2, BMC_CALL_MIN = 3 } bmc_payoff;
 
 /* I&Z boundary-point search: the plain fixed point s <- G(s) (Section 2.4), or

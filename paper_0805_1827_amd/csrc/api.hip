@@ -789,11 +789,18 @@ bmc_status bmc::sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_
     } else {
         const unsigned long long* best = nullptr;
         if (d - 1 >= 2 && N > 2) {
+            // the generator depends on (J, q) only: searched once, kept for
+            // the following dates and calls
             if ((e = ctx->korobov.ensure(sizeof(unsigned long long)))) return hip_fail(e, "korobov");
-            if ((e = hipMemsetAsync(ctx->korobov.ptr, 0, sizeof(unsigned long long), ctx->stream)))
-                return hip_fail(e, "korobov");
-            if ((e = launch_korobov(N, d - 1, (unsigned long long*)ctx->korobov.ptr, ctx->stream)))
-                return hip_fail(e, "korobov");
+            if (ctx->korobov_J != N || ctx->korobov_q != d - 1) {
+                ctx->korobov_J = -1;
+                if ((e = hipMemsetAsync(ctx->korobov.ptr, 0, sizeof(unsigned long long), ctx->stream)))
+                    return hip_fail(e, "korobov");
+                if ((e = launch_korobov(N, d - 1, (unsigned long long*)ctx->korobov.ptr, ctx->stream)))
+                    return hip_fail(e, "korobov");
+                ctx->korobov_J = N;
+                ctx->korobov_q = d - 1;
+            }
             best = (const unsigned long long*)ctx->korobov.ptr;
         }
         if ((e = launch_lattice(ds, d, date, region, nreg, N, best, x, ctx->stream))) return hip_fail(e, "lattice");

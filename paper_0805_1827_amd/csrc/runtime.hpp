@@ -54,6 +54,9 @@ struct bmc_ctx {
     // replayed while the signature (launch shapes and buffers) is unchanged
     std::vector<hipEvent_t> ev_pool;   // reusable timing events
     hipEvent_t poll_ev[2] = {nullptr, nullptr};   // I&Z search progress polls (host_io + 128)
+    // (J, q) whose Korobov generator the korobov buffer holds (-1: none)
+    int64_t korobov_J = -1;
+    int korobov_q = -1;
     bmc::DBuf srules;                  // rule table of bmc_price when the caller keeps none
     bool graphs = false;
     std::string graph_sig;

@@ -156,6 +156,12 @@ def test_iz_lattice_parity(bmc, ctx, orc, torch_mod, inputs):
                 x = host(bmc.bmc_sample_points(ctx, spec, bmc.IZ, m, J, 1, region=region))
                 assert_close(x, orc.points_iz(spec, m, J, region=region), spec.K, rel=1e-12,
                              what=f"lattice m={m} region={region}")
+    # the context keeps the last (J, q) generator: back to earlier shapes,
+    # twice in a row
+    for spec, J in ((inputs.geometric_put5(), 256), (inputs.geometric_put5(), 256),
+                    (inputs.min_call(3, [95.0, 100.0, 108.0], sigma=[0.2, 0.3, 0.25]), 97)):
+        x = host(bmc.bmc_sample_points(ctx, spec, bmc.IZ, 2, J, 1))
+        assert_close(x, orc.points_iz(spec, 2, J), spec.K, rel=1e-12, what=f"lattice again J={J}")
 
 
 # --- continuation estimates -------------------------------------------------

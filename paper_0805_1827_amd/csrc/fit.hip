@@ -149,22 +149,30 @@ hipError_t launch_fit_cmc(const DevSpec* s, int d, const double* x, const double
 
 // ---------------------------------------------------------------------------
 // I&Z regression of one region: tile normal equations of ln s* on
-// xi = [1, v, v_a v_c] over the converged points (the region's own row holds
-// s*_j > 0; v over the other assets in increasing order), then one solve.
+// xi = [1, v, v_a v_c] over the converged points (s*_j > 0; v over the other
+// assets in increasing order), then one solve.  Regions region0 + y side by
+// side (blockIdx.y = y): region y's J points are columns y J .. y J + J - 1 of
+// x (rows of ld entries), its partials and solve scratch at y times the
+// given strides, its boundary block at y p of the row.  s* comes from
+// sstar[y J + j] when given, else from the region's own row of x.
 
-__global__ void k_fitiz_part(const DevSpec* __restrict__ s, const double* __restrict__ x, int region, int64_t J,
-                             int64_t ld, int p, double* part)
+__global__ void k_fitiz_part(const DevSpec* __restrict__ s, const double* __restrict__ x,
+                             const double* __restrict__ sstar, int region0, int64_t J, int64_t ld, int p,
+                             double* part, size_t part_stride)
 {
     extern __shared__ double sh[];
     const SpecT<double>& S = s->f64;
     const int d = S.d, q = d - 1;
     const int T = blockDim.x;
+    const int region = region0 + (int)blockIdx.y;
+    x += (size_t)blockIdx.y * J;
+    part += (size_t)blockIdx.y * part_stride;
     double* xi = sh;                     // [T][p]
     double* ym = xi + (size_t)T * p;     // [T][2]
     const int64_t j0 = (int64_t)blockIdx.x * T;
     const int64_t j = j0 + threadIdx.x;
     const int tl = threadIdx.x;
-    const double sst = j < J ? x[region * ld + j] : -1.0;
+    const double sst = j >= J ? -1.0 : (sstar ? sstar[(size_t)blockIdx.y * J + j] : x[region * ld + j]);
     if (sst > 0.0) {
         xi[tl * p] = 1.0;
         for (int a = 0; a < q; ++a) xi[tl * p + 1 + a] = log(x[(a < region ? a : a + 1) * ld + j]) - S.lnK;
@@ -201,10 +209,14 @@ __global__ void k_fitiz_part(const DevSpec* __restrict__ s, const double* __rest
 }
 
 __global__ void k_fitiz_solve(const DevSpec* __restrict__ s, int p, int ntiles, const double* __restrict__ part,
-                              double* Awork, double* row64, float* row32)
+                              size_t part_stride, double* Awork, size_t awork_stride, double* row64, float* row32)
 {
     __shared__ int flag;
     __shared__ double lam, cnt;
+    part += (size_t)blockIdx.x * part_stride;
+    Awork += (size_t)blockIdx.x * awork_stride;
+    row64 += (size_t)blockIdx.x * p;
+    row32 += (size_t)blockIdx.x * p;
     // no converged point: a boundary no price crosses (puts below, the call above)
     const double never = (s->f64.payoff == CALL_MAX || s->f64.payoff == CALL_MIN) ? 1e300 : -1e300;
     const int npairs = p * (p + 1) / 2;
@@ -251,17 +263,23 @@ size_t fitiz_scratch_doubles(int64_t J, int p)
 }
 
 hipError_t launch_fit_iz(const DevSpec* s, int d, int region, const double* x, int64_t J, int64_t ld,
-                         double* scratch, double* row64, float* row32, hipStream_t st)
+                         double* scratch, double* row64, float* row32, hipStream_t st, int nreg,
+                         const double* sstar)
 {
     const int p = rule_width(IZ, d);
     const int T = fitiz_tile(p);
     const int tiles = (int)((J + T - 1) / T);
     const int npairs = p * (p + 1) / 2;
+    // per region: tile partials, then the solve's work area
+    const size_t part_stride = (size_t)tiles * (npairs + p + 1);
+    const size_t region_stride = fitiz_scratch_doubles(J, p);
     double* part = scratch;
-    double* Awork = scratch + (size_t)tiles * (npairs + p + 1);
+    double* Awork = scratch + part_stride;
     const size_t lds = sizeof(double) * ((size_t)T * p + 2 * T);
-    hipLaunchKernelGGL(k_fitiz_part, dim3(tiles), dim3(T), lds, st, s, x, region, J, ld, p, part);
-    hipLaunchKernelGGL(k_fitiz_solve, dim3(1), dim3(256), 0, st, s, p, tiles, part, Awork, row64, row32);
+    hipLaunchKernelGGL(k_fitiz_part, dim3(tiles, nreg), dim3(T), lds, st, s, x, sstar, region, J, ld, p, part,
+                       region_stride);
+    hipLaunchKernelGGL(k_fitiz_solve, dim3(nreg), dim3(256), 0, st, s, p, tiles, part, region_stride, Awork,
+                       region_stride, row64, row32);
     return hipGetLastError();
 }
 

@@ -153,10 +153,14 @@ size_t fitiz_scratch_doubles(int64_t J, int p);
 size_t fit_ada_scratch_bytes(int64_t N, int d);
 hipError_t launch_fit_ada(const DevSpec* s, int d, const double* x, const double* cont, int64_t N, int rounds,
                           void* scratch, double* row64, float* row32, int width, hipStream_t st);
-// Boundary block of one region (row64/row32 point at the block) from J
-// points in rows of ld entries.
+// Boundary blocks of regions region .. region + nreg - 1 (row64/row32 point
+// at the first one; the others follow every p entries) from nreg sets of J
+// points side by side in rows of ld entries (region r's in columns r J ..);
+// s* from sstar[r J + j] when given, else from each region's own row of x.
+// Scratch: nreg fitiz_scratch_doubles(J, p).
 hipError_t launch_fit_iz(const DevSpec* s, int d, int region, const double* x, int64_t J, int64_t ld,
-                         double* scratch, double* row64, float* row32, hipStream_t st);
+                         double* scratch, double* row64, float* row32, hipStream_t st, int nreg = 1,
+                         const double* sstar = nullptr);
 
 hipError_t launch_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t M, uint32_t* out,
                          hipStream_t st);

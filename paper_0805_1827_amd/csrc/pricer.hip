@@ -148,14 +148,16 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
                                 s_out, iters, nullptr, tune, tally);
             if (st) break;
             timer.mark(PH_FIT);
-            for (int r = 0; r < regions && !st; ++r) {
-                // s* of region r into the region's own asset row of its columns
-                double* xr = x + (size_t)r * N;
-                if ((e = hipMemcpyAsync(xr + (size_t)r * NR, s_out + (size_t)r * N, sizeof(double) * N,
-                                        hipMemcpyDeviceToDevice, ctx->stream)))
-                    st = hip_fail(e, "boundary copy");
-                else
-                    st = fit_rule_impl(ctx, ds, d, rules, m, xr, nullptr, N, rounds, r, NR);
+            // every region's regression in one launch pair, s* read from the
+            // search output (region r's points in columns r N ..)
+            {
+                const int p = rule_width(BMC_IZ, d);
+                if ((e = ctx->fit.ensure(sizeof(double) * fitiz_scratch_doubles(N, p) * regions)))
+                    st = hip_fail(e, "fit scratch");
+                else if ((e = launch_fit_iz((const DevSpec*)ds, d, 0, x, N, NR, (double*)ctx->fit.ptr,
+                                            rules->w64 + (size_t)m * rules->width,
+                                            rules->w32 + (size_t)m * rules->width, ctx->stream, regions, s_out)))
+                    st = hip_fail(e, "fit launch");
             }
             if (st) break;
             timer.mark(-1);

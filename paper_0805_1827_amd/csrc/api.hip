@@ -873,7 +873,10 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     auto read_poll = [&](bool wait) -> hipError_t {
         hipEvent_t ev = ctx->poll_ev[polls_read & 1];
         const hipError_t q = wait ? hipEventSynchronize(ev) : hipEventQuery(ev);
-        if (q == hipErrorNotReady) return hipSuccess;
+        if (q == hipErrorNotReady) {
+            (void)hipGetLastError();   // not an error: keep it out of the next launch check
+            return hipSuccess;
+        }
         if (q != hipSuccess) return q;
         if (poll_host[polls_read & 1] == 0) done = true;
         ++polls_read;

@@ -307,44 +307,68 @@ __global__ void __launch_bounds__(256) k_ada_update(int t, double* w, const int8
 __global__ void k_ada_fold(int nf, int width, const AdaState* __restrict__ st, double* row64, float* row32)
 {
 #pragma clang fp contract(off)
-    if (threadIdx.x != 0) return;
+    // the state in LDS first, the row built in LDS, then written out: the
+    // insertion below reads back what it wrote, which in global memory would
+    // cost a round trip per step
+    __shared__ double alpha_s[ADA_TMAX], lo_s[NFMAX], hi_s[NFMAX];
+    __shared__ int f_s[ADA_TMAX], k_s[ADA_TMAX], s_s[ADA_TMAX];
+    __shared__ double out[1 + NFMAX + 2 * ADA_TMAX];
+    __shared__ int used;
     const int T = st->T;
-    double base = 0.0;
-    for (int t = 0; t < T; ++t) base -= st->alpha[t] * (double)st->s[t];
-    row64[0] = base;
-    int at = 1 + nf;
-    for (int f = 0; f < nf; ++f) {
-        // the feature's stumps inserted by threshold, stable (round order on
-        // ties), straight into the row: thresholds at at.., increments after
-        // the last stump of the feature, summed once the count is known
-        int cnt = 0;
-        for (int t = 0; t < T; ++t) cnt += st->f[t] == f;
-        double* th = row64 + at;
-        double* de = row64 + at + cnt;
-        int c = 0;
-        const double step = (st->hi[f] - st->lo[f]) / (double)ADA_BINS;
-        for (int t = 0; t < T; ++t) {
-            if (st->f[t] != f) continue;
-            const double v = st->k[t] == 0 ? -1e300 : st->lo[f] + (double)st->k[t] * step;
-            const double dl = 2.0 * st->alpha[t] * (double)st->s[t];
-            int q = c++;
-            for (; q > 0 && th[q - 1] > v; --q) {
-                th[q] = th[q - 1];
-                de[q] = de[q - 1];
-            }
-            th[q] = v;
-            de[q] = dl;
-        }
-        double run = 0.0;
-        for (int e = 0; e < cnt; ++e) {
-            run += de[e];
-            de[e] = run;
-        }
-        at += 2 * cnt;
-        row64[1 + f] = (double)cnt;
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        alpha_s[t] = st->alpha[t];
+        f_s[t] = st->f[t];
+        k_s[t] = st->k[t];
+        s_s[t] = st->s[t];
     }
-    for (int e = at; e < width; ++e) row64[e] = 0.0;
-    for (int e = 0; e < width; ++e) row32[e] = (float)row64[e];
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+        lo_s[f] = st->lo[f];
+        hi_s[f] = st->hi[f];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double base = 0.0;
+        for (int t = 0; t < T; ++t) base -= alpha_s[t] * (double)s_s[t];
+        out[0] = base;
+        int at = 1 + nf;
+        for (int f = 0; f < nf; ++f) {
+            // the feature's stumps inserted by threshold, stable (round order
+            // on ties): thresholds at at.., increments after the last stump of
+            // the feature, summed once the count is known
+            int cnt = 0;
+            for (int t = 0; t < T; ++t) cnt += f_s[t] == f;
+            double* th = out + at;
+            double* de = out + at + cnt;
+            int c = 0;
+            const double step = (hi_s[f] - lo_s[f]) / (double)ADA_BINS;
+            for (int t = 0; t < T; ++t) {
+                if (f_s[t] != f) continue;
+                const double v = k_s[t] == 0 ? -1e300 : lo_s[f] + (double)k_s[t] * step;
+                const double dl = 2.0 * alpha_s[t] * (double)s_s[t];
+                int q = c++;
+                for (; q > 0 && th[q - 1] > v; --q) {
+                    th[q] = th[q - 1];
+                    de[q] = de[q - 1];
+                }
+                th[q] = v;
+                de[q] = dl;
+            }
+            double run = 0.0;
+            for (int e = 0; e < cnt; ++e) {
+                run += de[e];
+                de[e] = run;
+            }
+            at += 2 * cnt;
+            out[1 + f] = (double)cnt;
+        }
+        used = at;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < width; e += blockDim.x) {
+        const double v = e < used ? out[e] : 0.0;
+        row64[e] = v;
+        row32[e] = (float)v;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -569,64 +569,72 @@ __global__ void __launch_bounds__(ADA_BT) k_ada_fit_block(const DevSpec* __restr
 // labels and bins of the in-the-money points.
 inline size_t ada_lds_bytes(int64_t N, int nf)
 {
-    return 2 * sizeof(unsigned long long) * nf * ADA_BINS * 2 + (size_t)N * (sizeof(double) + 1 + nf);
+    return 2 * sizeof(unsigned long long) * nf * ADA_BINS * 2 +
+           (size_t)N * (sizeof(double) + sizeof(int32_t) + 1 + nf);
 }
 
 // The whole fit of a date in one workgroup with the training set resident in
-// LDS: the in-the-money points are packed (in arrival order: every step after
-// is independent of the order, the histogram sums being exact integers), and
-// each round's weight update adds the updated weights straight into the next
-// round's histogram, so a round costs two barriers.  Same stumps, weights and
-// state as k_ada_fit_block.
-__global__ void __launch_bounds__(ADA_BT) k_ada_fit_lds(const DevSpec* __restrict__ s, const double* __restrict__ x,
-                                                       const double* __restrict__ cont, int64_t N, int rounds,
-                                                       double* psi, AdaState* st)
+// LDS.  k_ada_prep (one thread per point, many workgroups) has computed the
+// features psi, labels y, weights w and the per-block feature extremes,
+// largest weight and count; this workgroup packs the in-the-money points
+// (in arrival order: every step after is independent of the order, the
+// histogram sums being exact integers), merges the block extremes, and
+// runs the rounds, each round's weight update adding the updated weights
+// straight into the next round's histogram (two barriers a round).  Same
+// stumps, weights and state as k_ada_fit_block.
+__global__ void __launch_bounds__(ADA_BT) k_ada_fit_lds(int64_t N, int nf, int rounds, const double* __restrict__ psi,
+                                                       const double* __restrict__ w, const int8_t* __restrict__ y,
+                                                       const double* __restrict__ part, int nblocks, AdaState* st)
 {
-    extern __shared__ unsigned long long hs[];   // [2][nf][B][2], w [N], y [N], bins [nf][N]
-    __shared__ double red[2][ADA_BT / 64];
+    extern __shared__ unsigned long long hs[];   // [2][nf][B][2], w [N], point [N], y [N], bins [nf][N]
     __shared__ long long best_e[NFMAX];
     __shared__ int best_k[NFMAX], best_s[NFMAX], n_pack;
     __shared__ long long total;
-    __shared__ double lo_s[NFMAX], hi_s[NFMAX], inv_s[NFMAX];
-    const SpecT<double>& S = s->f64;
-    const int d = S.d, nf = d + 1, nh = nf * ADA_BINS * 2, tid = threadIdx.x;
+    __shared__ double lo_s[NFMAX], hi_s[NFMAX], inv_s[NFMAX], wmax_s, cnt_s;
+    const int nh = nf * ADA_BINS * 2, tid = threadIdx.x;
     double* wl = reinterpret_cast<double*>(hs + 2 * nh);
-    int8_t* yl = reinterpret_cast<int8_t*>(wl + N);
+    int32_t* jl = reinterpret_cast<int32_t*>(wl + N);
+    int8_t* yl = reinterpret_cast<int8_t*>(jl + N);
     uint8_t* bl = reinterpret_cast<uint8_t*>(yl + N);
     if (tid == 0) n_pack = 0;
     __syncthreads();
     for (int64_t j = tid; j < N; j += ADA_BT) {
-        const double pay = ada_payoff(S, x, N, j);
-        if (pay > 0.0) {
+        const int8_t yj = y[j];
+        if (yj != 0) {
             const int q = atomicAdd(&n_pack, 1);
-            for (int i = 0; i < d; ++i) psi[i * N + q] = log(x[i * N + j]) - S.lnK;
-            psi[d * N + q] = pay / S.K;
-            const double beta = pay - cont[j];
-            yl[q] = beta > 0.0 ? 1 : -1;
-            wl[q] = fabs(beta);
+            yl[q] = yj;
+            wl[q] = w[j];
+            jl[q] = (int32_t)j;
         }
+    }
+    // feature extremes, largest weight and count from the blocks' partials
+    // (minimum, maximum and an integer count: order-free)
+    const size_t ps = 2 * (size_t)nf + 2;
+    for (int f = tid; f < nf; f += ADA_BT) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int b = 0; b < nblocks; ++b) {
+            lo = fmin(lo, part[b * ps + 2 * f]);
+            hi = fmax(hi, part[b * ps + 2 * f + 1]);
+        }
+        const double inv = hi > lo ? (double)ADA_BINS / (hi - lo) : 0.0;
+        st->lo[f] = lo_s[f] = lo;
+        st->hi[f] = hi_s[f] = hi;
+        st->inv[f] = inv_s[f] = inv;
+    }
+    if (tid == ADA_BT - 1) {
+        double cmax = 0.0, cnt = 0.0;
+        for (int b = 0; b < nblocks; ++b) {
+            cmax = fmax(cmax, part[b * ps + 2 * nf]);
+            cnt += part[b * ps + 2 * nf + 1];
+        }
+        wmax_s = cmax;
+        cnt_s = cnt;
     }
     __syncthreads();
     const int nI = n_pack;
-    for (int f = 0; f < nf; ++f) {
-        double a = INFINITY, b = -INFINITY;
-        for (int q = tid; q < nI; q += ADA_BT) {
-            a = fmin(a, psi[(int64_t)f * N + q]);
-            b = fmax(b, psi[(int64_t)f * N + q]);
-        }
-        ada_block_reduce(a, b, true, red);
-        if (tid == 0) {
-            const double inv = b > a ? (double)ADA_BINS / (b - a) : 0.0;
-            st->lo[f] = lo_s[f] = a;
-            st->hi[f] = hi_s[f] = b;
-            st->inv[f] = inv_s[f] = inv;
-        }
-    }
-    double wmax = 0.0, unused = 0.0;
-    for (int q = tid; q < nI; q += ADA_BT) wmax = fmax(wmax, wl[q]);
-    ada_block_reduce(wmax, unused, false, red);   // ends with a barrier: lo_s .. inv_s are visible
+    const double wmax = wmax_s;
     int e2 = 0;
-    frexp((double)nI * wmax, &e2);   // total weight < 2^e2
+    frexp((double)(int)cnt_s * wmax, &e2);   // total weight < 2^e2
     const int shift = 50 - e2;
     bool stop = nI == 0 || !(wmax > 0.0);
     if (tid == 0) {
@@ -638,7 +646,7 @@ __global__ void __launch_bounds__(ADA_BT) k_ada_fit_lds(const DevSpec* __restric
     for (int e = tid; e < nh; e += ADA_BT) hs[e] = 0ull;
     for (int q = tid; q < nI; q += ADA_BT)
         for (int f = 0; f < nf; ++f)
-            bl[f * N + q] = (uint8_t)ada_bin(psi[(int64_t)f * N + q], lo_s[f], hi_s[f], inv_s[f]);
+            bl[f * N + q] = (uint8_t)ada_bin(psi[(int64_t)f * N + jl[q]], lo_s[f], hi_s[f], inv_s[f]);
     __syncthreads();
     for (int q = tid; q < nI; q += ADA_BT) {
         const unsigned long long W = (unsigned long long)ada_fixed(wl[q], shift);
@@ -743,8 +751,9 @@ hipError_t launch_fit_ada(const DevSpec* s, int d, const double* x, const double
     }();
     (void)lds_ok;
     if (ada_lds_bytes(N, nf) <= lds_res) {
-        hipLaunchKernelGGL(k_ada_fit_lds, dim3(1), dim3(ADA_BT), ada_lds_bytes(N, nf), st, s, x, cont, N, rounds,
-                           psi, state);
+        hipLaunchKernelGGL(k_ada_prep, dim3(blocks), dim3(256), 0, st, s, x, cont, N, psi, w, y, part);
+        hipLaunchKernelGGL(k_ada_fit_lds, dim3(1), dim3(ADA_BT), ada_lds_bytes(N, nf), st, N, nf, rounds, psi, w, y,
+                           part, blocks, state);
         hipLaunchKernelGGL(k_ada_fold, dim3(1), dim3(64), 0, st, nf, width, state, row64, row32);
         return hipGetLastError();
     }

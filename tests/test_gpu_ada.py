@@ -91,11 +91,11 @@ def specs(inputs):
 @pytest.mark.parametrize("case,N,rounds", [("put1", 1000, 64), ("geo5", 4097, 64), ("maxcall3", 333, 40),
                                            ("basket2", 2048, 64), ("wide12", 1500, 64), ("wide40", 700, 24),
                                            ("put1", 70001, 48), ("wide64", 900, 32), ("mincall2", 66000, 20),
-                                           ("geo5", 20000, 64), ("geo5", 9830, 64), ("geo5", 9831, 64)])
+                                           ("geo5", 20000, 64), ("geo5", 7760, 64), ("geo5", 7761, 64)])
 def test_ada_fit_parity(bmc, ctx, orc, torch_mod, inputs, case, N, rounds):
-    # three fit forms: training set resident in LDS (small N d; geo5 at 9830
-    # is the largest that fits 156 KiB, 9831 the smallest that does not), one
-    # workgroup over HBM (geo5 at 9831 and 20000, wide64), one launch per step
+    # three fit forms: training set resident in LDS (small N d; geo5 at 7760
+    # is the largest that fits 156 KiB, 7761 the smallest that does not), one
+    # workgroup over HBM (geo5 at 7761 and 20000, wide64), one launch per step
     # (N above 65536)
     spec = specs(inputs)[case]
     m = max(1, spec.n_dates // 2)

@@ -420,27 +420,29 @@ __device__ inline void ada_pick_wave(const unsigned long long* h, int f, long lo
             Pp += up;
         }
     }
-    const long long Wm = __shfl(Pm, 63), Wp = __shfl(Pp, 63), Wt = Wm + Wp;
+    // lane 63's totals through the scalar unit
+    auto lane63 = [](long long v) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((unsigned long long)v >> 32), 63);
+        return (long long)(((unsigned long long)hi << 32) | lo);
+    };
+    const long long Wm = lane63(Pm), Wp = lane63(Pp), Wt = Wm + Wp;
     Pm -= m0;   // bins below k
     Pp -= p0;
     const long long Eplus = Pp + (Wm - Pm), Eminus = Wt - Eplus;
-    long long e = Eplus <= Eminus ? Eplus : Eminus;
-    int sg = Eplus <= Eminus ? 1 : -1;
-    int kk = k;
-    if (k == 0 && f > 0) e = LLONG_MAX;   // the constant stump lives on feature 0
+    const long long e = Eplus <= Eminus ? Eplus : Eminus;
+    // one key per lane ordered as (error, k, s = +1 first): errors stay below
+    // 2^50 (the fixed-point total does), so the key fits 57 bits
+    long long key = (e << 7) | ((long long)k << 1) | (Eplus <= Eminus ? 0 : 1);
+    if (k == 0 && f > 0) key = LLONG_MAX;   // the constant stump lives on feature 0
     for (int off = 32; off > 0; off >>= 1) {
-        const long long eo = __shfl_xor(e, off);
-        const int ko = __shfl_xor(kk, off), so = __shfl_xor(sg, off);
-        if (eo < e || (eo == e && ko < kk)) {
-            e = eo;
-            kk = ko;
-            sg = so;
-        }
+        const long long ko = __shfl_xor(key, off);
+        key = ko < key ? ko : key;
     }
     if (k == 0) {
-        best_e[f] = e;
-        best_k[f] = kk;
-        best_s[f] = sg;
+        best_e[f] = key >> 7;
+        best_k[f] = (int)((key >> 1) & 63);
+        best_s[f] = (key & 1) ? -1 : 1;
         if (f == 0) *total = Wt;
     }
 }

@@ -631,15 +631,17 @@ static bmc_status prepare_cont(bmc_ctx* ctx, const void* devspec, int d, int n_d
                                const void* rules64, const void* rules32, int prec, int m, const double* x, int64_t N,
                                const int32_t* ids, const int32_t* n_ids, uint32_t n, uint32_t k0, uint32_t k1,
                                const Tuning* tune, uint32_t slot, uint32_t region_pts, ContArgs& a, int& block,
-                               size_t& lds, int64_t& grid)
+                               size_t& lds, int64_t& grid, double* part = nullptr, const IzFuse* fz = nullptr)
 {
     block = (tune && tune->block > 0) ? tune->block : 256;
     const uint32_t ppt = choose_ppt(ctx, d, prec, N, n, tune);
     const uint32_t per_wg = (uint32_t)block * ppt;
     const uint32_t nchunk = (n + per_wg - 1) / per_wg;
-    const size_t part_bytes = sizeof(double) * 3 * (size_t)N * nchunk;
-    hipError_t e = ctx->part.ensure(part_bytes);
-    if (e) return hip_fail(e, "partials allocation");
+    if (!part) {
+        const size_t part_bytes = sizeof(double) * 3 * (size_t)N * nchunk;
+        hipError_t e = ctx->part.ensure(part_bytes);
+        if (e) return hip_fail(e, "partials allocation");
+    }
     lds = cont_lds_bytes(prec, d, n_dates, width);
     if (lds > cont_lds_limit()) return fail(BMC_EUNSUPPORTED, "rule table too large for LDS (%zu bytes)", lds);
     grid = (int64_t)N * nchunk;
@@ -660,8 +662,17 @@ static bmc_status prepare_cont(bmc_ctx* ctx, const void* devspec, int d, int n_d
     a.k1 = k1;
     a.slot = slot;
     a.region_pts = region_pts;
-    a.part = (double*)ctx->part.ptr;
+    a.part = part ? part : (double*)ctx->part.ptr;
+    a.fz = fz ? *fz : IzFuse{};
     return BMC_OK;
+}
+
+// Chunks per point of a continuation pass (the split prepare_cont makes).
+static uint32_t cont_nchunk(const bmc_ctx* ctx, int d, int prec, int64_t N, uint32_t n, const Tuning* tune)
+{
+    const int block = (tune && tune->block > 0) ? tune->block : 256;
+    const uint32_t per_wg = (uint32_t)block * choose_ppt(ctx, d, prec, N, n, tune);
+    return (n + per_wg - 1) / per_wg;
 }
 
 bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int method,
@@ -669,14 +680,15 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
                          const double* x, int64_t N, const int32_t* ids, const int32_t* n_ids,
                          uint32_t n, uint32_t k0, uint32_t k1, double* cont, double* se,
                          int64_t* steps, double* sums, unsigned long long* steps_total,
-                         const Tuning* tune, uint32_t slot, uint32_t region_pts, uint32_t* nchunk_out)
+                         const Tuning* tune, uint32_t slot, uint32_t region_pts, uint32_t* nchunk_out,
+                         double* part, const IzFuse* fz)
 {
-    ContArgs a;
+    ContArgs a{};
     int block = 256;
     size_t lds = 0;
     int64_t grid = 0;
     bmc_status st = prepare_cont(ctx, devspec, d, n_dates, method, width, rules64, rules32, prec, m, x, N, ids,
-                                 n_ids, n, k0, k1, tune, slot, region_pts, a, block, lds, grid);
+                                 n_ids, n, k0, k1, tune, slot, region_pts, a, block, lds, grid, part, fz);
     if (st) return st;
     const uint32_t nchunk = a.nchunk;
     hipError_t e;
@@ -838,25 +850,37 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     const int64_t Jr = J;   // points per region
     J *= nreg;              // columns of all regions
     hipError_t e;
-    // x_work [d][J], s_cur, s_prev, r_prev [J], steps_acc [J], ids x2
-    const size_t need = sizeof(double) * ((size_t)d * J + 3 * J) + sizeof(unsigned long long) * J +
+    // Iteration it is one continuation launch over the columns active after
+    // step it - 1, which also takes that step (IzFuse; iteration 0: a plain
+    // pass over all columns); a last step launch follows the last pass.
+    // Double-buffered across iterations: the partials P[it % 2] of pass it,
+    // the search state St[t % 2] read by step t, the active lists A[it % 2].
+    // Buffers: x_work [d][J], St 2 x [3][J], P 2 x [3 J nchunk], steps_acc [J],
+    // ids 2 x [J].
+    const uint32_t nch = cont_nchunk(ctx, d, prec, J, n, tune);
+    const size_t part_n = (size_t)3 * J * nch;
+    const size_t need = sizeof(double) * ((size_t)d * J + 6 * J + 2 * part_n) + sizeof(unsigned long long) * J +
                         sizeof(int32_t) * 2 * J + 64;
     if ((e = ctx->iz.ensure(need))) return hip_fail(e, "search buffers");
     if ((e = ctx->counters.ensure(64))) return hip_fail(e, "counters");
     char* c = (char*)ctx->iz.ptr;
     double* x_work = (double*)c; c += sizeof(double) * d * J;
-    double* s_cur = (double*)c; c += sizeof(double) * J;
-    double* s_prev = (double*)c; c += sizeof(double) * J;
-    double* r_prev = (double*)c; c += sizeof(double) * J;
+    double* St[2];
+    St[0] = (double*)c; c += sizeof(double) * 3 * J;
+    St[1] = (double*)c; c += sizeof(double) * 3 * J;
+    double* P[2];
+    P[0] = (double*)c; c += sizeof(double) * part_n;
+    P[1] = (double*)c; c += sizeof(double) * part_n;
     unsigned long long* acc = (unsigned long long*)c; c += sizeof(unsigned long long) * J;
-    int32_t* ids_a = (int32_t*)c; c += sizeof(int32_t) * J;
-    int32_t* ids_b = (int32_t*)c;
+    int32_t* A[2];
+    A[0] = (int32_t*)c; c += sizeof(int32_t) * J;
+    A[1] = (int32_t*)c;
     // counters buffer: [0,8) step total, [16,40) final sums/steps, [48,60) three
-    // rotating active counts: iteration it reads cnt[it % 3], appends to
-    // cnt[(it + 1) % 3] and clears cnt[(it + 2) % 3] for the next iteration
+    // rotating active counts: cnt[it % 3] counts A[it % 2]; the launch of
+    // iteration it appends to it and clears cnt[(it + 1) % 3]
     int32_t* cnt = (int32_t*)((char*)ctx->counters.ptr + 48);
     const DevSpec* ds = (const DevSpec*)devspec;
-    if ((e = launch_iz_init(ds, x, d, region, nreg, Jr, x_work, s_cur, s_out, iters, ids_a, &cnt[0], acc,
+    if ((e = launch_iz_init(ds, x, d, region, nreg, Jr, x_work, St[0], s_out, iters, A[0], &cnt[0], acc,
                             ctx->stream)))
         return hip_fail(e, "search init");
     const uint32_t k1 = key_hi(BMC_STREAM_INNER, date);
@@ -882,26 +906,39 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
         ++polls_read;
         return hipSuccess;
     };
+    int last = -1;
     for (int it = 0; it < max_iter && !done; ++it) {
-        int32_t* ids_in = (it & 1) ? ids_b : ids_a;
-        int32_t* ids_out = (it & 1) ? ids_a : ids_b;
-        int32_t* n_in = &cnt[it % 3];
-        int32_t* n_out = &cnt[(it + 1) % 3];
-        int32_t* n_next = &cnt[(it + 2) % 3];
+        IzFuse fz{};
+        if (it > 0) {
+            fz.on = 1;
+            fz.it = it - 1;
+            fz.max_iter = max_iter;
+            fz.mode = mode;
+            fz.eps = eps;
+            fz.part = P[(it - 1) & 1];
+            fz.st_r = St[(it - 1) & 1];
+            fz.st_w = St[it & 1];
+            fz.x_work = x_work;
+            fz.s_out = s_out;
+            fz.iters = iters;
+            fz.steps_acc = acc;
+            fz.ids_out = A[it & 1];
+            fz.n_out = &cnt[it % 3];
+            fz.n_next = &cnt[(it + 1) % 3];
+        }
+        const int prev = it > 0 ? it - 1 : 0;
         uint32_t nchunk = 0;
         bmc_status st = run_cont(ctx, devspec, d, spec->n_dates, rules->method, rules->width, rules->w64,
-                                 rules->w32, prec, date, x_work, J, ids_in, n_in, n, seed, k1, nullptr,
-                                 nullptr, nullptr, nullptr, nullptr, tune, (uint32_t)region,
-                                 nreg > 1 ? (uint32_t)Jr : 0u, &nchunk);
+                                 rules->w32, prec, date, x_work, J, A[prev & 1], &cnt[prev % 3], n, seed, k1,
+                                 nullptr, nullptr, nullptr, nullptr, nullptr, tune, (uint32_t)region,
+                                 nreg > 1 ? (uint32_t)Jr : 0u, &nchunk, P[it & 1], &fz);
         if (st) return st;
-        if ((e = launch_iz_update(ds, d, region, nreg, Jr, (const double*)ctx->part.ptr, nchunk, n, ids_in, n_in,
-                                  ids_out, n_out, n_next, s_cur, s_prev, r_prev, x_work, s_out, iters, acc, eps,
-                                  max_iter, mode, it, ctx->stream)))
-            return hip_fail(e, "search update");
+        if (nchunk != nch) return fail(BMC_EDEVICE, "search pass split %u chunks, expected %u", nchunk, nch);
+        last = it;
         if ((it & 3) == 3 && it != max_iter - 1) {
             if (polls_issued - polls_read == 2 && (e = read_poll(true))) return hip_fail(e, "search progress");
             if (done) break;
-            if ((e = hipMemcpyAsync((void*)&poll_host[polls_issued & 1], n_out, sizeof(int32_t),
+            if ((e = hipMemcpyAsync((void*)&poll_host[polls_issued & 1], &cnt[it % 3], sizeof(int32_t),
                                     hipMemcpyDeviceToHost, ctx->stream)) ||
                 (e = hipEventRecord(ctx->poll_ev[polls_issued & 1], ctx->stream)))
                 return hip_fail(e, "search progress");
@@ -913,6 +950,13 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
             if (polls_read == before) break;   // the oldest poll has not passed yet
         }
     }
+    // the step of the last pass
+    if (last >= 0 &&
+        (e = launch_iz_update(ds, d, region, nreg, Jr, P[last & 1], nch, n, A[last & 1], &cnt[last % 3],
+                              A[(last + 1) & 1], &cnt[(last + 1) % 3], &cnt[(last + 2) % 3], St[last & 1],
+                              St[(last + 1) & 1], x_work, s_out, iters, acc, eps, max_iter, mode, last,
+                              ctx->stream)))
+        return hip_fail(e, "search update");
     if (tally && (e = launch_iz_tally(acc, s_out, iters, J, tally, ctx->stream))) return hip_fail(e, "search tally");
     if (steps_out) {
         std::vector<unsigned long long> h(J);

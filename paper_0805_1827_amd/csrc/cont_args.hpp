@@ -10,6 +10,27 @@
 
 namespace bmc {
 
+// I&Z search launches (I&Z rules only): before its pass, a job takes the
+// search step of the previous pass for its point (merge of that pass's
+// partials, next point or stop) and starts from the new point; a stopped
+// point's jobs return at once.  The job of chunk 0 stores the step.
+struct IzFuse {
+    int32_t on;                 // 0: a plain pass from x
+    int32_t it;                 // iteration of the step taken
+    int32_t max_iter, mode;     // iteration limit, SEARCH_PLAIN / SEARCH_SECANT
+    double eps;                 // convergence tolerance
+    const double* part;         // previous pass's partials [N * nchunk * 3]
+    const double* st_r;         // search state read [3][N]: point, previous point, previous residual
+    double* st_w;               // search state written [3][N]
+    double* x_work;             // the points [d][N] (a.x), searched coordinate updated
+    double* s_out;              // [N] boundary point of a stopped column, -1: dropped
+    int32_t* iters;             // [N] steps taken
+    unsigned long long* steps_acc;   // [N] executed path-steps
+    int32_t* ids_out;           // columns that continue (appended)
+    int32_t* n_out;             // their count
+    int32_t* n_next;            // count of the iteration after, cleared here
+};
+
 // One continuation launch: points (ids or 0..N-1) x chunks of paths.
 struct ContArgs {
     const DevSpec* spec;
@@ -30,6 +51,7 @@ struct ContArgs {
                               // each; point j counts as point j % region_pts of
                               // region slot + j / region_pts in the counters
     double* part;             // [N * nchunk * 3]: sum, sum of squares, steps
+    IzFuse fz;                // fused search step (on = 0 otherwise)
 };
 
 // Dimension buckets: every d <= 32 has its own instantiation (bucket_exact);

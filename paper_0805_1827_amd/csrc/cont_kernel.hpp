@@ -3,6 +3,7 @@
 #pragma once
 
 #include "internal.hpp"
+#include "iz_step.hpp"
 
 namespace bmc {
 
@@ -135,7 +136,30 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
     } else {
         for (int i = (m + 1) * W + threadIdx.x; i < NT * W; i += blockDim.x) wt[i] = rules[i];
     }
-    if ((int)threadIdx.x < D)
+    // Fused I&Z search step: the last thread takes the step of the previous
+    // pass while the others load the tables, and sets the searched
+    // coordinate of the new point; a stopped point's job ends after the
+    // barrier.
+    __shared__ int fz_go;
+    int fz_region = -1;
+    if constexpr (IZK) {
+        if (a.fz.on) {
+            fz_region = (int)(a.slot + (a.region_pts ? j / a.region_pts : 0u));
+            if (threadIdx.x == blockDim.x - 1) {
+                const double* st = a.fz.st_r;
+                const IzStepOut o = iz_step_compute(a.spec->f64, d, fz_region, a.N, a.fz.part, a.nchunk, a.n, j,
+                                                    a.x, st[j], st[a.N + j], st[2 * a.N + j], a.fz.eps,
+                                                    a.fz.max_iter, a.fz.mode, a.fz.it);
+                if (chunk == 0)
+                    iz_step_apply(o, fz_region, a.N, j, a.fz.it, a.fz.ids_out, a.fz.n_out, a.fz.st_w,
+                                  a.fz.st_w + a.N, a.fz.st_w + 2 * a.N, a.fz.x_work, a.fz.s_out, a.fz.iters,
+                                  a.fz.steps_acc);
+                fz_go = o.cont;
+                if (o.cont) lx[fz_region] = (R)log(o.next);
+            }
+        }
+    }
+    if ((int)threadIdx.x < D && (int)threadIdx.x != fz_region)
         lx[threadIdx.x] = (int)threadIdx.x < d ? (R)log(a.x[(int64_t)threadIdx.x * a.N + j])
                                                 : (payk == PUT_GEO ? R(0) : payk == CALL_MIN ? R(1e30) : R(-1e30));
     if constexpr (LC) {
@@ -148,6 +172,9 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
         for (int i = threadIdx.x; i < D4; i += blockDim.x) drift[i] = i < d ? S.drift[i] : R(0);
     }
     __syncthreads();
+    if constexpr (IZK) {
+        if (a.fz.on && !fz_go) return;
+    }
 
     const uint32_t lo = chunk * a.paths_per_wg;
     const uint32_t hi = min(a.n, lo + a.paths_per_wg);
@@ -329,6 +356,9 @@ __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
     __shared__ double red[3][16];
     const uint32_t slot = blockIdx.x / a.nchunk;
     const uint32_t chunk = blockIdx.x - slot * a.nchunk;
+    if constexpr (IZK) {
+        if (a.fz.on && blockIdx.x == 0 && threadIdx.x == 0) *a.fz.n_next = 0;
+    }
     if (a.n_ids && slot >= (uint32_t)*a.n_ids) return;   // retired job (whole block)
     const uint32_t j = a.ids ? (uint32_t)a.ids[slot] : slot;
     cont_job<D, EXACT, R, ACC, IZK>(a, j, chunk, lds, red);

@@ -134,7 +134,7 @@ bmc_status plan_round(const std::vector<RoundItem>& items, Table& tab, std::vect
             const OptPlan& q = *jb.it->q;
             const OptDev& v = *jb.it->dev;
             const int m = jb.it->stage;
-            ContArgs a;
+            ContArgs a{};
             std::memset(&a, 0, sizeof(a));
             a.spec = v.spec;
             a.rules = q.prec == BMC_FP64 ? (const void*)v.w64 : (const void*)v.w32;

@@ -86,14 +86,14 @@ hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int regio
                           int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st);
 // One search step: merges the continuation partials (part, nchunk chunks of
 // n paths in all) of the active points and updates them; mode SEARCH_PLAIN or
-// SEARCH_SECANT (s_prev, r_prev: the secant's previous point and residual per
-// column); clears *n_next.
+// SEARCH_SECANT; search state [3][nreg * J] (point, the secant's previous
+// point and residual per column) read from st_r and written to st_w; clears
+// *n_next.
 hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* part,
                             uint32_t nchunk, uint32_t n, const int32_t* ids_in, const int32_t* n_in,
-                            int32_t* ids_out, int32_t* n_out, int32_t* n_next, double* s_cur, double* s_prev,
-                            double* r_prev, double* x_work, double* s_out, int32_t* iters,
-                            unsigned long long* steps_acc, double eps, int max_iter, int mode, int it,
-                            hipStream_t st);
+                            int32_t* ids_out, int32_t* n_out, int32_t* n_next, const double* st_r, double* st_w,
+                            double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
+                            double eps, int max_iter, int mode, int it, hipStream_t st);
 // tally[0] += sum of steps_acc, tally[1] += number of s_out <= 0 (or NaN),
 // tally[2] += sum of iters, over count points.
 hipError_t launch_iz_tally(const unsigned long long* steps_acc, const double* s_out, const int32_t* iters,

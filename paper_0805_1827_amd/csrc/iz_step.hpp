@@ -38,22 +38,34 @@ __device__ __forceinline__ void merge_serial(const double* __restrict__ part, ui
 // chunk partials (chunk order), c = mean payoff, s' = Phi^{-1}(c) for the
 // searched coordinate (the region's own asset), then stop (converged,
 // dropped, or out of iterations) or move to the next point (plain or
-// secant) and append j to the next active list.
+// secant).
 //   geometric put (K - c)^d / prod_{i>=2} x_i, arithmetic put d (K - c) -
 //   sum_{i>=2} x_i, max- and min-call K + c.  Non-positive: dropped; a fixed
 //   point outside the region (not above / below every other asset): dropped.
-__device__ inline void iz_step_slot(const SpecT<double>& S, int d, int region0, int64_t J, int64_t Jt,
-                                    const double* __restrict__ part, uint32_t nchunk, uint32_t n, int64_t j,
-                                    int32_t* ids_out, int32_t* n_out, double* s_cur, double* s_prev,
-                                    double* r_prev, double* x_work, double* s_out, int32_t* iters,
-                                    unsigned long long* steps_acc, double eps, int max_iter, int mode, int it)
+// iz_step_compute takes the step from the point's state (sv = s, sp, rp: the
+// secant's previous point and residual) and writes nothing; iz_step_apply
+// stores it and appends a continuing point to the next active list.
+struct IzStepOut {
+    int cont;                  // 1: the point continues at `next`
+    double s_final;            // stopped: the boundary point, or -1 (dropped)
+    double next, sv, res;      // continuing: next point, current point, residual
+    unsigned long long pst;    // executed path-steps of the pass
+};
+
+__device__ inline IzStepOut iz_step_compute(const SpecT<double>& S, int d, int region, int64_t Jt,
+                                            const double* __restrict__ part, uint32_t nchunk, uint32_t n, int64_t j,
+                                            const double* __restrict__ x_work, double sv, double sp, double rp,
+                                            double eps, int max_iter, int mode, int it)
 {
 #pragma clang fp contract(off)
-    const int region = region0 + (int)(j / J);
+    IzStepOut o;
+    o.cont = 0;
+    o.s_final = -1.0;
+    o.next = o.sv = o.res = 0.0;
     double psum, psq, pst;
     merge_serial(part, nchunk, j, psum, psq, pst);
     const double c = psum / (double)n;
-    steps_acc[j] += (unsigned long long)(int64_t)pst;
+    o.pst = (unsigned long long)(int64_t)pst;
     double snew;
     if (S.payoff == CALL_MAX || S.payoff == CALL_MIN) {
         snew = S.K + c;
@@ -68,10 +80,8 @@ __device__ inline void iz_step_slot(const SpecT<double>& S, int d, int region0, 
         for (int i = 1; i < d; ++i) rest += x_work[i * Jt + j];
         snew = (double)d * (S.K - c) - rest;
     }
-    const int it1 = it + 1;
-    iters[j] = it1;
-    if (!(snew > 0.0) || !isfinite(snew)) { s_out[j] = -1.0; return; }
-    const double sv = s_cur[j], res = snew - sv;
+    if (!(snew > 0.0) || !isfinite(snew)) return o;
+    const double res = snew - sv;
     if (fabs(res) < eps) {
         // inside the region: above every other asset (max-call), below
         // every other asset (min-call)
@@ -83,27 +93,61 @@ __device__ inline void iz_step_slot(const SpecT<double>& S, int d, int region0, 
                     omin = fmin(omin, x_work[i * Jt + j]);
                 }
         const bool outside = (S.payoff == CALL_MAX && snew <= omax) || (S.payoff == CALL_MIN && snew >= omin);
-        s_out[j] = outside ? -1.0 : snew;
-        return;
+        o.s_final = outside ? -1.0 : snew;
+        return o;
     }
-    if (it1 >= max_iter) { s_out[j] = -1.0; return; }
+    if (it + 1 >= max_iter) return o;
     double next = snew;
     if (mode == SEARCH_SECANT && it > 0) {
-        const double den = res - r_prev[j];
+        const double den = res - rp;
         if (den != 0.0) {
-            double step = -res * (sv - s_prev[j]) / den;
+            double step = -res * (sv - sp) / den;
             const double lim = 20.0 * fabs(res);
             if (step > lim) step = lim;
             if (step < -lim) step = -lim;
             if (isfinite(step) && sv + step > 0.0) next = sv + step;
         }
     }
-    s_prev[j] = sv;
-    r_prev[j] = res;
-    s_cur[j] = next;
-    x_work[region * Jt + j] = next;
+    o.cont = 1;
+    o.next = next;
+    o.sv = sv;
+    o.res = res;
+    return o;
+}
+
+__device__ inline void iz_step_apply(const IzStepOut& o, int region, int64_t Jt, int64_t j, int it,
+                                     int32_t* ids_out, int32_t* n_out, double* s_cur_w, double* s_prev_w,
+                                     double* r_prev_w, double* x_work, double* s_out, int32_t* iters,
+                                     unsigned long long* steps_acc)
+{
+    steps_acc[j] += o.pst;
+    iters[j] = it + 1;
+    if (!o.cont) {
+        s_out[j] = o.s_final;
+        return;
+    }
+    s_prev_w[j] = o.sv;
+    r_prev_w[j] = o.res;
+    s_cur_w[j] = o.next;
+    x_work[region * Jt + j] = o.next;
     const int pos = atomicAdd(n_out, 1);
     ids_out[pos] = (int32_t)j;
+}
+
+// The step of one active point by one thread: state read from the _r
+// arrays (iteration it's), written to the _w arrays (iteration it + 1's).
+__device__ inline void iz_step_slot(const SpecT<double>& S, int d, int region0, int64_t J, int64_t Jt,
+                                    const double* __restrict__ part, uint32_t nchunk, uint32_t n, int64_t j,
+                                    int32_t* ids_out, int32_t* n_out, const double* s_cur_r, const double* s_prev_r,
+                                    const double* r_prev_r, double* s_cur_w, double* s_prev_w, double* r_prev_w,
+                                    double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
+                                    double eps, int max_iter, int mode, int it)
+{
+    const int region = region0 + (int)(j / J);
+    const IzStepOut o = iz_step_compute(S, d, region, Jt, part, nchunk, n, j, x_work, s_cur_r[j], s_prev_r[j],
+                                        r_prev_r[j], eps, max_iter, mode, it);
+    iz_step_apply(o, region, Jt, j, it, ids_out, n_out, s_cur_w, s_prev_w, r_prev_w, x_work, s_out, iters,
+                  steps_acc);
 }
 
 }  // namespace bmc

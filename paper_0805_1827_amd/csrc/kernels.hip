@@ -489,33 +489,35 @@ hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int regio
     return hipGetLastError();
 }
 
-// One search step per active point (iz_step_slot), one thread per slot.
-// Also clears n_next, the active count of the iteration after next.
+// One search step per active point (iz_step_slot), one thread per slot:
+// state read from st_r, written to st_w ([3][Jt] each: point, previous
+// point, previous residual).  Also clears n_next, the active count of the
+// iteration after next.
 __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region0, int64_t J, int64_t Jt,
                             const double* __restrict__ part, uint32_t nchunk, uint32_t n,
                             const int32_t* __restrict__ ids_in, const int32_t* __restrict__ n_in,
-                            int32_t* ids_out, int32_t* n_out, int32_t* n_next, double* s_cur, double* s_prev,
-                            double* r_prev, double* x_work, double* s_out, int32_t* iters,
-                            unsigned long long* steps_acc, double eps, int max_iter, int mode, int it)
+                            int32_t* ids_out, int32_t* n_out, int32_t* n_next, const double* st_r, double* st_w,
+                            double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
+                            double eps, int max_iter, int mode, int it)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot == 0) *n_next = 0;
     if (slot >= *n_in) return;
-    iz_step_slot(s->f64, d, region0, J, Jt, part, nchunk, n, ids_in[slot], ids_out, n_out, s_cur, s_prev, r_prev,
-                 x_work, s_out, iters, steps_acc, eps, max_iter, mode, it);
+    iz_step_slot(s->f64, d, region0, J, Jt, part, nchunk, n, ids_in[slot], ids_out, n_out, st_r, st_r + Jt,
+                 st_r + 2 * Jt, st_w, st_w + Jt, st_w + 2 * Jt, x_work, s_out, iters, steps_acc, eps, max_iter,
+                 mode, it);
 }
 
 hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* part,
                             uint32_t nchunk, uint32_t n, const int32_t* ids_in, const int32_t* n_in,
-                            int32_t* ids_out, int32_t* n_out, int32_t* n_next, double* s_cur, double* s_prev,
-                            double* r_prev, double* x_work, double* s_out, int32_t* iters,
-                            unsigned long long* steps_acc, double eps, int max_iter, int mode, int it,
-                            hipStream_t st)
+                            int32_t* ids_out, int32_t* n_out, int32_t* n_next, const double* st_r, double* st_w,
+                            double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
+                            double eps, int max_iter, int mode, int it, hipStream_t st)
 {
     const int64_t Jt = (int64_t)nreg * J;
     hipLaunchKernelGGL(k_iz_update, dim3((unsigned)((Jt + 255) / 256)), dim3(256), 0, st, s, d, region0, J, Jt,
-                       part, nchunk, n, ids_in, n_in, ids_out, n_out, n_next, s_cur, s_prev, r_prev, x_work, s_out,
-                       iters, steps_acc, eps, max_iter, mode, it);
+                       part, nchunk, n, ids_in, n_in, ids_out, n_out, n_next, st_r, st_w, x_work, s_out, iters,
+                       steps_acc, eps, max_iter, mode, it);
     return hipGetLastError();
 }
 

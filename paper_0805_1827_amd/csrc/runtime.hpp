@@ -12,6 +12,7 @@
 #include "bmc.h"
 
 namespace bmc {
+struct IzFuse;
 
 struct HostSpecPack;
 
@@ -92,7 +93,8 @@ bmc_status run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int m
                     int64_t N, const int32_t* ids, const int32_t* n_ids, uint32_t n, uint32_t k0,
                     uint32_t k1, double* cont, double* se, int64_t* steps, double* sums,
                     unsigned long long* steps_total, const Tuning* tune, uint32_t slot = 0,
-                    uint32_t region_pts = 0, uint32_t* nchunk_out = nullptr);
+                    uint32_t region_pts = 0, uint32_t* nchunk_out = nullptr, double* part = nullptr,
+                    const IzFuse* fz = nullptr);
 // region: the I&Z region whose boundary row block is fitted (0 for CMC), from
 // N points in rows of ld entries (0: N).
 bmc_status fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rules* rules, int date,

@@ -54,14 +54,37 @@ def mfma_flops_per_step(d: int) -> float:
     return float(d * (d + 1))
 
 
-def slots_per_step_fp32(d: int, payoff: int, method: int) -> float:
+def philox_block_slots(cost=None) -> float:
+    """One Philox4x32-10 block: 10 rounds of 2 wide multiplies and 4 xors
+    (the key schedule is uniform across the wavefront, i.e. scalar)."""
+    c = cost or COST
+    return 10 * (2 * c["mul64"] + 4 * c["int"])
+
+
+def bm_pair_slots_fp32() -> float:
+    """One Box-Muller pair in FP32: 2 word->float conversions and 2 scalings,
+    log2, a multiply, sqrt, sin, cos, 2 multiplies."""
+    c = COST
+    return 4 * c["f32"] + c["trans"] + c["f32"] + c["trans"] + 2 * c["trans"] + 2 * c["f32"]
+
+
+def rng_units(d: int, layout: bool) -> tuple[float, float]:
+    """Philox blocks and Box-Muller pairs per path-step: d/4 and d/2 for the
+    d random words a path-step consumes (the algorithmic count); with layout,
+    the ceil(d/4) blocks and ceil(d/2) pairs the kernel draws (it spends
+    whole blocks per step, so that each step's counter is addressable on its
+    own)."""
+    if layout:
+        return float((d + 3) // 4), float((d + 1) // 2)
+    return d / 4.0, d / 2.0
+
+
+def slots_per_step_fp32(d: int, payoff: int, method: int, layout: bool = False) -> float:
     """Algorithmic VALU issue slots of one inner path-step (FP32 form).
 
-    Philox4x32-10 block: 10 rounds x (2 wide multiplies + 4 two-input xors;
-    the key schedule is scalar).  Box-Muller pair: 2 word->float conversions
-    and 2 scalings, log2, a multiply, sqrt, sin, cos, 2 multiplies.  Step:
-    sqrt(dt) z (d), the lower-triangular correlation d(d+1)/2 FMAs, the drift
-    d FMAs.  Payoff: max-call / geometric one exp plus d+3 simple ops;
+    Random numbers: d/4 Philox blocks and d/2 Box-Muller pairs (rng_units).
+    Step: sqrt(dt) z (d), the lower-triangular correlation d(d+1)/2 FMAs, the
+    drift d FMAs.  Payoff: max-call / geometric one exp plus d+3 simple ops;
     arithmetic basket d exps plus d+3.  CMC rule: d subtractions, 2d FMAs, 4
     more for g and the comparison; I&Z boundary: q + q(q+1)/2 FMAs and
     q(q+1)/2 products (q = d-1).  Per path (amortised over its steps and left
@@ -69,11 +92,9 @@ def slots_per_step_fp32(d: int, payoff: int, method: int) -> float:
     runs on the matrix cores and is left out of the VALU count (reported as
     matrix-core flops, mfma_flops_per_step).
     """
-    blocks = (d + 3) // 4
-    pairs = (d + 1) // 2
-    philox = blocks * 10 * (2 * COST["mul64"] + 4 * COST["int"])
-    bm = pairs * (4 * COST["f32"] + COST["trans"] + COST["f32"] + COST["trans"] + 2 * COST["trans"]
-                  + 2 * COST["f32"])
+    blocks, pairs = rng_units(d, layout)
+    philox = blocks * philox_block_slots()
+    bm = pairs * bm_pair_slots_fp32()
     corr = 0 if uses_mfma(d) else d * (d + 1) / 2
     step = (d + corr + d) * COST["f32"]
     if payoff == 0:
@@ -85,6 +106,38 @@ def slots_per_step_fp32(d: int, payoff: int, method: int) -> float:
     else:
         q = d - 1
         rule = (1 + q + q * (q + 1)) * COST["f32"]
+    return philox + bm + step + pay + rule
+
+
+# FP64 form: issue cost of each operation class in FP64-FMA slots (one FP64
+# FMA per lane; MI355X issues 256 CUs x 4 SIMDs x 16 lanes of them per clock,
+# 78.6 TFLOP/s at 2.4 GHz).  Integer classes are the FP32 calibration's
+# figures rescaled by the FP64 FMA's own cost (1.114 FP32 slots); the FP64
+# device-library calls (log, exp, sqrt, sincospi) and the u32 <-> f64
+# conversion pair are measured on gfx950 by paper_0805_1827_amd/calib/valu_rates.hip.
+COST64 = {"f64": 1.0, "int": 0.601 / 1.114, "mul64": 1.147 / 1.114,
+          "log": 72.0, "exp": 18.4, "sqrt": 17.2, "sincospi": 37.8, "cvt_pair": 1.5}
+
+
+def slots_per_step_fp64(d: int, payoff: int, method: int, layout: bool = False) -> float:
+    """Algorithmic VALU issue slots of one inner path-step of the FP64 form,
+    in FP64-FMA slots: the FP32 form's operation list with FP64 arithmetic
+    and the device library's FP64 log, sqrt, sincospi and exp."""
+    c = COST64
+    blocks, pairs = rng_units(d, layout)
+    philox = blocks * philox_block_slots(c)
+    # two conversions and two scalings, log, -2x, sqrt, 2 u_b, sincospi, 2 products
+    bm = pairs * (c["cvt_pair"] + 2 + c["log"] + 1 + c["sqrt"] + 1 + c["sincospi"] + 2)
+    step = d + d * (d + 1) / 2 + d
+    if payoff == 0:
+        pay = d * c["exp"] + (d + 3)
+    else:
+        pay = c["exp"] + (d + 3)
+    if method == 0:
+        rule = 3 * d + 4
+    else:
+        q = d - 1
+        rule = 1 + q + q * (q + 1)
     return philox + bm + step + pay + rule
 
 
@@ -109,13 +162,25 @@ def measured_traffic():
     return rec["hbm_bytes_per_launch"] if rec.get("src_sha256") == h else None
 
 
+def cpu_threads() -> int:
+    """Host threads of the oracle baseline: every core of the affinity mask,
+    capped by OMP_NUM_THREADS when the machine sets it (the CPU share of one
+    GPU on a shared host)."""
+    n = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
 def cpu_baseline(spec, N, n, seed, target_seconds: float) -> dict:
     """The FP64 oracle timed on this host: the inner-path continuation
     estimates of a subset of the CMC training points, at every date, with the
-    same draws as the GPU run (rules: never exercise)."""
+    same draws as the GPU run, under exercise rules the oracle learns itself
+    (its own CMC pricer at N = n = 256)."""
     from oracle import oracle as orc
-    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
-    rules = orc.empty_rules(spec, orc.CMC)
+    threads = cpu_threads()
+    rules = orc.price(spec, orc.CMC, 256, 256, 2, seed, nthreads=threads)["rules"]
     pts = {m: orc.points_cmc(spec, m, N, seed) for m in range(1, spec.n_dates)}
 
     def run(k):
@@ -132,9 +197,11 @@ def cpu_baseline(spec, N, n, seed, target_seconds: float) -> dict:
     if dt < target_seconds:
         k = int(min(N, max(k, k * target_seconds / max(dt, 1e-3))))
         steps, dt = run(k)
-    return {"value": steps / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+    return {"value": steps / dt, "unit": "path-steps/s", "cores": threads,
+            "affinity_cores": len(os.sched_getaffinity(0)), "kind": "oracle",
             "sample": f"continuation estimates of {k} of the {N} training points at each of the "
-                      f"{spec.n_dates - 1} dates, n = {n} inner paths, FP64 ({steps} path-steps in {dt:.1f} s)"}
+                      f"{spec.n_dates - 1} dates, n = {n} inner paths, FP64, rules learned by the oracle "
+                      f"at N = n = 256 ({steps} path-steps in {dt:.1f} s)"}
 
 
 def batch_form(ctx, bmc, inputs, count: int, N: int, n_final: int) -> dict:
@@ -324,7 +391,12 @@ def maxcall5_form(ctx, bmc, inputs) -> dict:
                      "ms_fp32_kahan": 1e3 * a["seconds"], "ms_fp64": 1e3 * b["seconds"],
                      "inner_path_steps": a["inner_path_steps"],
                      "inner_path_steps_per_s_fp32_kahan": a["inner_path_steps"] / a["calc_seconds"],
-                     "inner_path_steps_per_s_fp64": b["inner_path_steps"] / b["calc_seconds"]})
+                     "inner_path_steps_per_s_fp64": b["inner_path_steps"] / b["calc_seconds"],
+                     "asset_steps_per_s_fp32_kahan": 5 * a["inner_path_steps"] / a["calc_seconds"],
+                     "valu_frac_fp32_kahan": slots_per_step_fp32(5, spec.payoff, bmc.CMC) * a["inner_path_steps"]
+                     / a["calc_seconds"] / PEAK_SLOTS,
+                     "valu_frac_fp64": slots_per_step_fp64(5, spec.payoff, bmc.CMC) * b["inner_path_steps"]
+                     / b["calc_seconds"] / PEAK_SLOTS})
     return {"workload": "call on the max of 5 independent assets, CMC, N=n=16384, 9 dates, 1e6 final paths, "
                         "seed 1", "runs": rows}
 
@@ -354,6 +426,81 @@ def mincall_form(ctx, bmc, inputs) -> dict:
                         "(N=n=4096), 1e6 final paths, seed 1", "runs": rows}
 
 
+# 2000-step CRR values of the Bermudan puts (10 dates, exercise at t_1..T):
+# the 1-asset put (S0 = K = 100, r = 0.05, sigma = 0.2, T = 1) and the
+# 5-asset geometric put reduced to one GBM (sigma_G^2 = 0.0176,
+# delta_G = 0.0112); the oracle's pins recompute both.
+CRR_PUT1 = 6.0334
+CRR_GEO5 = 3.832
+# Table 4: binomial values of the 3-asset max-call (S0 = 90, 100, 110) and the
+# paper's CMC prices with 5000 training points, 500 inner paths, 1e6 final paths.
+TABLE4_BINOMIAL = {90: 11.29, 100: 18.69, 110: 27.58}
+TABLE4_PAPER_CMC = {90: 11.295, 100: 18.706, 110: 27.604}
+
+
+def put1_form(ctx, bmc, inputs, reps: int = 3) -> dict:
+    """The 1-asset Bermudan put (S0 = K = 100, r = 0.05, sigma = 0.2, T = 1,
+    10 dates), CMC with N = n = 500, 1e5 final paths, seed 1, against the
+    2000-step binomial tree."""
+    spec = inputs.one_asset_put()
+    kw = dict(N=500, n=500, n_final=100_000, seed=1)
+    out = {"workload": "1-asset Bermudan put, CMC, N=n=500, 10 dates, 1e5 final paths, seed 1",
+           "tree_price": CRR_PUT1}
+    for name, prec in (("fp64", bmc.FP64), ("fp32", bmc.FP32)):
+        bmc.bmc_price(ctx, spec, bmc.CMC, prec, **kw)
+        runs = [bmc.bmc_price(ctx, spec, bmc.CMC, prec, **kw) for _ in range(reps)]
+        r = runs[-1]
+        out[name] = {"price": r["price"], "std_err": r["std_err"], "error_vs_tree": r["price"] - CRR_PUT1,
+                     "error_in_std_err": (r["price"] - CRR_PUT1) / r["std_err"],
+                     "ms": 1e3 * float(np.median([x["seconds"] for x in runs])),
+                     "inner_path_steps": r["inner_path_steps"]}
+    out["fp32_vs_fp64_in_std_err"] = abs(out["fp32"]["price"] - out["fp64"]["price"]) / out["fp64"]["std_err"]
+    return out
+
+
+def table4_form(ctx, bmc, inputs) -> dict:
+    """Table 4's CMC setting: the 3-asset max-call (K = 100, r = 0.05,
+    delta = 0.1, sigma = 0.2, independent, T = 3, 9 dates) with 5000 training
+    points per date, 500 inner paths and 1e6 final paths, S0 = 90, 100, 110,
+    in FP64 and FP32, against the binomial column."""
+    rows = []
+    for S0 in (90, 100, 110):
+        spec = inputs.max_call(3, float(S0))
+        kw = dict(N=5000, n=500, n_final=1_000_000, seed=1)
+        bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP32, **kw)
+        a = bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP32, **kw)
+        b = bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP64, **kw)
+        rows.append({"S0": S0, "price_fp64": b["price"], "ci95_fp64": b["ci95"],
+                     "error_vs_binomial_fp64": TABLE4_BINOMIAL[S0] - b["price"],
+                     "price_fp32": a["price"], "fp32_error_in_std_err": abs(a["price"] - b["price"]) / b["std_err"],
+                     "paper_cmc_price": TABLE4_PAPER_CMC[S0], "binomial": TABLE4_BINOMIAL[S0],
+                     "ms_fp32": 1e3 * a["seconds"], "ms_fp64": 1e3 * b["seconds"],
+                     "inner_path_steps": a["inner_path_steps"]})
+    return {"workload": "call on the max of 3 assets (Table 4), CMC, N=5000 training points, n=500 inner paths, "
+                        "9 dates, 1e6 final paths, seed 1", "runs": rows}
+
+
+def geo5_iz_form(ctx, bmc, inputs) -> dict:
+    """The headline option (5-asset geometric put) priced by I&Z with
+    J = N = 4096 lattice points per date and n = 4096 inner paths, 1e6 final
+    paths, FP32 and FP64, against the reduced binomial tree."""
+    spec = inputs.geometric_put5()
+    kw = dict(N=4096, n=4096, n_final=1_000_000, seed=1)
+    out = {"workload": "5-asset geometric-average Bermudan put, I&Z, J=n=4096, 10 dates, 1e6 final paths, seed 1",
+           "tree_price": CRR_GEO5}
+    for name, prec in (("fp32", bmc.FP32), ("fp64", bmc.FP64)):
+        bmc.bmc_price(ctx, spec, bmc.IZ, prec, **kw)
+        r = bmc.bmc_price(ctx, spec, bmc.IZ, prec, **kw)
+        out[name] = {"price": r["price"], "std_err": r["std_err"], "error_vs_tree": r["price"] - CRR_GEO5,
+                     "ms": 1e3 * r["seconds"], "calc_ms": 1e3 * r["calc_seconds"],
+                     "inner_path_steps": r["inner_path_steps"],
+                     "inner_path_steps_per_s": r["inner_path_steps"] / r["calc_seconds"],
+                     "iterations_per_point": r["iz_iterations"] / ((spec.n_dates - 1) * 4096),
+                     "unconverged": r["iz_unconverged"]}
+    out["fp32_vs_fp64_in_std_err"] = abs(out["fp32"]["price"] - out["fp64"]["price"]) / out["fp64"]["std_err"]
+    return out
+
+
 _T0 = time.perf_counter()
 
 
@@ -377,13 +524,15 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="heuristic launch shapes for the headline")
     ap.add_argument("--batch", type=int, default=256, help="options in the batched form (0 disables it)")
     ap.add_argument("--batch-N", type=int, default=256)
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson arrival window of the serving form (0 disables it)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="arrival rate of the serving form (1/s)")
     ap.add_argument("--no-iz", action="store_true", help="skip the I&Z max-call form (Tables 1-3)")
     ap.add_argument("--no-ada", action="store_true", help="skip the AdaBoost-stump line")
     ap.add_argument("--no-maxcall5", action="store_true", help="skip the five-asset max-call line")
     ap.add_argument("--no-mincall", action="store_true", help="skip the min-call line")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 1-asset put, Table 4 and I&Z geometric-put lines")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the pricer runs on a single device and has no "
@@ -432,12 +581,20 @@ def main():
     se = p64["std_err"]
 
     slots = slots_per_step_fp32(spec.d, spec.payoff, bmc.CMC)
+    slots_layout = slots_per_step_fp32(spec.d, spec.payoff, bmc.CMC, layout=True)
     achieved = slots * inner32 / calc32
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                 "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(),
                 "kernel": "k_cont<5, float> (continuation, FP32 stepping)",
                 "slots_per_path_step": slots,
+                "slots_per_path_step_as_drawn": slots_layout,
+                "frac_as_drawn": slots_layout * inner32 / calc32 / PEAK_SLOTS,
                 "avg_launch_ms": 1e3 * calc32 / launches32, "launches": launches32}
+    slots64 = slots_per_step_fp64(spec.d, spec.payoff, bmc.CMC)
+    roofline64 = {"bound": "alu", "achieved": slots64 * inner64 / calc64 / 1e12, "peak": PEAK_SLOTS / 1e12,
+                  "unit": "T fp64-slot/s", "frac": slots64 * inner64 / calc64 / PEAK_SLOTS,
+                  "kernel": "k_cont<5, double> (continuation, FP64)", "slots_per_path_step": slots64,
+                  "avg_launch_ms": 1e3 * calc64 / (fp64_steps * (spec.n_dates - 1))}
 
     out = {
         "metric": "inner path-steps/s (FP32 stepping, FP64 accumulation)",
@@ -457,14 +614,19 @@ def main():
                    "d": spec.d, "dates": spec.n_dates, "N": args.N, "n": args.n, "n_final": args.n_final,
                    "method": "CMC"},
         "kernel_path_steps_per_s": inner32 / calc32,
+        "asset_steps_per_s": spec.d * inner32 / t32,
+        "nominal_inner_path_steps_per_price": sum(args.N * args.n * (spec.n_dates - m)
+                                                  for m in range(1, spec.n_dates)),
         "fp64": {"value": inner64 / t64, "ms_per_step": 1e3 * t64 / fp64_steps,
-                 "kernel_path_steps_per_s": inner64 / calc64, "steps": fp64_steps},
+                 "kernel_path_steps_per_s": inner64 / calc64, "asset_steps_per_s": spec.d * inner64 / t64,
+                 "steps": fp64_steps, "roofline": roofline64},
         "fp32_over_fp64": (inner32 / t32) / (inner64 / t64),
         "price_fp32": p32["price"], "price_fp64": p64["price"], "std_err": se,
         "fp32_error_in_std_err": abs(p32["price"] - p64["price"]) / se,
         "latency_ms": {"p50": 1e3 * percentile([r["seconds"] for r in res32], 50),
                        "p99": 1e3 * percentile([r["seconds"] for r in res32], 99)},
         "phase_ms": {"calc": 1e3 * calc32 / args.steps,
+                     "refine": 1e3 * sum(r["refine_seconds"] for r in res32) / args.steps,
                      "fit": 1e3 * sum(r["fit_seconds"] for r in res32) / args.steps,
                      "final": 1e3 * sum(r["final_seconds"] for r in res32) / args.steps},
         "inner_path_steps_per_price": inner32 // args.steps,
@@ -497,6 +659,11 @@ def main():
     if not args.no_mincall:
         out["mincall"] = mincall_form(ctx, bmc, inputs)
         note("min-call done")
+    if not args.no_configs:
+        out["put1"] = put1_form(ctx, bmc, inputs)
+        out["table4_cmc"] = table4_form(ctx, bmc, inputs)
+        out["geo5_iz"] = geo5_iz_form(ctx, bmc, inputs)
+        note("1-asset put, Table 4 and I&Z geometric put done")
     if args.serve_seconds > 0:
         out["serving"] = {
             "workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s from a catalogue "
@@ -507,6 +674,7 @@ def main():
             "saturation_fp32": saturation_form(ctx, bmc, inputs, bmc.FP32),
             "saturation_fp64": saturation_form(ctx, bmc, inputs, bmc.FP64)}
         note("serving done")
+    ctx.close()   # before the interpreter (and the HIP runtime) shuts down
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(spec, args.N, args.n, args.seed, args.cpu_seconds)
         note("CPU baseline done")

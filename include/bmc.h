@@ -114,6 +114,7 @@ typedef struct {
     double calc_seconds;                     /* continuation (data generation) */
     double fit_seconds;                      /* rule fits */
     double final_seconds;                    /* final pricing */
+    double refine_seconds;                   /* FP32 forms: FP64 re-estimates of near ties */
 } bmc_result;
 
 typedef struct bmc_ctx bmc_ctx;

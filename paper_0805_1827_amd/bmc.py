@@ -8,6 +8,7 @@ Importing this module fails loudly when the built library is missing.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 from pathlib import Path
 
 import numpy as np
@@ -59,7 +60,7 @@ class bmc_result(C.Structure):
                 ("final_path_steps", C.c_int64), ("iz_unconverged", C.c_int64),
                 ("iz_iterations", C.c_int64), ("seconds", C.c_double),
                 ("calc_seconds", C.c_double), ("fit_seconds", C.c_double),
-                ("final_seconds", C.c_double)]
+                ("final_seconds", C.c_double), ("refine_seconds", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -199,7 +200,12 @@ class Context:
             load().bmc_ctx_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # At interpreter shutdown the HIP runtime may already be torn down:
+        # a handle still open then is left to the process exit (close()
+        # explicitly to release it earlier).
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -222,7 +228,12 @@ class Rules:
             load().bmc_rules_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # At interpreter shutdown the HIP runtime may already be torn down:
+        # a handle still open then is left to the process exit (close()
+        # explicitly to release it earlier).
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -340,7 +351,12 @@ class Server:
             load().bmc_server_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # At interpreter shutdown the HIP runtime may already be torn down:
+        # a handle still open then is left to the process exit (close()
+        # explicitly to release it earlier).
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:

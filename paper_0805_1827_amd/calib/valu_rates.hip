@@ -33,6 +33,33 @@ CHAIN_KERNEL(k_log_f32, float, 0.5f + threadIdx.x * 1e-6f + c, __builtin_amdgcn_
 CHAIN_KERNEL(k_exp_f32, float, 0.5f + threadIdx.x * 1e-6f + c, __builtin_amdgcn_exp2f(x))
 CHAIN_KERNEL(k_sin_f32, float, 0.5f + threadIdx.x * 1e-6f + c, __builtin_amdgcn_sinf(x))
 CHAIN_KERNEL(k_sqrt_f32, float, 0.5f + threadIdx.x * 1e-6f + c, __builtin_amdgcn_sqrtf(x))
+// FP64 device-library calls as the FP64 form of the continuation kernel makes
+// them; each chain step adds one FP64 add or multiply to keep the argument in
+// range (its cost, one FP64 FMA slot, is subtracted in the report).
+CHAIN_KERNEL(k_log_f64, double, 0.5 + threadIdx.x * 1e-6 + c, log(x + 2.0))
+CHAIN_KERNEL(k_exp_f64, double, 0.5 + threadIdx.x * 1e-6 + c, exp(x * -0.5))
+CHAIN_KERNEL(k_sqrt_f64, double, 0.5 + threadIdx.x * 1e-6 + c, sqrt(x + 0.25))
+// a conversion pair (FP64 to u32 and back) per step
+CHAIN_KERNEL(k_cvt_f64, double, 0.5 + threadIdx.x * 1e-6 + c, (double)(uint32_t)(x * 0.5 + 1.0))
+
+// sin and cos of pi x (one sincospi call) per chain step; the next argument
+// is s + c (one FP64 add, subtracted in the report).
+__global__ void k_sincospi_f64(double* out, double s0)
+{
+    double a[CH];
+    for (int c = 0; c < CH; ++c) a[c] = 0.25 + threadIdx.x * 1e-6 + c * 0.01 + s0;
+    for (int i = 0; i < ITERS; ++i) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            double sn, cs;
+            sincospi(a[c], &sn, &cs);
+            a[c] = sn + cs;
+        }
+    }
+    double r = a[0];
+    for (int c = 1; c < CH; ++c) r = r + a[c];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
 
 // 32x32->64 multiply-accumulate: acc = lo32(acc) * s + acc, one v_mad_u64_u32.
 __global__ void k_mad_u64(uint64_t* out, uint64_t s)
@@ -77,11 +104,13 @@ int main()
     if (hipMalloc(&buf, n * 8) != hipSuccess) return 1;
     // ops: instructions of the class per lane per iteration, as emitted
     // (the xor chains lose one instruction in eight to the compiler).
-    struct Row { const char* name; double t; double ops; } rows[16];
+    struct Row { const char* name; double t; double ops; double glue; } rows[24];
     int k = 0;
-#define RUN(label, kern, T, s, per_iter)  \
+#define RUN(label, kern, T, s, per_iter) RUNG(label, kern, T, s, per_iter, 0.0)
+#define RUNG(label, kern, T, s, per_iter, glue_f64) \
     rows[k].name = label;                 \
     rows[k].ops = per_iter;               \
+    rows[k].glue = glue_f64;              \
     rows[k++].t = seconds([&] { hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, 0, (T*)buf, (T)(s)); })
     RUN("fma_f32", k_fma32, float, 0.999f, 8);
     RUN("fma_f64", k_fma64, double, 0.999, 8);
@@ -92,13 +121,23 @@ int main()
     RUN("exp_f32", k_exp_f32, float, 0.f, 8);
     RUN("sin_f32", k_sin_f32, float, 0.f, 8);
     RUN("sqrt_f32", k_sqrt_f32, float, 0.f, 8);
+    RUNG("log_f64", k_log_f64, double, 0.0, 8, 1.0);
+    RUNG("exp_f64", k_exp_f64, double, 0.0, 8, 1.0);
+    RUNG("sqrt_f64", k_sqrt_f64, double, 0.0, 8, 1.0);
+    RUNG("sincospi_f64", k_sincospi_f64, double, 0.0, 8, 1.0);
+    RUNG("cvt_pair_f64", k_cvt_f64, double, 0.0, 8, 1.0);
     const double fma_rate = (double)n * ITERS * rows[0].ops / rows[0].t;
     printf("CUs %d; fp32 fma: %.4e lane-ops/s (= %.3f GHz x 64 lanes x CUs)\n", cus, fma_rate,
            fma_rate / (64.0 * cus) * 1e-9);
+    const double fma64_rate = (double)n * ITERS * rows[1].ops / rows[1].t;
     for (int i = 0; i < k; ++i) {
         const double rate = (double)n * ITERS * rows[i].ops / rows[i].t;
-        printf("%-12s %8.3f ms  %.4e lane-ops/s  cost %.3f fma-slots\n", rows[i].name, rows[i].t * 1e3, rate,
+        printf("%-12s %8.3f ms  %.4e lane-ops/s  cost %.3f fma-slots", rows[i].name, rows[i].t * 1e3, rate,
                fma_rate / rate);
+        // FP64 rows: cost in FP64-FMA slots with the chain's glue (FP64
+        // adds/multiplies, one FP64 FMA slot each) taken out
+        if (rows[i].glue > 0.0) printf("  = %.2f fp64-fma-slots", fma64_rate / rate - rows[i].glue);
+        printf("\n");
     }
     (void)hipFree(buf);
     return 0;

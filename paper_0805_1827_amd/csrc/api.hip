@@ -205,7 +205,7 @@ extern "C" bmc_status bmc_ctx_create(int32_t device, void* hip_stream, bmc_ctx**
 bmc_ctx::~bmc_ctx()
 {
     for (DBuf* b : {&spec, &spec2, &pack_dev, &part, &B, &x, &x2, &cont, &se, &steps, &fit, &iz,
-                    &counters, &korobov, &bspec, &barena, &btab})
+                    &counters, &korobov, &rf, &bspec, &barena, &btab})
         b->release();
     if (pack_host) (void)hipHostFree(pack_host);
     if (bhost) (void)hipHostFree(bhost);
@@ -681,7 +681,7 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
                          uint32_t n, uint32_t k0, uint32_t k1, double* cont, double* se,
                          int64_t* steps, double* sums, unsigned long long* steps_total,
                          const Tuning* tune, uint32_t slot, uint32_t region_pts, uint32_t* nchunk_out,
-                         double* part, const IzFuse* fz)
+                         double* part, const IzFuse* fz, const RefineSel* sel)
 {
     ContArgs a{};
     int block = 256;
@@ -698,8 +698,36 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
         return BMC_OK;
     }
     if ((e = launch_finalize(a.part, nchunk, n, N, ids, n_ids, cont, se, steps, sums, steps_total,
-                             ctx->stream)))
+                             ctx->stream, sel)))
         return hip_fail(e, "finalize launch");
+    return BMC_OK;
+}
+
+bool bmc::refine_supported(int prec, int d, int n_dates, int width)
+{
+    return prec != BMC_FP64 && cont_lds_bytes(BMC_FP64, d, n_dates, width) <= cont_lds_limit();
+}
+
+bmc_status bmc::refine_labels(bmc_ctx* ctx, const void* devspec, int d, int n_dates, const bmc_rules* rules, int m,
+                              const double* x, int64_t N, uint32_t n, uint32_t seed, double* cont, const int32_t* ids,
+                              const int32_t* n_ids)
+{
+    hipError_t e;
+    ContArgs a{};
+    int block = 256;
+    size_t lds = 0;
+    int64_t grid = 0;
+    const Tuning one{256, REFINE_PPT};
+    bmc_status st = prepare_cont(ctx, devspec, d, n_dates, rules->method, rules->width, rules->w64, rules->w32,
+                                 BMC_FP64, m, x, N, ids, n_ids, n, seed, key_hi(BMC_STREAM_INNER, m), &one, 0, 0, a,
+                                 block, lds, grid);
+    if (st) return st;
+    a.slot_stride = (uint32_t)std::min<int64_t>(N, REFINE_SLOTS);
+    if ((e = launch_cont(d, BMC_FP64, a, (int)(a.slot_stride * a.nchunk), block, lds, ctx->stream)))
+        return hip_fail(e, "refinement launch");
+    if ((e = launch_finalize(a.part, a.nchunk, n, N, ids, n_ids, cont, nullptr, nullptr, nullptr, nullptr,
+                             ctx->stream)))
+        return hip_fail(e, "refinement finalize");
     return BMC_OK;
 }
 
@@ -844,12 +872,15 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
                                int date, int region, int nreg, const double* x, int64_t J, uint32_t n,
                                uint32_t seed, int prec, double eps, int max_iter, int mode, double* s_out,
                                int32_t* iters, int64_t* steps_out, const Tuning* tune,
-                               unsigned long long* tally)
+                               unsigned long long* tally, int32_t* ties, int again)
 {
     const int d = spec->d;
     const int64_t Jr = J;   // points per region
     J *= nreg;              // columns of all regions
     hipError_t e;
+    // FP32 searches with tie flags: the buffers also fit the FP64 search of
+    // the flagged points that follows (again = 1), which keeps the others' results
+    const double tau = (ties && !again) ? IZ_TIE_TAU * spec->K : 0.0;
     // Iteration it is one continuation launch over the columns active after
     // step it - 1, which also takes that step (IzFuse; iteration 0: a plain
     // pass over all columns); a last step launch follows the last pass.
@@ -858,7 +889,7 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     // Buffers: x_work [d][J], St 2 x [3][J], P 2 x [3 J nchunk], steps_acc [J],
     // ids 2 x [J].
     const uint32_t nch = cont_nchunk(ctx, d, prec, J, n, tune);
-    const size_t part_n = (size_t)3 * J * nch;
+    const size_t part_n = (size_t)3 * J * (ties ? std::max(nch, cont_nchunk(ctx, d, BMC_FP64, J, n, tune)) : nch);
     const size_t need = sizeof(double) * ((size_t)d * J + 6 * J + 2 * part_n) + sizeof(unsigned long long) * J +
                         sizeof(int32_t) * 2 * J + 64;
     if ((e = ctx->iz.ensure(need))) return hip_fail(e, "search buffers");
@@ -880,8 +911,9 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     // iteration it appends to it and clears cnt[(it + 1) % 3]
     int32_t* cnt = (int32_t*)((char*)ctx->counters.ptr + 48);
     const DevSpec* ds = (const DevSpec*)devspec;
+    if (again && (e = hipMemsetAsync(cnt, 0, 3 * sizeof(int32_t), ctx->stream))) return hip_fail(e, "search init");
     if ((e = launch_iz_init(ds, x, d, region, nreg, Jr, x_work, St[0], s_out, iters, A[0], &cnt[0], acc,
-                            ctx->stream)))
+                            ctx->stream, ties, again)))
         return hip_fail(e, "search init");
     const uint32_t k1 = key_hi(BMC_STREAM_INNER, date);
     // Progress polls without stalling the stream: after every fourth
@@ -925,6 +957,8 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
             fz.ids_out = A[it & 1];
             fz.n_out = &cnt[it % 3];
             fz.n_next = &cnt[(it + 1) % 3];
+            fz.ties = tau > 0.0 ? ties : nullptr;
+            fz.tau = tau;
         }
         const int prev = it > 0 ? it - 1 : 0;
         uint32_t nchunk = 0;
@@ -955,7 +989,7 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
         (e = launch_iz_update(ds, d, region, nreg, Jr, P[last & 1], nch, n, A[last & 1], &cnt[last % 3],
                               A[(last + 1) & 1], &cnt[(last + 1) % 3], &cnt[(last + 2) % 3], St[last & 1],
                               St[(last + 1) & 1], x_work, s_out, iters, acc, eps, max_iter, mode, last,
-                              ctx->stream)))
+                              ctx->stream, tau, tau > 0.0 ? ties : nullptr)))
         return hip_fail(e, "search update");
     if (tally && (e = launch_iz_tally(acc, s_out, iters, J, tally, ctx->stream))) return hip_fail(e, "search tally");
     if (steps_out) {

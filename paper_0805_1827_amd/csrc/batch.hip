@@ -31,7 +31,7 @@ static std::string sweep_signature(const std::vector<Step>& steps, const char* d
     for (const Step& st : steps) {
         if (st.kind == K_MARK) continue;
         const int64_t v[] = {st.kind, st.bucket, st.prec, st.ntasks, st.T, st.blocks, (int64_t)st.tasks,
-                             (int64_t)st.prefix, (int64_t)st.lds, st.date};
+                             (int64_t)st.prefix, (int64_t)st.lds, st.date, st.stride};
         add(v, sizeof(v));
         if (st.kind == K_FIT_SINGLE) {
             add(&st.single_dev, sizeof(st.single_dev));

@@ -29,6 +29,8 @@ struct IzFuse {
     int32_t* ids_out;           // columns that continue (appended)
     int32_t* n_out;             // their count
     int32_t* n_next;            // count of the iteration after, cleared here
+    int32_t* ties;              // [N] near-tie flags of an FP32 search (or null)
+    double tau;                 // near-tie width (0: no flags)
 };
 
 // One continuation launch: points (ids or 0..N-1) x chunks of paths.
@@ -51,6 +53,9 @@ struct ContArgs {
                               // each; point j counts as point j % region_pts of
                               // region slot + j / region_pts in the counters
     double* part;             // [N * nchunk * 3]: sum, sum of squares, steps
+    uint32_t slot_stride;     // > 0: a workgroup runs the jobs of slots s, s + slot_stride, ...
+                              // below *n_ids (chunk as its block gives); 0: one job
+    uint32_t pad_;
     IzFuse fz;                // fused search step (on = 0 otherwise)
 };
 

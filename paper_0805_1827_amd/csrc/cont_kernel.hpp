@@ -115,6 +115,10 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 
     const_as<double>* t64 = as_const(a.spec)->f64.t;
     const double r64 = as_const(a.spec)->f64.r;
+    // FP32 path state: log-moneyness u = ln(S/K) (the rules' own variable);
+    // FP64: the log-price, the oracle's variable
+    constexpr bool UST = sizeof(R) == 4;
+    const double lnshift = UST ? (double)as_const(a.spec)->f64.lnK : 0.0;
     const double tm = t64[m];
     for (int k = threadIdx.x; k <= NT; k += blockDim.x) {
         disc[k] = exp(-r64 * (t64[k] - tm));
@@ -149,18 +153,18 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
                 const double* st = a.fz.st_r;
                 const IzStepOut o = iz_step_compute(a.spec->f64, d, fz_region, a.N, a.fz.part, a.nchunk, a.n, j,
                                                     a.x, st[j], st[a.N + j], st[2 * a.N + j], a.fz.eps,
-                                                    a.fz.max_iter, a.fz.mode, a.fz.it);
+                                                    a.fz.max_iter, a.fz.mode, a.fz.it, a.fz.tau);
                 if (chunk == 0)
                     iz_step_apply(o, fz_region, a.N, j, a.fz.it, a.fz.ids_out, a.fz.n_out, a.fz.st_w,
                                   a.fz.st_w + a.N, a.fz.st_w + 2 * a.N, a.fz.x_work, a.fz.s_out, a.fz.iters,
-                                  a.fz.steps_acc);
+                                  a.fz.steps_acc, a.fz.ties);
                 fz_go = o.cont;
-                if (o.cont) lx[fz_region] = (R)log(o.next);
+                if (o.cont) lx[fz_region] = (R)(log(o.next) - lnshift);
             }
         }
     }
     if ((int)threadIdx.x < D && (int)threadIdx.x != fz_region)
-        lx[threadIdx.x] = (int)threadIdx.x < d ? (R)log(a.x[(int64_t)threadIdx.x * a.N + j])
+        lx[threadIdx.x] = (int)threadIdx.x < d ? (R)(log(a.x[(int64_t)threadIdx.x * a.N + j]) - lnshift)
                                                 : (payk == PUT_GEO ? R(0) : payk == CALL_MIN ? R(1e30) : R(-1e30));
     if constexpr (LC) {
         // FP32: row-major A[i][l] (matrix-core operand rows); FP64: column-major
@@ -191,6 +195,9 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
     const bool min_dir = payk == CALL_MIN;
     const int W1 = rule_width(IZ, d);   // one I&Z region's boundary block
     const R K = S.K, lnK = S.lnK, invK = S.invK, inv_d = S.inv_d;
+    // the rules read u = state - lnKr; an I&Z boundary (a log-price) is
+    // compared with the state after subtracting bshift
+    const R lnKr = UST ? R(0) : lnK, bshift = UST ? lnK : R(0);
 
     // dp: the extent of the per-asset loops (D for padded buckets)
     const int dp = PAD ? D : d;
@@ -273,13 +280,20 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
                 }
             }
         }
-        const R phi = payoff<D4, R>(payk, dp, K, inv_d, ls);
+        R phi, g;   // payoff and payoff / K
+        if constexpr (UST) {
+            g = payoff_moneyness<D4, R>(payk, dp, inv_d, ls);
+            phi = K * g;
+        } else {
+            phi = payoff<D4, R>(payk, dp, K, inv_d, ls);
+            g = phi * invK;
+        }
         bool stop = (k == NT);
         if (!stop && phi > R(0)) {
             const R* w = wt + k * WL;
             if constexpr (!IZK) {
-                if (a.method == CMC) stop = cmc_score<D4, R>(dp, w, lnK, phi * invK, ls) > R(0);
-                else stop = ada_score<D4, R>(d, w, lnK, phi * invK, ls) > R(0);
+                if (a.method == CMC) stop = cmc_score<D4, R>(dp, w, lnKr, g, ls) > R(0);
+                else stop = ada_score<D4, R>(d, w, lnKr, g, ls) > R(0);
             } else {
                 if constexpr (has_iz_kernel<D, EXACT>()) {
                     if (call_dir) {
@@ -294,9 +308,9 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
                                 mx = ls[i];
                                 reg = i;
                             }
-                        stop = mx > iz_boundary<D4, R>(d, w + reg * W1, lnK, ls, reg);
+                        stop = mx > iz_boundary<D4, R>(d, w + reg * W1, lnKr, ls, reg) - bshift;
                     } else {
-                        stop = ls[0] < iz_boundary<D4, R>(d, w, lnK, ls, 0);
+                        stop = ls[0] < iz_boundary<D4, R>(d, w, lnKr, ls, 0) - bshift;
                     }
                 }
             }
@@ -348,8 +362,30 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
     }
 }
 
+// The job(s) of one workgroup: slot's (point, chunk) job, or (STRIDE, the
+// FP64 label-refinement kernels) every slot s = slot, slot + slot_stride, ...
+// below the active count.  A slot at or past the active count is a retired
+// job (the whole block returns).  The loop lives in kernels of its own: in
+// the one-job kernels it would cost registers (and occupancy).
+template <int D, bool EXACT, class R, class ACC, bool IZK, bool STRIDE>
+__device__ __forceinline__ void cont_slots(const ContArgs& a, uint32_t slot, const uint32_t chunk, double* lds,
+                                           double (*red)[16])
+{
+    if constexpr (!STRIDE) {
+        if (a.n_ids && slot >= (uint32_t)*a.n_ids) return;
+        const uint32_t j = a.ids ? (uint32_t)a.ids[slot] : slot;
+        cont_job<D, EXACT, R, ACC, IZK>(a, j, chunk, lds, red);
+    } else {
+        const uint32_t lim = (uint32_t)*a.n_ids;
+        for (; slot < lim; slot += a.slot_stride) {
+            cont_job<D, EXACT, R, ACC, IZK>(a, (uint32_t)a.ids[slot], chunk, lds, red);
+            __syncthreads();   // the LDS tables and partials of the next job
+        }
+    }
+}
+
 // One launch per (spec, date): block = one (point, chunk) job.
-template <int D, bool EXACT, class R, class ACC, bool IZK = false>
+template <int D, bool EXACT, class R, class ACC, bool IZK = false, bool STRIDE = false>
 __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
 {
     extern __shared__ __align__(16) double lds[];
@@ -359,9 +395,7 @@ __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
     if constexpr (IZK) {
         if (a.fz.on && blockIdx.x == 0 && threadIdx.x == 0) *a.fz.n_next = 0;
     }
-    if (a.n_ids && slot >= (uint32_t)*a.n_ids) return;   // retired job (whole block)
-    const uint32_t j = a.ids ? (uint32_t)a.ids[slot] : slot;
-    cont_job<D, EXACT, R, ACC, IZK>(a, j, chunk, lds, red);
+    cont_slots<D, EXACT, R, ACC, IZK, STRIDE>(a, slot, chunk, lds, red);
 }
 
 // One launch over the jobs of many tasks (options at their own dates): block
@@ -369,7 +403,7 @@ __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
 // prefix sums of the tasks' job counts.  Every job writes its own partial
 // sums, so results do not depend on the launch it ran in.  The task table and
 // prefix sums are read through the scalar unit (uniform loads).
-template <int D, bool EXACT, class R, class ACC>
+template <int D, bool EXACT, class R, class ACC, bool STRIDE = false>
 __global__ void __launch_bounds__(256) k_cont_multi(const ContArgs* __restrict__ tasks,
                                                     const uint32_t* __restrict__ prefix, int ntasks, uint32_t job0)
 {
@@ -386,7 +420,7 @@ __global__ void __launch_bounds__(256) k_cont_multi(const ContArgs* __restrict__
     const ContArgs a = load_const(tasks + lo);
     const uint32_t local = job - pre[lo];
     const uint32_t slot = local / a.nchunk;
-    cont_job<D, EXACT, R, ACC>(a, slot, local - slot * a.nchunk, lds, red);
+    cont_slots<D, EXACT, R, ACC, false, STRIDE>(a, slot, local - slot * a.nchunk, lds, red);
 }
 
 // Lets every kernel of bound D use the device's whole LDS (done once).
@@ -401,6 +435,9 @@ bool cont_allow_lds()
                         reinterpret_cast<const void*>(k_cont_multi<D, EXACT, float, Acc<double>>),
                         reinterpret_cast<const void*>(k_cont_multi<D, EXACT, float, KahanAcc>)};
     for (const void* f : ks) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    const void* kr[] = {reinterpret_cast<const void*>(k_cont<D, EXACT, double, Acc<double>, false, true>),
+                        reinterpret_cast<const void*>(k_cont_multi<D, EXACT, double, Acc<double>, true>)};
+    for (const void* f : kr) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
     if constexpr (has_iz_kernel<D, EXACT>()) {
         const void* kz[] = {reinterpret_cast<const void*>(k_cont<D, EXACT, double, Acc<double>, true>),
                             reinterpret_cast<const void*>(k_cont<D, EXACT, float, Acc<double>, true>),
@@ -431,7 +468,11 @@ hipError_t launch_cont_d(int prec, const ContArgs& a, int grid, int block, size_
         }
         return hipErrorInvalidValue;   // I&Z rules exist for d <= 16 only
     }
-    if (prec == PREC_FP64)
+    if (a.slot_stride) {   // FP64 label refinement
+        if (prec != PREC_FP64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_cont<D, EXACT, double, Acc<double>, false, true>), dim3(grid), dim3(block), lds, st,
+                           a);
+    } else if (prec == PREC_FP64)
         hipLaunchKernelGGL((k_cont<D, EXACT, double, Acc<double>>), dim3(grid), dim3(block), lds, st, a);
     else if (prec == PREC_FP32)
         hipLaunchKernelGGL((k_cont<D, EXACT, float, Acc<double>>), dim3(grid), dim3(block), lds, st, a);
@@ -442,11 +483,15 @@ hipError_t launch_cont_d(int prec, const ContArgs& a, int grid, int block, size_
 
 template <int D, bool EXACT>
 hipError_t launch_cont_multi_d(int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks, uint32_t job0,
-                               uint32_t jobs, int block, size_t lds, hipStream_t st)
+                               uint32_t jobs, int block, size_t lds, hipStream_t st, bool stride)
 {
     static const bool lds_ok = cont_allow_lds<D, EXACT>();
     (void)lds_ok;
-    if (prec == PREC_FP64)
+    if (stride) {   // FP64 label refinement
+        if (prec != PREC_FP64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_cont_multi<D, EXACT, double, Acc<double>, true>), dim3(jobs), dim3(block), lds, st,
+                           tasks, prefix, ntasks, job0);
+    } else if (prec == PREC_FP64)
         hipLaunchKernelGGL((k_cont_multi<D, EXACT, double, Acc<double>>), dim3(jobs), dim3(block), lds, st, tasks,
                            prefix, ntasks, job0);
     else if (prec == PREC_FP32)

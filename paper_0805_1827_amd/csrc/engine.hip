@@ -44,6 +44,10 @@ bmc_status plan_option(const bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts*
     q->fnchunk = (q->n_final + q->fper_wg - 1) / q->fper_wg;
     q->lds = cont_lds_bytes(q->prec, q->d, q->NT, q->p);
     if (q->lds > cont_lds_limit()) return fail(BMC_EUNSUPPORTED, "option %d: rule table too large for LDS", i);
+    q->lds64 = cont_lds_bytes(BMC_FP64, q->d, q->NT, q->p);
+    q->refine = refine_supported(q->prec, q->d, q->NT, q->p);
+    q->rper_wg = 256u * REFINE_PPT;
+    q->rnchunk = (q->n + q->rper_wg - 1) / q->rper_wg;
     if ((uint64_t)q->N * q->nchunk > 0x7FFFFFFFull) return fail(BMC_EINVAL, "option %d: too many jobs", i);
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -59,8 +63,11 @@ bmc_status plan_option(const bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts*
     q->oB = take(sizeof(double) * q->d * q->N);
     q->ox = take(sizeof(double) * q->d * q->N);
     q->ocont = take(sizeof(double) * q->N);
-    q->opart = take(sizeof(double) * 3 * std::max<size_t>((size_t)q->N * q->nchunk, q->fnchunk));
+    size_t parts = std::max<size_t>((size_t)q->N * q->nchunk, q->fnchunk);
+    if (q->refine) parts = std::max<size_t>(parts, (size_t)q->N * q->rnchunk);
+    q->opart = take(sizeof(double) * 3 * parts);
     q->ofit = take(sizeof(double) * fit_scratch_doubles(q->N, q->p, q->rounds));
+    q->oids = q->refine ? take(256 + sizeof(int32_t) * q->N) : 0;
     q->bytes = off;
     return BMC_OK;
 }
@@ -77,6 +84,8 @@ OptDev carve_option(const OptPlan& q, const DevSpec* spec, char* base)
     v.cont = (double*)(base + q.ocont);
     v.part = (double*)(base + q.opart);
     v.fit = (double*)(base + q.ofit);
+    v.n_ids = q.refine ? (int32_t*)(base + q.oids) : nullptr;
+    v.ids = q.refine ? (int32_t*)(base + q.oids + 256) : nullptr;
     return v;
 }
 
@@ -92,7 +101,8 @@ bmc_status plan_round(const std::vector<RoundItem>& items, Table& tab, std::vect
         for (const RoundItem* it : train) {
             const OptPlan& q = *it->q;
             if (end && it->stage != q.NT - 1) continue;
-            bt.push_back({it->dev->spec, it->dev->B, end ? nullptr : it->dev->x, q.N, q.seed, it->stage});
+            bt.push_back({it->dev->spec, it->dev->B, end ? nullptr : it->dev->x, end ? nullptr : it->dev->n_ids, q.N,
+                          q.seed, it->stage});
             pre.push_back(pre.back() + (uint32_t)((q.N + 255) / 256));
         }
         if (bt.empty()) return;
@@ -155,6 +165,7 @@ bmc_status plan_round(const std::vector<RoundItem>& items, Table& tab, std::vect
                 a.k1 = key_hi(BMC_STREAM_INNER, m);
                 f.cont = v.cont;
                 f.steps_total = (unsigned long long*)&v.cnt[0];
+                if (q.refine) f.sel = RefineSel{v.spec, v.x, v.ids, v.n_ids};
             } else {
                 a.x = dev_S0(v.spec);
                 a.N = 1;
@@ -196,6 +207,75 @@ bmc_status plan_round(const std::vector<RoundItem>& items, Table& tab, std::vect
         s.blocks = fpre.back();
         s.tasks = tab.put(ft);
         s.prefix = tab.put(fpre);
+        steps.push_back(s);
+    }
+    // FP32 label refinement: the finalize above listed the near-tie points;
+    // their FP64 re-estimates and the finalize of those
+    std::map<int, std::vector<const RoundItem*>> by_bucket;
+    for (const RoundItem* it : train)
+        if (it->q->refine) by_bucket[it->q->bucket].push_back(it);
+    if (!by_bucket.empty()) {
+        std::vector<FinTask> rft;
+        std::vector<uint32_t> rfpre{0};
+        for (auto& g : by_bucket) {
+            std::vector<ContArgs> ca;
+            std::vector<uint32_t> pre{0};
+            size_t lds = 0;
+            for (const RoundItem* it : g.second) {
+                const OptPlan& q = *it->q;
+                const OptDev& v = *it->dev;
+                const int m = it->stage;
+                ContArgs a;
+                std::memset(&a, 0, sizeof(a));
+                a.spec = v.spec;
+                a.rules = v.w64;
+                a.method = BMC_CMC;
+                a.width = q.p;
+                a.k0 = q.seed;
+                a.k1 = key_hi(BMC_STREAM_INNER, m);
+                a.part = v.part;
+                a.x = v.x;
+                a.N = q.N;
+                a.ids = v.ids;
+                a.n_ids = v.n_ids;
+                a.n = q.n;
+                a.m = m;
+                a.paths_per_wg = q.rper_wg;
+                a.nchunk = q.rnchunk;
+                a.slot_stride = (uint32_t)std::min<int64_t>(q.N, REFINE_SLOTS);
+                pre.push_back(pre.back() + a.slot_stride * a.nchunk);
+                ca.push_back(a);
+                lds = std::max(lds, q.lds64);
+                FinTask f;
+                std::memset(&f, 0, sizeof(f));
+                f.part = v.part;
+                f.cont = v.cont;
+                f.ids = v.ids;
+                f.n_ids = v.n_ids;
+                f.N = q.N;
+                f.nchunk = q.rnchunk;
+                f.n = q.n;
+                rft.push_back(f);
+                rfpre.push_back(rfpre.back() + (uint32_t)((q.N + 255) / 256));
+            }
+            Step s;
+            s.kind = K_CONT;
+            s.bucket = g.first;
+            s.prec = BMC_FP64;
+            s.stride = true;
+            s.ntasks = (int)ca.size();
+            s.blocks = pre.back();
+            s.tasks = tab.put(ca);
+            s.prefix = tab.put(pre);
+            s.lds = lds;
+            steps.push_back(s);
+        }
+        Step s;
+        s.kind = K_FIN;
+        s.ntasks = (int)rft.size();
+        s.blocks = rfpre.back();
+        s.tasks = tab.put(rft);
+        s.prefix = tab.put(rfpre);
         steps.push_back(s);
     }
     if (train.empty()) {
@@ -260,7 +340,7 @@ hipError_t run_step(const Step& s, const char* dtab, hipStream_t st)
     case K_CONT:
         for (uint32_t j0 = 0; j0 < s.blocks && !e; j0 += MAX_GRID)
             e = launch_cont_multi(s.bucket, s.prec, (const ContArgs*)tasks, pre, s.ntasks, j0,
-                                  std::min(MAX_GRID, s.blocks - j0), 256, s.lds, st);
+                                  std::min(MAX_GRID, s.blocks - j0), 256, s.lds, st, s.stride);
         return e;
     case K_FIN: return launch_finalize_multi((const FinTask*)tasks, pre, s.ntasks, s.blocks, st);
     case K_FIT: return launch_fit_cmc_multi((const FitTask*)tasks, s.ntasks, s.T, s.lds, st);

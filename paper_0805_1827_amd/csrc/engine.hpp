@@ -19,13 +19,17 @@ namespace bmc {
 // One pricing as the engine runs it.  Byte offsets locate its buffers in one
 // contiguous device region: [rules64][rules32][counters][B][x][cont][part][fit];
 // the first three (zero_bytes) start at zero.
+// FP32 pricings also hold the list of their label refinement (refine: the
+// FP64 tables fit the LDS), whose FP64 pass runs rnchunk chunks of rper_wg
+// paths per point (one path per lane).
 struct OptPlan {
     int d, NT, p, prec, rounds, bucket;
     int64_t N;
     uint32_t n, n_final, seed;
-    uint32_t nchunk, per_wg, fnchunk, fper_wg;
-    size_t lds;                                              // continuation LDS bytes
-    size_t ow64, ow32, ocnt, oB, ox, ocont, opart, ofit;
+    uint32_t nchunk, per_wg, fnchunk, fper_wg, rnchunk, rper_wg;
+    int refine;
+    size_t lds, lds64;                                       // continuation LDS bytes
+    size_t ow64, ow32, ocnt, oB, ox, ocont, opart, ofit, oids;
     size_t zero_bytes, bytes;
 };
 
@@ -39,6 +43,7 @@ struct OptDev {
     double *B, *x, *cont, *part, *fit, *w64;
     float* w32;
     uint64_t* cnt;
+    int32_t *ids, *n_ids;   // refinement list and its count (FP32 pricings)
 };
 OptDev carve_option(const OptPlan& q, const DevSpec* spec, char* base);
 
@@ -56,6 +61,7 @@ enum { PH_CALC = 0, PH_FIT = 1, PH_FINAL = 2 };
 struct Step {
     int kind = K_MARK;
     int bucket = 0, prec = 0, ntasks = 0, T = 0, phase = -1;
+    bool stride = false;             // K_CONT: tasks with a slot stride (label refinement)
     uint32_t blocks = 0;             // grid (K_CONT: total jobs)
     size_t tasks = 0, prefix = 0;    // table offsets
     size_t lds = 0;

@@ -254,6 +254,18 @@ __device__ inline double point_payoff(const SpecT<double>& S, const double* __re
     return v > 0.0 ? v : 0.0;
 }
 
+// FP32 label refinement (REFINE_KAPPA): lists in-the-money point j (payoff
+// Phi) when its estimate c lies within REFINE_KAPPA standard errors se (plus
+// REFINE_ETA (Phi + |c|) for rounding) of Phi.
+__device__ inline void refine_point(const SpecT<double>& S, const double* __restrict__ x, int64_t N, int64_t j,
+                                    double c, double se, int32_t* ids, int32_t* n_ids)
+{
+    const double pay = point_payoff(S, x, N, j);
+    if (!(pay > 0.0)) return;   // out of the money: never in the fit
+    const double tol = REFINE_KAPPA * se + REFINE_ETA * (pay + fabs(c));
+    if (fabs(pay - c) <= tol) ids[atomicAdd(n_ids, 1)] = (int32_t)j;
+}
+
 // CMC training data of point j: raw features phi = [1, u, u^2, g, g^2]
 // (column f at phi[f*N + j]), label e = [Phi - C > 0], in-the-money mask.
 __device__ inline void fit_prep_point(const SpecT<double>& S, const double* __restrict__ x,

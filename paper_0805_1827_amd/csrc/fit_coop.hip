@@ -14,14 +14,6 @@ namespace cg = cooperative_groups;
 
 namespace bmc {
 
-// Optional phase timestamps of block 0 (compiled out unless BMC_FIT_TRACE).
-#ifdef BMC_FIT_TRACE
-__device__ unsigned long long g_fit_trace[256];
-#define FIT_MARK(i) do { if (blockIdx.x == 0 && threadIdx.x == 0) g_fit_trace[i] = wall_clock64(); } while (0)
-#else
-#define FIT_MARK(i) do { } while (0)
-#endif
-
 // Normal-equation path by rule width: 1 = one 16x16 MFMA block (p <= 15),
 // 2 = 16x16 MFMA blocks (p <= 96, tiles of 64+ points), 0 = scalar.
 __host__ __device__ inline int coop_mode(int p) { return p <= 15 ? 1 : (p <= 96 ? 2 : 0); }
@@ -110,7 +102,6 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
     const FitScratch& fs = a.fs;
     const int64_t N = a.N;
 
-    FIT_MARK(0);
     // features, labels, in-the-money mask; tile sums of features and count
     for (int t = grp.rank(); t < a.ntiles; t += grp.size()) {
         const int64_t j0 = (int64_t)t * T;
@@ -121,9 +112,7 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
         tile_sum2(p + 1, nt, [&](int f, int q) { return f < p ? wz[q] * psi[f * T + q] : wz[q]; }, aux,
                   fs.part1 + (size_t)t * (p + 1));
     }
-    FIT_MARK(1);
     grp.sync();
-    FIT_MARK(2);
     // means (every block), tile sums of squared deviations
     merge_tiles(fs.part1, a.ntiles, p + 1, A);
     if (tid == 0) cnt_s = A[p];
@@ -142,9 +131,7 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
                   },
                   aux, fs.part2 + (size_t)t * p);
     }
-    FIT_MARK(3);
     grp.sync();
-    FIT_MARK(4);
     merge_tiles(fs.part1, a.ntiles, p + 1, A);          // feature sums
     merge_tiles(fs.part2, a.ntiles, p, A + (p + 1));    // squared deviations
     for (int f = tid; f < p; f += T) {
@@ -177,52 +164,42 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
     }
     for (int r = 0; r < a.rounds; ++r) {
         double* partA = fs.partA + (size_t)(r & 1) * part_stride;
-        FIT_MARK(8 + 8 * r);
         for (int t = grp.rank(); t < a.ntiles; t += grp.size()) {
             const int64_t j0 = (int64_t)t * T;
             const int nt = (int)min((int64_t)T, N - j0);
             if (resident && r > 0) {
                 fit_round_point_resident(p, SW, own_in, beta, F_reg, lab_reg, msk_reg, psi, wz);
                 __syncthreads();
-                FIT_MARK(9 + 8 * r);
                 if (mode == 1) fit_tile_normal_eqs_mfma(psi, wz, p, nt, aux, partA + (size_t)t * Q);
                 else fit_tile_normal_eqs_mfma_wide(psi, SW, wz, p, nt, partA + (size_t)t * Q);
             } else if (mode == 1) {
                 fit_round_point16(fs.phi, fs.lab, fs.msk, N, p, mu, sd, r > 0 ? beta : nullptr, j0 + tid, fs.F,
                                   fs.pi, psi, wz);
                 __syncthreads();
-                FIT_MARK(9 + 8 * r);
                 fit_tile_normal_eqs_mfma(psi, wz, p, nt, aux, partA + (size_t)t * Q);
             } else if (mode == 2) {
                 fit_round_point_s(fs.phi, fs.lab, fs.msk, N, p, SW, mu, sd, r > 0 ? beta : nullptr, j0 + tid, fs.F,
                                   fs.pi, psi, wz);
                 __syncthreads();
-                FIT_MARK(9 + 8 * r);
                 fit_tile_normal_eqs_mfma_wide(psi, SW, wz, p, nt, partA + (size_t)t * Q);
             } else {
                 fit_round_point(fs.phi, fs.lab, fs.msk, N, p, mu, sd, r > 0 ? beta : nullptr, j0 + tid, fs.F,
                                 fs.pi, psi, wz);
                 __syncthreads();
-                FIT_MARK(9 + 8 * r);
                 fit_tile_normal_eqs(psi, wz, p, nt, partA + (size_t)t * Q);
             }
             __syncthreads();
         }
         if (resident && r == 0 && own_in) F_reg = fs.F[j_own];   // round 0 wrote it
-        FIT_MARK(10 + 8 * r);
         grp.sync();
-        FIT_MARK(11 + 8 * r);
         merge_tiles(partA, a.ntiles, Q, A);   // A then bv
-        FIT_MARK(12 + 8 * r);
         // ridge 1e-8 tr / p, the trace summed inside the solver's wavefront
         if (!spd_solve_ridge(p, A, 1e-8, bv, beta, &flag, &lam))
             for (int f = tid; f < p; f += T) beta[f] = 0.0;
         __syncthreads();
-        FIT_MARK(13 + 8 * r);
         if (grp.rank() == 0)
             for (int f = tid; f < p; f += T) fs.beta[(size_t)r * p + f] = beta[f];
     }
-    FIT_MARK(200);
     if (grp.rank() == 0) {
         __syncthreads();
         fit_fold(p, a.rounds, a.musd, fs.beta, a.row64, a.row32);

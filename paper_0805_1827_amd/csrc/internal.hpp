@@ -19,7 +19,51 @@ struct HostSpecPack {
     double dates[NT_MAX];
 };
 
+// Task of a multi-task launch whose blocks are numbered through the
+// exclusive prefix sums of the tasks' block counts.
+__device__ __forceinline__ int task_of_block(const uint32_t* __restrict__ prefix, int ntasks, uint32_t b)
+{
+    int lo = 0, hi = ntasks;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// FP32 label refinement: a training point whose FP32 continuation estimate
+// C lies within REFINE_KAPPA standard errors (plus REFINE_ETA of |Phi| + |C|
+// for rounding) of its in-the-money exercise value Phi is re-estimated in
+// FP64 before the fit.  A label can differ from the FP64 form's only where
+// Phi lies between the two estimates, so |Phi - C| <= |C - C_FP64|; the
+// largest |C - C_FP64| measured over every point and date of the 256-option
+// uneven workload is 0.61 standard errors, a third of REFINE_KAPPA.  The
+// finalize of the FP32 estimates lists the points (RefineSel); the FP64
+// re-estimates run one path per lane (REFINE_PPT), REFINE_SLOTS (or N, if
+// fewer) points at a time.
+constexpr double REFINE_KAPPA = 2.0;
+// I&Z searches of the FP32 forms flag every point with a decision within
+// IZ_TIE_TAU K of its threshold (iz_step_compute: stopping test, sign of the
+// inverse, region test); the pricer searches those points again in FP64.
+// The FP32 map's own error at a given point is a few 10^-8 K (rounding of
+// the payoff sums; median 4e-6 at K = 100 on the 5-asset geometric put),
+// well inside the band.
+constexpr double IZ_TIE_TAU = 1e-6;
+constexpr double REFINE_ETA = 1e-5;
+constexpr uint32_t REFINE_SLOTS = 256;
+constexpr int REFINE_PPT = 1;
+// Selection made by a finalize: s == null selects nothing.  The list ids
+// (count *n_ids, cleared beforehand) receives the points to refine.
+struct RefineSel {
+    const DevSpec* s;
+    const double* x;
+    int32_t* ids;
+    int32_t* n_ids;
+};
+
 // Finalize of one task inside a multi-task launch (see launch_finalize).
+// ids/n_ids: merge only the listed points (narrow tasks).
 struct FinTask {
     const double* part;
     double* cont;
@@ -27,17 +71,22 @@ struct FinTask {
     int64_t* steps;
     double* sums;
     unsigned long long* steps_total;
+    const int32_t* ids;
+    const int32_t* n_ids;
+    RefineSel sel;
     int64_t N;
     uint32_t nchunk, n;
     int32_t wide;
     int32_t pad;
 };
 
-// Bridge step of one option inside a multi-task launch.
+// Bridge step of one option inside a multi-task launch; zero_count (or
+// null): a counter the bridge-back step clears for the launches after it.
 struct BridgeTask {
     const DevSpec* s;
     double* B;
     double* x;
+    int32_t* zero_count;
     int64_t N;
     uint32_t seed;
     int32_t m;
@@ -55,9 +104,11 @@ hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStre
 hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, size_t lds,
                        hipStream_t st);
 // One launch over jobs job0 .. job0+jobs-1 of many tasks of one bucket;
-// prefix[t] is the first job of task t, prefix[ntasks] the total.
+// prefix[t] is the first job of task t, prefix[ntasks] the total.  stride:
+// the tasks run their slots with a slot stride (FP64 label refinement).
 hipError_t launch_cont_multi(int bucket, int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks,
-                             uint32_t job0, uint32_t jobs, int block, size_t lds, hipStream_t st);
+                             uint32_t job0, uint32_t jobs, int block, size_t lds, hipStream_t st,
+                             bool stride = false);
 bool finalize_is_wide(uint32_t nchunk, int64_t N, bool has_ids);
 // prefix: first block of each task (wide: N blocks, else ceil(N/256)).
 hipError_t launch_finalize_multi(const FinTask* tasks, const uint32_t* prefix, int ntasks, uint32_t blocks,
@@ -69,11 +120,12 @@ hipError_t launch_bridge_multi(const BridgeTask* tasks, const uint32_t* prefix, 
 hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int64_t N,
                            const int32_t* ids, const int32_t* n_ids, double* cont, double* se,
                            int64_t* steps, double* sums, unsigned long long* steps_total,
-                           hipStream_t st);
+                           hipStream_t st, const RefineSel* sel = nullptr);
 hipError_t launch_bridge_end(const DevSpec* s, int d, int64_t N, uint32_t seed, double* B,
                              hipStream_t st);
+// zero_count (or null) is cleared by the launch.
 hipError_t launch_bridge_back(const DevSpec* s, int d, int m, int64_t N, uint32_t seed, double* B,
-                              double* x, int bridge, hipStream_t st);
+                              double* x, int bridge, hipStream_t st, int32_t* zero_count = nullptr);
 hipError_t launch_korobov(int64_t J, int q, unsigned long long* best, hipStream_t st);
 // I&Z regions region0 .. region0 + nreg - 1 side by side: J points each,
 // region region0 + r in columns r J .. r J + J - 1 of rows of nreg J entries.
@@ -81,9 +133,13 @@ hipError_t launch_korobov(int64_t J, int q, unsigned long long* best, hipStream_
 // state: the region's own asset is the searched coordinate.
 hipError_t launch_lattice(const DevSpec* s, int d, int m, int region0, int nreg, int64_t J,
                           const unsigned long long* best, double* x, hipStream_t st);
+// ties (or null): near-tie flags [nreg J], cleared; with subset = 1 only the
+// flagged columns start again, appended to ids by the count n_ids[0] (cleared
+// by the caller), and the other columns keep their results.
 hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int region0, int nreg, int64_t J,
                           double* x_work, double* s_cur, double* s_out, int32_t* iters, int32_t* ids,
-                          int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st);
+                          int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st, int32_t* ties = nullptr,
+                          int subset = 0);
 // One search step: merges the continuation partials (part, nchunk chunks of
 // n paths in all) of the active points and updates them; mode SEARCH_PLAIN or
 // SEARCH_SECANT; search state [3][nreg * J] (point, the secant's previous
@@ -93,7 +149,8 @@ hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int6
                             uint32_t nchunk, uint32_t n, const int32_t* ids_in, const int32_t* n_in,
                             int32_t* ids_out, int32_t* n_out, int32_t* n_next, const double* st_r, double* st_w,
                             double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
-                            double eps, int max_iter, int mode, int it, hipStream_t st);
+                            double eps, int max_iter, int mode, int it, hipStream_t st, double tau = 0.0,
+                            int32_t* ties = nullptr);
 // tally[0] += sum of steps_acc, tally[1] += number of s_out <= 0 (or NaN),
 // tally[2] += sum of iters, over count points.
 hipError_t launch_iz_tally(const unsigned long long* steps_acc, const double* s_out, const int32_t* iters,

@@ -45,8 +45,13 @@ __device__ __forceinline__ void merge_serial(const double* __restrict__ part, ui
 // iz_step_compute takes the step from the point's state (sv = s, sp, rp: the
 // secant's previous point and residual) and writes nothing; iz_step_apply
 // stores it and appends a continuing point to the next active list.
+// tau > 0 (FP32 searches): tie = 1 when a decision of the step lies within
+// tau of its threshold: the stopping test (|r| against eps), the sign of
+// the inverse, the region test of a call's fixed point, the secant's
+// positivity test.  The pricer searches such points again in FP64 (IZ_TIE_TAU).
 struct IzStepOut {
     int cont;                  // 1: the point continues at `next`
+    int tie;                   // a decision of this step was a near tie
     double s_final;            // stopped: the boundary point, or -1 (dropped)
     double next, sv, res;      // continuing: next point, current point, residual
     unsigned long long pst;    // executed path-steps of the pass
@@ -55,11 +60,12 @@ struct IzStepOut {
 __device__ inline IzStepOut iz_step_compute(const SpecT<double>& S, int d, int region, int64_t Jt,
                                             const double* __restrict__ part, uint32_t nchunk, uint32_t n, int64_t j,
                                             const double* __restrict__ x_work, double sv, double sp, double rp,
-                                            double eps, int max_iter, int mode, int it)
+                                            double eps, int max_iter, int mode, int it, double tau = 0.0)
 {
 #pragma clang fp contract(off)
     IzStepOut o;
     o.cont = 0;
+    o.tie = 0;
     o.s_final = -1.0;
     o.next = o.sv = o.res = 0.0;
     double psum, psq, pst;
@@ -67,6 +73,7 @@ __device__ inline IzStepOut iz_step_compute(const SpecT<double>& S, int d, int r
     const double c = psum / (double)n;
     o.pst = (unsigned long long)(int64_t)pst;
     double snew;
+    if (S.payoff != CALL_MAX && S.payoff != CALL_MIN && fabs(S.K - c) < tau) o.tie = 1;
     if (S.payoff == CALL_MAX || S.payoff == CALL_MIN) {
         snew = S.K + c;
     } else if (!(S.K - c > 0.0)) {
@@ -82,6 +89,7 @@ __device__ inline IzStepOut iz_step_compute(const SpecT<double>& S, int d, int r
     }
     if (!(snew > 0.0) || !isfinite(snew)) return o;
     const double res = snew - sv;
+    if (fabs(fabs(res) - eps) < tau) o.tie = 1;
     if (fabs(res) < eps) {
         // inside the region: above every other asset (max-call), below
         // every other asset (min-call)
@@ -93,6 +101,8 @@ __device__ inline IzStepOut iz_step_compute(const SpecT<double>& S, int d, int r
                     omin = fmin(omin, x_work[i * Jt + j]);
                 }
         const bool outside = (S.payoff == CALL_MAX && snew <= omax) || (S.payoff == CALL_MIN && snew >= omin);
+        if ((S.payoff == CALL_MAX && fabs(snew - omax) < tau) || (S.payoff == CALL_MIN && fabs(snew - omin) < tau))
+            o.tie = 1;
         o.s_final = outside ? -1.0 : snew;
         return o;
     }
@@ -105,6 +115,7 @@ __device__ inline IzStepOut iz_step_compute(const SpecT<double>& S, int d, int r
             const double lim = 20.0 * fabs(res);
             if (step > lim) step = lim;
             if (step < -lim) step = -lim;
+            if (isfinite(step) && fabs(sv + step) < tau) o.tie = 1;
             if (isfinite(step) && sv + step > 0.0) next = sv + step;
         }
     }
@@ -118,8 +129,9 @@ __device__ inline IzStepOut iz_step_compute(const SpecT<double>& S, int d, int r
 __device__ inline void iz_step_apply(const IzStepOut& o, int region, int64_t Jt, int64_t j, int it,
                                      int32_t* ids_out, int32_t* n_out, double* s_cur_w, double* s_prev_w,
                                      double* r_prev_w, double* x_work, double* s_out, int32_t* iters,
-                                     unsigned long long* steps_acc)
+                                     unsigned long long* steps_acc, int32_t* ties = nullptr)
 {
+    if (o.tie && ties) ties[j] = 1;
     steps_acc[j] += o.pst;
     iters[j] = it + 1;
     if (!o.cont) {
@@ -141,13 +153,13 @@ __device__ inline void iz_step_slot(const SpecT<double>& S, int d, int region0, 
                                     int32_t* ids_out, int32_t* n_out, const double* s_cur_r, const double* s_prev_r,
                                     const double* r_prev_r, double* s_cur_w, double* s_prev_w, double* r_prev_w,
                                     double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
-                                    double eps, int max_iter, int mode, int it)
+                                    double eps, int max_iter, int mode, int it, double tau, int32_t* ties)
 {
     const int region = region0 + (int)(j / J);
     const IzStepOut o = iz_step_compute(S, d, region, Jt, part, nchunk, n, j, x_work, s_cur_r[j], s_prev_r[j],
-                                        r_prev_r[j], eps, max_iter, mode, it);
+                                        r_prev_r[j], eps, max_iter, mode, it, tau);
     iz_step_apply(o, region, Jt, j, it, ids_out, n_out, s_cur_w, s_prev_w, r_prev_w, x_work, s_out, iters,
-                  steps_acc);
+                  steps_acc, ties);
 }
 
 }  // namespace bmc

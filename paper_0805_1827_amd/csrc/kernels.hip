@@ -2,7 +2,7 @@
 // (inner-path) kernel, I&Z search updates and the FP64 rule fits.
 #include <math.h>
 
-#include "internal.hpp"
+#include "fit_common.hpp"
 #include "iz_step.hpp"
 
 namespace bmc {
@@ -78,19 +78,6 @@ hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStre
     return hipGetLastError();
 }
 
-// Task of a multi-task launch whose blocks are numbered through the
-// exclusive prefix sums of the tasks' block counts.
-__device__ __forceinline__ int task_of_block(const uint32_t* __restrict__ prefix, int ntasks, uint32_t b)
-{
-    int lo = 0, hi = ntasks;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (prefix[mid] <= b) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // ---------------------------------------------------------------------------
 // Continuation launch dispatch over the compiled dimension bounds.
 
@@ -145,13 +132,13 @@ hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, 
 
 template <int D, bool EXACT>
 hipError_t launch_cont_multi_d(int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks, uint32_t job0,
-                               uint32_t jobs, int block, size_t lds, hipStream_t st);
+                               uint32_t jobs, int block, size_t lds, hipStream_t st, bool stride);
 
 hipError_t launch_cont_multi(int bucket, int prec, const ContArgs* tasks, const uint32_t* prefix, int ntasks,
-                             uint32_t job0, uint32_t jobs, int block, size_t lds, hipStream_t st)
+                             uint32_t job0, uint32_t jobs, int block, size_t lds, hipStream_t st, bool stride)
 {
 #define BMC_ONE(DD, EX) \
-    case DD: return launch_cont_multi_d<DD, EX>(prec, tasks, prefix, ntasks, job0, jobs, block, lds, st);
+    case DD: return launch_cont_multi_d<DD, EX>(prec, tasks, prefix, ntasks, job0, jobs, block, lds, st, stride);
     switch (bucket) {
         BMC_BUCKETS(BMC_ONE)
     default: return hipErrorInvalidValue;
@@ -163,13 +150,15 @@ hipError_t launch_cont_multi(int bucket, int prec, const ContArgs* tasks, const 
 // var = (sumsq - sum^2/n)/(n-1), from a point's merged sums.
 __device__ __forceinline__ void finalize_point(int64_t j, double s, double q, double c, uint32_t n, double* cont,
                                                double* se, int64_t* steps, double* sums,
-                                               unsigned long long* steps_total)
+                                               unsigned long long* steps_total, const RefineSel& sel = {},
+                                               int64_t N = 0)
 {
     const double nn = (double)n;
     double var = (q - s * s / nn) / (nn - 1.0);
     if (var < 0.0) var = 0.0;
     if (cont) cont[j] = s / nn;
     if (se) se[j] = sqrt(var / nn);
+    if (sel.s) refine_point(sel.s->f64, sel.x, N, j, s / nn, sqrt(var / nn), sel.ids, sel.n_ids);
     if (steps) steps[j] = (int64_t)c;
     if (sums) {
         sums[2 * j] = s;
@@ -213,7 +202,7 @@ __device__ __forceinline__ void merge_wide(const double* __restrict__ part, uint
 __global__ void k_finalize(const double* __restrict__ part, uint32_t nchunk, uint32_t n, int64_t N,
                            const int32_t* __restrict__ ids, const int32_t* __restrict__ n_ids,
                            double* cont, double* se, int64_t* steps, double* sums,
-                           unsigned long long* steps_total)
+                           unsigned long long* steps_total, const RefineSel sel)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t j = slot;
@@ -225,18 +214,19 @@ __global__ void k_finalize(const double* __restrict__ part, uint32_t nchunk, uin
     }
     double s, q, c;
     merge_serial(part, nchunk, j, s, q, c);
-    finalize_point(j, s, q, c, n, cont, se, steps, sums, steps_total);
+    finalize_point(j, s, q, c, n, cont, se, steps, sums, steps_total, sel, N);
 }
 
 __global__ void __launch_bounds__(256) k_finalize_wide(const double* __restrict__ part, uint32_t nchunk,
-                                                       uint32_t n, double* cont, double* se, int64_t* steps,
-                                                       double* sums, unsigned long long* steps_total)
+                                                       uint32_t n, int64_t N, double* cont, double* se,
+                                                       int64_t* steps, double* sums, unsigned long long* steps_total,
+                                                       const RefineSel sel)
 {
     __shared__ double red[3][256];
     const int64_t j = blockIdx.x;
     double s, q, c;
     merge_wide(part, nchunk, j, red, s, q, c);
-    if (threadIdx.x == 0) finalize_point(j, s, q, c, n, cont, se, steps, sums, steps_total);
+    if (threadIdx.x == 0) finalize_point(j, s, q, c, n, cont, se, steps, sums, steps_total, sel, N);
 }
 
 // Finalize of many tasks in one launch: a wide task has one block per point,
@@ -251,12 +241,19 @@ __global__ void __launch_bounds__(256) k_finalize_multi(const FinTask* __restric
     double s, q, c;
     if (f.wide) {
         merge_wide(f.part, f.nchunk, local, red, s, q, c);
-        if (threadIdx.x == 0) finalize_point(local, s, q, c, f.n, f.cont, f.se, f.steps, f.sums, f.steps_total);
+        if (threadIdx.x == 0)
+            finalize_point(local, s, q, c, f.n, f.cont, f.se, f.steps, f.sums, f.steps_total, f.sel, f.N);
     } else {
-        const int64_t j = (int64_t)local * blockDim.x + threadIdx.x;
-        if (j >= f.N) return;
+        const int64_t slot = (int64_t)local * blockDim.x + threadIdx.x;
+        int64_t j = slot;
+        if (f.ids) {
+            if (slot >= *f.n_ids) return;
+            j = f.ids[slot];
+        } else if (slot >= f.N) {
+            return;
+        }
         merge_serial(f.part, f.nchunk, j, s, q, c);
-        finalize_point(j, s, q, c, f.n, f.cont, f.se, f.steps, f.sums, f.steps_total);
+        finalize_point(j, s, q, c, f.n, f.cont, f.se, f.steps, f.sums, f.steps_total, f.sel, f.N);
     }
 }
 
@@ -272,16 +269,17 @@ hipError_t launch_finalize_multi(const FinTask* tasks, const uint32_t* prefix, i
 hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int64_t N,
                            const int32_t* ids, const int32_t* n_ids, double* cont, double* se,
                            int64_t* steps, double* sums, unsigned long long* steps_total,
-                           hipStream_t st)
+                           hipStream_t st, const RefineSel* sel)
 {
+    const RefineSel sl = sel ? *sel : RefineSel{};
     if (finalize_is_wide(nchunk, N, ids != nullptr)) {
-        hipLaunchKernelGGL(k_finalize_wide, dim3((unsigned)N), dim3(256), 0, st, part, nchunk, n, cont, se, steps,
-                           sums, steps_total);
+        hipLaunchKernelGGL(k_finalize_wide, dim3((unsigned)N), dim3(256), 0, st, part, nchunk, n, N, cont, se, steps,
+                           sums, steps_total, sl);
         return hipGetLastError();
     }
     const int grid = (int)((N + 255) / 256);
     hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, st, part, nchunk, n, N, ids, n_ids,
-                       cont, se, steps, sums, steps_total);
+                       cont, se, steps, sums, steps_total, sl);
     return hipGetLastError();
 }
 
@@ -345,9 +343,10 @@ __global__ void k_bridge_end(const DevSpec* __restrict__ s, int64_t N, uint32_t 
 }
 
 __global__ void k_bridge_back(const DevSpec* __restrict__ s, int m, int64_t N, uint32_t seed,
-                              double* B, double* x, int bridge)
+                              double* B, double* x, int bridge, int32_t* zero_count)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (zero_count && j == 0) *zero_count = 0;
     if (j < N) bridge_back_point(s, m, N, seed, B, x, bridge, j);
 }
 
@@ -358,6 +357,7 @@ __global__ void k_bridge_multi(const BridgeTask* __restrict__ tasks, const uint3
     const int ti = task_of_block(prefix, ntasks, blockIdx.x);
     const BridgeTask& t = tasks[ti];
     const int64_t j = (int64_t)(blockIdx.x - prefix[ti]) * blockDim.x + threadIdx.x;
+    if (!end && t.zero_count && j == 0) *t.zero_count = 0;
     if (j >= t.N) return;
     if (end) bridge_end_point(t.s, t.N, t.seed, t.B, j);
     else bridge_back_point(t.s, t.m, t.N, t.seed, t.B, t.x, 1, j);
@@ -372,11 +372,11 @@ hipError_t launch_bridge_end(const DevSpec* s, int d, int64_t N, uint32_t seed, 
 }
 
 hipError_t launch_bridge_back(const DevSpec* s, int d, int m, int64_t N, uint32_t seed, double* B,
-                              double* x, int bridge, hipStream_t st)
+                              double* x, int bridge, hipStream_t st, int32_t* zero_count)
 {
     (void)d;
     hipLaunchKernelGGL(k_bridge_back, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, s, m, N,
-                       seed, B, x, bridge);
+                       seed, B, x, bridge, zero_count);
     return hipGetLastError();
 }
 
@@ -458,20 +458,30 @@ hipError_t launch_lattice(const DevSpec* s, int d, int m, int region0, int nreg,
 // Columns j of nreg regions side by side (J each, rows of Jt = nreg J).
 // n_ids: the three rotating active counts; the first starts at every column,
 // the other two at zero.
+// ties: null, or [Jt] near-tie flags.  subset = 0: every column starts
+// (its flag cleared); subset = 1: only the flagged columns start again (a
+// search of them in another precision), listed in ids by an atomic count
+// that the caller clears beforehand; the others keep their results.
 __global__ void k_iz_init(const DevSpec* __restrict__ s, const double* __restrict__ x_in, int d, int region0,
                           int64_t J, int64_t Jt, double* x_work, double* s_cur, double* s_out, int32_t* iters,
-                          int32_t* ids, int32_t* n_ids, unsigned long long* steps_acc)
+                          int32_t* ids, int32_t* n_ids, unsigned long long* steps_acc, int32_t* ties, int subset)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= Jt) return;
+    if (subset && !ties[j]) return;
     const int region = region0 + (int)(j / J);
     const double K = s->f64.K;
     for (int i = 0; i < d; ++i) x_work[i * Jt + j] = i == region ? K : x_in[i * Jt + j];
     s_cur[j] = K;
     s_out[j] = -1.0;
     iters[j] = 0;
-    ids[j] = (int32_t)j;
     steps_acc[j] = 0;
+    if (subset) {
+        ids[atomicAdd(&n_ids[0], 1)] = (int32_t)j;
+        return;
+    }
+    if (ties) ties[j] = 0;
+    ids[j] = (int32_t)j;
     if (j == 0) {
         n_ids[0] = (int32_t)Jt;
         n_ids[1] = 0;
@@ -481,11 +491,11 @@ __global__ void k_iz_init(const DevSpec* __restrict__ s, const double* __restric
 
 hipError_t launch_iz_init(const DevSpec* s, const double* x_in, int d, int region0, int nreg, int64_t J,
                           double* x_work, double* s_cur, double* s_out, int32_t* iters, int32_t* ids,
-                          int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st)
+                          int32_t* n_ids, unsigned long long* steps_acc, hipStream_t st, int32_t* ties, int subset)
 {
     const int64_t Jt = (int64_t)nreg * J;
     hipLaunchKernelGGL(k_iz_init, dim3((unsigned)((Jt + 255) / 256)), dim3(256), 0, st, s, x_in, d, region0, J, Jt,
-                       x_work, s_cur, s_out, iters, ids, n_ids, steps_acc);
+                       x_work, s_cur, s_out, iters, ids, n_ids, steps_acc, ties, subset);
     return hipGetLastError();
 }
 
@@ -498,26 +508,26 @@ __global__ void k_iz_update(const DevSpec* __restrict__ s, int d, int region0, i
                             const int32_t* __restrict__ ids_in, const int32_t* __restrict__ n_in,
                             int32_t* ids_out, int32_t* n_out, int32_t* n_next, const double* st_r, double* st_w,
                             double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
-                            double eps, int max_iter, int mode, int it)
+                            double eps, int max_iter, int mode, int it, double tau, int32_t* ties)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot == 0) *n_next = 0;
     if (slot >= *n_in) return;
     iz_step_slot(s->f64, d, region0, J, Jt, part, nchunk, n, ids_in[slot], ids_out, n_out, st_r, st_r + Jt,
                  st_r + 2 * Jt, st_w, st_w + Jt, st_w + 2 * Jt, x_work, s_out, iters, steps_acc, eps, max_iter,
-                 mode, it);
+                 mode, it, tau, ties);
 }
 
 hipError_t launch_iz_update(const DevSpec* s, int d, int region0, int nreg, int64_t J, const double* part,
                             uint32_t nchunk, uint32_t n, const int32_t* ids_in, const int32_t* n_in,
                             int32_t* ids_out, int32_t* n_out, int32_t* n_next, const double* st_r, double* st_w,
                             double* x_work, double* s_out, int32_t* iters, unsigned long long* steps_acc,
-                            double eps, int max_iter, int mode, int it, hipStream_t st)
+                            double eps, int max_iter, int mode, int it, hipStream_t st, double tau, int32_t* ties)
 {
     const int64_t Jt = (int64_t)nreg * J;
     hipLaunchKernelGGL(k_iz_update, dim3((unsigned)((Jt + 255) / 256)), dim3(256), 0, st, s, d, region0, J, Jt,
                        part, nchunk, n, ids_in, n_in, ids_out, n_out, n_next, st_r, st_w, x_work, s_out, iters,
-                       steps_acc, eps, max_iter, mode, it);
+                       steps_acc, eps, max_iter, mode, it, tau, ties);
     return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ struct PhaseTimer {
     }
 };
 
-enum { PH_CALC = 0, PH_FIT = 1, PH_FINAL = 2 };
+enum { PH_CALC = 0, PH_FIT = 1, PH_FINAL = 2, PH_REFINE = 3 };
 
 }  // namespace
 
@@ -113,16 +113,31 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     }
 
     if (method != BMC_IZ) {
+        // FP32 forms: the finalize of each date's estimates lists the
+        // near-tie training points, re-estimated in FP64 before the fit
+        const bool refine = refine_supported(prec, d, NT, rules->width);
+        RefineSel sel{};
+        if (refine) {
+            if ((e = ctx->rf.ensure(256 + sizeof(int32_t) * (size_t)N))) {
+                release();
+                return fail(BMC_ENOMEM, "device buffers: %s", hipGetErrorString(e));
+            }
+            sel = RefineSel{(const DevSpec*)ds, x, (int32_t*)((char*)ctx->rf.ptr + 256), (int32_t*)ctx->rf.ptr};
+        }
         if ((e = launch_bridge_end((const DevSpec*)ds, d, N, seed, B, ctx->stream))) st = hip_fail(e, "bridge");
         for (int m = NT - 1; m >= 1 && !st; --m) {
-            if ((e = launch_bridge_back((const DevSpec*)ds, d, m, N, seed, B, x, 1, ctx->stream))) {
+            if ((e = launch_bridge_back((const DevSpec*)ds, d, m, N, seed, B, x, 1, ctx->stream, sel.n_ids))) {
                 st = hip_fail(e, "bridge");
                 break;
             }
             timer.mark(PH_CALC);
             st = run_cont(ctx, ds, d, NT, method, rules->width, rules->w64, rules->w32, prec, m, x, N, nullptr,
                           nullptr, n, seed, key_hi(BMC_STREAM_INNER, m), cont, nullptr, nullptr, nullptr,
-                          steps_total, tune);
+                          steps_total, tune, 0, 0, nullptr, nullptr, nullptr, refine ? &sel : nullptr);
+            if (!st && refine) {
+                timer.mark(PH_REFINE);
+                st = refine_labels(ctx, ds, d, NT, rules, m, x, N, n, seed, cont, sel.ids, sel.n_ids);
+            }
             if (st) break;
             timer.mark(PH_FIT);
             st = fit_rule_impl(ctx, ds, d, rules, m, x, cont, N, rounds);
@@ -141,11 +156,21 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
         // regression per region.  The regions' searches are independent (each
         // uses the rules of later dates only), so they run side by side in the
         // same launches: region r in columns r N .. r N + N - 1.
+        // FP32 forms: points whose search met a near tie are searched again in FP64
+        int32_t* ties = nullptr;
+        if (prec != BMC_FP64) {
+            if ((e = ctx->rf.ensure(sizeof(int32_t) * (size_t)NR))) st = hip_fail(e, "search flags");
+            ties = (int32_t*)ctx->rf.ptr;
+        }
         for (int m = NT - 1; m >= 1 && !st; --m) {
             if ((st = sample_points_impl(ctx, ds, spec, BMC_IZ, m, N, seed, x, B, 0, regions))) break;
             timer.mark(PH_CALC);
             st = iz_search_impl(ctx, ds, spec, rules, m, 0, regions, x, N, n, seed, prec, eps, max_iter, search,
-                                s_out, iters, nullptr, tune, tally);
+                                s_out, iters, nullptr, tune, ties ? nullptr : tally, ties);
+            if (!st && ties) timer.mark(PH_REFINE);
+            if (!st && ties)
+                st = iz_search_impl(ctx, ds, spec, rules, m, 0, regions, x, N, n, seed, BMC_FP64, eps, max_iter,
+                                    search, s_out, iters, nullptr, tune, tally, ties, 1);
             if (st) break;
             timer.mark(PH_FIT);
             // every region's regression in one launch pair, s* read from the
@@ -197,11 +222,12 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     r.inner_path_steps = method != BMC_IZ ? (int64_t)inner : iz_steps;
     r.iz_unconverged = unconv;
     r.iz_iterations = iz_iters;
-    double sec[3] = {0, 0, 0};
+    double sec[4] = {0, 0, 0, 0};
     timer.totals(sec);
     r.calc_seconds = sec[PH_CALC];
     r.fit_seconds = sec[PH_FIT];
     r.final_seconds = sec[PH_FINAL];
+    r.refine_seconds = sec[PH_REFINE];
     r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     *out = r;
     if (rules_out) *rules_out = rules;

@@ -13,6 +13,7 @@
 
 namespace bmc {
 struct IzFuse;
+struct RefineSel;
 
 struct HostSpecPack;
 
@@ -44,6 +45,7 @@ struct bmc_ctx {
     bmc::HostSpecPack* pack_host = nullptr;   // pinned staging
     void* host_io = nullptr;                  // pinned 4 KB for small results
     bmc::DBuf spec, spec2, pack_dev, part, B, x, x2, cont, se, steps, fit, iz, counters, korobov;
+    bmc::DBuf rf;   // FP32 label refinement: [count (256 B)][ids N]
     // batched pricing: device specs, per-option arena, task tables; pinned staging
     bmc::DBuf bspec, barena, btab;
     void* bhost = nullptr;
@@ -94,7 +96,7 @@ bmc_status run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int m
                     uint32_t k1, double* cont, double* se, int64_t* steps, double* sums,
                     unsigned long long* steps_total, const Tuning* tune, uint32_t slot = 0,
                     uint32_t region_pts = 0, uint32_t* nchunk_out = nullptr, double* part = nullptr,
-                    const IzFuse* fz = nullptr);
+                    const IzFuse* fz = nullptr, const RefineSel* sel = nullptr);
 // region: the I&Z region whose boundary row block is fitted (0 for CMC), from
 // N points in rows of ld entries (0: N).
 bmc_status fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rules* rules, int date,
@@ -107,6 +109,9 @@ bmc_status sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec*
                               int nreg = 1);
 // Searches regions region .. region + nreg - 1 together: x, s_out and iters
 // hold nreg J points side by side, as sample_points_impl lays them out.
+// ties (FP32 searches of the pricer): near-tie flags [nreg J] written by the
+// search (IZ_TIE_TAU); again = 1 searches only the flagged points again, in
+// precision prec, keeping every other point's results.
 // tally (device, optional): adds the executed path-steps, the points left
 // without a boundary point and the iterations to tally[0..2] on the stream,
 // so that a caller sweeping dates reads them once at the end.
@@ -114,7 +119,15 @@ bmc_status iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spe
                           const bmc_rules* rules, int date, int region, int nreg, const double* x, int64_t J,
                           uint32_t n, uint32_t seed, int prec, double eps, int max_iter, int mode,
                           double* s_out, int32_t* iters, int64_t* steps_out, const Tuning* tune,
-                          unsigned long long* tally = nullptr);
+                          unsigned long long* tally = nullptr, int32_t* ties = nullptr, int again = 0);
+// FP32 label refinement of the CMC pricers: whether a
+// pricing refines (an FP32 form whose FP64 rule tables fit the LDS), and
+// the FP64 re-estimates of the points the FP32 finalize listed at date m
+// (ids, count *n_ids; same draws, one path per lane), written over cont.
+bool refine_supported(int prec, int d, int n_dates, int width);
+bmc_status refine_labels(bmc_ctx* ctx, const void* devspec, int d, int n_dates, const bmc_rules* rules, int m,
+                         const double* x, int64_t N, uint32_t n, uint32_t seed, double* cont, const int32_t* ids,
+                         const int32_t* n_ids);
 bmc_status final_price_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec,
                             const bmc_rules* rules, int64_t n_final, uint32_t seed, int prec,
                             double* host_sums, const Tuning* tune, bool sync = true);

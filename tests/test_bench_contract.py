@@ -22,17 +22,35 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_slot_model_of_the_headline_step():
-    # d = 5 geometric put under a CMC rule: 2 Philox blocks (10 rounds of two
-    # 32x32->64 multiplies and four xors), 3 Box-Muller pairs, 2d + d(d+1)/2
-    # step FMAs, one exp and d + 3 payoff ops, 3d + 4 rule ops
+    # d = 5 geometric put under a CMC rule: the 5 random words of a path-step
+    # are 5/4 Philox blocks (10 rounds of two 32x32->64 multiplies and four
+    # xors) and 5/2 Box-Muller pairs; 2d + d(d+1)/2 step FMAs, one exp and
+    # d + 3 payoff ops, 3d + 4 rule ops
     c = bench.COST
-    philox = 2 * 10 * (2 * c["mul64"] + 4 * c["int"])
-    bm = 3 * (4 + 1 + 2 + 4 * c["trans"])
+    philox = 10 * (2 * c["mul64"] + 4 * c["int"])
+    bm = 4 + 1 + 2 + 4 * c["trans"]
     step = 5 + 15 + 5
     pay = c["trans"] + 8
     rule = 19
-    assert bench.slots_per_step_fp32(5, inputs.PUT_GEO, 0) == pytest.approx(philox + bm + step + pay + rule)
-    assert bench.slots_per_step_fp32(5, inputs.PUT_GEO, 0) == pytest.approx(191.7)
+    assert bench.slots_per_step_fp32(5, inputs.PUT_GEO, 0) == pytest.approx(1.25 * philox + 2.5 * bm + step + pay + rule)
+    assert bench.slots_per_step_fp32(5, inputs.PUT_GEO, 0) == pytest.approx(149.15)
+    # as the kernel draws them: whole blocks (2) and pairs (3) per step
+    assert bench.slots_per_step_fp32(5, inputs.PUT_GEO, 0, layout=True) == pytest.approx(
+        2 * philox + 3 * bm + step + pay + rule)
+    # the two counts agree where d fills whole blocks
+    for d in (4, 8):
+        assert bench.slots_per_step_fp32(d, inputs.PUT_GEO, 0) == pytest.approx(
+            bench.slots_per_step_fp32(d, inputs.PUT_GEO, 0, layout=True))
+
+
+def test_fp64_slot_model_counts_library_calls():
+    # FP64 form: same operation list with the FP64 library calls; every class
+    # has a positive cost and the count grows with d
+    c = bench.COST64
+    assert all(v > 0 for v in c.values())
+    s5 = bench.slots_per_step_fp64(5, inputs.PUT_GEO, 0)
+    assert s5 > bench.slots_per_step_fp32(5, inputs.PUT_GEO, 0) * 0.5
+    assert bench.slots_per_step_fp64(6, inputs.PUT_GEO, 0) > s5
 
 
 def test_slot_model_leaves_matrix_core_correlation_out():

@@ -182,4 +182,4 @@ def test_price_fp32(bmc, ctx, orc, torch_mod, inputs, case, prec):
     dist = abs(res["price"] - ref["price"]) / ref["std_err"]
     print(f"{case} {prec}: whole FP32 price {res['price']:.6f}, FP64 oracle {ref['price']:.6f}, "
           f"{dist:.3f} standard errors apart")
-    assert dist <= 1.0
+    assert dist <= 0.1

@@ -164,3 +164,44 @@ def test_batch_min_call_and_padded_buckets(bmc, ctx, inputs):
         alone = bmc.bmc_price(ctx, s, **o)
         assert res[k]["price"] == alone["price"] and res[k]["inner_path_steps"] == alone["inner_path_steps"], k
         assert res[k]["price"] > 0.0, k            # every option pays on some paths
+
+
+# Options of the 256-option uneven workload (seeds of inputs.uneven_batch)
+# with n = 1024 inner paths and at most 30 dates, so that the oracle prices
+# each in about a second: d from 1 to 20, all three payoffs.
+C4_SUBSET = [186, 81, 207, 38, 231, 54, 168, 95, 103, 70, 8, 182, 20, 156]
+
+
+def test_fp32_batch_prices_within_tenth_of_std_err(bmc, ctx, orc, inputs):
+    """FP32 and FP32-Kahan batched prices of a seeded subset of the uneven
+    workload (N = 256 training points) against the FP64 oracle: within a tenth
+    of the oracle's standard error, with rule tables identical to the FP64
+    form's (the near-tie labels are re-estimated in FP64)."""
+    specs = [inputs.random_option(s) for s in C4_SUBSET]
+    assert sorted({s.d for s in specs}) == [1, 2, 3, 5, 7, 8, 9, 12, 13, 15, 16, 18, 20]
+    assert {s.payoff for s in specs} == {inputs.PUT_BASKET, inputs.CALL_MAX, inputs.PUT_GEO}
+
+    def opts(prec):
+        return [dict(method=bmc.CMC, precision=prec, N=256, n=s.meta["n"], n_final=40000, seed=s.meta["seed"])
+                for s in specs]
+
+    r64, rl64 = bmc.bmc_price_batch(ctx, specs, opts(bmc.FP64), want_rules=True)
+    t64 = [bmc.rules_table(r) for r in rl64]
+    for prec in (bmc.FP32, bmc.FP32_KAHAN):
+        r32, rl32 = bmc.bmc_price_batch(ctx, specs, opts(prec), want_rules=True)
+        for k, s in enumerate(specs):
+            assert np.array_equal(bmc.rules_table(rl32[k])[1:s.n_dates], t64[k][1:s.n_dates]), (prec, C4_SUBSET[k])
+        for r in rl32:
+            r.close()
+        for k, s in enumerate(specs):
+            if prec == bmc.FP32:
+                print(f"option {C4_SUBSET[k]} (d={s.d}, {s.n_dates} dates, payoff {s.payoff})", flush=True)
+                ref = orc.price(s, orc.CMC, 256, s.meta["n"], 40000, s.meta["seed"], nthreads=NT_CPU)
+                s.meta["ref"] = ref
+                tol = 1e-10 * max(abs(r64[k]["price"]), abs(ref["price"])) + 1e-12 * s.K
+                assert abs(r64[k]["price"] - ref["price"]) <= tol, (C4_SUBSET[k], r64[k]["price"], ref["price"])
+            ref = s.meta["ref"]
+            dist = abs(r32[k]["price"] - ref["price"]) / ref["std_err"]
+            assert dist <= 0.1, (prec, C4_SUBSET[k], r32[k]["price"], ref["price"], ref["std_err"])
+    for r in rl64:
+        r.close()

@@ -314,6 +314,25 @@ bmc_status bmc_iz_search(bmc_ctx *ctx, const bmc_spec *spec, const bmc_rules *ru
 bmc_status bmc_final_price(bmc_ctx *ctx, const bmc_spec *spec, const bmc_rules *rules,
                            int64_t n_final, uint64_t seed, int32_t precision, bmc_result *out);
 
+/* Continuation values as bmc_estimate_continuation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The call allocates nothing: the device
+ * spec tables and the per-job partial sums live in a static device array of
+ * BMC_NOALLOC_SCRATCH_BYTES per device, held until the process ends.  The
+ * caller passes device x, cont, std_err (and steps or NULL) and rules made
+ * beforehand.  Same arguments and results as bmc_estimate_continuation on
+ * the same context (identical values); synchronous (it waits for the spec
+ * upload, then enqueues on the context's stream).  BMC_ENOMEM if the
+ * partial sums, 24 bytes per (point, path chunk) of the launch shape,
+ * exceed the array less 256 KB.  Every call on a device shares that
+ * device's array and leaves its contents behind: calls that overlap on one
+ * device (several contexts or threads) race. */
+#define BMC_NOALLOC_SCRATCH_BYTES (16u << 20)
+bmc_status bmc_estimate_continuation_noalloc(bmc_ctx *ctx, const bmc_spec *spec, const bmc_rules *rules,
+                                             int32_t date, const double *x, int64_t N, int64_t n,
+                                             uint64_t seed, int32_t precision, double *cont,
+                                             double *std_err, int64_t *steps);
+
 /* Raw generator access for verification: M Philox4x32-10 blocks at device
  * counters ctr[4*M] -> device out[4*M]; and the four Box-Muller normals of
  * each block in the given precision (FP32 results widened to double). */

@@ -31,7 +31,7 @@ SYMBOLS = [
     "bmc_fit_rule", "bmc_iz_search", "bmc_final_price", "bmc_philox", "bmc_normals", "bmc_price_batch",
     "bmc_tuning_set", "bmc_tuning_get", "bmc_server_create", "bmc_server_destroy", "bmc_server_submit",
     "bmc_server_poll", "bmc_server_wait", "bmc_server_stats_get", "bmc_ctx_set_graphs", "bmc_ctx_graph_stats",
-    "bmc_autotune", "bmc_iz_regions",
+    "bmc_autotune", "bmc_iz_regions", "bmc_estimate_continuation_noalloc",
 ]
 
 
@@ -128,6 +128,8 @@ def load():
     L.bmc_sample_points.argtypes = [vp, sp, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_uint64, vp]
     L.bmc_estimate_continuation.argtypes = [vp, sp, vp, C.c_int32, vp, C.c_int64, C.c_int64, C.c_uint64,
                                             C.c_int32, vp, vp, vp]
+    L.bmc_estimate_continuation_noalloc.argtypes = [vp, sp, vp, C.c_int32, vp, C.c_int64, C.c_int64,
+                                                    C.c_uint64, C.c_int32, vp, vp, vp]
     L.bmc_fit_rule.argtypes = [vp, sp, vp, C.c_int32, C.c_int32, vp, vp, C.c_int64, C.c_int32]
     L.bmc_iz_search.argtypes = [vp, sp, vp, C.c_int32, C.c_int32, vp, C.c_int64, C.c_int64, C.c_uint64,
                                 C.c_int32, C.c_double, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_int64)]
@@ -450,6 +452,17 @@ def bmc_estimate_continuation(ctx: Context, spec, rules: Rules, date: int, x, n:
     _check(load().bmc_estimate_continuation(ctx.h, s.ptr, rules.h, date, _ptr(x), N, n, seed, precision,
                                             _ptr(cont), _ptr(se), _ptr(steps)))
     return cont, se, steps
+
+
+def bmc_estimate_continuation_noalloc(ctx: Context, spec, rules: Rules, date: int, x, cont, std_err, steps,
+                                      n: int, seed: int, precision: int = FP64) -> None:
+    """bmc_estimate_continuation into caller-made device tensors cont [N],
+    std_err [N] (float64) and steps [N] (int64, or None), with no device
+    allocation in the call."""
+    s = as_spec(spec)
+    N = int(x.shape[1])
+    _check(load().bmc_estimate_continuation_noalloc(ctx.h, s.ptr, rules.h, date, _ptr(x), N, n, seed, precision,
+                                                    _ptr(cont), _ptr(std_err), _ptr(steps)))
 
 
 def bmc_fit_rule(ctx: Context, spec, rules: Rules, date: int, x, values=None, rounds: int = 0,

@@ -185,6 +185,8 @@ extern "C" bmc_status bmc_ctx_create(int32_t device, void* hip_stream, bmc_ctx**
     if (e != hipSuccess || count == 0) return fail(BMC_EDEVICE, "no HIP device available");
     if (device < 0 || device >= count) return fail(BMC_EINVAL, "device %d outside 0..%d", device, count - 1);
     if ((e = hipSetDevice(device))) return hip_fail(e, "hipSetDevice");
+    bmc_status st = noalloc_setup(device);
+    if (st) return st;
     bmc_ctx* c = new bmc_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;

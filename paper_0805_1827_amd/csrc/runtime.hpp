@@ -78,6 +78,9 @@ struct bmc_rules {
 
 namespace bmc {
 
+// Takes the device address of the no-allocation entry point's scratch array
+// on `device` (the current device) once; bmc_ctx_create calls it.
+bmc_status noalloc_setup(int device);
 bmc_status upload_spec(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot);
 // As upload_spec without waiting: the setup status (0 or -2) is copied to
 // *status_host (pinned) on the stream; the caller checks it after a sync.

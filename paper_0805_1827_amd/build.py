@@ -78,8 +78,9 @@ def build_calib() -> list[Path]:
     exes = []
     for src in sorted((PKG / "calib").glob("*.hip")):
         exe = out / src.stem
-        subprocess.run([HIPCC, "--offload-arch=" + ARCH, "-O3", "-Xclang", "-target-feature", "-Xclang",
-                        "-packed-fp32-ops", str(src), "-o", str(exe)], check=True, capture_output=True)
+        subprocess.run([HIPCC, "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                        "-packed-fp32-ops", "-I" + str(CSRC), str(src), "-o", str(exe)], check=True,
+                       capture_output=True)
         exes.append(exe)
     return exes
 

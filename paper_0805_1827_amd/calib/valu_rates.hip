@@ -9,6 +9,8 @@
 #include <stdint.h>
 #include <stdio.h>
 
+#include "device.hpp"
+
 #define CH 8
 #define ITERS 8192
 
@@ -58,6 +60,35 @@ __global__ void k_sincospi_f64(double* out, double s0)
     }
     double r = a[0];
     for (int c = 1; c < CH; ++c) r = r + a[c];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
+
+// The continuation kernel's FP64 normal-map pieces (bmc::log_u32,
+// bmc::sincos_2pi_u32, bmc::sqrt_pos) on words from a counter: F = 0 is the
+// same loop with the word converted and added (the glue, subtracted).
+template <int F>
+__global__ void k_map64(double* out, uint32_t s)
+{
+    double acc[CH];
+    for (int c = 0; c < CH; ++c) acc[c] = 0.0;
+    const uint32_t x0 = threadIdx.x * 2654435761u + blockIdx.x * 40503u + s;
+    for (int i = 0; i < ITERS; ++i) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const uint32_t w = x0 + (uint32_t)c * 69069u + (uint32_t)i * 1664525u;
+            if (F == 0) acc[c] += (double)w;
+            else if (F == 1) acc[c] += bmc::log_u32(w);
+            else if (F == 2) {
+                double sn, cs;
+                bmc::sincos_2pi_u32(w, sn, cs);
+                acc[c] += sn * cs;
+            } else {
+                acc[c] += bmc::sqrt_pos((double)w + 1.0);
+            }
+        }
+    }
+    double r = acc[0];
+    for (int c = 1; c < CH; ++c) r += acc[c];
     out[blockIdx.x * blockDim.x + threadIdx.x] = r;
 }
 
@@ -126,6 +157,11 @@ int main()
     RUNG("sqrt_f64", k_sqrt_f64, double, 0.0, 8, 1.0);
     RUNG("sincospi_f64", k_sincospi_f64, double, 0.0, 8, 1.0);
     RUNG("cvt_pair_f64", k_cvt_f64, double, 0.0, 8, 1.0);
+    RUN("map_glue", k_map64<0>, double, 0u, 8);
+    const int g_map = k - 1;
+    RUN("log_u32", k_map64<1>, double, 0u, 8);
+    RUN("sincos_2pi_u32", k_map64<2>, double, 0u, 8);
+    RUN("sqrt_pos", k_map64<3>, double, 0u, 8);
     const double fma_rate = (double)n * ITERS * rows[0].ops / rows[0].t;
     printf("CUs %d; fp32 fma: %.4e lane-ops/s (= %.3f GHz x 64 lanes x CUs)\n", cus, fma_rate,
            fma_rate / (64.0 * cus) * 1e-9);
@@ -138,6 +174,12 @@ int main()
         // adds/multiplies, one FP64 FMA slot each) taken out
         if (rows[i].glue > 0.0) printf("  = %.2f fp64-fma-slots", fma64_rate / rate - rows[i].glue);
         printf("\n");
+    }
+    // the normal-map pieces net of their loop glue (the sincos row also
+    // pays one FP64 multiply), in FP64-FMA slots
+    for (int i = g_map + 1; i < g_map + 4; ++i) {
+        const double net = (rows[i].t - rows[g_map].t) * fma64_rate / ((double)n * ITERS * rows[i].ops);
+        printf("%-14s net of glue: %.2f fp64-fma-slots\n", rows[i].name, net - (i == g_map + 2 ? 1.0 : 0.0));
     }
     (void)hipFree(buf);
     return 0;

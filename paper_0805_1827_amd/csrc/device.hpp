@@ -96,15 +96,104 @@ __device__ __forceinline__ Words philox(uint32_t k0, uint32_t k1, uint32_t c0, u
     return o;
 }
 
+// FP64 pieces of the uniform-to-normal map, written for its arguments
+// u = (x + 1/2) 2^-32 (x a 32-bit word), within ~1.5 ulp of the exact values.
+//
+// ln u: x + 1/2 = m 2^e with m in [sqrt(1/2), sqrt(2)) (exact), f = m - 1,
+// s = f / (2 + f), and ln m = 2 artanh s = f - s (f - R(s^2)) with the
+// series R(z) = sum_k 2 z^k / (2k + 1) (|s| <= 0.1716, ten terms); then
+// ln u = (e - 32) ln 2 + ln m with ln 2 split into a short high part (exact
+// products) and the rest.
+__device__ __forceinline__ double log_u32(uint32_t x)
+{
+    const double v = (double)x + 0.5;   // exact
+    int e;
+    double m = frexp(v, &e);            // [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double f = m - 1.0;           // exact
+    const double den = 2.0 + f;
+    // s = f / den: reciprocal estimate, two Newton steps, a residual correction
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    double sq = f * r;
+    sq = fma(r, fma(-den, sq, f), sq);
+    const double z = sq * sq;
+    double R = 2.0 / 23;
+    R = fma(R, z, 2.0 / 21);
+    R = fma(R, z, 2.0 / 19);
+    R = fma(R, z, 2.0 / 17);
+    R = fma(R, z, 2.0 / 15);
+    R = fma(R, z, 2.0 / 13);
+    R = fma(R, z, 2.0 / 11);
+    R = fma(R, z, 2.0 / 9);
+    R = fma(R, z, 2.0 / 7);
+    R = fma(R, z, 2.0 / 5);
+    R = fma(R, z, 2.0 / 3);
+    R *= z;
+    const double t = f - sq * (f - R);
+    const double E = (double)(e - 32);
+    return fma(E, 0x1.62e42feep-1, t + E * 1.9082149292705877e-10);
+}
+
+// sin and cos of 2 pi u, u = (x + 1/2) 2^-32: t = 4u (exact) = q + f with q
+// the nearest integer (quarter turns) and |f| <= 1/2; sin(pi f / 2) and
+// cos(pi f / 2) from their Taylor series in f (coefficients (pi/2)^n / n!),
+// then the quarter-turn rotation by q.
+__device__ __forceinline__ void sincos_2pi_u32(uint32_t x, double& sn, double& cs)
+{
+    const double t = ((double)x + 0.5) * 0x1p-30;
+    const double q = rint(t);
+    const double f = t - q;             // exact
+    const double f2 = f * f;
+    double ps = 6.0669357311061955e-12;
+    ps = fma(ps, f2, -6.688035109811468e-10);
+    ps = fma(ps, f2, 5.692172921967927e-08);
+    ps = fma(ps, f2, -3.598843235212085e-06);
+    ps = fma(ps, f2, 0.00016044118478735983);
+    ps = fma(ps, f2, -0.004681754135318688);
+    ps = fma(ps, f2, 0.07969262624616705);
+    ps = fma(ps, f2, -0.6459640975062463);
+    ps = fma(ps, f2, 1.5707963267948966);
+    double pc = -5.294400200734623e-13;
+    pc = fma(pc, f2, 6.565963114979473e-11);
+    pc = fma(pc, f2, -6.386603083791852e-09);
+    pc = fma(pc, f2, 4.710874778818172e-07);
+    pc = fma(pc, f2, -2.5202042373060607e-05);
+    pc = fma(pc, f2, 0.0009192602748394266);
+    pc = fma(pc, f2, -0.02086348076335296);
+    pc = fma(pc, f2, 0.25366950790104803);
+    pc = fma(pc, f2, -1.2337005501361697);
+    pc = fma(pc, f2, 1.0);
+    const double s0 = f * ps;
+    const int qi = (int)q & 3;
+    const double a = (qi & 1) ? pc : s0;    // sin: s0, c0, -s0, -c0 for q = 0..3
+    const double b = (qi & 1) ? s0 : pc;    // cos: c0, -s0, -c0, s0
+    sn = (qi & 2) ? -a : a;
+    cs = ((qi + 1) & 2) ? -b : b;
+}
+
+// sqrt(a) for a > 0 (normal): reciprocal square root estimate, two Newton
+// steps, then the product and one residual correction.
+__device__ __forceinline__ double sqrt_pos(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    y = y * fma(-0.5 * a * y, y, 1.5);
+    y = y * fma(-0.5 * a * y, y, 1.5);
+    const double s0 = a * y;
+    return fma(0.5 * y, fma(-s0, s0, a), s0);
+}
+
 // Box-Muller on one word pair: u = (x + 1/2) 2^-32 in (0, 1),
 // z0 = sqrt(-2 ln u_a) cos(2 pi u_b), z1 = sqrt(-2 ln u_a) sin(2 pi u_b).
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1)
 {
-    const double ua = ((double)a + 0.5) * 0x1p-32;   // exact
-    const double ub = ((double)b + 0.5) * 0x1p-32;
-    const double rad = sqrt(-2.0 * log(ua));
+    const double rad = sqrt_pos(-2.0 * log_u32(a));
     double s, c;
-    sincospi(2.0 * ub, &s, &c);
+    sincos_2pi_u32(b, s, c);
     z0 = rad * c;
     z1 = rad * s;
 }

@@ -21,7 +21,7 @@ namespace bmc {
 // the first three (zero_bytes) start at zero.
 // FP32 pricings also hold the list of their label refinement (refine: the
 // FP64 tables fit the LDS), whose FP64 pass runs rnchunk chunks of rper_wg
-// paths per point (one path per lane).
+// paths per point (REFINE_PPT paths per lane).
 struct OptPlan {
     int d, NT, p, prec, rounds, bucket;
     int64_t N;

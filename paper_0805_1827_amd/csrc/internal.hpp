@@ -40,7 +40,8 @@ __device__ __forceinline__ int task_of_block(const uint32_t* __restrict__ prefix
 // largest |C - C_FP64| measured over every point and date of the 256-option
 // uneven workload is 0.61 standard errors, a third of REFINE_KAPPA.  The
 // finalize of the FP32 estimates lists the points (RefineSel); the FP64
-// re-estimates run one path per lane (REFINE_PPT), REFINE_SLOTS (or N, if
+// re-estimates run REFINE_PPT paths per lane (the fastest measured shape at
+// N = n = 4096 and on the uneven batch), REFINE_SLOTS (or N, if
 // fewer) points at a time.
 constexpr double REFINE_KAPPA = 2.0;
 // I&Z searches of the FP32 forms flag every point with a decision within
@@ -52,7 +53,7 @@ constexpr double REFINE_KAPPA = 2.0;
 constexpr double IZ_TIE_TAU = 1e-6;
 constexpr double REFINE_ETA = 1e-5;
 constexpr uint32_t REFINE_SLOTS = 256;
-constexpr int REFINE_PPT = 1;
+constexpr int REFINE_PPT = 2;
 // Selection made by a finalize: s == null selects nothing.  The list ids
 // (count *n_ids, cleared beforehand) receives the points to refine.
 struct RefineSel {

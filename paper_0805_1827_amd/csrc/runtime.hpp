@@ -126,7 +126,7 @@ bmc_status iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spe
 // FP32 label refinement of the CMC pricers: whether a
 // pricing refines (an FP32 form whose FP64 rule tables fit the LDS), and
 // the FP64 re-estimates of the points the FP32 finalize listed at date m
-// (ids, count *n_ids; same draws, one path per lane), written over cont.
+// (ids, count *n_ids; same draws, REFINE_PPT paths per lane), written over cont.
 bool refine_supported(int prec, int d, int n_dates, int width);
 bmc_status refine_labels(bmc_ctx* ctx, const void* devspec, int d, int n_dates, const bmc_rules* rules, int m,
                          const double* x, int64_t N, uint32_t n, uint32_t seed, double* cont, const int32_t* ids,

@@ -45,8 +45,8 @@ PEAK_MFMA_F32 = 157.3e12
 
 
 def uses_mfma(d: int) -> bool:
-    """FP32 kernels for d > 8 run the correlation on the matrix cores."""
-    return d > 8
+    """FP32 kernels for d >= 25 run the correlation on the matrix cores."""
+    return d >= 25
 
 
 def mfma_flops_per_step(d: int) -> float:
@@ -122,8 +122,10 @@ COST64 = {"f64": 1.0, "int": 0.606 / 1.112, "mul64": 1.145 / 1.112,
 
 def slots_per_step_fp64(d: int, payoff: int, method: int, layout: bool = False) -> float:
     """Algorithmic VALU issue slots of one inner path-step of the FP64 form,
-    in FP64-FMA slots: the FP32 form's operation list with FP64 arithmetic
-    and the device library's FP64 log, sqrt, sincospi and exp."""
+    in FP64-FMA slots: the FP32 form's operation list with FP64 arithmetic,
+    the library's own FP64 normal map (log of a word, sine and cosine of a
+    turn fraction, square root; measured net of their word conversions) and
+    the device library's FP64 exp."""
     c = COST64
     blocks, pairs = rng_units(d, layout)
     philox = blocks * philox_block_slots(c)
@@ -266,8 +268,9 @@ def batch_form(ctx, bmc, inputs, count: int, N: int, n_final: int) -> dict:
                                   "captures_replays": list(graph_stats)},
             "unit": "path-steps/s",
             "fp32_valu_slot_frac_of_peak": slots / calc / PEAK_SLOTS,
-            "fp32_mfma_tflops": mflops / calc / 1e12,
-            "fp32_mfma_frac_of_peak": mflops / calc / PEAK_MFMA_F32,
+            # matrix-core correlation only from d = 25 on (none in this mix)
+            **({"fp32_mfma_tflops": mflops / calc / 1e12, "fp32_mfma_frac_of_peak": mflops / calc / PEAK_MFMA_F32}
+               if mflops > 0 else {}),
             "fp32_vs_fp64_price_in_std_err": {"median": float(np.median(dist)), "max": float(dist.max()),
                                               "frac_within_0.1": float(np.mean(dist <= 0.1))},
             "fp32_final_under_fp64_rules_in_std_err": {"median": float(np.median(same)), "max": float(same.max()),

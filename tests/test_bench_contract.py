@@ -54,13 +54,13 @@ def test_fp64_slot_model_counts_library_calls():
 
 
 def test_slot_model_leaves_matrix_core_correlation_out():
-    # from d = 9 the correlation runs on the matrix cores: the VALU count drops
+    # from d = 25 the correlation runs on the matrix cores: the VALU count drops
     # by d(d+1)/2 and the flops are reported separately
-    v8 = bench.slots_per_step_fp32(8, inputs.PUT_GEO, 0)
-    v9 = bench.slots_per_step_fp32(9, inputs.PUT_GEO, 0)
-    assert not bench.uses_mfma(8) and bench.uses_mfma(9)
-    assert v9 < v8 + 40
-    assert bench.mfma_flops_per_step(9) == 90.0
+    v24 = bench.slots_per_step_fp32(24, inputs.PUT_GEO, 0)
+    v25 = bench.slots_per_step_fp32(25, inputs.PUT_GEO, 0)
+    assert not bench.uses_mfma(24) and bench.uses_mfma(25)
+    assert v25 < v24 - 200
+    assert bench.mfma_flops_per_step(25) == 650.0
     for d in range(1, 65):
         for pay in (inputs.PUT_BASKET, inputs.PUT_GEO, inputs.CALL_MAX, inputs.CALL_MIN):
             assert bench.slots_per_step_fp32(d, pay, 0) > 0

@@ -194,10 +194,11 @@ extern "C" bmc_status bmc_ctx_create(int32_t device, void* hip_stream, bmc_ctx**
         delete c;
         return hip_fail(e, "pinned staging");
     }
-    if ((e = hipHostMalloc((void**)&c->host_io, 4096, hipHostMallocDefault))) {
+    if ((e = hipHostMalloc((void**)&c->host_io, 4096, hipHostMallocDefault)) ||
+        (e = hipHostGetDevicePointer(&c->host_io_dev, c->host_io, 0))) {
         (void)hipHostFree(c->pack_host);
         c->pack_host = nullptr;
-        delete c;
+        delete c;   // frees host_io
         return hip_fail(e, "pinned staging");
     }
     *out = c;
@@ -918,14 +919,15 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
                             ctx->stream, ties, again)))
         return hip_fail(e, "search init");
     const uint32_t k1 = key_hi(BMC_STREAM_INNER, date);
-    // Progress polls without stalling the stream: after every fourth
-    // iteration the active count is copied to pinned memory behind an event,
-    // and the host reads it once the event has passed, with at most two polls
-    // outstanding.  Iterations enqueued after the count reached zero find no
-    // active point and change nothing.
+    // Progress polls without stalling the stream: every fourth launch writes
+    // the active count it starts from (the previous pass's) to pinned memory
+    // and an event follows it; the host reads the count once the event has
+    // passed, with at most two polls outstanding.  Iterations enqueued after
+    // the count reached zero find no active point and change nothing.
     for (hipEvent_t& ev : ctx->poll_ev)
         if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming))) return hip_fail(e, "search events");
     volatile int32_t* poll_host = (volatile int32_t*)((char*)ctx->host_io + 128);
+    int32_t* poll_dev = (int32_t*)((char*)ctx->host_io_dev + 128);
     int polls_issued = 0, polls_read = 0;
     bool done = false;
     auto read_poll = [&](bool wait) -> hipError_t {
@@ -963,6 +965,13 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
             fz.tau = tau;
         }
         const int prev = it > 0 ? it - 1 : 0;
+        // launch it >= 4 with it % 4 == 0 reports the count after pass it - 1
+        const bool poll = it > 0 && (it & 3) == 0;
+        if (poll) {
+            if (polls_issued - polls_read == 2 && (e = read_poll(true))) return hip_fail(e, "search progress");
+            if (done) break;
+            fz.poll = poll_dev + (polls_issued & 1);
+        }
         uint32_t nchunk = 0;
         bmc_status st = run_cont(ctx, devspec, d, spec->n_dates, rules->method, rules->width, rules->w64,
                                  rules->w32, prec, date, x_work, J, A[prev & 1], &cnt[prev % 3], n, seed, k1,
@@ -971,13 +980,8 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
         if (st) return st;
         if (nchunk != nch) return fail(BMC_EDEVICE, "search pass split %u chunks, expected %u", nchunk, nch);
         last = it;
-        if ((it & 3) == 3 && it != max_iter - 1) {
-            if (polls_issued - polls_read == 2 && (e = read_poll(true))) return hip_fail(e, "search progress");
-            if (done) break;
-            if ((e = hipMemcpyAsync((void*)&poll_host[polls_issued & 1], &cnt[it % 3], sizeof(int32_t),
-                                    hipMemcpyDeviceToHost, ctx->stream)) ||
-                (e = hipEventRecord(ctx->poll_ev[polls_issued & 1], ctx->stream)))
-                return hip_fail(e, "search progress");
+        if (poll) {
+            if ((e = hipEventRecord(ctx->poll_ev[polls_issued & 1], ctx->stream))) return hip_fail(e, "search progress");
             ++polls_issued;
         }
         while (!done && polls_read < polls_issued) {

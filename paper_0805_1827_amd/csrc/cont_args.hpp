@@ -31,6 +31,8 @@ struct IzFuse {
     int32_t* n_next;            // count of the iteration after, cleared here
     int32_t* ties;              // [N] near-tie flags of an FP32 search (or null)
     double tau;                 // near-tie width (0: no flags)
+    int32_t* poll;              // pinned host word that receives this launch's active count (or null)
+    int32_t pad_;
 };
 
 // One continuation launch: points (ids or 0..N-1) x chunks of paths.

@@ -44,6 +44,7 @@ struct bmc_ctx {
     hipStream_t stream = nullptr;
     bmc::HostSpecPack* pack_host = nullptr;   // pinned staging
     void* host_io = nullptr;                  // pinned 4 KB for small results
+    void* host_io_dev = nullptr;              // its device address (kernels write progress polls there)
     bmc::DBuf spec, spec2, pack_dev, part, B, x, x2, cont, se, steps, fit, iz, counters, korobov;
     bmc::DBuf rf;   // FP32 label refinement: [count (256 B)][ids N]
     // batched pricing: device specs, per-option arena, task tables; pinned staging

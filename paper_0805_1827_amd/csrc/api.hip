@@ -891,8 +891,10 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     // the search state St[t % 2] read by step t, the active lists A[it % 2].
     // Buffers: x_work [d][J], St 2 x [3][J], P 2 x [3 J nchunk], steps_acc [J],
     // ids 2 x [J].
+    const Tuning research{256, IZ_RESEARCH_PPT};
+    if (again) tune = &research;
     const uint32_t nch = cont_nchunk(ctx, d, prec, J, n, tune);
-    const size_t part_n = (size_t)3 * J * (ties ? std::max(nch, cont_nchunk(ctx, d, BMC_FP64, J, n, tune)) : nch);
+    const size_t part_n = (size_t)3 * J * (ties ? std::max(nch, cont_nchunk(ctx, d, BMC_FP64, J, n, &research)) : nch);
     const size_t need = sizeof(double) * ((size_t)d * J + 6 * J + 2 * part_n) + sizeof(unsigned long long) * J +
                         sizeof(int32_t) * 2 * J + 64;
     if ((e = ctx->iz.ensure(need))) return hip_fail(e, "search buffers");

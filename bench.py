@@ -35,9 +35,10 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # Issue cost of one lane-operation of each class, in FP32-FMA slots, measured
 # on gfx950 by paper_0805_1827_amd/calib/valu_rates.hip (8 independent chains
 # of one instruction class per lane, 8 waves per SIMD on all 256 CUs):
-# 2-input integer/logic 0.6, v_mad_u64_u32 (32x32->64 multiply) 1.15, FP32
-# transcendental (v_log/v_exp/v_sin/v_cos/v_sqrt) 1.9, FP32 FMA/add/mul 1.0.
-COST = {"int": 0.6, "mul64": 1.15, "trans": 1.9, "f32": 1.0}
+# 2-input integer/logic 0.6, three-input xor (v_bitop3_b32) 0.64, v_mad_u64_u32
+# (32x32->64 multiply) 1.15, FP32 transcendental (v_log/v_exp/v_sin/v_cos/v_sqrt)
+# 1.9, FP32 FMA/add/mul 1.0.
+COST = {"int": 0.6, "xor3": 0.64, "mul64": 1.15, "trans": 1.9, "f32": 1.0}
 
 
 # FP32 dense matrix-core peak of MI355X (TFLOP/s).
@@ -55,10 +56,11 @@ def mfma_flops_per_step(d: int) -> float:
 
 
 def philox_block_slots(cost=None) -> float:
-    """One Philox4x32-10 block: 10 rounds of 2 wide multiplies and 4 xors
-    (the key schedule is uniform across the wavefront, i.e. scalar)."""
+    """One Philox4x32-10 block: 10 rounds of 2 wide multiplies and 2
+    three-input xors (high half ^ counter word ^ key; the key schedule is
+    uniform across the wavefront, i.e. scalar)."""
     c = cost or COST
-    return 10 * (2 * c["mul64"] + 4 * c["int"])
+    return 10 * (2 * c["mul64"] + 2 * c["xor3"])
 
 
 def bm_pair_slots_fp32() -> float:
@@ -116,7 +118,7 @@ def slots_per_step_fp32(d: int, payoff: int, method: int, layout: bool = False) 
 # map's ln u, sin/cos(2 pi u) and sqrt are the kernel's own functions
 # (log_u32, sincos_2pi_u32, sqrt_pos) and exp the device library's, net
 # costs measured on gfx950 by paper_0805_1827_amd/calib/valu_rates.hip.
-COST64 = {"f64": 1.0, "int": 0.606 / 1.112, "mul64": 1.145 / 1.112,
+COST64 = {"f64": 1.0, "int": 0.606 / 1.112, "xor3": 0.636 / 1.112, "mul64": 1.145 / 1.112,
           "log": 31.6, "exp": 18.5, "sqrt": 13.5, "sincospi": 30.6, "cvt_pair": 1.5}
 
 

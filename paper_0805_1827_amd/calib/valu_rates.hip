@@ -31,6 +31,9 @@ CHAIN_KERNEL(k_fma32, float, 0.25f + threadIdx.x * 1e-6f + c, fmaf(x, s, 0.5f))
 CHAIN_KERNEL(k_fma64, double, 0.25 + threadIdx.x * 1e-6 + c, fma(x, s, 0.5))
 CHAIN_KERNEL(k_add_u32, uint32_t, threadIdx.x + c, x + s)
 CHAIN_KERNEL(k_xor_b32, uint32_t, threadIdx.x * 7919u + c * 104729u + s, x ^ a[(c + 3) & (CH - 1)])
+// three-input xor in one instruction (v_bitop3_b32, truth table 0x96)
+CHAIN_KERNEL(k_xor3_b32, uint32_t, threadIdx.x * 7919u + c * 104729u + s,
+             __builtin_amdgcn_bitop3_b32(x, a[(c + 3) & (CH - 1)], a[(c + 5) & (CH - 1)], 0x96))
 CHAIN_KERNEL(k_log_f32, float, 0.5f + threadIdx.x * 1e-6f + c, __builtin_amdgcn_logf(x))
 CHAIN_KERNEL(k_exp_f32, float, 0.5f + threadIdx.x * 1e-6f + c, __builtin_amdgcn_exp2f(x))
 CHAIN_KERNEL(k_sin_f32, float, 0.5f + threadIdx.x * 1e-6f + c, __builtin_amdgcn_sinf(x))
@@ -147,6 +150,7 @@ int main()
     RUN("fma_f64", k_fma64, double, 0.999, 8);
     RUN("add_u32", k_add_u32, uint32_t, 12345u, 8);
     RUN("xor_b32", k_xor_b32, uint32_t, 12345u, 7);
+    RUN("xor3_b32", k_xor3_b32, uint32_t, 12345u, 8);
     RUN("mad_u64_u32", k_mad_u64, uint64_t, 0xD2511F53ull, 8);
     RUN("log_f32", k_log_f32, float, 0.f, 8);
     RUN("exp_f32", k_exp_f32, float, 0.f, 8);

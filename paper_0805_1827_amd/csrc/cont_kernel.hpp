@@ -71,8 +71,8 @@ __device__ __forceinline__ void corr_mfma(const float* __restrict__ arow, const 
 
 // FP32 kernels put the correlation product on the matrix cores from d = 25 on:
 // below that the VALU form with the coefficients in LDS was faster when timed
-// (never-exercise geometric put, N = n = 4096: 6-17 % at d = 9..24, about
-// even at 26..28, the matrix cores 4-22 % ahead from d = 29 to 64).
+// (never-exercise geometric put, N = n = 4096: by 5-17 % at d = 9..24; from
+// d = 26 the matrix cores were 4-37 % ahead, d = 28 within the spread).
 template <int D, class R> constexpr bool uses_mfma() { return D >= 25 && sizeof(R) == 4; }
 template <int D> constexpr bool uses_lds_coef() { return D >= 9; }
 

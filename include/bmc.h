@@ -289,7 +289,10 @@ bmc_status bmc_estimate_continuation(bmc_ctx *ctx, const bmc_spec *spec, const b
  * x[region*N + j] holds the converged boundary coordinate s*_j (<= 0 marks a
  * dropped point) and values is ignored; quadratic least squares of ln s*
  * (Section 2.3 [reg]).  rounds: boosting rounds, <= 64 (0: 8 for BMC_CMC, 64
- * for BMC_CMC_ADA). */
+ * for BMC_CMC_ADA).  A BMC_CMC fit runs as one launch whose blocks (at most one
+ * per CU) meet at grid barriers; the call waits for it and returns
+ * BMC_EDEVICE if a barrier gave up because its blocks were not all resident
+ * (bmc_price reports the same). */
 bmc_status bmc_fit_rule(bmc_ctx *ctx, const bmc_spec *spec, bmc_rules *rules, int32_t date,
                         int32_t region, const double *x, const double *values, int64_t N,
                         int32_t rounds);

@@ -169,6 +169,21 @@ bmc_status bmc::upload_spec(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot)
     return BMC_OK;
 }
 
+int32_t* bmc::fit_barrier_flag_dev(bmc_ctx* ctx) { return (int32_t*)((char*)ctx->host_io_dev + 136); }
+
+bmc_status bmc::check_fit_barrier(bmc_ctx* ctx)
+{
+    volatile int32_t* flag = (volatile int32_t*)((char*)ctx->host_io + 136);
+    if (*flag == 0) return BMC_OK;
+    *flag = 0;
+    // a barrier that gave up leaves its words in an unknown state
+    if (ctx->gbar.ptr) {
+        (void)hipMemsetAsync(ctx->gbar.ptr, 0, 256, ctx->stream);
+        (void)hipStreamSynchronize(ctx->stream);
+    }
+    return fail(BMC_EDEVICE, "rule fit: a grid barrier timed out (its blocks were not all resident)");
+}
+
 const double* bmc::dev_S0(const void* devspec)
 {
     return (const double*)((const char*)devspec + offsetof(DevSpec, f64) + offsetof(SpecT<double>, S0));
@@ -208,7 +223,7 @@ extern "C" bmc_status bmc_ctx_create(int32_t device, void* hip_stream, bmc_ctx**
 bmc_ctx::~bmc_ctx()
 {
     for (DBuf* b : {&spec, &spec2, &pack_dev, &part, &B, &x, &x2, &cont, &se, &steps, &fit, &iz,
-                    &counters, &korobov, &rf, &bspec, &barena, &btab})
+                    &counters, &korobov, &rf, &gbar, &bspec, &barena, &btab})
         b->release();
     if (pack_host) (void)hipHostFree(pack_host);
     if (bhost) (void)hipHostFree(bhost);
@@ -768,7 +783,12 @@ bmc_status bmc::fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rule
             return hip_fail(e, "fit scratch");
         FitScratch fs;
         fit_scratch_carve((double*)ctx->fit.ptr, N, p, rounds, &fs);
-        if ((e = launch_fit_cmc((const DevSpec*)devspec, d, x, values, N, rounds, fs, row64, row32, ctx->stream)))
+        if (!ctx->gbar.ptr) {   // barrier words: zero once; every launch leaves them zero
+            if ((e = ctx->gbar.ensure(256)) || (e = hipMemsetAsync(ctx->gbar.ptr, 0, 256, ctx->stream)))
+                return hip_fail(e, "fit barrier");
+        }
+        if ((e = launch_fit_cmc((const DevSpec*)devspec, d, x, values, N, rounds, fs, row64, row32, ctx->stream,
+                                (unsigned*)ctx->gbar.ptr, fit_barrier_flag_dev(ctx))))
             return hip_fail(e, "fit launch");
     } else if (rules->method == BMC_CMC_ADA) {
         if ((e = ctx->fit.ensure(fit_ada_scratch_bytes(N, d)))) return hip_fail(e, "fit scratch");
@@ -813,7 +833,11 @@ extern "C" bmc_status bmc_fit_rule(bmc_ctx* ctx, const bmc_spec* spec, bmc_rules
     if (rules->method != BMC_IZ && !values) return fail(BMC_EINVAL, "CMC fit needs continuation values");
     if (rounds <= 0) rounds = rules->method == BMC_CMC_ADA ? ADA_TMAX : 8;
     if (rounds > 64) return fail(BMC_EINVAL, "rounds must be <= 64");
-    return fit_rule_impl(ctx, ctx->spec.ptr, spec->d, rules, date, x, values, N, rounds, region);
+    if ((st = fit_rule_impl(ctx, ctx->spec.ptr, spec->d, rules, date, x, values, N, rounds, region))) return st;
+    if (rules->method != BMC_CMC) return BMC_OK;
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(e, "stream sync");
+    return check_fit_barrier(ctx);
 }
 
 bmc_status bmc::sample_points_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec* spec, int method,

@@ -290,7 +290,7 @@ bmc_status plan_round(const std::vector<RoundItem>& items, Table& tab, std::vect
     // boosting fits: one block per pricing, grouped by tile size
     std::map<int, std::vector<const RoundItem*>> by_tile;
     for (const RoundItem* it : train) {
-        if (fit_coop_supported(it->q->p)) {
+        if (fit_one_launch_supported(it->q->p)) {
             by_tile[fit_tile(it->q->p)].push_back(it);
         } else {
             Step s;

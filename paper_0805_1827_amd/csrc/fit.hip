@@ -1,5 +1,5 @@
 // FP64 rule fits: the CMC boosting classifier (multi-launch form, used when
-// the cooperative one-launch form does not fit in LDS) and the I&Z quadratic
+// the one-launch form does not fit in LDS) and the I&Z quadratic
 // boundary regression.
 #include "fit_common.hpp"
 
@@ -120,10 +120,12 @@ void fit_scratch_carve(double* base, int64_t N, int p, int rounds, FitScratch* f
 }
 
 hipError_t launch_fit_cmc(const DevSpec* s, int d, const double* x, const double* cont, int64_t N, int rounds,
-                          const FitScratch& fs, double* row64, float* row32, hipStream_t st)
+                          const FitScratch& fs, double* row64, float* row32, hipStream_t st, unsigned* bar,
+                          int32_t* err)
 {
     const int p = rule_width(CMC, d);
-    if (fit_coop_supported(p)) return launch_fit_cmc_coop(s, d, x, cont, N, rounds, fs, row64, row32, st);
+    if (bar && fit_one_launch_supported(p))
+        return launch_fit_cmc_grid(s, d, x, cont, N, rounds, fs, row64, row32, bar, err, st);
     const int T = fit_tile(p);
     const int tiles = (int)((N + T - 1) / T);
     const int npairs = p * (p + 1) / 2;

@@ -1,5 +1,5 @@
-// Device arithmetic of the FP64 rule fits, shared by the one-launch
-// (cooperative) and multi-launch forms so that both give identical rules.
+// Device arithmetic of the FP64 rule fits, shared by the one-launch (grid
+// barrier) and multi-launch forms so that both give identical rules.
 // Reductions are deterministic: a tile is reduced sequentially by one thread
 // per output quantity; tiles are merged in tile order.
 #pragma once
@@ -605,8 +605,11 @@ __device__ inline void fit_tile_normal_eqs_mfma(const double* psi16, const doubl
     }
 }
 
-bool fit_coop_supported(int p);
-hipError_t launch_fit_cmc_coop(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
-                               int rounds, const FitScratch& fs, double* row64, float* row32, hipStream_t st);
+bool fit_one_launch_supported(int p);
+// bar: two device words, zero before the first launch (the launch leaves
+// them so); err: a pinned host word set to 1 if a grid barrier gave up.
+hipError_t launch_fit_cmc_grid(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
+                               int rounds, const FitScratch& fs, double* row64, float* row32, unsigned* bar,
+                               int32_t* err, hipStream_t st);
 
 }  // namespace bmc

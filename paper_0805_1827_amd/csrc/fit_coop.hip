@@ -1,16 +1,12 @@
-// One-launch CMC boosting fit (cooperative grid): the tiles of training
-// points are spread over the blocks; each boosting round ends with one grid
+// One-launch CMC boosting fit: the tiles of training points are spread over
+// the blocks (at most one per CU); each boosting round ends with one grid
 // barrier, after which every block merges the tile partials (in tile order)
 // and solves the small system itself, so the coefficients never leave the
 // block between rounds.  Used while the block's LDS layout fits the
 // device's per-workgroup LDS (every p up to d = 64 on gfx950's 160 KB); the
 // multi-launch form in fit.hip is the fallback for smaller LDS.  For p <= 15 the tile's weighted normal
 // equations run on the FP64 matrix cores.
-#include <hip/hip_cooperative_groups.h>
-
 #include "fit_common.hpp"
-
-namespace cg = cooperative_groups;
 
 namespace bmc {
 
@@ -68,11 +64,49 @@ __device__ void stage_tile(const double* __restrict__ phi, const double* __restr
 // block (many options fitted side by side, one per block).  Tile t belongs
 // to group member t mod size; every member merges all tiles in tile order,
 // so the result does not depend on the group size.
+//
+// The grid barrier of the one-launch fit.  The launch has at most one block
+// per CU, so on a device that is not full every block is resident at once.
+// bar[0] counts arrivals and bar[1] is the generation; bar[0] returns to zero
+// at every barrier, so the words are zeroed once, before the first launch.
+// Thread 0 of each block reads the generation, then arrives with an
+// acquire-release add at device scope; the last arrival clears the count and
+// publishes the next generation with a release store, the others poll the
+// generation and take an acquire fence once it moved.  The block barriers
+// before and after order the other threads' tile partials and reads.  A
+// wait longer than FIT_BARRIER_SPINS polls (about a second) sets *err and
+// gives up, so a launch whose blocks cannot all be resident ends with an
+// error instead of waiting for ever.
+constexpr uint32_t FIT_BARRIER_SPINS = 1u << 20;
+
 struct GridGroup {
-    cg::grid_group g;
+    unsigned* bar;
+    int32_t* err;   // pinned host word
     __device__ int rank() const { return blockIdx.x; }
     __device__ int size() const { return gridDim.x; }
-    __device__ void sync() { g.sync(); }
+    __device__ void sync()
+    {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (arrived == gridDim.x - 1) {
+                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                uint32_t spins = 0;
+                while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                    if (++spins > FIT_BARRIER_SPINS) {
+                        *err = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+        }
+        __syncthreads();
+    }
 };
 struct BlockGroup {
     __device__ int rank() const { return 0; }
@@ -206,7 +240,10 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
     }
 }
 
-__global__ void __launch_bounds__(256) k_fit_cmc_coop(FitTask a) { fit_cmc_body(a, GridGroup{cg::this_grid()}); }
+__global__ void __launch_bounds__(256) k_fit_cmc_grid(FitTask a, unsigned* bar, int32_t* err)
+{
+    fit_cmc_body(a, GridGroup{bar, err});
+}
 
 // One option per block.
 __global__ void __launch_bounds__(256) k_fit_cmc_multi(const FitTask* __restrict__ tasks)
@@ -233,7 +270,7 @@ static size_t fit_lds_limit()
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
             v = 64 * 1024;
         size_t lim = (size_t)v;
-        for (const void* f : {reinterpret_cast<const void*>(k_fit_cmc_coop),
+        for (const void* f : {reinterpret_cast<const void*>(k_fit_cmc_grid),
                               reinterpret_cast<const void*>(k_fit_cmc_multi)}) {
             hipFuncAttributes fa;
             size_t dyn = 64 * 1024 - 256;
@@ -250,7 +287,7 @@ static size_t fit_lds_limit()
     return limit;
 }
 
-bool fit_coop_supported(int p) { return fit_task_lds(p) <= fit_lds_limit(); }
+bool fit_one_launch_supported(int p) { return fit_task_lds(p) <= fit_lds_limit(); }
 
 FitTask fit_task_make(const DevSpec* s, int d, const double* x, const double* cont, int64_t N, int rounds,
                       const FitScratch& fs, double* row64, float* row32)
@@ -271,25 +308,20 @@ FitTask fit_task_make(const DevSpec* s, int d, const double* x, const double* co
     return a;
 }
 
-hipError_t launch_fit_cmc_coop(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
-                               int rounds, const FitScratch& fs, double* row64, float* row32,
-                               hipStream_t st)
+hipError_t launch_fit_cmc_grid(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
+                               int rounds, const FitScratch& fs, double* row64, float* row32, unsigned* bar,
+                               int32_t* err, hipStream_t st)
 {
     FitTask a = fit_task_make(s, d, x, cont, N, rounds, fs, row64, row32);
     const int T = fit_tile(a.p);
     const size_t lds = fit_task_lds(a.p);
-    int per_cu = 0, dev = 0, cus = 0;
+    int dev = 0, cus = 0;
     hipError_t e;
     if ((e = hipGetDevice(&dev))) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))) return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_fit_cmc_coop),
-                                                          T, lds)))
-        return e;
-    if (per_cu < 1) return hipErrorInvalidConfiguration;
-    const int grid = (int)std::min<int64_t>(a.ntiles, (int64_t)per_cu * cus);
-    void* args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_fit_cmc_coop), dim3(grid), dim3(T), args,
-                                      (unsigned)lds, st);
+    const int grid = (int)std::min<int64_t>(a.ntiles, cus);   // at most one block per CU
+    hipLaunchKernelGGL(k_fit_cmc_grid, dim3(grid), dim3(T), lds, st, a, bar, err);
+    return hipGetLastError();
 }
 
 hipError_t launch_fit_cmc_multi(const FitTask* tasks, int ntasks, int T, size_t lds, hipStream_t st)

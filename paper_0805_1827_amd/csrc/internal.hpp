@@ -184,7 +184,7 @@ __host__ __device__ __forceinline__ int fit_tile(int p)
     return 32;
 }
 
-// One CMC fit as run by the cooperative grid or by one block of a
+// One CMC fit as run by the one-launch grid or by one block of a
 // multi-option launch.
 struct FitTask {
     const DevSpec* s;
@@ -200,14 +200,16 @@ struct FitTask {
 FitTask fit_task_make(const DevSpec* s, int d, const double* x, const double* cont, int64_t N, int rounds,
                       const FitScratch& fs, double* row64, float* row32);
 size_t fit_task_lds(int p);
-bool fit_coop_supported(int p);
+bool fit_one_launch_supported(int p);
 // One block per task; all tasks share the tile size T = fit_tile(p).
 hipError_t launch_fit_cmc_multi(const FitTask* tasks, int ntasks, int T, size_t lds, hipStream_t st);
 size_t fit_scratch_doubles(int64_t N, int p, int rounds);
 void fit_scratch_carve(double* base, int64_t N, int p, int rounds, FitScratch* fs);
+// bar/err: the one-launch form's barrier words and error flag (null: the
+// multi-launch form).
 hipError_t launch_fit_cmc(const DevSpec* s, int d, const double* x, const double* cont, int64_t N,
                           int rounds, const FitScratch& fs, double* row64, float* row32,
-                          hipStream_t st);
+                          hipStream_t st, unsigned* bar = nullptr, int32_t* err = nullptr);
 // I&Z quadratic regression of rule row m; x[0*J + j] = s*_j.
 size_t fitiz_scratch_doubles(int64_t J, int p);
 // AdaBoost-stump fit of one date (rounds <= ADA_TMAX) into a rule row of width

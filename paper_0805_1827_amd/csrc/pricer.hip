@@ -211,6 +211,10 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
         }
     }
     if (!st && *status_host != 0) st = fail(BMC_ENOTSPD, "correlation matrix is not positive definite");
+    if (method != BMC_IZ) {
+        const bmc_status fb = check_fit_barrier(ctx);
+        if (!st) st = fb;
+    }
     const unsigned long long inner = st ? 0 : *inner_host;
     if (st) {
         release();

@@ -47,6 +47,7 @@ struct bmc_ctx {
     void* host_io_dev = nullptr;              // its device address (kernels write progress polls there)
     bmc::DBuf spec, spec2, pack_dev, part, B, x, x2, cont, se, steps, fit, iz, counters, korobov;
     bmc::DBuf rf;   // FP32 label refinement: [count (256 B)][ids N]
+    bmc::DBuf gbar;   // the one-launch fit's grid-barrier words (zeroed once; host_io + 136: its error flag)
     // batched pricing: device specs, per-option arena, task tables; pinned staging
     bmc::DBuf bspec, barena, btab;
     void* bhost = nullptr;
@@ -91,6 +92,11 @@ bmc_status upload_spec_async(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot, int32_
 bmc_status scratch_rules(bmc_ctx* ctx, const bmc_spec* spec, int method, bmc_rules* out);
 void pack_spec(const bmc_spec* s, HostSpecPack* p);
 const double* dev_S0(const void* devspec);
+// Error flag of the one-launch fit's grid barrier (a pinned host word; the
+// device address for the kernel), and its check after a synchronization:
+// BMC_EDEVICE (and the flag and barrier words reset) if a barrier gave up.
+int32_t* fit_barrier_flag_dev(bmc_ctx* ctx);
+bmc_status check_fit_barrier(bmc_ctx* ctx);
 uint32_t choose_ppt(const bmc_ctx* ctx, int d, int prec, int64_t points, int64_t n, const Tuning* tune);
 uint64_t ppt_key(int bucket, int prec_plus1, int nclass);
 int n_class(int64_t n);

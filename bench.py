@@ -363,8 +363,10 @@ def iz_form(ctx, bmc, inputs, reps: int = 3) -> dict:
         r = runs[-1]
         wall = float(np.median([x["seconds"] for x in runs]))
         calc = float(np.median([x["calc_seconds"] for x in runs]))
+        research = float(np.median([x["refine_seconds"] for x in runs]))
         return {"S0": S0, "J": J, "N1": N1, "price": r["price"], "std_err": r["std_err"],
                 "error_vs_binomial": IZ_BINOMIAL[S0] - r["price"], "ms": 1e3 * wall, "calc_ms": 1e3 * calc,
+                "near_tie_fp64_search_ms": 1e3 * research,
                 "inner_path_steps": r["inner_path_steps"],
                 "inner_path_steps_per_s": r["inner_path_steps"] / calc,
                 "iterations_per_point": r["iz_iterations"] / (3 * (spec.n_dates - 1) * J),

@@ -991,8 +991,10 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
             fz.tau = tau;
         }
         const int prev = it > 0 ? it - 1 : 0;
-        // launch it >= 4 with it % 4 == 0 reports the count after pass it - 1
-        const bool poll = it > 0 && (it & 3) == 0;
+        // launch it >= 4 with it % 4 == 0 reports the count after pass it - 1;
+        // the FP64 search of the near-tie points also reports its first count
+        // (often zero), so that an empty one ends after a launch or two
+        const bool poll = (it > 0 && (it & 3) == 0) || (again && it == 0);
         if (poll) {
             if (polls_issued - polls_read == 2 && (e = read_poll(true))) return hip_fail(e, "search progress");
             if (done) break;

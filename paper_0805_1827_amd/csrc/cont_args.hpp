@@ -31,7 +31,8 @@ struct IzFuse {
     int32_t* n_next;            // count of the iteration after, cleared here
     int32_t* ties;              // [N] near-tie flags of an FP32 search (or null)
     double tau;                 // near-tie width (0: no flags)
-    int32_t* poll;              // pinned host word that receives this launch's active count (or null)
+    int32_t* poll;              // pinned host word that receives the count of the launch's list (or null;
+                                // also read when on = 0)
     int32_t pad_;
 };
 

@@ -397,10 +397,10 @@ __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
     const uint32_t slot = blockIdx.x / a.nchunk;
     const uint32_t chunk = blockIdx.x - slot * a.nchunk;
     if constexpr (IZK) {
-        if (a.fz.on && blockIdx.x == 0 && threadIdx.x == 0) {
-            *a.fz.n_next = 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (a.fz.on) *a.fz.n_next = 0;
             // progress poll: the count of the list this launch runs over, which
-            // the previous launch completed
+            // an earlier launch completed
             if (a.fz.poll) *a.fz.poll = *a.n_ids;
         }
     }

@@ -60,7 +60,7 @@ __device__ void stage_tile(const double* __restrict__ phi, const double* __restr
     __syncthreads();
 }
 
-// The fit runs on a group of blocks: the whole cooperative grid, or one
+// The fit runs on a group of blocks: the whole grid of its launch, or one
 // block (many options fitted side by side, one per block).  Tile t belongs
 // to group member t mod size; every member merges all tiles in tile order,
 // so the result does not depend on the group size.

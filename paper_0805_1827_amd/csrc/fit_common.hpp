@@ -176,7 +176,7 @@ __device__ inline bool spd_solve(int p, double* A, double lam, double* b, double
 // The same with the ridge lam = scale tr(A) / p: for p <= 32 the trace is
 // summed by the solving wavefront itself (no block barrier before the solve);
 // *lam_out (LDS) receives lam.
-__device__ inline bool spd_solve_ridge(int p, double* A, double scale, double* b, double* x, int* flag,
+__device__ __forceinline__ bool spd_solve_ridge(int p, double* A, double scale, double* b, double* x, int* flag,
                                        double* lam_out)
 {
     if (p <= 32) {

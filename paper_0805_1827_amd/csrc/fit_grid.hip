@@ -26,9 +26,9 @@ __host__ __device__ inline int coop_aux(int p, int T)
 
 // Sum over tiles, in tile order, of the Q columns of a [ntiles][Q] array
 // into out[Q] (LDS): thread q reads its column straight from memory (the
-// threads of a tile row read consecutive words), eight tiles' loads in
-// flight before their adds, which keep the order of a sequential merge from
-// zero.
+// threads of a tile row read consecutive words), sixteen (then eight) tiles'
+// loads in flight before their adds, which keep the order of a sequential
+// merge from zero.
 __device__ void merge_tiles(const double* __restrict__ part, int ntiles, int Q, double* out)
 {
     const int T = blockDim.x, tid = threadIdx.x;
@@ -36,6 +36,13 @@ __device__ void merge_tiles(const double* __restrict__ part, int ntiles, int Q, 
     for (int q = tid; q < Q; q += T) {
         double acc = 0.0;
         int t = 0;
+        for (; t + 16 <= ntiles; t += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = part[(size_t)(t + u) * Q + q];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += v[u];
+        }
         for (; t + 8 <= ntiles; t += 8) {
             double v[8];
 #pragma unroll
@@ -87,6 +94,7 @@ struct GridGroup {
     __device__ void sync()
     {
         __syncthreads();
+        if (gridDim.x == 1) return;   // one block: the block barrier is the grid barrier
         if (threadIdx.x == 0) {
             const unsigned g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);

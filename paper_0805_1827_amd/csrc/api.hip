@@ -137,11 +137,12 @@ bmc_status bmc::upload_spec_async(bmc_ctx* ctx, const bmc_spec* s, DBuf& slot, i
     if ((e = ctx->pack_dev.ensure(sizeof(HostSpecPack)))) return hip_fail(e, "spec staging");
     if ((e = hipStreamSynchronize(ctx->stream))) return hip_fail(e, "stream sync");   // staging free
     pack_spec(s, ctx->pack_host);
+    // the setup kernel writes its status word straight into the pinned status_host
+    int32_t* status_dev = (int32_t*)((char*)ctx->host_io_dev + ((char*)status_host - (char*)ctx->host_io));
     if ((e = hipMemcpyAsync(ctx->pack_dev.ptr, ctx->pack_host, sizeof(HostSpecPack), hipMemcpyHostToDevice,
                             ctx->stream)) ||
-        (e = launch_setup((const HostSpecPack*)ctx->pack_dev.ptr, (DevSpec*)slot.ptr, 1, ctx->stream)) ||
-        (e = hipMemcpyAsync(status_host, (char*)slot.ptr + offsetof(DevSpec, status), sizeof(int32_t),
-                            hipMemcpyDeviceToHost, ctx->stream)))
+        (e = launch_setup((const HostSpecPack*)ctx->pack_dev.ptr, (DevSpec*)slot.ptr, 1, ctx->stream, nullptr,
+                          status_dev)))
         return hip_fail(e, "spec upload");
     return BMC_OK;
 }
@@ -1068,16 +1069,14 @@ bmc_status bmc::final_price_impl(bmc_ctx* ctx, const void* devspec, const bmc_sp
                                  const Tuning* tune, bool sync)
 {
     hipError_t e;
-    if ((e = ctx->counters.ensure(64))) return hip_fail(e, "counters");
-    double* sums = (double*)((char*)ctx->counters.ptr + 16);   // [2]
-    int64_t* fsteps = (int64_t*)((char*)ctx->counters.ptr + 32);
+    // the finalize of the one point stores its sums and step count straight
+    // into the pinned host_io (plain stores, visible once the stream is synchronized)
+    double* sums = (double*)ctx->host_io_dev;                         // [2]
+    int64_t* fsteps = (int64_t*)((char*)ctx->host_io_dev + 16);
     bmc_status st = run_cont(ctx, devspec, spec->d, spec->n_dates, rules->method, rules->width, rules->w64,
                              rules->w32, prec, 0, dev_S0(devspec), 1, nullptr, nullptr, (uint32_t)n_final,
                              seed, key_hi(BMC_STREAM_FINAL, 0), nullptr, nullptr, fsteps, sums, nullptr, tune);
     if (st) return st;
-    if ((e = hipMemcpyAsync(ctx->host_io, sums, 16, hipMemcpyDeviceToHost, ctx->stream)) ||
-        (e = hipMemcpyAsync((char*)ctx->host_io + 16, fsteps, 8, hipMemcpyDeviceToHost, ctx->stream)))
-        return hip_fail(e, "final read");
     if (!sync) return BMC_OK;
     if ((e = hipStreamSynchronize(ctx->stream))) return hip_fail(e, "final read");
     read_final_sums(ctx, host_sums);

@@ -104,8 +104,10 @@ struct LaunchCfg {
 
 // Kernels (kernels.hip).  All enqueue on `st` and return hipError_t.
 // Spec setup of count packs; pack i goes to out[slots ? slots[i] : i].
+// status_host (count = 1): device address of a pinned host word that also
+// receives the setup status (0, or -2 if rho is not positive definite).
 hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st,
-                        const uint32_t* slots = nullptr);
+                        const uint32_t* slots = nullptr, int32_t* status_host = nullptr);
 hipError_t launch_cont(int d, int prec, const ContArgs& a, int grid, int block, size_t lds,
                        hipStream_t st);
 // One launch over jobs job0 .. job0+jobs-1 of many tasks of one bucket;

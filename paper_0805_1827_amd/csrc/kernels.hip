@@ -11,7 +11,8 @@ namespace bmc {
 // Spec setup: Cholesky of rho (FP64), A = diag(sigma) L, drifts, date tables.
 
 __global__ void __launch_bounds__(256) k_setup(const HostSpecPack* __restrict__ in,
-                                               DevSpec* __restrict__ out, const uint32_t* __restrict__ slots)
+                                               DevSpec* __restrict__ out, const uint32_t* __restrict__ slots,
+                                               int32_t* status_host)
 {
     __shared__ double L[D_MAX * D_MAX];
     __shared__ int bad;
@@ -46,6 +47,7 @@ __global__ void __launch_bounds__(256) k_setup(const HostSpecPack* __restrict__ 
         b.K = (float)a.K; b.lnK = (float)a.lnK; b.invK = (float)a.invK; b.r = (float)a.r;
         b.inv_d = (float)a.inv_d;
         out->status = bad ? -2 : 0;
+        if (status_host) *status_host = out->status;   // single-spec setups: straight to pinned memory
     }
     for (int i = tid; i < D_MAX; i += blockDim.x) {
         const bool on = i < d;
@@ -72,9 +74,10 @@ __global__ void __launch_bounds__(256) k_setup(const HostSpecPack* __restrict__ 
     }
 }
 
-hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st, const uint32_t* slots)
+hipError_t launch_setup(const HostSpecPack* in, DevSpec* out, int count, hipStream_t st, const uint32_t* slots,
+                        int32_t* status_host)
 {
-    hipLaunchKernelGGL(k_setup, dim3(count), dim3(256), 0, st, in, out, slots);
+    hipLaunchKernelGGL(k_setup, dim3(count), dim3(256), 0, st, in, out, slots, status_host);
     return hipGetLastError();
 }
 

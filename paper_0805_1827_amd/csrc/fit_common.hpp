@@ -83,8 +83,14 @@ __device__ __forceinline__ double bcast_lane(double v, int src)
 // of the factor in registers and the columns travel by lane broadcasts,
 // with no block barrier.  Same per-entry subtraction order as above; the
 // divisions by a pivot become products with its reciprocal, which comes
-// with the pivot from a refined reciprocal square root (no division).  A
-// (packed, in LDS) is overwritten with the factor.
+// with the pivot from a refined reciprocal square root (no division).  The
+// forward substitution runs inside the factorisation: column c of L is final
+// once pivot c has scaled it, so y_c and the updates of the later y_i follow
+// at once, in the same order as a separate pass.  Updates run on every lane:
+// entries above the diagonal, and a lane's y once its own pivot has taken
+// it, receive values that are never read.  Pivot lane c scales its diagonal
+// like the rest of the column, dc / sqrt(dc) = L_cc.  A (packed, in LDS) is
+// overwritten with the factor.
 // Returns false (on every lane) if a pivot is not positive.
 template <int P>
 __device__ bool wave_spd_solve(int p, double* A, double lam, const double* b, double* x)
@@ -101,6 +107,8 @@ __device__ bool wave_spd_solve(int p, double* A, double lam, const double* b, do
     }
     bool ok = true;
     double invd = 1.0;   // lane c: 1 / L_cc
+    double y = lane < p ? b[lane] : 0.0;
+    double yf = 0.0;     // lane c: y_c of L y = b
 #pragma unroll
     for (int c = 0; c < P; ++c) {
         double dc = bcast_lane(row[c], c);
@@ -109,30 +117,22 @@ __device__ bool wave_spd_solve(int p, double* A, double lam, const double* b, do
             dc = 1.0;
         }
         // 1/sqrt(dc) from the hardware estimate and two Newton steps
-        // y <- y (3 - dc y^2) / 2, then L_cc = dc / sqrt(dc)
+        // y <- y (3 - dc y^2) / 2
         double inv = __builtin_amdgcn_rsq(dc);
         inv = inv * (1.5 - 0.5 * dc * inv * inv);
         inv = inv * (1.5 - 0.5 * dc * inv * inv);
-        const double lcc = dc * inv;
+        row[c] *= inv;
+        const double yc = bcast_lane(y, c) * inv;
         if (lane == c) {
-            row[c] = lcc;
             invd = inv;
-        } else if (lane > c) {
-            row[c] *= inv;
+            yf = yc;
         }
+        y -= row[c] * yc;
 #pragma unroll
         for (int l = c + 1; l < P; ++l) {
             const double llc = bcast_lane(row[c], l);
-            if (lane >= l) row[l] -= row[c] * llc;
+            row[l] -= row[c] * llc;
         }
-    }
-    // forward substitution L y = b
-    double y = lane < p ? b[lane] : 0.0;
-#pragma unroll
-    for (int c = 0; c < P; ++c) {
-        const double yc = bcast_lane(y, c) * bcast_lane(invd, c);
-        if (lane == c) y = yc;
-        else if (lane > c) y -= row[c] * yc;
     }
     // L back into the packed triangle; each lane then reads its column, so
     // that the back substitution L^T x = y needs no per-entry broadcasts
@@ -146,11 +146,12 @@ __device__ bool wave_spd_solve(int p, double* A, double lam, const double* b, do
 #pragma unroll
     for (int c = 0; c < P; ++c) col[c] = (lane < p && c >= lane && c < p) ? A[tri(c, lane)] : 0.0;
     double xv = 0.0;
+    y = yf;
 #pragma unroll
     for (int c = P - 1; c >= 0; --c) {
-        const double xc = bcast_lane(y, c) * bcast_lane(invd, c);
+        const double xc = bcast_lane(y * invd, c);
         if (lane == c) xv = xc;
-        if (lane < c) y -= col[c] * xc;
+        y -= col[c] * xc;
     }
     if (lane < p) x[lane] = xv;
     return ok;

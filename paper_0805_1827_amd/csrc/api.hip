@@ -224,7 +224,7 @@ extern "C" bmc_status bmc_ctx_create(int32_t device, void* hip_stream, bmc_ctx**
 bmc_ctx::~bmc_ctx()
 {
     for (DBuf* b : {&spec, &spec2, &pack_dev, &part, &B, &x, &x2, &cont, &se, &steps, &fit, &iz,
-                    &counters, &korobov, &rf, &gbar, &bspec, &barena, &btab})
+                    &counters, &korobov, &rf, &order, &gbar, &bspec, &barena, &btab})
         b->release();
     if (pack_host) (void)hipHostFree(pack_host);
     if (bhost) (void)hipHostFree(bhost);
@@ -650,7 +650,8 @@ static bmc_status prepare_cont(bmc_ctx* ctx, const void* devspec, int d, int n_d
                                const void* rules64, const void* rules32, int prec, int m, const double* x, int64_t N,
                                const int32_t* ids, const int32_t* n_ids, uint32_t n, uint32_t k0, uint32_t k1,
                                const Tuning* tune, uint32_t slot, uint32_t region_pts, ContArgs& a, int& block,
-                               size_t& lds, int64_t& grid, double* part = nullptr, const IzFuse* fz = nullptr)
+                               size_t& lds, int64_t& grid, double* part = nullptr, const IzFuse* fz = nullptr,
+                               const JobOrder* ord = nullptr)
 {
     block = (tune && tune->block > 0) ? tune->block : 256;
     const uint32_t ppt = choose_ppt(ctx, d, prec, N, n, tune);
@@ -683,6 +684,7 @@ static bmc_status prepare_cont(bmc_ctx* ctx, const void* devspec, int d, int n_d
     a.region_pts = region_pts;
     a.part = part ? part : (double*)ctx->part.ptr;
     a.fz = fz ? *fz : IzFuse{};
+    a.ord = (ord && !ids) ? *ord : JobOrder{};
     return BMC_OK;
 }
 
@@ -700,14 +702,14 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
                          uint32_t n, uint32_t k0, uint32_t k1, double* cont, double* se,
                          int64_t* steps, double* sums, unsigned long long* steps_total,
                          const Tuning* tune, uint32_t slot, uint32_t region_pts, uint32_t* nchunk_out,
-                         double* part, const IzFuse* fz, const RefineSel* sel)
+                         double* part, const IzFuse* fz, const RefineSel* sel, const JobOrder* ord)
 {
     ContArgs a{};
     int block = 256;
     size_t lds = 0;
     int64_t grid = 0;
     bmc_status st = prepare_cont(ctx, devspec, d, n_dates, method, width, rules64, rules32, prec, m, x, N, ids,
-                                 n_ids, n, k0, k1, tune, slot, region_pts, a, block, lds, grid, part, fz);
+                                 n_ids, n, k0, k1, tune, slot, region_pts, a, block, lds, grid, part, fz, ord);
     if (st) return st;
     const uint32_t nchunk = a.nchunk;
     hipError_t e;

@@ -37,6 +37,14 @@ struct IzFuse {
 };
 
 // One continuation launch: points (ids or 0..N-1) x chunks of paths.
+// Job order of a launch over all N points (cnt null: point order): the
+// points listed bucket by bucket, cnt[b] points of bucket b at list[b N ..].
+constexpr int ORDER_BUCKETS = 16;
+struct JobOrder {
+    const int32_t* cnt;    // [ORDER_BUCKETS]
+    const int32_t* list;   // [ORDER_BUCKETS][N]
+};
+
 struct ContArgs {
     const DevSpec* spec;
     const void* rules;        // R[(NT+1) * width], row k = date k
@@ -60,6 +68,7 @@ struct ContArgs {
                               // below *n_ids (chunk as its block gives); 0: one job
     uint32_t pad_;
     IzFuse fz;                // fused search step (on = 0 otherwise)
+    JobOrder ord;             // start order of the jobs (ids null)
 };
 
 // Dimension buckets: every d <= 32 has its own instantiation (bucket_exact);

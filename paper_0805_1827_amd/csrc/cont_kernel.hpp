@@ -377,7 +377,18 @@ __device__ __forceinline__ void cont_slots(const ContArgs& a, uint32_t slot, con
 {
     if constexpr (!STRIDE) {
         if (a.n_ids && slot >= (uint32_t)*a.n_ids) return;
-        const uint32_t j = a.ids ? (uint32_t)a.ids[slot] : slot;
+        uint32_t j = a.ids ? (uint32_t)a.ids[slot] : slot;
+        if (a.ord.cnt) {   // the slot-th point of the bucket lists (uniform loads)
+            uint32_t rem = slot;
+            int b = 0;
+            for (; b < ORDER_BUCKETS - 1; ++b) {
+                const uint32_t c = (uint32_t)a.ord.cnt[b];
+                if (rem < c) break;
+                rem -= c;
+            }
+            j = (uint32_t)a.ord.list[(size_t)b * (size_t)a.N + rem];
+            if (j >= (uint32_t)a.N) return;   // not reached: the lists hold the N points
+        }
         cont_job<D, EXACT, R, ACC, IZK>(a, j, chunk, lds, red);
     } else {
         const uint32_t lim = (uint32_t)*a.n_ids;

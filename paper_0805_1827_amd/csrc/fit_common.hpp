@@ -230,8 +230,9 @@ __device__ inline bool spd_solve(int p, double* A, double lam, double* b, double
     return block_spd_solve(p, A, lam, b, x, flag);
 }
 
-// Payoff of point j from its log-prices (FP64, runtime d).
-__device__ inline double point_payoff(const SpecT<double>& S, const double* __restrict__ x, int64_t N, int64_t j)
+// Intrinsic value of point j from its log-prices, before its positive part
+// is taken (FP64, runtime d): negative out of the money.
+__device__ inline double point_intrinsic(const SpecT<double>& S, const double* __restrict__ x, int64_t N, int64_t j)
 {
     const int d = S.d;
     double v;
@@ -252,6 +253,13 @@ __device__ inline double point_payoff(const SpecT<double>& S, const double* __re
         for (int i = 0; i < d; ++i) sm += exp(log(x[i * N + j]));
         v = S.K - sm * S.inv_d;
     }
+    return v;
+}
+
+// Payoff of point j (FP64, runtime d).
+__device__ inline double point_payoff(const SpecT<double>& S, const double* __restrict__ x, int64_t N, int64_t j)
+{
+    const double v = point_intrinsic(S, x, N, j);
     return v > 0.0 ? v : 0.0;
 }
 

@@ -130,9 +130,17 @@ hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int6
                            hipStream_t st, const RefineSel* sel = nullptr);
 hipError_t launch_bridge_end(const DevSpec* s, int d, int64_t N, uint32_t seed, double* B,
                              hipStream_t st);
-// zero_count (or null) is cleared by the launch.
+// zero_count (or null) is cleared by the launch.  ord_cnt (or null, with
+// x): the launch appends every point to the bucket list of its intrinsic
+// value (ord_cnt[ORDER_BUCKETS] counts, zero beforehand; ord_list
+// [ORDER_BUCKETS][N]) and clears ord_clear[ORDER_BUCKETS], the other date
+// parity's counts.
 hipError_t launch_bridge_back(const DevSpec* s, int d, int m, int64_t N, uint32_t seed, double* B,
-                              double* x, int bridge, hipStream_t st, int32_t* zero_count = nullptr);
+                              double* x, int bridge, hipStream_t st, int32_t* zero_count = nullptr,
+                              int32_t* ord_cnt = nullptr, int32_t* ord_list = nullptr, int32_t* ord_clear = nullptr);
+// Largest N whose date launches are given a job order (bucket lists of
+// ORDER_BUCKETS N entries).
+constexpr int64_t ORDER_MAX_N = 65536;
 hipError_t launch_korobov(int64_t J, int q, unsigned long long* best, hipStream_t st);
 // I&Z regions region0 .. region0 + nreg - 1 side by side: J points each,
 // region region0 + r in columns r J .. r J + J - 1 of rows of nreg J entries.

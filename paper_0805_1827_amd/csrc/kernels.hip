@@ -287,6 +287,42 @@ hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int6
 }
 
 // ---------------------------------------------------------------------------
+// Start order of a date's continuation jobs.  The inner paths of a point far
+// out of the money mostly run to maturity and those of a point deep in the
+// money stop at once, so a launch that starts its jobs by increasing
+// intrinsic value of the point runs the long jobs first and ends on short
+// ones (in point order the last jobs to start left much of the device idle
+// for their whole length).  Only the schedule depends on the order: every
+// job writes its own partial sums.  The bridge step that draws the date's
+// points appends each one to one of ORDER_BUCKETS lists by a squashed
+// intrinsic value; the continuation launch walks the lists in bucket order.
+
+// Intrinsic value of point j in single precision (an ordering key only).
+__device__ __forceinline__ float order_key(const SpecT<double>& S, const double* __restrict__ x, int64_t N, int64_t j)
+{
+    const int d = S.d;
+    const int pay = S.payoff;
+    const float K = (float)S.K;
+    float acc = pay == PUT_GEO || pay == PUT_BASKET ? 0.f : logf((float)x[j]);
+    for (int i = (pay == PUT_GEO || pay == PUT_BASKET) ? 0 : 1; i < d; ++i) {
+        const float v = (float)x[i * N + j];
+        if (pay == CALL_MAX) acc = fmaxf(acc, logf(v));
+        else if (pay == CALL_MIN) acc = fminf(acc, logf(v));
+        else if (pay == PUT_GEO) acc += logf(v);
+        else acc += v;
+    }
+    if (pay == PUT_GEO) return K - expf(acc * (float)S.inv_d);
+    if (pay == PUT_BASKET) return K - acc * (float)S.inv_d;
+    return expf(acc) - K;
+}
+
+__device__ __forceinline__ int order_bucket_of(float k, float K)
+{
+    const float t = (float)ORDER_BUCKETS * (0.5f + 0.5f * tanhf(4.f * k / K));   // NaN -> bucket 0
+    return t > 0.f ? (t < (float)(ORDER_BUCKETS - 1) ? (int)t : ORDER_BUCKETS - 1) : 0;
+}
+
+// ---------------------------------------------------------------------------
 // CMC training points: Brownian components drawn at T and bridged backward.
 
 __device__ __forceinline__ void outer_block(uint32_t seed, uint32_t k1, uint32_t b, uint32_t j,
@@ -346,11 +382,33 @@ __global__ void k_bridge_end(const DevSpec* __restrict__ s, int64_t N, uint32_t 
 }
 
 __global__ void k_bridge_back(const DevSpec* __restrict__ s, int m, int64_t N, uint32_t seed,
-                              double* B, double* x, int bridge, int32_t* zero_count)
+                              double* B, double* x, int bridge, int32_t* zero_count, int32_t* ord_cnt,
+                              int32_t* ord_list, int32_t* ord_clear)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (zero_count && j == 0) *zero_count = 0;
-    if (j < N) bridge_back_point(s, m, N, seed, B, x, bridge, j);
+    if (ord_clear && j < ORDER_BUCKETS) ord_clear[j] = 0;
+    if (!ord_cnt) {
+        if (j < N) bridge_back_point(s, m, N, seed, B, x, bridge, j);
+        return;
+    }
+    // bucket appends: ranks inside the block, then one range per bucket
+    __shared__ int lcnt[ORDER_BUCKETS], lbase[ORDER_BUCKETS];
+    if (threadIdx.x < ORDER_BUCKETS) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    int b = -1, r = 0;
+    if (j < N) {
+        bridge_back_point(s, m, N, seed, B, x, bridge, j);
+        b = order_bucket_of(order_key(s->f64, x, N, j), (float)s->f64.K);
+        r = atomicAdd(&lcnt[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < ORDER_BUCKETS) {
+        const int c = lcnt[threadIdx.x];
+        lbase[threadIdx.x] = c ? atomicAdd(&ord_cnt[threadIdx.x], c) : 0;
+    }
+    __syncthreads();
+    if (b >= 0) ord_list[(size_t)b * (size_t)N + (size_t)(lbase[b] + r)] = (int32_t)j;
 }
 
 // Bridge steps of many options in one launch (256 points per block).
@@ -375,11 +433,13 @@ hipError_t launch_bridge_end(const DevSpec* s, int d, int64_t N, uint32_t seed, 
 }
 
 hipError_t launch_bridge_back(const DevSpec* s, int d, int m, int64_t N, uint32_t seed, double* B,
-                              double* x, int bridge, hipStream_t st, int32_t* zero_count)
+                              double* x, int bridge, hipStream_t st, int32_t* zero_count, int32_t* ord_cnt,
+                              int32_t* ord_list, int32_t* ord_clear)
 {
     (void)d;
+    if (ord_cnt && (!x || !ord_list || N > ORDER_MAX_N)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bridge_back, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, s, m, N,
-                       seed, B, x, bridge, zero_count);
+                       seed, B, x, bridge, zero_count, ord_cnt, ord_list, ord_clear);
     return hipGetLastError();
 }
 

@@ -124,16 +124,34 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
             }
             sel = RefineSel{(const DevSpec*)ds, x, (int32_t*)((char*)ctx->rf.ptr + 256), (int32_t*)ctx->rf.ptr};
         }
+        // each date's jobs start in order of increasing intrinsic value: the
+        // bridge step of date m fills count set m % 2 and the lists, and
+        // clears the other set for the next date
+        int32_t *ord_cnt = nullptr, *ord_list = nullptr;
+        if (N <= ORDER_MAX_N) {
+            if ((e = ctx->order.ensure(256 + sizeof(int32_t) * ORDER_BUCKETS * (size_t)N)) ||
+                (e = hipMemsetAsync(ctx->order.ptr, 0, 256, ctx->stream))) {
+                release();
+                return fail(BMC_ENOMEM, "device buffers: %s", hipGetErrorString(e));
+            }
+            ord_cnt = (int32_t*)ctx->order.ptr;
+            ord_list = (int32_t*)((char*)ctx->order.ptr + 256);
+        }
         if ((e = launch_bridge_end((const DevSpec*)ds, d, N, seed, B, ctx->stream))) st = hip_fail(e, "bridge");
         for (int m = NT - 1; m >= 1 && !st; --m) {
-            if ((e = launch_bridge_back((const DevSpec*)ds, d, m, N, seed, B, x, 1, ctx->stream, sel.n_ids))) {
+            int32_t* cnt_m = ord_cnt ? ord_cnt + ORDER_BUCKETS * (m & 1) : nullptr;
+            int32_t* cnt_clear = ord_cnt ? ord_cnt + ORDER_BUCKETS * ((m & 1) ^ 1) : nullptr;
+            if ((e = launch_bridge_back((const DevSpec*)ds, d, m, N, seed, B, x, 1, ctx->stream, sel.n_ids, cnt_m,
+                                        ord_list, cnt_clear))) {
                 st = hip_fail(e, "bridge");
                 break;
             }
             timer.mark(PH_CALC);
+            const JobOrder ord{cnt_m, ord_list};
             st = run_cont(ctx, ds, d, NT, method, rules->width, rules->w64, rules->w32, prec, m, x, N, nullptr,
                           nullptr, n, seed, key_hi(BMC_STREAM_INNER, m), cont, nullptr, nullptr, nullptr,
-                          steps_total, tune, 0, 0, nullptr, nullptr, nullptr, refine ? &sel : nullptr);
+                          steps_total, tune, 0, 0, nullptr, nullptr, nullptr, refine ? &sel : nullptr,
+                          cnt_m ? &ord : nullptr);
             if (!st && refine) {
                 timer.mark(PH_REFINE);
                 st = refine_labels(ctx, ds, d, NT, rules, m, x, N, n, seed, cont, sel.ids, sel.n_ids);

@@ -47,6 +47,7 @@ struct bmc_ctx {
     void* host_io_dev = nullptr;              // its device address (kernels write progress polls there)
     bmc::DBuf spec, spec2, pack_dev, part, B, x, x2, cont, se, steps, fit, iz, counters, korobov;
     bmc::DBuf rf;   // FP32 label refinement: [count (256 B)][ids N]
+    bmc::DBuf order;   // job order of the pricer's date launches: [count (256 B)][ids N]
     bmc::DBuf gbar;   // the one-launch fit's grid-barrier words (zeroed once; host_io + 136: its error flag)
     // batched pricing: device specs, per-option arena, task tables; pinned staging
     bmc::DBuf bspec, barena, btab;
@@ -106,7 +107,7 @@ bmc_status run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int m
                     uint32_t k1, double* cont, double* se, int64_t* steps, double* sums,
                     unsigned long long* steps_total, const Tuning* tune, uint32_t slot = 0,
                     uint32_t region_pts = 0, uint32_t* nchunk_out = nullptr, double* part = nullptr,
-                    const IzFuse* fz = nullptr, const RefineSel* sel = nullptr);
+                    const IzFuse* fz = nullptr, const RefineSel* sel = nullptr, const JobOrder* ord = nullptr);
 // region: the I&Z region whose boundary row block is fitted (0 for CMC), from
 // N points in rows of ld entries (0: N).
 bmc_status fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rules* rules, int date,

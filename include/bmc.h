@@ -44,7 +44,8 @@ typedef enum {
     BMC_EDEVICE = -4,       /* HIP runtime error */
     BMC_EUNSUPPORTED = -5,  /* combination not supported */
     BMC_ENOCONV = -6,       /* reserved (I&Z drops and counts non-converged points) */
-    BMC_EBUSY = -7          /* request not finished yet */
+    BMC_EBUSY = -7,         /* request not finished yet */
+    BMC_ECANCELED = -8      /* request cancelled (bmc_server_cancel) */
 } bmc_status;
 
 /* Payoffs (Section 2.1-2.2, Section 3.2): arithmetic-basket put
@@ -215,6 +216,7 @@ typedef struct {
     int64_t rounds, inner_path_steps, final_path_steps;
     int64_t queued, inflight, hbm_in_use, hbm_peak;
     double busy_seconds;    /* wall time of the server's rounds */
+    int64_t canceled;       /* requests ended by bmc_server_cancel */
 } bmc_server_stats;
 bmc_status bmc_server_create(bmc_ctx *ctx, const bmc_server_opts *opts, bmc_server **out);
 void bmc_server_destroy(bmc_server *server);
@@ -226,6 +228,16 @@ bmc_status bmc_server_submit(bmc_server *server, const bmc_spec *spec, const bmc
 bmc_status bmc_server_poll(bmc_server *server, uint64_t ticket, bmc_result *out);
 /* As poll, blocking up to timeout_s seconds (< 0: no limit). */
 bmc_status bmc_server_wait(bmc_server *server, uint64_t ticket, double timeout_s, bmc_result *out);
+/* Cancels a request, which then ends with BMC_ECANCELED (poll and wait
+ * return it and release the ticket).  A queued request leaves the queue at
+ * once.  A request on the device is flagged in pinned host memory: the
+ * continuation jobs of its pricing read the flag when they start and return
+ * at once, so the launch in flight skips the request's remaining work, and
+ * at the end of the round the server frees its device memory and slot and
+ * caches none of its rules.  The other requests' results are unchanged.
+ * BMC_EINVAL for an unknown ticket or a request that has already finished
+ * (its result stays available). */
+bmc_status bmc_server_cancel(bmc_server *server, uint64_t ticket);
 bmc_status bmc_server_stats_get(bmc_server *server, bmc_server_stats *out);
 
 /* Exercise-rule table of one spec and method: one row of width w per date

@@ -15,7 +15,7 @@ import numpy as np
 
 LIB_PATH = Path(__file__).resolve().parent / "libbmc.so"
 
-OK, EINVAL, ENOTSPD, ENOMEM, EDEVICE, EUNSUPPORTED, ENOCONV, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOTSPD, ENOMEM, EDEVICE, EUNSUPPORTED, ENOCONV, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PUT_BASKET, CALL_MAX, PUT_GEO, CALL_MIN = 0, 1, 2, 3
 SEARCH_PLAIN, SEARCH_SECANT = 0, 1
 CMC, IZ, CMC_ADA = 0, 1, 2
@@ -30,7 +30,8 @@ SYMBOLS = [
     "bmc_rules_export", "bmc_rules_import", "bmc_sample_points", "bmc_estimate_continuation",
     "bmc_fit_rule", "bmc_iz_search", "bmc_final_price", "bmc_philox", "bmc_normals", "bmc_price_batch",
     "bmc_tuning_set", "bmc_tuning_get", "bmc_server_create", "bmc_server_destroy", "bmc_server_submit",
-    "bmc_server_poll", "bmc_server_wait", "bmc_server_stats_get", "bmc_ctx_set_graphs", "bmc_ctx_graph_stats",
+    "bmc_server_poll", "bmc_server_wait", "bmc_server_cancel", "bmc_server_stats_get", "bmc_ctx_set_graphs",
+    "bmc_ctx_graph_stats",
     "bmc_autotune", "bmc_iz_regions", "bmc_estimate_continuation_noalloc",
 ]
 
@@ -74,7 +75,7 @@ class bmc_server_stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("submitted", "rejected", "completed", "failed", "cache_hits",
                                           "cache_misses", "cached_rules", "rounds", "inner_path_steps",
                                           "final_path_steps", "queued", "inflight", "hbm_in_use",
-                                          "hbm_peak")] + [("busy_seconds", C.c_double)]
+                                          "hbm_peak")] + [("busy_seconds", C.c_double), ("canceled", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -112,6 +113,7 @@ def load():
     L.bmc_server_destroy.restype = None
     L.bmc_server_submit.argtypes = [vp, sp, C.POINTER(bmc_opts), C.POINTER(C.c_uint64)]
     L.bmc_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(bmc_result)]
+    L.bmc_server_cancel.argtypes = [vp, C.c_uint64]
     L.bmc_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(bmc_result)]
     L.bmc_server_stats_get.argtypes = [vp, C.POINTER(bmc_server_stats)]
     L.bmc_rules_create.argtypes = [vp, sp, C.c_int32, C.POINTER(vp)]
@@ -342,6 +344,11 @@ class Server:
             return None
         _check(st)
         return res.as_dict()
+
+    def cancel(self, ticket: int) -> None:
+        """Cancels a queued or running request (BmcError EINVAL if it has
+        already finished); its poll and wait then raise ECANCELED."""
+        _check(load().bmc_server_cancel(self.h, ticket))
 
     def stats(self) -> dict:
         s = bmc_server_stats()

@@ -370,11 +370,14 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 // FP64 label-refinement kernels) every slot s = slot, slot + slot_stride, ...
 // below the active count.  A slot at or past the active count is a retired
 // job (the whole block returns).  The loop lives in kernels of its own: in
-// the one-job kernels it would cost registers (and occupancy).
+// the one-job kernels it would cost registers (and occupancy).  A job of a
+// cancelled served request (its host-mapped cancel word set) returns before
+// any work.
 template <int D, bool EXACT, class R, class ACC, bool IZK, bool STRIDE>
 __device__ __forceinline__ void cont_slots(const ContArgs& a, uint32_t slot, const uint32_t chunk, double* lds,
                                            double (*red)[16])
 {
+    if (a.cancel && __hip_atomic_load(a.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0) return;
     if constexpr (!STRIDE) {
         if (a.n_ids && slot >= (uint32_t)*a.n_ids) return;
         uint32_t j = a.ids ? (uint32_t)a.ids[slot] : slot;

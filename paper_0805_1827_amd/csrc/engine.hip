@@ -86,6 +86,7 @@ OptDev carve_option(const OptPlan& q, const DevSpec* spec, char* base)
     v.fit = (double*)(base + q.ofit);
     v.n_ids = q.refine ? (int32_t*)(base + q.oids) : nullptr;
     v.ids = q.refine ? (int32_t*)(base + q.oids + 256) : nullptr;
+    v.cancel = nullptr;
     return v;
 }
 
@@ -152,6 +153,7 @@ bmc_status plan_round(const std::vector<RoundItem>& items, Table& tab, std::vect
             a.width = q.p;
             a.k0 = q.seed;
             a.part = v.part;
+            a.cancel = v.cancel;
             FinTask f;
             std::memset(&f, 0, sizeof(f));
             f.part = a.part;
@@ -243,6 +245,7 @@ bmc_status plan_round(const std::vector<RoundItem>& items, Table& tab, std::vect
                 a.paths_per_wg = q.rper_wg;
                 a.nchunk = q.rnchunk;
                 a.slot_stride = (uint32_t)std::min<int64_t>(q.N, REFINE_SLOTS);
+                a.cancel = v.cancel;
                 pre.push_back(pre.back() + a.slot_stride * a.nchunk);
                 ca.push_back(a);
                 lds = std::max(lds, q.lds64);

@@ -102,6 +102,7 @@ struct Request {
     OptDev dev;
     int stage = 0;          // next stage (see RoundItem); -1 when finished
     bool hit = false, fresh = false;
+    bool cancel = false;    // cancelled while on the device: dropped at the end of the round
     bmc_status status = BMC_OK;
     bmc_result result;
 };
@@ -130,6 +131,8 @@ struct bmc_server {
     bmc_server_stats st{};
     void* host = nullptr;     // pinned staging
     size_t host_bytes = 0;
+    int32_t* cancel_host = nullptr;       // pinned cancel word per slot, read by the request's jobs
+    const int32_t* cancel_dev = nullptr;  // its device address
     bmc::DBuf dtab;
     bmc::DBuf dpack;
     double busy = 0.0;
@@ -198,6 +201,7 @@ void bmc_server::finish(Request* r, bmc_status s)
     r->result.seconds = std::chrono::duration<double>(r->done - r->submitted).count();
     r->result.calc_seconds = std::chrono::duration<double>(r->admitted - r->submitted).count();
     if (s == BMC_OK) ++st.completed;
+    else if (s == BMC_ECANCELED) ++st.canceled;
     else ++st.failed;
 }
 
@@ -281,7 +285,7 @@ bmc_status bmc_server::round(std::vector<Request*>& fresh)
     {
         std::lock_guard<std::mutex> g(mu);
         for (Request* r : learned) {
-            if (cache.count(r->key)) continue;
+            if (r->cancel || cache.count(r->key)) continue;   // a cancelled request's jobs may have been skipped
             while ((int)cache.size() >= cache_cap && evict_one()) {
             }
             if ((int)cache.size() >= cache_cap) continue;
@@ -312,6 +316,7 @@ bmc_status bmc_server::round(std::vector<Request*>& fresh)
     ++st.rounds;
     for (size_t i = 0; i < ending.size(); ++i) {
         Request* r = ending[i];
+        if (r->cancel) continue;
         const uint64_t* rb = (const uint64_t*)(hb + rb_off + 32 * i);
         double sums[3];
         std::memcpy(&sums[0], &rb[1], sizeof(double));
@@ -328,6 +333,12 @@ bmc_status bmc_server::round(std::vector<Request*>& fresh)
         free_slots.push_back(r->slot);
         finish(r, BMC_OK);
     }
+    for (Request* r : active)
+        if (r->cancel && r->stage >= 0) {
+            arena.release(r->off, r->q.bytes);
+            free_slots.push_back(r->slot);
+            finish(r, BMC_ECANCELED);
+        }
     for (Request* r : active)
         if (r->stage >= 1) --r->stage;
     active.erase(std::remove_if(active.begin(), active.end(), [](Request* r) { return r->stage < 0; }),
@@ -375,6 +386,8 @@ void bmc_server::loop()
                 r->slot = free_slots.back();
                 free_slots.pop_back();
                 r->dev = carve_option(r->q, specs + r->slot, dev_arena + off);
+                __atomic_store_n(&cancel_host[r->slot], 0, __ATOMIC_RELAXED);
+                r->dev.cancel = cancel_dev + r->slot;
                 r->stage = r->hit ? 0 : r->q.NT - 1;
                 r->admitted = clk::now();
                 if (r->hit) {
@@ -419,14 +432,21 @@ extern "C" bmc_status bmc_server_create(bmc_ctx* ctx, const bmc_server_opts* opt
     s->max_inflight = inflight;
     s->cache_cap = cache_cap;
     hipError_t e;
+    void* cdev = nullptr;
     if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) ||
         (e = hipMalloc((void**)&s->dev_arena, (size_t)budget)) ||
-        (e = hipMalloc((void**)&s->specs, sizeof(DevSpec) * (size_t)inflight))) {
+        (e = hipMalloc((void**)&s->specs, sizeof(DevSpec) * (size_t)inflight)) ||
+        (e = hipHostMalloc((void**)&s->cancel_host, sizeof(int32_t) * (size_t)inflight, 0)) ||
+        (e = hipHostGetDevicePointer(&cdev, s->cancel_host, 0))) {
+        if (s->cancel_host) (void)hipHostFree(s->cancel_host);
+        if (s->specs) (void)hipFree(s->specs);
         if (s->dev_arena) (void)hipFree(s->dev_arena);
         if (s->stream) (void)hipStreamDestroy(s->stream);
         delete s;
         return fail(BMC_ENOMEM, "server device memory (%lld bytes): %s", (long long)budget, hipGetErrorString(e));
     }
+    s->cancel_dev = (const int32_t*)cdev;
+    std::memset(s->cancel_host, 0, sizeof(int32_t) * (size_t)inflight);
     s->arena.init((size_t)budget);
     for (int i = inflight - 1; i >= 0; --i) s->free_slots.push_back((uint32_t)i);
     s->worker = std::thread([s] { s->loop(); });
@@ -451,6 +471,7 @@ extern "C" void bmc_server_destroy(bmc_server* s)
     s->dtab.release();
     s->dpack.release();
     if (s->host) (void)hipHostFree(s->host);
+    if (s->cancel_host) (void)hipHostFree(s->cancel_host);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -495,6 +516,7 @@ static bmc_status take_result(bmc_server* s, std::unordered_map<uint64_t, Reques
     s->all.erase(it);
     delete r;
     if (st == BMC_ENOTSPD) return fail(st, "correlation matrix is not positive definite");
+    if (st == BMC_ECANCELED) return fail(st, "request cancelled");
     if (st) return fail(st, "request failed on the device");
     return BMC_OK;
 }
@@ -520,6 +542,30 @@ extern "C" bmc_status bmc_server_wait(bmc_server* s, uint64_t ticket, double tim
     if (timeout_s < 0) s->cv_done.wait(g, ready);
     else if (!s->cv_done.wait_for(g, std::chrono::duration<double>(timeout_s), ready)) return BMC_EBUSY;
     return take_result(s, s->all.find(ticket), out);
+}
+
+extern "C" bmc_status bmc_server_cancel(bmc_server* s, uint64_t ticket)
+{
+    if (!s) return fail(BMC_EINVAL, "NULL argument");
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        auto it = s->all.find(ticket);
+        if (it == s->all.end()) return fail(BMC_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        Request* r = it->second;
+        if (r->stage < 0 && r->done.time_since_epoch().count() != 0)
+            return fail(BMC_EINVAL, "request %llu has already finished", (unsigned long long)ticket);
+        auto q = std::find(s->queue.begin(), s->queue.end(), r);
+        if (q != s->queue.end()) {   // not admitted yet
+            s->queue.erase(q);
+            s->finish(r, BMC_ECANCELED);
+        } else {                     // on the device: its jobs see the flag, the round end drops it
+            r->cancel = true;
+            __atomic_store_n(&s->cancel_host[r->slot], 1, __ATOMIC_RELAXED);
+        }
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_one();
+    return BMC_OK;
 }
 
 extern "C" bmc_status bmc_server_stats_get(bmc_server* s, bmc_server_stats* out)

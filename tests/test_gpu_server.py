@@ -134,3 +134,55 @@ def test_request_errors(bmc, ctx, inputs):
         srv.close()
     assert same(good, bmc.bmc_price(ctx, s, **o))
     assert st["failed"] == 1 and st["rejected"] == 1
+
+
+def test_cancel_queued_and_running(bmc, ctx, inputs):
+    """A cancelled queued request leaves without running; a cancelled request
+    on the device has its jobs skipped through the host-mapped flag and is
+    dropped at the end of the round; the request that shared its launches
+    keeps the result of bmc_price."""
+    big, = requests(bmc, inputs, [(5, 24, 8192, 8192, "FP64")], first_seed=900)
+    small, queued = requests(bmc, inputs, [(3, 6, 1024, 96, "FP32"), (2, 5, 512, 64, "FP64")], first_seed=910)
+    srv = bmc.Server(ctx, hbm_budget=1 << 30, max_inflight=2, rule_cache=-1)
+    try:
+        ta = srv.submit(big[0], **big[1])
+        ts = srv.submit(small[0], **small[1])
+        tq = srv.submit(queued[0], **queued[1])   # both slots taken: waits in the queue
+        srv.cancel(tq)
+        with pytest.raises(bmc.BmcError) as ei:
+            srv.wait(tq, 60.0)
+        assert ei.value.status == bmc.ECANCELED
+        deadline = time.time() + 60.0
+        while srv.stats()["inflight"] == 0 and time.time() < deadline:
+            time.sleep(0.001)
+        srv.cancel(ta)   # 24 FP64 dates at N = n = 8192: still on the device
+        with pytest.raises(bmc.BmcError) as ei:
+            srv.wait(ta, 120.0)
+        assert ei.value.status == bmc.ECANCELED
+        got = srv.wait(ts, 120.0)
+        with pytest.raises(bmc.BmcError) as ei:
+            srv.cancel(ta)   # released by its wait
+        assert ei.value.status == bmc.EINVAL
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert got is not None and same(got, bmc.bmc_price(ctx, small[0], **small[1]))
+    assert st["canceled"] == 2 and st["completed"] == 1 and st["failed"] == 0
+    assert st["inflight"] == 0 and st["queued"] == 0 and st["hbm_in_use"] == 0
+
+
+def test_cancel_after_finish_keeps_result(bmc, ctx, inputs):
+    (s, o), = requests(bmc, inputs, [(2, 4, 512, 32, "FP64")], first_seed=920)
+    srv = bmc.Server(ctx, hbm_budget=1 << 26)
+    try:
+        t = srv.submit(s, **o)
+        deadline = time.time() + 60.0
+        while srv.stats()["completed"] == 0 and time.time() < deadline:
+            time.sleep(0.001)
+        with pytest.raises(bmc.BmcError) as ei:
+            srv.cancel(t)
+        assert ei.value.status == bmc.EINVAL
+        got = srv.wait(t, 60.0)
+    finally:
+        srv.close()
+    assert same(got, bmc.bmc_price(ctx, s, **o))

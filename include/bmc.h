@@ -230,10 +230,11 @@ bmc_status bmc_server_poll(bmc_server *server, uint64_t ticket, bmc_result *out)
 bmc_status bmc_server_wait(bmc_server *server, uint64_t ticket, double timeout_s, bmc_result *out);
 /* Cancels a request, which then ends with BMC_ECANCELED (poll and wait
  * return it and release the ticket).  A queued request leaves the queue at
- * once.  A request on the device is flagged in pinned host memory: the
- * continuation jobs of its pricing read the flag when they start and return
- * at once, so the launch in flight skips the request's remaining work, and
- * at the end of the round the server frees its device memory and slot and
+ * once.  For a request on the device a one-thread kernel on a control stream
+ * sets a cancel word in its device memory: the continuation jobs of its
+ * pricing read the word while they load their tables and stop before their
+ * paths, so the launch in flight skips the request's remaining work, and at
+ * the end of the round the server frees its device memory and slot and
  * caches none of its rules.  The other requests' results are unchanged.
  * BMC_EINVAL for an unknown ticket or a request that has already finished
  * (its result stays available). */

@@ -69,7 +69,7 @@ struct ContArgs {
     uint32_t pad_;
     IzFuse fz;                // fused search step (on = 0 otherwise)
     JobOrder ord;             // start order of the jobs (ids null)
-    const int32_t* cancel;    // (or null) host-mapped word: nonzero = jobs return at once
+    const int32_t* cancel;    // (or null) device word: nonzero = the jobs stop after their setup
 };
 
 // Dimension buckets: every d <= 32 has its own instantiation (bucket_exact);

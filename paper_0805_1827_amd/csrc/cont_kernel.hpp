@@ -124,6 +124,11 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
     constexpr bool UST = sizeof(R) == 4;
     const double lnshift = UST ? (double)as_const(a.spec)->f64.lnK : 0.0;
     const double tm = t64[m];
+    // cancel word of a served request: read by one thread while the tables
+    // load, shared through LDS by the barrier below
+    __shared__ int32_t job_cancel;
+    if (threadIdx.x == 0)
+        job_cancel = a.cancel ? __hip_atomic_load(a.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     for (int k = threadIdx.x; k <= NT; k += blockDim.x) {
         disc[k] = exp(-r64 * (t64[k] - tm));
         dtv[k] = S.dt[k];
@@ -183,6 +188,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
     if constexpr (IZK) {
         if (a.fz.on && !fz_go) return;
     }
+    if (job_cancel) return;   // uniform: one LDS word after the barrier
 
     const uint32_t lo = chunk * a.paths_per_wg;
     const uint32_t hi = min(a.n, lo + a.paths_per_wg);
@@ -371,13 +377,11 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 // below the active count.  A slot at or past the active count is a retired
 // job (the whole block returns).  The loop lives in kernels of its own: in
 // the one-job kernels it would cost registers (and occupancy).  A job of a
-// cancelled served request (its host-mapped cancel word set) returns before
-// any work.
+// cancelled served request (its cancel word set) stops after its table setup.
 template <int D, bool EXACT, class R, class ACC, bool IZK, bool STRIDE>
 __device__ __forceinline__ void cont_slots(const ContArgs& a, uint32_t slot, const uint32_t chunk, double* lds,
                                            double (*red)[16])
 {
-    if (a.cancel && __hip_atomic_load(a.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0) return;
     if constexpr (!STRIDE) {
         if (a.n_ids && slot >= (uint32_t)*a.n_ids) return;
         uint32_t j = a.ids ? (uint32_t)a.ids[slot] : slot;

@@ -58,7 +58,8 @@ bmc_status plan_option(const bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts*
     const size_t rows = (size_t)(q->NT + 1) * q->p;
     q->ow64 = take(sizeof(double) * rows);
     q->ow32 = take(sizeof(float) * rows);
-    q->ocnt = take(sizeof(uint64_t) * 4);
+    q->ocnt = take(sizeof(uint64_t) * 4);   // a 256-byte block: results in the first 32 bytes, a served
+                                            // request's cancel word at byte 64
     q->zero_bytes = off;
     q->oB = take(sizeof(double) * q->d * q->N);
     q->ox = take(sizeof(double) * q->d * q->N);

@@ -29,6 +29,14 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
+// Byte offset of a request's cancel word in its counters block (the block's
+// first 32 bytes hold the pricing's results).
+constexpr size_t CANCEL_WORD_OFFSET = 64;
+
+// Sets a cancel word with an agent-scope store (read by the jobs of launches
+// already running on the server's other stream).
+__global__ void k_cancel_set(int32_t* w) { __hip_atomic_store(w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
 // First-fit allocator over one device allocation (offsets, 256-byte units).
 class Arena {
 public:
@@ -103,6 +111,7 @@ struct Request {
     int stage = 0;          // next stage (see RoundItem); -1 when finished
     bool hit = false, fresh = false;
     bool cancel = false;    // cancelled while on the device: dropped at the end of the round
+    int32_t* cancel_word = nullptr;   // device word read by its continuation jobs (zeroed with its counters)
     bmc_status status = BMC_OK;
     bmc_result result;
 };
@@ -131,8 +140,7 @@ struct bmc_server {
     bmc_server_stats st{};
     void* host = nullptr;     // pinned staging
     size_t host_bytes = 0;
-    int32_t* cancel_host = nullptr;       // pinned cancel word per slot, read by the request's jobs
-    const int32_t* cancel_dev = nullptr;  // its device address
+    hipStream_t ctrl = nullptr;   // cancel-word stores, beside the rounds on `stream`
     bmc::DBuf dtab;
     bmc::DBuf dpack;
     double busy = 0.0;
@@ -333,6 +341,10 @@ bmc_status bmc_server::round(std::vector<Request*>& fresh)
         free_slots.push_back(r->slot);
         finish(r, BMC_OK);
     }
+    bool any_cancel = false;
+    for (Request* r : active) any_cancel |= r->cancel && r->stage >= 0;
+    // a cancel-word store still queued must land before the memory is reused
+    if (any_cancel && (e = hipStreamSynchronize(ctrl))) return hip_fail(e, "cancel");
     for (Request* r : active)
         if (r->cancel && r->stage >= 0) {
             arena.release(r->off, r->q.bytes);
@@ -386,8 +398,10 @@ void bmc_server::loop()
                 r->slot = free_slots.back();
                 free_slots.pop_back();
                 r->dev = carve_option(r->q, specs + r->slot, dev_arena + off);
-                __atomic_store_n(&cancel_host[r->slot], 0, __ATOMIC_RELAXED);
-                r->dev.cancel = cancel_dev + r->slot;
+                // the cancel word sits in the counters block, which the
+                // request's setup zeroes before its first launch
+                r->cancel_word = (int32_t*)((char*)r->dev.cnt + CANCEL_WORD_OFFSET);
+                r->dev.cancel = r->cancel_word;
                 r->stage = r->hit ? 0 : r->q.NT - 1;
                 r->admitted = clk::now();
                 if (r->hit) {
@@ -432,21 +446,17 @@ extern "C" bmc_status bmc_server_create(bmc_ctx* ctx, const bmc_server_opts* opt
     s->max_inflight = inflight;
     s->cache_cap = cache_cap;
     hipError_t e;
-    void* cdev = nullptr;
     if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) ||
+        (e = hipStreamCreateWithFlags(&s->ctrl, hipStreamNonBlocking)) ||
         (e = hipMalloc((void**)&s->dev_arena, (size_t)budget)) ||
-        (e = hipMalloc((void**)&s->specs, sizeof(DevSpec) * (size_t)inflight)) ||
-        (e = hipHostMalloc((void**)&s->cancel_host, sizeof(int32_t) * (size_t)inflight, 0)) ||
-        (e = hipHostGetDevicePointer(&cdev, s->cancel_host, 0))) {
-        if (s->cancel_host) (void)hipHostFree(s->cancel_host);
+        (e = hipMalloc((void**)&s->specs, sizeof(DevSpec) * (size_t)inflight))) {
         if (s->specs) (void)hipFree(s->specs);
         if (s->dev_arena) (void)hipFree(s->dev_arena);
+        if (s->ctrl) (void)hipStreamDestroy(s->ctrl);
         if (s->stream) (void)hipStreamDestroy(s->stream);
         delete s;
         return fail(BMC_ENOMEM, "server device memory (%lld bytes): %s", (long long)budget, hipGetErrorString(e));
     }
-    s->cancel_dev = (const int32_t*)cdev;
-    std::memset(s->cancel_host, 0, sizeof(int32_t) * (size_t)inflight);
     s->arena.init((size_t)budget);
     for (int i = inflight - 1; i >= 0; --i) s->free_slots.push_back((uint32_t)i);
     s->worker = std::thread([s] { s->loop(); });
@@ -471,7 +481,10 @@ extern "C" void bmc_server_destroy(bmc_server* s)
     s->dtab.release();
     s->dpack.release();
     if (s->host) (void)hipHostFree(s->host);
-    if (s->cancel_host) (void)hipHostFree(s->cancel_host);
+    if (s->ctrl) {
+        (void)hipStreamSynchronize(s->ctrl);
+        (void)hipStreamDestroy(s->ctrl);
+    }
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -558,9 +571,11 @@ extern "C" bmc_status bmc_server_cancel(bmc_server* s, uint64_t ticket)
         if (q != s->queue.end()) {   // not admitted yet
             s->queue.erase(q);
             s->finish(r, BMC_ECANCELED);
-        } else {                     // on the device: its jobs see the flag, the round end drops it
+        } else if (!r->cancel) {     // on the device: its jobs see the word, the round end drops it
             r->cancel = true;
-            __atomic_store_n(&s->cancel_host[r->slot], 1, __ATOMIC_RELAXED);
+            (void)hipSetDevice(s->ctx->device);
+            hipLaunchKernelGGL(k_cancel_set, dim3(1), dim3(1), 0, s->ctrl, r->cancel_word);
+            (void)hipGetLastError();   // a refused store only delays the cancel to the round end
         }
     }
     s->cv_done.notify_all();

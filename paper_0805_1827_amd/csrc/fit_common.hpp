@@ -324,6 +324,32 @@ __device__ inline void fit_tile_var_sums(const double* phi, const double* msk, i
     }
 }
 
+// One tile (count c, feature sum s, squared deviations q from its own mean)
+// added to the running count n, mean m and squared deviations M2.
+__device__ __forceinline__ void chan_merge(double c, double s, double q, double& n, double& m, double& M2)
+{
+    if (!(c > 0.0)) return;
+    const double mt = s / c, dm = mt - m, nn = n + c;
+    m += dm * (c / nn);
+    M2 += q + dm * dm * (n * c / nn);
+    n = nn;
+}
+
+// Standardisation of column f from the merged count, mean and squared
+// deviations; the constant column and a (numerically) constant feature keep
+// scale 1.
+__device__ __forceinline__ void fit_mu_sd_merged(int f, double cnt, double mean, double M2, double* mu, double* sd)
+{
+    double m = 0.0, s = 1.0;
+    if (f > 0 && cnt > 0.0) {
+        m = mean;
+        s = sqrt(M2 / cnt);
+        if (!(s > 1e-12 * (1.0 + fabs(m)))) s = 1.0;
+    }
+    *mu = m;
+    *sd = s;
+}
+
 // Standardisation of column f from the merged sums; the constant column and
 // a (numerically) constant feature keep scale 1.
 __device__ __forceinline__ void fit_mu_sd(int f, double cnt, double sf, double sv, double* mu, double* sd)

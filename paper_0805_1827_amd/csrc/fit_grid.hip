@@ -144,28 +144,18 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
     const FitScratch& fs = a.fs;
     const int64_t N = a.N;
 
-    // features, labels, in-the-money mask; tile sums of features and count
+    // features, labels, in-the-money mask; per tile the count, the feature
+    // sums and the squared deviations from the tile's own means
     for (int t = grp.rank(); t < a.ntiles; t += grp.size()) {
         const int64_t j0 = (int64_t)t * T;
         fit_prep_point(S, a.x, a.cont, N, j0 + tid, fs.phi, fs.lab, fs.msk);
         __syncthreads();
         stage_tile(fs.phi, fs.msk, N, p, j0, psi, wz);
         const int nt = (int)min((int64_t)T, N - j0);
-        tile_sum2(p + 1, nt, [&](int f, int q) { return f < p ? wz[q] * psi[f * T + q] : wz[q]; }, aux,
-                  fs.part1 + (size_t)t * (p + 1));
-    }
-    grp.sync();
-    // means (every block), tile sums of squared deviations
-    merge_tiles(fs.part1, a.ntiles, p + 1, A);
-    if (tid == 0) cnt_s = A[p];
-    __syncthreads();
-    const double cnt = cnt_s;
-    for (int f = tid; f < p; f += T) mu[f] = cnt > 0.0 ? A[f] / cnt : 0.0;
-    __syncthreads();
-    for (int t = grp.rank(); t < a.ntiles; t += grp.size()) {
-        const int64_t j0 = (int64_t)t * T;
-        stage_tile(fs.phi, fs.msk, N, p, j0, psi, wz);
-        const int nt = (int)min((int64_t)T, N - j0);
+        tile_sum2(p + 1, nt, [&](int f, int q) { return f < p ? wz[q] * psi[f * T + q] : wz[q]; }, aux, A);
+        for (int f = tid; f <= p; f += T) fs.part1[(size_t)t * (p + 1) + f] = A[f];
+        for (int f = tid; f < p; f += T) mu[f] = A[p] > 0.0 ? A[f] / A[p] : 0.0;   // the tile's means
+        __syncthreads();
         tile_sum2(p, nt,
                   [&](int f, int q) {
                       const double dv = psi[f * T + q] - mu[f];
@@ -174,17 +164,35 @@ __device__ void fit_cmc_body(const FitTask& a, G grp)
                   aux, fs.part2 + (size_t)t * p);
     }
     grp.sync();
-    merge_tiles(fs.part1, a.ntiles, p + 1, A);          // feature sums
-    merge_tiles(fs.part2, a.ntiles, p, A + (p + 1));    // squared deviations
+    // every block: the tiles combined in tile order by the pairwise update of
+    // count, mean and sum of squared deviations (Chan, Golub and LeVeque)
     for (int f = tid; f < p; f += T) {
-        fit_mu_sd(f, cnt, A[f], A[p + 1 + f], &mu[f], &sd[f]);
+        double n = 0.0, m = 0.0, M2 = 0.0;
+        int t = 0;
+        for (; t + 8 <= a.ntiles; t += 8) {
+            double c8[8], s8[8], q8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                c8[u] = fs.part1[(size_t)(t + u) * (p + 1) + p];
+                s8[u] = fs.part1[(size_t)(t + u) * (p + 1) + f];
+                q8[u] = fs.part2[(size_t)(t + u) * p + f];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) chan_merge(c8[u], s8[u], q8[u], n, m, M2);
+        }
+        for (; t < a.ntiles; ++t)
+            chan_merge(fs.part1[(size_t)t * (p + 1) + p], fs.part1[(size_t)t * (p + 1) + f],
+                       fs.part2[(size_t)t * p + f], n, m, M2);
+        if (f == 0) cnt_s = n;
+        fit_mu_sd_merged(f, n, m, M2, &mu[f], &sd[f]);
         if (grp.rank() == 0) {
             a.musd[f] = mu[f];
             a.musd[p + f] = sd[f];
         }
     }
-    if (grp.rank() == 0 && tid == 0) a.musd[2 * p] = cnt;
     __syncthreads();
+    const double cnt = cnt_s;
+    if (grp.rank() == 0 && tid == 0) a.musd[2 * p] = cnt;
     if (!(cnt > 0.0)) {   // no in-the-money point: never exercise (same in every block)
         if (grp.rank() == 0)
             for (int f = tid; f < p; f += T) { a.row64[f] = 0.0; a.row32[f] = 0.0f; }

@@ -552,6 +552,22 @@ def test_full_size_geometric_put_whole_price_fp64(bmc, ctx, orc, inputs):
     rules.close()
 
 
+@pytest.mark.parametrize("N", [65536, 70000])
+def test_whole_price_bucket_and_point_order(bmc, ctx, orc, inputs, N):
+    """The pricer's date launches start their jobs bucket by bucket (by the
+    points' intrinsic values) up to 65536 points and in point order above;
+    either way the FP64 price equals the oracle's with identical step counts.
+    N = 70000 also runs the one-launch fit with more tiles than blocks."""
+    spec = inputs.basket(2, 100.0, 100.0, 0.05, 0.0, 0.2, 0.3, 1.0, 4, inputs.PUT_BASKET)
+    print(f"two-asset basket put, N = {N}, n = 64: GPU", flush=True)
+    res = bmc.bmc_price(ctx, spec, bmc.CMC, bmc.FP64, N=N, n=64, n_final=20000, seed=5)
+    print(f"two-asset basket put, N = {N}, n = 64: oracle", flush=True)
+    ref = orc.price(spec, orc.CMC, N, 64, 20000, 5, nthreads=NT_CPU)
+    assert_close(res["price"], ref["price"], spec.K, what=f"whole FP64 price at N = {N}")
+    assert res["inner_path_steps"] == ref["inner_path_steps"]
+    assert res["final_path_steps"] == ref["final_path_steps"]
+
+
 def test_full_size_final_pricing(bmc, ctx, orc, torch_mod, inputs):
     spec = inputs.geometric_put5()
     table = _small_rules(orc, spec, N=256, n=256)

@@ -327,6 +327,42 @@ __device__ __forceinline__ R cmc_score(int d, const R* __restrict__ w, R lnK, R 
 template <int D, class R>
 __device__ __forceinline__ R ada_score(int d, const R* __restrict__ w, R lnK, R g, const R (&x)[D])
 {
+    if constexpr (D <= 8 && sizeof(R) == 4) {   // (the FP64 kernels would lose a wave per SIMD)
+        // The features' binary searches in lockstep: every feature steps
+        // through h = ADA_TMAX, .., 2, 1 (a count never exceeds ADA_TMAX, so
+        // the steps above a feature's largest power of two are skipped and
+        // the rest are the sequential search's), and the reads of one step
+        // are independent of each other.  Same k, same sum order.
+        R v[D + 1];
+        int cnt[D + 1], off[D + 1], k[D + 1];
+        int o = 2 + d;
+#pragma unroll
+        for (int i = 0; i <= D; ++i) {
+            v[i] = R(0);
+            cnt[i] = 0;
+            off[i] = 0;
+            k[i] = 0;
+            if (i <= d) {
+                v[i] = i < d ? x[i < D ? i : 0] - lnK : g;
+                cnt[i] = (int)w[1 + i];
+                off[i] = o;
+                o += 2 * cnt[i];
+            }
+        }
+#pragma unroll
+        for (int h = ADA_TMAX; h > 0; h >>= 1) {
+#pragma unroll
+            for (int i = 0; i <= D; ++i) {
+                const int t = k[i] + h;
+                if (i <= d && t <= cnt[i] && w[off[i] + t - 1] <= v[i]) k[i] = t;
+            }
+        }
+        R F = w[0];
+#pragma unroll
+        for (int i = 0; i <= D; ++i)
+            if (i <= d && k[i] > 0) F += w[off[i] + cnt[i] + k[i] - 1];
+        return F;
+    }
     R F = w[0];
     const R* pr = w + 2 + d;
 #pragma unroll

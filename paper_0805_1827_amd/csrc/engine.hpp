@@ -44,7 +44,7 @@ struct OptDev {
     float* w32;
     uint64_t* cnt;
     int32_t *ids, *n_ids;   // refinement list and its count (FP32 pricings)
-    const int32_t* cancel;  // host-mapped cancel word of a served request (or null)
+    const int32_t* cancel;  // device cancel word of a served request (or null)
 };
 OptDev carve_option(const OptPlan& q, const DevSpec* spec, char* base);
 

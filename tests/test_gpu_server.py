@@ -138,7 +138,7 @@ def test_request_errors(bmc, ctx, inputs):
 
 def test_cancel_queued_and_running(bmc, ctx, inputs):
     """A cancelled queued request leaves without running; a cancelled request
-    on the device has its jobs skipped through the host-mapped flag and is
+    on the device has its jobs skipped through its device cancel word and is
     dropped at the end of the round; the request that shared its launches
     keeps the result of bmc_price."""
     big, = requests(bmc, inputs, [(5, 24, 8192, 8192, "FP64")], first_seed=900)

@@ -645,13 +645,16 @@ extern "C" bmc_status bmc_tuning_get(bmc_ctx* ctx, int32_t d, int32_t precision,
 }
 
 // Launch shape, partial-sum buffer and arguments of one continuation pass
-// over N points (ids/n_ids: the active ones, or null for all).
+// over N points (ids/n_ids: the active ones, or null for all).  With an
+// active list, max_active > 0 is a bound on its count known to the host: the
+// grid then holds that many points' jobs (the jobs are slot-major, and the
+// slots past the count return at once, so the results are unchanged).
 static bmc_status prepare_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int method, int width,
                                const void* rules64, const void* rules32, int prec, int m, const double* x, int64_t N,
                                const int32_t* ids, const int32_t* n_ids, uint32_t n, uint32_t k0, uint32_t k1,
                                const Tuning* tune, uint32_t slot, uint32_t region_pts, ContArgs& a, int& block,
                                size_t& lds, int64_t& grid, double* part = nullptr, const IzFuse* fz = nullptr,
-                               const JobOrder* ord = nullptr)
+                               const JobOrder* ord = nullptr, int64_t max_active = 0)
 {
     block = (tune && tune->block > 0) ? tune->block : 256;
     const uint32_t ppt = choose_ppt(ctx, d, prec, N, n, tune);
@@ -664,7 +667,8 @@ static bmc_status prepare_cont(bmc_ctx* ctx, const void* devspec, int d, int n_d
     }
     lds = cont_lds_bytes(prec, d, n_dates, width);
     if (lds > cont_lds_limit()) return fail(BMC_EUNSUPPORTED, "rule table too large for LDS (%zu bytes)", lds);
-    grid = (int64_t)N * nchunk;
+    const int64_t cols = (ids && max_active > 0 && max_active < N) ? max_active : N;
+    grid = cols * nchunk;
     if (grid > 0x7FFFFFFF) return fail(BMC_EINVAL, "too many jobs in one launch");
     a.spec = (const DevSpec*)devspec;
     a.rules = prec == BMC_FP64 ? rules64 : rules32;
@@ -702,14 +706,16 @@ bmc_status bmc::run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, 
                          uint32_t n, uint32_t k0, uint32_t k1, double* cont, double* se,
                          int64_t* steps, double* sums, unsigned long long* steps_total,
                          const Tuning* tune, uint32_t slot, uint32_t region_pts, uint32_t* nchunk_out,
-                         double* part, const IzFuse* fz, const RefineSel* sel, const JobOrder* ord)
+                         double* part, const IzFuse* fz, const RefineSel* sel, const JobOrder* ord,
+                         int64_t max_active)
 {
     ContArgs a{};
     int block = 256;
     size_t lds = 0;
     int64_t grid = 0;
     bmc_status st = prepare_cont(ctx, devspec, d, n_dates, method, width, rules64, rules32, prec, m, x, N, ids,
-                                 n_ids, n, k0, k1, tune, slot, region_pts, a, block, lds, grid, part, fz, ord);
+                                 n_ids, n, k0, k1, tune, slot, region_pts, a, block, lds, grid, part, fz, ord,
+                                 max_active);
     if (st) return st;
     const uint32_t nchunk = a.nchunk;
     hipError_t e;
@@ -959,6 +965,9 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
     int32_t* poll_dev = (int32_t*)((char*)ctx->host_io_dev + 128);
     int polls_issued = 0, polls_read = 0;
     bool done = false;
+    // a bound on the active count: the last count a poll returned (the lists
+    // only shrink), which caps the grid of the launches enqueued after it
+    int64_t active_max = J;
     auto read_poll = [&](bool wait) -> hipError_t {
         hipEvent_t ev = ctx->poll_ev[polls_read & 1];
         const hipError_t q = wait ? hipEventSynchronize(ev) : hipEventQuery(ev);
@@ -967,7 +976,9 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
             return hipSuccess;
         }
         if (q != hipSuccess) return q;
-        if (poll_host[polls_read & 1] == 0) done = true;
+        const int32_t v = poll_host[polls_read & 1];
+        if (v == 0) done = true;
+        else if (v > 0 && v < active_max) active_max = v;
         ++polls_read;
         return hipSuccess;
     };
@@ -1007,7 +1018,8 @@ bmc_status bmc::iz_search_impl(bmc_ctx* ctx, const void* devspec, const bmc_spec
         bmc_status st = run_cont(ctx, devspec, d, spec->n_dates, rules->method, rules->width, rules->w64,
                                  rules->w32, prec, date, x_work, J, A[prev & 1], &cnt[prev % 3], n, seed, k1,
                                  nullptr, nullptr, nullptr, nullptr, nullptr, tune, (uint32_t)region,
-                                 nreg > 1 ? (uint32_t)Jr : 0u, &nchunk, P[it & 1], &fz);
+                                 nreg > 1 ? (uint32_t)Jr : 0u, &nchunk, P[it & 1], &fz, nullptr, nullptr,
+                                 active_max);
         if (st) return st;
         if (nchunk != nch) return fail(BMC_EDEVICE, "search pass split %u chunks, expected %u", nchunk, nch);
         last = it;

@@ -107,7 +107,8 @@ bmc_status run_cont(bmc_ctx* ctx, const void* devspec, int d, int n_dates, int m
                     uint32_t k1, double* cont, double* se, int64_t* steps, double* sums,
                     unsigned long long* steps_total, const Tuning* tune, uint32_t slot = 0,
                     uint32_t region_pts = 0, uint32_t* nchunk_out = nullptr, double* part = nullptr,
-                    const IzFuse* fz = nullptr, const RefineSel* sel = nullptr, const JobOrder* ord = nullptr);
+                    const IzFuse* fz = nullptr, const RefineSel* sel = nullptr, const JobOrder* ord = nullptr,
+                    int64_t max_active = 0);
 // region: the I&Z region whose boundary row block is fitted (0 for CMC), from
 // N points in rows of ld entries (0: N).
 bmc_status fit_rule_impl(bmc_ctx* ctx, const void* devspec, int d, bmc_rules* rules, int date,

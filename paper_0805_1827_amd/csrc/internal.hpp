@@ -128,8 +128,11 @@ hipError_t launch_finalize(const double* part, uint32_t nchunk, uint32_t n, int6
                            const int32_t* ids, const int32_t* n_ids, double* cont, double* se,
                            int64_t* steps, double* sums, unsigned long long* steps_total,
                            hipStream_t st, const RefineSel* sel = nullptr);
+// zero_u64 and zero_words[0 .. nwords) (each or null; nwords <= 256) are
+// cleared by the launch, before any later launch on the stream reads them.
 hipError_t launch_bridge_end(const DevSpec* s, int d, int64_t N, uint32_t seed, double* B,
-                             hipStream_t st);
+                             hipStream_t st, unsigned long long* zero_u64 = nullptr,
+                             int32_t* zero_words = nullptr, int nwords = 0);
 // zero_count (or null) is cleared by the launch.  ord_cnt (or null, with
 // x): the launch appends every point to the bucket list of its intrinsic
 // value (ord_cnt[ORDER_BUCKETS] counts, zero beforehand; ord_list

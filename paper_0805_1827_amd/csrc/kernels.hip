@@ -375,9 +375,12 @@ __device__ __forceinline__ void bridge_back_point(const DevSpec* __restrict__ s,
     }
 }
 
-__global__ void k_bridge_end(const DevSpec* __restrict__ s, int64_t N, uint32_t seed, double* B)
+__global__ void k_bridge_end(const DevSpec* __restrict__ s, int64_t N, uint32_t seed, double* B,
+                             unsigned long long* zero_u64, int32_t* zero_words, int nwords)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (zero_u64 && j == 0) *zero_u64 = 0;
+    if (zero_words && j < nwords) zero_words[j] = 0;
     if (j < N) bridge_end_point(s, N, seed, B, j);
 }
 
@@ -425,10 +428,12 @@ __global__ void k_bridge_multi(const BridgeTask* __restrict__ tasks, const uint3
 }
 
 hipError_t launch_bridge_end(const DevSpec* s, int d, int64_t N, uint32_t seed, double* B,
-                             hipStream_t st)
+                             hipStream_t st, unsigned long long* zero_u64, int32_t* zero_words, int nwords)
 {
     (void)d;
-    hipLaunchKernelGGL(k_bridge_end, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, s, N, seed, B);
+    if (nwords < 0 || (zero_words && nwords > 256)) return hipErrorInvalidValue;   // block 0 clears them
+    hipLaunchKernelGGL(k_bridge_end, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, s, N, seed, B,
+                       zero_u64, zero_words, nwords);
     return hipGetLastError();
 }
 

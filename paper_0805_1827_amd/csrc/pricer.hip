@@ -107,7 +107,9 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
     double* x = (double*)ctx->x.ptr;
     double* cont = (double*)ctx->cont.ptr;
     double* B = (double*)ctx->B.ptr;
-    if ((e = hipMemsetAsync(steps_total, 0, sizeof(unsigned long long), ctx->stream))) {
+    // the CMC forms clear the step total (and the job-order counts) in their
+    // first bridge launch
+    if (method == BMC_IZ && (e = hipMemsetAsync(steps_total, 0, sizeof(unsigned long long), ctx->stream))) {
         release();
         return hip_fail(e, "counter reset");
     }
@@ -129,15 +131,16 @@ bmc_status bmc_price_impl(bmc_ctx* ctx, const bmc_spec* spec, const bmc_opts* op
         // clears the other set for the next date
         int32_t *ord_cnt = nullptr, *ord_list = nullptr;
         if (N <= ORDER_MAX_N) {
-            if ((e = ctx->order.ensure(256 + sizeof(int32_t) * ORDER_BUCKETS * (size_t)N)) ||
-                (e = hipMemsetAsync(ctx->order.ptr, 0, 256, ctx->stream))) {
+            if ((e = ctx->order.ensure(256 + sizeof(int32_t) * ORDER_BUCKETS * (size_t)N))) {
                 release();
                 return fail(BMC_ENOMEM, "device buffers: %s", hipGetErrorString(e));
             }
             ord_cnt = (int32_t*)ctx->order.ptr;
             ord_list = (int32_t*)((char*)ctx->order.ptr + 256);
         }
-        if ((e = launch_bridge_end((const DevSpec*)ds, d, N, seed, B, ctx->stream))) st = hip_fail(e, "bridge");
+        if ((e = launch_bridge_end((const DevSpec*)ds, d, N, seed, B, ctx->stream, steps_total, ord_cnt,
+                                   ord_cnt ? 64 : 0)))   // both count sets (256 B)
+            st = hip_fail(e, "bridge");
         for (int m = NT - 1; m >= 1 && !st; --m) {
             int32_t* cnt_m = ord_cnt ? ord_cnt + ORDER_BUCKETS * (m & 1) : nullptr;
             int32_t* cnt_clear = ord_cnt ? ord_cnt + ORDER_BUCKETS * ((m & 1) ^ 1) : nullptr;

@@ -88,11 +88,18 @@ __host__ __device__ inline int cont_rule_stride(int D, int width)
     return !bucket_exact(D) && width < 2 * D + 3 ? 2 * D + 3 : width;
 }
 
+// Whether a continuation kernel of bound D reads the correlation coefficients
+// and drifts from LDS (rsize: bytes of its stepping precision) rather than
+// from scalar registers: from D = 9 on, and in FP64 from D = 2 on, where the
+// coefficients' register pairs would not fit beside the generator's keys and
+// the compiler would keep them in vector-register lanes instead.
+__host__ __device__ constexpr bool cont_lds_coef(int D, size_t rsize) { return D >= 9 || (rsize == 8 && D >= 2); }
+
 // LDS bytes of a continuation job: discount table (double), then in the
 // stepping precision: log-point [D_MAX], dt and sqrt(dt) [NT+1], rule rows
-// [(NT+1) stride], and for D >= 9 the correlation coefficients [D4][D4]
-// (D4 = D rounded up to a multiple of 4; 16-byte aligned, at *coef_off)
-// and the drifts [D4].
+// [(NT+1) stride], and where cont_lds_coef holds the correlation
+// coefficients [D4][D4] (D4 = D rounded up to a multiple of 4; 16-byte
+// aligned, at *coef_off) and the drifts [D4].
 __host__ __device__ inline size_t cont_lds_layout(size_t rsize, int D, int n_dates, int width, size_t* coef_off)
 {
     size_t off = sizeof(double) * (n_dates + 1) +
@@ -100,7 +107,7 @@ __host__ __device__ inline size_t cont_lds_layout(size_t rsize, int D, int n_dat
     off = (off + 15) & ~(size_t)15;
     if (coef_off) *coef_off = off;
     const size_t D4 = (size_t)((D + 3) & ~3);
-    if (D >= 9) off += rsize * (D4 * D4 + D4);
+    if (cont_lds_coef(D, rsize)) off += rsize * (D4 * D4 + D4);
     return off + 16;
 }
 size_t cont_lds_bytes(int prec, int d, int n_dates, int width);

@@ -74,7 +74,7 @@ __device__ __forceinline__ void corr_mfma(const float* __restrict__ arow, const 
 // (never-exercise geometric put, N = n = 4096: by 5-17 % at d = 9..24; from
 // d = 26 the matrix cores were 4-37 % ahead, d = 28 within the spread).
 template <int D, class R> constexpr bool uses_mfma() { return D >= 25 && sizeof(R) == 4; }
-template <int D> constexpr bool uses_lds_coef() { return D >= 9; }
+template <int D, class R> constexpr bool uses_lds_coef() { return cont_lds_coef(D, sizeof(R)); }
 
 // I&Z rules need their own kernels (IZK): the boundary test of d <= 16 assets
 // (a full quadratic, and the region search of the max-call) would otherwise
@@ -89,7 +89,7 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
                                          double (*red)[16])
 {
     constexpr bool MF = uses_mfma<D, R>();
-    constexpr bool LC = uses_lds_coef<D>();
+    constexpr bool LC = uses_lds_coef<D, R>();
     constexpr int D4 = (D + 3) & ~3;   // matrix-core chunks of four assets
     // Bucket kernels (d < D possible) pad the path state to D entries with
     // neutral values, so that every per-asset loop runs to D without tests:

@@ -378,9 +378,11 @@ __device__ __forceinline__ void cont_job(const ContArgs& a, const uint32_t j, co
 // job (the whole block returns).  The loop lives in kernels of its own: in
 // the one-job kernels it would cost registers (and occupancy).  A job of a
 // cancelled served request (its cancel word set) stops after its table setup.
+// src: where the strided loop re-reads the arguments for every job (the
+// kernel's argument block, or the task's table entry).
 template <int D, bool EXACT, class R, class ACC, bool IZK, bool STRIDE>
 __device__ __forceinline__ void cont_slots(const ContArgs& a, uint32_t slot, const uint32_t chunk, double* lds,
-                                           double (*red)[16])
+                                           double (*red)[16], const ContArgs* src = nullptr)
 {
     if constexpr (!STRIDE) {
         if (a.n_ids && slot >= (uint32_t)*a.n_ids) return;
@@ -398,9 +400,17 @@ __device__ __forceinline__ void cont_slots(const ContArgs& a, uint32_t slot, con
         }
         cont_job<D, EXACT, R, ACC, IZK>(a, j, chunk, lds, red);
     } else {
-        const uint32_t lim = (uint32_t)*a.n_ids;
-        for (; slot < lim; slot += a.slot_stride) {
-            cont_job<D, EXACT, R, ACC, IZK>(a, (uint32_t)a.ids[slot], chunk, lds, red);
+        const uint32_t lim = (uint32_t)*a.n_ids, stride = a.slot_stride;
+        const int32_t* ids = a.ids;
+        for (; slot < lim; slot += stride) {
+            // Each job reads its arguments again through the scalar unit from a
+            // location the compiler cannot see through, so that none of them
+            // stays in scalar registers across the jobs: held there, they
+            // crowded the path loop's scalar registers into vector lanes.
+            const ContArgs* p = src;
+            asm volatile("" : "+s"(p));
+            const ContArgs b = load_const(p);
+            cont_job<D, EXACT, R, ACC, IZK>(b, (uint32_t)ids[slot], chunk, lds, red);
             __syncthreads();   // the LDS tables and partials of the next job
         }
     }
@@ -422,7 +432,9 @@ __global__ void __launch_bounds__(256) k_cont(const ContArgs a)
             if (a.fz.poll) *a.fz.poll = *a.n_ids;
         }
     }
-    cont_slots<D, EXACT, R, ACC, IZK, STRIDE>(a, slot, chunk, lds, red);
+    // the argument block starts the kernel's argument segment
+    cont_slots<D, EXACT, R, ACC, IZK, STRIDE>(
+        a, slot, chunk, lds, red, (const ContArgs*)__builtin_amdgcn_kernarg_segment_ptr());
 }
 
 // One launch over the jobs of many tasks (options at their own dates): block
@@ -447,7 +459,7 @@ __global__ void __launch_bounds__(256) k_cont_multi(const ContArgs* __restrict__
     const ContArgs a = load_const(tasks + lo);
     const uint32_t local = job - pre[lo];
     const uint32_t slot = local / a.nchunk;
-    cont_slots<D, EXACT, R, ACC, false, STRIDE>(a, slot, local - slot * a.nchunk, lds, red);
+    cont_slots<D, EXACT, R, ACC, false, STRIDE>(a, slot, local - slot * a.nchunk, lds, red, tasks + lo);
 }
 
 // Lets every kernel of bound D use the device's whole LDS (done once).

@@ -536,6 +536,9 @@ def main():
                     help="target CPU time of the oracle baseline (0 disables it)")
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-autotune", action="store_true", help="heuristic launch shapes for the headline")
+    ap.add_argument("--ppt", type=int, default=0,
+                    help="paths per lane of the FP32 headline's date launches instead of the autotuner's "
+                         "(profiling runs that must repeat one launch shape)")
     ap.add_argument("--batch", type=int, default=256, help="options in the batched form (0 disables it)")
     ap.add_argument("--batch-N", type=int, default=256)
     ap.add_argument("--serve-seconds", type=float, default=60.0,
@@ -566,6 +569,9 @@ def main():
         for name, prec in (("fp32", bmc.FP32), ("fp64", bmc.FP64)):
             tuning[name] = {"ppt": bmc.bmc_autotune(ctx, spec, prec, args.N, args.n),
                             "final_ppt": bmc.bmc_autotune(ctx, spec, prec, 1, args.n_final)}
+    if args.ppt > 0:
+        bmc.bmc_tuning_set(ctx, d=spec.d, precision=bmc.FP32, n=args.n, ppt=args.ppt)
+        tuning.setdefault("fp32", {})["ppt"] = args.ppt
 
     def timed(prec, steps, warmup):
         for _ in range(warmup):

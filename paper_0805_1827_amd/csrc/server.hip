@@ -21,6 +21,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "admission.hpp"
 #include "engine.hpp"
 
 using namespace bmc;
@@ -36,68 +37,6 @@ constexpr size_t CANCEL_WORD_OFFSET = 64;
 // Sets a cancel word with an agent-scope store (read by the jobs of launches
 // already running on the server's other stream).
 __global__ void k_cancel_set(int32_t* w) { __hip_atomic_store(w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-
-// First-fit allocator over one device allocation (offsets, 256-byte units).
-class Arena {
-public:
-    bool init(size_t bytes)
-    {
-        size_ = bytes & ~(size_t)255;
-        free_.clear();
-        if (size_) free_[0] = size_;
-        return true;
-    }
-    bool alloc(size_t bytes, size_t* off)
-    {
-        bytes = (bytes + 255) & ~(size_t)255;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t at = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                used_ += bytes;
-                peak_ = std::max(peak_, used_);
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        bytes = (bytes + 255) & ~(size_t)255;
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
-    size_t size() const { return size_; }
-
-private:
-    size_t size_ = 0, used_ = 0, peak_ = 0;
-    std::map<size_t, size_t> free_;
-};
-
-struct CacheEntry {
-    std::string key;
-    size_t off = 0, bytes = 0;   // [w64 rows][w32 rows] in the arena
-    int rows = 0;                // (N_T + 1) * p
-    int users = 0;               // requests copying from it this round
-    std::list<std::string>::iterator lru;
-};
 
 struct Request {
     uint64_t ticket = 0;
@@ -132,7 +71,7 @@ struct bmc_server {
     std::deque<Request*> queue;
     std::vector<Request*> active;
     std::unordered_map<uint64_t, Request*> all;     // by ticket, until polled
-    std::unordered_map<std::string, CacheEntry> cache;
+    RuleCache cache;
     std::list<std::string> lru;                       // front = most recent
     uint64_t next_ticket = 1;
     bool stop = false;
@@ -159,25 +98,7 @@ struct bmc_server {
     void loop();
     bmc_status round(std::vector<Request*>& fresh);
     void finish(Request* r, bmc_status s);
-    void cache_touch(CacheEntry& c)
-    {
-        lru.erase(c.lru);
-        lru.push_front(c.key);
-        c.lru = lru.begin();
-    }
-    bool evict_one()   // least recently used entry not in use; caller holds mu
-    {
-        for (auto it = lru.rbegin(); it != lru.rend(); ++it) {
-            auto c = cache.find(*it);
-            if (c != cache.end() && c->second.users == 0) {
-                arena.release(c->second.off, c->second.bytes);
-                lru.erase(std::next(it).base());
-                cache.erase(c);
-                return true;
-            }
-        }
-        return false;
-    }
+    bool evict_one() { return cache_evict_one(cache, lru, arena); }   // caller holds mu
 };
 
 namespace {
@@ -313,9 +234,7 @@ bmc_status bmc_server::round(std::vector<Request*>& fresh)
             c.off = off;
             c.bytes = bytes;
             c.rows = rows;
-            lru.push_front(c.key);
-            c.lru = lru.begin();
-            cache.emplace(c.key, c);
+            cache_insert(cache, lru, std::move(c));
         }
     }
     if ((e = hipStreamSynchronize(stream))) return hip_fail(e, "round");
@@ -375,28 +294,13 @@ void bmc_server::loop()
             if (cache_cap > 0)
                 for (Request* a : active)
                     if (!a->hit && a->stage >= 1) ++learning[a->key];
-            for (auto qi = queue.begin(); qi != queue.end() && (int)active.size() < max_inflight &&
-                                          !free_slots.empty();) {
-                Request* r = *qi;
-                auto c = cache.find(r->key);
-                r->hit = c != cache.end();
-                if (!r->hit && learning.count(r->key)) {
-                    ++qi;
-                    continue;
-                }
-                size_t off;
-                bool ok = arena.alloc(r->q.bytes, &off);
-                while (!ok && evict_one()) ok = arena.alloc(r->q.bytes, &off);
-                if (!ok) break;   // wait for memory to free up
-                if (r->hit) {
-                    c = cache.find(r->key);   // eviction above may have removed it
-                    r->hit = c != cache.end();
-                }
-                qi = queue.erase(qi);
-                if (!r->hit && cache_cap > 0) ++learning[r->key];
+            auto key_of = [](Request* r) -> const std::string& { return r->key; };
+            auto bytes_of = [](Request* r) { return r->q.bytes; };
+            auto inflight = [&] { return (int)active.size(); };
+            auto on_admit = [&](Request* r, size_t off, uint32_t slot, bool hit) {
+                r->hit = hit;
                 r->off = off;
-                r->slot = free_slots.back();
-                free_slots.pop_back();
+                r->slot = slot;
                 r->dev = carve_option(r->q, specs + r->slot, dev_arena + off);
                 // the cancel word sits in the counters block, which the
                 // request's setup zeroes before its first launch
@@ -406,14 +310,17 @@ void bmc_server::loop()
                 r->admitted = clk::now();
                 if (r->hit) {
                     ++st.cache_hits;
-                    ++c->second.users;
-                    cache_touch(c->second);
+                    CacheEntry& c = cache.at(r->key);
+                    ++c.users;
+                    cache_touch(lru, c);
                 } else {
                     ++st.cache_misses;
                 }
                 active.push_back(r);
                 fresh.push_back(r);
-            }
+            };
+            admit_pass(queue, arena, cache, lru, free_slots, max_inflight, learning, cache_cap > 0, key_of, bytes_of,
+                       inflight, on_admit);
         }
         const auto t0 = clk::now();
         const bmc_status s = round(fresh);
@@ -498,11 +405,12 @@ extern "C" bmc_status bmc_server_submit(bmc_server* s, const bmc_spec* spec, con
         delete r;
         return st;
     }
-    if (r->q.bytes > s->arena.size()) {
+    if (!s->arena.could_ever_hold(r->q.bytes)) {
+        const size_t need = r->q.bytes;
         delete r;
         std::lock_guard<std::mutex> g(s->mu);
         ++s->st.rejected;
-        return fail(BMC_ENOMEM, "request needs %zu bytes of device memory, the server has %zu", r->q.bytes,
+        return fail(BMC_ENOMEM, "request needs %zu bytes of device memory, the server has %zu", need,
                     s->arena.size());
     }
     std::memset(&r->pack, 0, sizeof(r->pack));
